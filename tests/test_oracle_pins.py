@@ -1,0 +1,452 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one part of the oracle to mathematics the paper fixes or to an
+independent computation: the deprojection (App. A) against a numerical
+line-of-sight integral of the deprojected density; the potential against
+Poisson's equation and its spherical closed form; the full closed form
+against a brute-force nested quadrature of the cylindrical Jeans equations;
+the spherical isotropic limit against the textbook projected-dispersion
+integral; the distance scaling of Sect. 2.4 (eq. scale Dd to Vlos); exact
+linearities and symmetries; the PSF convolution and bin sums against library
+routines and loops; and the autograd gradient against central differences.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import integrate, signal, special
+
+from oracle import jam
+from paper_2504_01302_amd import inputs
+
+DT = torch.float64
+
+
+def _geom(**kw):
+    """A hand-made geometry (no randomness) for analytic pins."""
+    base = dict(
+        lum_sigma=np.array([0.8]), lum_q=np.array([0.7]), lum_I0=np.array([1.0]),
+        mass_sigma=np.array([0.5, 1.5]), mass_q=np.array([0.75, 0.85]),
+        mass_S0=np.array([3000.0, 800.0]), bh_sigma=0.01, distance_mpc=1000.0,
+        nx=5, ny=5, pixsize=0.2, xc=0.0, yc=0.0, supersample=1,
+        psf=np.ones((1, 1)), n_bins=1, bin_index=np.zeros((5, 5), np.int32), n_u=128)
+    base.update(kw)
+    return inputs.Geometry(**base)
+
+
+def _params(g, inc_deg=60.0, beta=0.3, ml=1.0, mbh=0.0):
+    return inputs.Params(np.deg2rad(inc_deg), np.full(g.n_lum, beta), ml, mbh)
+
+
+# --------------------------------------------------------------------------
+# Constants.
+# --------------------------------------------------------------------------
+
+def test_gravitational_constant_textbook_value():
+    # G = 4.3009e-3 pc (km/s)^2 / Msun is the commonly quoted value.
+    assert abs(jam.G_PC_KMS2 / 4.3009e-3 - 1.0) < 5e-5
+
+
+def test_arcsec_scale():
+    # 1 arcsec at 1 Mpc = 4.8481 pc (small-angle, radians per arcsec).
+    assert abs(jam.pc_per_arcsec(1.0) - 4.84813681) < 1e-7
+
+
+def test_gauss_legendre_exact_on_polynomials():
+    u, w = jam.gauss_legendre_unit(7)
+    for deg in range(14):
+        assert abs(np.sum(w * u ** deg) - 1.0 / (deg + 1)) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# P1: App. A deprojection projects back onto the observed Gaussian.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("inc_deg,qobs", [(60.0, 0.7), (85.0, 0.6), (48.0, 0.8)])
+def test_deprojection_projects_back(inc_deg, qobs):
+    inc = torch.tensor(np.deg2rad(inc_deg), dtype=DT)
+    sig, I0 = 0.9, 2.5
+    q = jam.intrinsic_axis_ratio(torch.tensor([qobs], dtype=DT), inc)[0].item()
+    nu0 = jam.peak_density(torch.tensor(I0, dtype=DT), sig, qobs, q).item()
+    si, ci = math.sin(np.deg2rad(inc_deg)), math.cos(np.deg2rad(inc_deg))
+    for xp, yp in [(0.0, 0.0), (0.4, -0.3), (1.1, 0.7)]:
+        def nu(zp):
+            # line of sight (0, sin i, cos i); sky y' along (0, -cos i, sin i)
+            y = -yp * ci + zp * si
+            z = yp * si + zp * ci
+            return nu0 * math.exp(-(xp ** 2 + y ** 2 + z ** 2 / q ** 2) / (2 * sig ** 2))
+        val, _ = integrate.quad(nu, -np.inf, np.inf, epsabs=0, epsrel=1e-13)
+        expect = I0 * math.exp(-(xp ** 2 + yp ** 2 / qobs ** 2) / (2 * sig ** 2))
+        assert abs(val / expect - 1.0) < 1e-11
+
+
+def test_deprojection_limit_raises():
+    with pytest.raises(ValueError):
+        jam.intrinsic_axis_ratio(torch.tensor([0.6], dtype=DT),
+                                 torch.tensor(np.deg2rad(50.0), dtype=DT))
+
+
+# --------------------------------------------------------------------------
+# The homoeoid potential used by the derivation: spherical closed form and
+# Poisson's equation for a flattened Gaussian.
+# --------------------------------------------------------------------------
+
+def _phi(R, z, sig, q, M=1.0, G=1.0):
+    e2 = 1.0 - q * q
+    f = lambda u: math.exp(-u * u * (R * R + z * z / (1 - e2 * u * u)) / (2 * sig * sig)) \
+        / math.sqrt(1 - e2 * u * u)
+    val, _ = integrate.quad(f, 0.0, 1.0, epsabs=0, epsrel=1e-13, limit=200)
+    return -math.sqrt(2 / math.pi) * G * M / sig * val
+
+
+def test_potential_spherical_closed_form():
+    for r in [0.05, 0.3, 1.0, 4.0]:
+        expect = -special.erf(r / (math.sqrt(2) * 0.7)) / r
+        assert abs(_phi(r, 0.0, 0.7, 1.0) / expect - 1) < 1e-12
+        assert abs(_phi(r * 0.6, r * 0.8, 0.7, 1.0) / expect - 1) < 1e-12
+
+
+@pytest.mark.parametrize("R,z", [(0.3, 0.2), (0.8, -0.5), (0.1, 0.9)])
+def test_potential_poisson(R, z):
+    sig, q = 0.7, 0.55
+    d = 2e-3
+    p = lambda R_, z_: _phi(R_, z_, sig, q)
+    lap = ((p(R + d, z) - 2 * p(R, z) + p(R - d, z)) / d ** 2
+           + (p(R + d, z) - p(R - d, z)) / (2 * d * R)
+           + (p(R, z + d) - 2 * p(R, z) + p(R, z - d)) / d ** 2)
+    rho = 1.0 / ((2 * math.pi) ** 1.5 * sig ** 3 * q) * \
+        math.exp(-(R * R + z * z / (q * q)) / (2 * sig * sig))
+    assert abs(lap / (4 * math.pi * rho) - 1) < 2e-5
+
+
+# --------------------------------------------------------------------------
+# P3: brute-force nested quadrature of the cylindrical Jeans solution.
+# --------------------------------------------------------------------------
+
+def _brute_numerator(g, p, xp, yp):
+    """N(x', y') from the Jeans equations by numerical integration only:
+    Phi by quadrature in u, its gradients by central differences, nu v_z^2 by
+    quadrature in z, d/dR by central differences, then the line-of-sight
+    integral of nu v_los^2."""
+    s = jam.pc_per_arcsec(g.distance_mpc)
+    G = jam.G_PC_KMS2
+    inc = p.inc
+    si, ci = math.sin(inc), math.cos(inc)
+    # deprojected tracer and masses (App. A), written out here
+    ql = math.sqrt(g.lum_q[0] ** 2 - ci ** 2) / si
+    sl = g.lum_sigma[0]
+    nu0 = g.lum_q[0] * g.lum_I0[0] / (math.sqrt(2 * math.pi) * sl * ql)
+    b = 1.0 / (1.0 - p.beta[0])
+    masses = []
+    for sj, qoj, S0 in zip(g.mass_sigma, g.mass_q, g.mass_S0):
+        qj = math.sqrt(qoj ** 2 - ci ** 2) / si
+        Mj = p.mass_scale * 2 * math.pi * S0 * (s * sj) ** 2 * qoj
+        masses.append((sj, qj, Mj))
+    ug, wg = np.polynomial.legendre.leggauss(160)
+    ug, wg = 0.5 * (ug + 1), 0.5 * wg
+
+    def phi(R, z):
+        tot = 0.0
+        for sj, qj, Mj in masses:
+            e2 = 1 - qj * qj
+            hh = 1 - e2 * ug * ug
+            f = np.exp(-ug * ug * (R * R + z * z / hh) / (2 * sj * sj)) / np.sqrt(hh)
+            tot += -math.sqrt(2 / math.pi) * G * Mj / (s * sj) * np.sum(wg * f)
+        return tot
+
+    def nu(R, z):
+        return nu0 * math.exp(-(R * R + z * z / ql ** 2) / (2 * sl * sl))
+
+    dd = 1e-5
+
+    def dphidz(R, z):
+        return (phi(R, z + dd) - phi(R, z - dd)) / (2 * dd)
+
+    def dphidR(R, z):
+        return (phi(R + dd, z) - phi(R - dd, z)) / (2 * dd)
+
+    def nuvz2(R, z):
+        v, _ = integrate.quad(lambda zz: nu(R, zz) * dphidz(R, zz), z, z + 8.0,
+                              epsabs=0, epsrel=1e-11, limit=200)
+        return v
+
+    def integrand(zp):
+        y = -yp * ci + zp * si
+        z = yp * si + zp * ci
+        R = math.hypot(xp, y)
+        S = nuvz2(R, z)
+        dR = 1e-4
+        dSdR = (nuvz2(R + dR, z) - nuvz2(R - dR, z)) / (2 * dR)
+        diff = b * R * dSdR + R * nu(R, z) * dphidR(R, z)      # nu (v_phi^2 - v_R^2)
+        return ci * ci * S + si * si * (b * S + diff * xp * xp / (R * R))
+
+    val, _ = integrate.quad(integrand, -6.0, 6.0, epsabs=0, epsrel=1e-9, limit=200)
+    return val
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("xp,yp", [(0.3, 0.2), (0.7, -0.45)])
+def test_closed_form_matches_brute_force_jeans(xp, yp):
+    g = _geom(n_u=200)
+    p = _params(g, inc_deg=62.0, beta=0.3, ml=1.0, mbh=0.0)
+    N, _ = jam.point_values(g, p, np.array([xp]), np.array([yp]))
+    ref = _brute_numerator(g, p, xp, yp)
+    assert abs(N.item() / ref - 1) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# P2: spherical isotropic limit = textbook projected dispersion.
+# --------------------------------------------------------------------------
+
+def test_spherical_isotropic_limit():
+    g = _geom(lum_sigma=np.array([0.3, 1.2]), lum_q=np.array([1.0, 1.0]),
+              lum_I0=np.array([5.0, 1.0]),
+              mass_sigma=np.array([0.4, 2.0]), mass_q=np.array([1.0, 1.0]),
+              mass_S0=np.array([5000.0, 500.0]), n_u=256)
+    p = inputs.Params(np.deg2rad(70.0), np.zeros(2), 1.1, 2e8)
+    s = jam.pc_per_arcsec(g.distance_mpc)
+    G = jam.G_PC_KMS2
+    Ms = [1.1 * 2 * math.pi * S0 * (s * sj) ** 2 for S0, sj in zip(g.mass_S0, g.mass_sigma)]
+    Ms.append(2e8)
+    sigs = list(g.mass_sigma) + [g.bh_sigma]
+
+    def nu(r):
+        return sum(I0 / (math.sqrt(2 * math.pi) * sk) * math.exp(-r * r / (2 * sk * sk))
+                   for I0, sk in zip(g.lum_I0, g.lum_sigma))
+
+    def mass(r):
+        return sum(M * (special.erf(r / (math.sqrt(2) * sj))
+                        - math.sqrt(2 / math.pi) * r / sj * math.exp(-r * r / (2 * sj * sj)))
+                   for M, sj in zip(Ms, sigs))
+
+    Rs = np.array([0.05, 0.3, 0.8])
+    N, I = jam.point_values(g, p, Rs * 0.6, Rs * 0.8)
+    for R, n_, i_ in zip(Rs, N.numpy(), I.numpy()):
+        val, _ = integrate.quad(lambda r: nu(r) * mass(r) * math.sqrt(r * r - R * R) / (r * r),
+                                R, np.inf, epsabs=0, epsrel=1e-13, limit=400)
+        assert abs(n_ / (2 * G / s * val) - 1) < 1e-9
+        Iexp = sum(I0 * math.exp(-R * R / (2 * sk * sk)) for I0, sk in zip(g.lum_I0, g.lum_sigma))
+        assert abs(i_ / Iexp - 1) < 1e-14
+
+
+def test_spherical_isotropic_independent_of_inclination():
+    g = _geom(lum_q=np.array([1.0]), mass_q=np.array([1.0, 1.0]), n_u=64)
+    x, y = np.array([0.2, 0.5, 0.9]), np.array([0.1, -0.4, 0.3])
+    N1, _ = jam.point_values(g, _params(g, 40.0, 0.0, mbh=1e8), x, y)
+    N2, _ = jam.point_values(g, _params(g, 85.0, 0.0, mbh=1e8), x, y)
+    assert torch.allclose(N1, N2, rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P6: distance scaling, eq. (scale Dd to Vlos): masses fixed in Msun,
+# v_rms^2 proportional to 1/D.
+# --------------------------------------------------------------------------
+
+def test_distance_scaling_fixed_masses():
+    g = inputs.small_geometry(seed=3)
+    p = inputs.small_params(g, seed=3)
+    V1 = jam.vrms2(g, p)
+    lam = 2.5
+    g2 = inputs.Geometry(**{**g.__dict__, "distance_mpc": g.distance_mpc * lam,
+                            "mass_S0": g.mass_S0 / lam ** 2})
+    V2 = jam.vrms2(g2, p)
+    assert torch.allclose(V2 * lam, V1, rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P4: exact linearities.
+# --------------------------------------------------------------------------
+
+def test_linear_in_mass():
+    g = inputs.small_geometry(seed=4)
+    p = inputs.small_params(g, seed=4)
+    x, y = np.array([0.05, 0.3]), np.array([0.2, -0.1])
+    N1, _ = jam.point_values(g, p, x, y)
+    p2 = inputs.with_overrides(p, mass_scale=p.mass_scale * 3.0, m_bh=p.m_bh * 3.0)
+    N2, _ = jam.point_values(g, p2, x, y)
+    assert torch.allclose(N2, 3.0 * N1, rtol=1e-13, atol=0)
+
+
+def test_mass_scale_leaves_black_hole_alone():
+    g = inputs.small_geometry(seed=4)
+    p = inputs.small_params(g, seed=4)
+    x, y = np.array([0.02, 0.3]), np.array([0.01, -0.2])
+    N = lambda ml, mbh: jam.point_values(g, inputs.with_overrides(p, mass_scale=ml, m_bh=mbh), x, y)[0]
+    lhs = N(2.0, 5e8)
+    rhs = 2.0 * N(1.0, 0.0) + N(0.0, 5e8)
+    assert torch.allclose(lhs, rhs, rtol=1e-13, atol=0)
+
+
+def test_affine_in_anisotropy():
+    g = inputs.small_geometry(seed=5)
+    p = inputs.small_params(g, seed=5)
+    vals = []
+    for bk in (0.8, 1.3, 1.8):           # b_k = 1/(1-beta_k)
+        beta = p.beta.copy()
+        beta[1] = 1.0 - 1.0 / bk
+        vals.append(jam.vrms2(g, inputs.with_overrides(p, beta=beta)))
+    d1 = (vals[1] - vals[0]) / 0.5
+    d2 = (vals[2] - vals[1]) / 0.5
+    assert torch.allclose(d1, d2, rtol=1e-9, atol=1e-9 * float(vals[0].abs().max()))
+    assert float(d1.abs().max()) > 0
+
+
+def test_bilinear_in_amplitudes():
+    g = inputs.small_geometry(seed=6)
+    p = inputs.small_params(g, seed=6)
+    x, y = np.array([0.1, 0.4]), np.array([0.0, 0.3])
+    I0 = g.lum_I0.copy()
+    S0 = g.mass_S0.copy()
+    base, _ = jam.point_values(g, inputs.with_overrides(p, lum_I0=I0, mass_S0=S0, m_bh=0.0), x, y)
+    I2 = I0.copy(); I2[0] *= 2.0
+    N_l, _ = jam.point_values(g, inputs.with_overrides(p, lum_I0=I2, mass_S0=S0, m_bh=0.0), x, y)
+    only0 = np.zeros_like(I0); only0[0] = I0[0]
+    N_0, _ = jam.point_values(g, inputs.with_overrides(p, lum_I0=only0, mass_S0=S0, m_bh=0.0), x, y)
+    assert torch.allclose(N_l, base + N_0, rtol=1e-13, atol=0)
+    S2 = S0 * 0.5
+    N_m, _ = jam.point_values(g, inputs.with_overrides(p, lum_I0=I0, mass_S0=S2, m_bh=0.0), x, y)
+    assert torch.allclose(N_m, 0.5 * base, rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P5: mirror symmetry of the sky maps about both axes.
+# --------------------------------------------------------------------------
+
+def test_mirror_symmetry():
+    g = inputs.small_geometry(seed=7)
+    p = inputs.small_params(g, seed=7)
+    x = np.array([0.13, 0.41, 0.77]); y = np.array([0.21, 0.05, 0.6])
+    N, I = jam.point_values(g, p, x, y)
+    for sx, sy in [(-1, 1), (1, -1), (-1, -1)]:
+        N2, I2 = jam.point_values(g, p, sx * x, sy * y)
+        assert torch.equal(N, N2) and torch.equal(I, I2)
+
+
+# --------------------------------------------------------------------------
+# P7: convergence of the u-quadrature.
+# --------------------------------------------------------------------------
+
+def test_quadrature_convergence():
+    g = inputs.small_geometry(seed=8)
+    p = inputs.small_params(g, seed=8)
+    x, y = np.array([0.05, 0.4, 1.2]), np.array([0.02, -0.3, 0.9])
+    vals = []
+    for n in (32, 64, 128, 256):
+        gn = inputs.Geometry(**{**g.__dict__, "n_u": n})
+        vals.append(jam.point_values(gn, p, x, y)[0])
+    errs = [float(torch.max(torch.abs(v / vals[-1] - 1))) for v in vals[:-1]]
+    assert errs[1] < errs[0] and errs[2] < 1e-9
+
+
+# --------------------------------------------------------------------------
+# P8/P9: PSF convolution, bin sums, special cases, positivity.
+# --------------------------------------------------------------------------
+
+def test_convolution_matches_scipy_asymmetric_kernel():
+    rng = np.random.default_rng(0)
+    m = rng.standard_normal((11, 14))
+    k = rng.standard_normal((5, 5))
+    ours = jam.convolve_valid(torch.as_tensor(m), k, 2).numpy()
+    ref = signal.convolve2d(m, k, mode="valid")
+    assert np.allclose(ours, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_bin_sums_loop():
+    g = inputs.small_geometry(seed=9, nx=5, ny=4, ss=2, n_bins=3)
+    bi = g.bin_index.copy(); bi[0, 0] = -1
+    g = inputs.Geometry(**{**g.__dict__, "bin_index": bi})
+    rng = np.random.default_rng(1)
+    c = rng.standard_normal((g.ny * 2, g.nx * 2))
+    got = jam.bin_sums(torch.as_tensor(c), g).numpy()
+    exp = np.zeros(g.n_bins)
+    for my in range(g.ny * 2):
+        for mx in range(g.nx * 2):
+            b = bi[my // 2, mx // 2]
+            if b >= 0:
+                exp[b] += c[my, mx]
+    assert np.allclose(got, exp, rtol=1e-14, atol=1e-14)
+
+
+def test_padded_grid_geometry():
+    g = inputs.small_geometry(seed=1, nx=4, ny=3, ss=2, psf_n=5, pixsize=0.1, xc=0.03, yc=-0.02)
+    x, y, h = jam.padded_subgrid(g)
+    assert h == 2 and x.shape == (4 * 2 + 4,) and y.shape == (3 * 2 + 4,)
+    assert np.allclose(np.diff(x), 0.05) and np.allclose(np.diff(y), 0.05)
+    # sub-pixels of pixel (0, 0) sit at its centre -/+ pitch/4
+    cx = 0.03 + (0 - 1.5) * 0.1
+    assert np.isclose(x[h], cx - 0.025) and np.isclose(x[h + 1], cx + 0.025)
+    assert np.isclose(0.5 * (x[h] + x[-h - 1]), 0.03)
+
+
+def test_delta_psf_single_pixel_bins_give_pixel_ratio():
+    g = inputs.small_geometry(seed=2, nx=3, ny=2, psf_n=1, n_bins=6)
+    g = inputs.Geometry(**{**g.__dict__, "psf": np.ones((1, 1)),
+                           "bin_index": np.arange(6, dtype=np.int32).reshape(2, 3)})
+    p = inputs.small_params(g, seed=2)
+    V = jam.vrms2(g, p)
+    x, y, _ = jam.padded_subgrid(g)
+    X, Y = np.meshgrid(x, y)
+    N, I = jam.point_values(g, p, X.ravel(), Y.ravel())
+    assert torch.allclose(V, N / I, rtol=1e-14, atol=0)
+
+
+def test_positive_maps_cfg1():
+    w = inputs.config1()
+    N, I = jam.maps(w.geometries[0], w.params[0])
+    assert torch.all(N > 0) and torch.all(I > 0)
+
+
+def test_bin_subset_equals_full():
+    g = inputs.small_geometry(seed=11, nx=8, ny=6, ss=2, psf_n=5, n_bins=5)
+    p = inputs.small_params(g, seed=11)
+    full = jam.vrms2(g, p)
+    sub = jam.vrms2_bins(g, p, [1, 3])
+    assert torch.allclose(sub, full[[1, 3]], rtol=1e-14, atol=0)
+
+
+# --------------------------------------------------------------------------
+# P11: the autograd gradient against central finite differences.
+# --------------------------------------------------------------------------
+
+def test_gradient_central_differences():
+    g = inputs.small_geometry(seed=12, n_lum=3, n_mass=2, nx=6, ny=5, psf_n=3, n_bins=3)
+    p = inputs.small_params(g, seed=12)
+    p = inputs.with_overrides(p, lum_I0=g.lum_I0.copy(), mass_S0=g.mass_S0.copy())
+    cot = np.random.default_rng(3).standard_normal(g.n_bins)
+    _, grads = jam.vrms2_and_grad(g, p, cot)
+
+    def L(pp):
+        return float(torch.sum(jam.vrms2(g, pp) * torch.as_tensor(cot)))
+
+    def fd(setter, x0):
+        """Richardson-extrapolated central difference, O(h^4); O(1)
+        parameters (angle, anisotropy) take an absolute step, masses and
+        amplitudes a relative one.  Returns (value, roundoff bound)."""
+        hstep = 1e-3 * max(abs(x0), 1.0)
+        d1 = (L(setter(x0 + hstep)) - L(setter(x0 - hstep))) / (2 * hstep)
+        d2 = (L(setter(x0 + hstep / 2)) - L(setter(x0 - hstep / 2))) / hstep
+        return (4 * d2 - d1) / 3, 1e-14 * Lscale / hstep
+
+    Lscale = float(torch.sum(torch.abs(jam.vrms2(g, p) * torch.as_tensor(cot))))
+    checks = [("inc", None, lambda v: inputs.with_overrides(p, inc=v), p.inc),
+              ("mass_scale", None, lambda v: inputs.with_overrides(p, mass_scale=v), p.mass_scale),
+              ("m_bh", None, lambda v: inputs.with_overrides(p, m_bh=v), p.m_bh)]
+    for k in range(g.n_lum):
+        def sb(v, k=k):
+            b = p.beta.copy(); b[k] = v
+            return inputs.with_overrides(p, beta=b)
+
+        def si(v, k=k):
+            a = p.lum_I0.copy(); a[k] = v
+            return inputs.with_overrides(p, lum_I0=a)
+        checks += [("beta", k, sb, p.beta[k]), ("lum_I0", k, si, p.lum_I0[k])]
+    for j in range(g.n_mass):
+        def sm(v, j=j):
+            a = p.mass_S0.copy(); a[j] = v
+            return inputs.with_overrides(p, mass_S0=a)
+        checks.append(("mass_S0", j, sm, p.mass_S0[j]))
+    for key, idx, setter, x0 in checks:
+        gv = grads[key] if idx is None else grads[key][idx]
+        ref, noise = fd(setter, x0)
+        assert abs(float(gv) - ref) <= 1e-7 * abs(ref) + noise, (key, idx, float(gv), ref)
