@@ -1,0 +1,204 @@
+/*
+ * jam.h - C ABI of the MI355X (gfx950) library for the cylindrically aligned
+ * Jeans Anisotropic Model (JAM) projected second moment of a
+ * Multi-Gaussian-Expansion (MGE) galaxy with a central black hole, followed
+ * by PSF convolution and luminosity-weighted binning, and its adjoint.
+ *
+ * What is computed (paper Sect. 2.4 and App. A):
+ *   - the light MGE, eq. (sb_mge_2D), and the mass MGE, eq. (smd_mge), are
+ *     deprojected at inclination i (App. A, requires cos^2 i < q'^2_min);
+ *   - the line-of-sight luminosity-weighted second moment, eq. (VLos), of a
+ *     cylindrically aligned, per-Gaussian anisotropic Jeans solution in the
+ *     potential of the mass MGE plus a BH Gaussian (sigma_BH, q' = 1);
+ *   - convolution of I v_los^2 and of I with the kinematic PSF and their
+ *     ratio summed over every bin (unnumbered equation before eq. (Vrms)),
+ *     giving v_rms^2 per bin; v_rms = sqrt of that (eq. (Vrms)) is left to
+ *     the caller.
+ *
+ * Units: lengths on the sky in arcsec, distance in Mpc, masses in Msun,
+ * Sigma0 in Msun/pc^2, luminous amplitudes in any unit (they cancel),
+ * inclination in radians (pi/2 = edge-on), output in (km/s)^2.
+ * Anisotropy beta_k = 1 - v_z^2 / v_R^2 per luminous Gaussian.
+ *
+ * Memory: every pointer is a HOST pointer unless its comment says DEVICE.
+ * Arrays are contiguous, float64 unless stated, row-major.  The library
+ * launches its kernels asynchronously on the caller's HIP stream (passed as
+ * void*, a hipStream_t); results are ready when that stream is.  Calls on
+ * one context must not overlap in time (one stream at a time); separate
+ * contexts are independent.
+ *
+ * Errors: every call returns a jam_status; on anything but JAM_OK nothing
+ * was launched unless stated, and jam_last_error() returns a message
+ * (thread-local, valid until the next call on the same thread).
+ */
+#ifndef JAM_H
+#define JAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jam_ctx jam_ctx;
+
+typedef enum {
+  JAM_OK = 0,
+  JAM_E_INVALID_ARG = 1,   /* a size, pointer or geometry value is invalid        */
+  JAM_E_DEPROJECTION = 2,  /* per model: cos^2 i >= q'^2_min (App. A)             */
+  JAM_E_NONPHYSICAL = 3,   /* per model: beta_k >= 1, negative mass or amplitude  */
+  JAM_E_WORKSPACE = 4,     /* workspace missing or smaller than required          */
+  JAM_E_DEVICE = 5,        /* a HIP runtime call or kernel launch failed          */
+  JAM_E_UNSUPPORTED = 6    /* option or size outside what this build supports     */
+} jam_status;
+
+/* One galaxy model's fixed description (what a sampler does not vary).
+ * All arrays are HOST memory and are deep-copied by jam_create.
+ *
+ * Light MGE, eq. (sb_mge_2D): n_lum >= 1 Gaussians of dispersion
+ *   lum_sigma[k] > 0 [arcsec] along the projected major axis, apparent axis
+ *   ratio 0 < lum_q[k] <= 1 and default peak lum_I0[k] >= 0.
+ * Mass MGE, eq. (smd_mge): n_mass >= 0 Gaussians (mass_sigma, mass_q as
+ *   above, default peak mass_S0[j] >= 0 in Msun/pc^2); the BH is appended as
+ *   one more mass Gaussian of dispersion bh_sigma > 0 [arcsec], q' = 1.
+ * Sky: nx x ny pixels of side pixsize [arcsec]; pixel (ix, iy) is centred at
+ *   (xc + (ix - (nx-1)/2) pixsize, yc + (iy - (ny-1)/2) pixsize) with the
+ *   galaxy at the origin and x along the major axis; each pixel is split
+ *   into supersample x supersample sub-pixels.
+ * PSF: psf_n x psf_n kernel (psf_n odd), row-major, sampled on the
+ *   sub-pixel grid; it is used as given (normalise it to unit sum).
+ * Bins: bin_index[iy * nx + ix] in [-1, n_bins), -1 = excluded; every bin
+ *   must own at least one pixel.  Sub-pixels inherit their pixel's bin.
+ * Quadrature: n_u in [1, 1024] Gauss-Legendre nodes on u in [0, 1].       */
+typedef struct {
+  int32_t n_lum;
+  const double *lum_sigma, *lum_q, *lum_I0;
+  int32_t n_mass;
+  const double *mass_sigma, *mass_q, *mass_S0;
+  double bh_sigma;
+  double distance_mpc;
+  int32_t nx, ny;
+  double pixsize, xc, yc;
+  int32_t supersample;
+  int32_t psf_n;
+  const double *psf;
+  int32_t n_bins;
+  const int32_t *bin_index;
+  int32_t n_u;
+} jam_geometry;
+
+/* form: 0 = automatic (tuned choice), 1 = per-pixel VALU quadrature kernel,
+ *       2 = separable matrix-core (MFMA) kernel.
+ * autotune: 1 = time the candidate kernel shapes once per shape bucket and
+ *       keep the fastest (cached in tune_cache, a JSON path, if not NULL).   */
+typedef struct {
+  int32_t form;
+  int32_t autotune;
+  const char *tune_cache;
+} jam_options;
+
+/* A batch of n >= 1 models.  geom_idx is HOST memory (n entries, each a
+ * geometry index given to jam_create).  Everything else is DEVICE memory:
+ * inc[n] (radians), mass_scale[n] (multiplies every mass Gaussian but the
+ * BH), m_bh[n] (Msun); beta packed model after model, n_lum(geometry) values
+ * each; lum_I0 / mass_S0 packed the same way, or NULL to use the geometry
+ * defaults.                                                                   */
+typedef struct {
+  int32_t n;
+  const int32_t *geom_idx;
+  const double *inc;
+  const double *mass_scale;
+  const double *m_bh;
+  const double *beta;
+  const double *lum_I0;
+  const double *mass_S0;
+} jam_batch;
+
+/* Gradients of sum_b cot_b v_rms^2_b, DEVICE memory packed like jam_batch
+ * (inc, mass_scale, m_bh: n each; beta, lum_I0: sum n_lum; mass_S0:
+ * sum n_mass).  Any pointer may be NULL to skip that output.                 */
+typedef struct {
+  double *inc, *mass_scale, *m_bh, *beta, *lum_I0, *mass_S0;
+} jam_grads;
+
+/* Create a context owning device copies of n_geom geometries (validated on
+ * the host; JAM_E_INVALID_ARG names the first bad field).  opt may be NULL.
+ * Allocates device memory; uses the current HIP device.                      */
+jam_status jam_create(int32_t n_geom, const jam_geometry *geoms,
+                      const jam_options *opt, jam_ctx **out);
+
+/* Release everything the context owns (NULL is ignored).  The caller must
+ * ensure no work using the context is still running.                        */
+void jam_destroy(jam_ctx *ctx);
+
+/* Sizes of a batch composition: total packed bins (length of the vrms2
+ * output and of the cotangent), total luminous and mass Gaussians (lengths
+ * of the packed beta / lum_I0 and mass_S0 arrays).  Any output may be NULL.  */
+jam_status jam_batch_sizes(const jam_ctx *ctx, int32_t n, const int32_t *geom_idx,
+                           int64_t *n_bins_total, int64_t *n_lum_total,
+                           int64_t *n_mass_total);
+
+/* Device workspace, in bytes, that jam_eval_batch (with_vjp = 0) or jam_vjp
+ * (with_vjp = 1) needs for this composition.                                 */
+jam_status jam_workspace_size(jam_ctx *ctx, int32_t n, const int32_t *geom_idx,
+                              int32_t with_vjp, size_t *bytes);
+
+/* Build (or find) the device-side work lists of a batch composition ahead of
+ * time.  The first evaluation of a new composition does this itself, which
+ * allocates and copies; once prepared, evaluations of that composition
+ * neither allocate nor copy and may be captured in a HIP graph.             */
+jam_status jam_prepare(jam_ctx *ctx, int32_t n, const int32_t *geom_idx);
+
+/* Forward model for a batch: vrms2 (DEVICE, sum n_bins doubles, model after
+ * model) receives v_rms^2 per bin; status (DEVICE int32[n], may be NULL)
+ * receives JAM_OK, JAM_E_DEPROJECTION or JAM_E_NONPHYSICAL per model, whose
+ * bins are then NaN (other models are unaffected).  ws: DEVICE workspace of
+ * ws_bytes >= jam_workspace_size(..., 0).                                    */
+jam_status jam_eval_batch(jam_ctx *ctx, const jam_batch *batch, double *vrms2,
+                          int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Same as jam_eval_batch for exactly one model (batch->n must be 1).       */
+jam_status jam_eval(jam_ctx *ctx, const jam_batch *one, double *vrms2,
+                    int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Unconvolved sky maps on the padded sub-pixel grid of every model:
+ * N = int rho_* v_los^2 dz' (numerator of eq. (VLos)) and I (eq.
+ * (sb_mge_2D)), each DEVICE, nyp x nxp doubles per model, model after model,
+ * with nxp = nx*supersample + psf_n - 1 (likewise nyp); N / I is the
+ * per-pixel v_los^2 of eq. (VLos).  Workspace as for jam_eval_batch.         */
+jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map,
+                         double *I_map, int32_t *status, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Adjoint: gradients of sum_b cot_b v_rms^2_b with respect to inclination,
+ * beta_k, mass scale, BH mass, lum_I0 and mass_S0.  vrms2 is the forward
+ * output for the same batch (DEVICE), or NULL to have it recomputed; cot is
+ * DEVICE, packed like vrms2.  Nothing from the forward is kept: intermediates
+ * are recomputed.  Models with a non-OK status get NaN gradients.
+ * ws_bytes >= jam_workspace_size(..., 1).                                    */
+jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
+                   const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* Kernel timing, for measurement.  enable = 1 clears the record and starts
+ * bracketing every launch of the quadrature (numerator) kernel and of the
+ * adjoint sensitivity kernel with HIP events on the caller's stream;
+ * enable = 0 stops, waits for the recorded events and returns the summed
+ * durations in ms and the launch counts (any output may be NULL).  At most
+ * 4096 launches of each are recorded; later ones are not timed.            */
+jam_status jam_timing(jam_ctx *ctx, int32_t enable, double *numerator_ms,
+                      int64_t *numerator_launches, double *sens_ms, int64_t *sens_launches);
+
+/* Host utility: the n-node Gauss-Legendre rule on [0, 1] that the library
+ * uses (nodes ascending), written to host arrays of n doubles.              */
+jam_status jam_gauss_legendre(int32_t n, double *nodes, double *weights);
+
+/* Message of the last non-OK status on this thread ("" if none).          */
+const char *jam_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JAM_H */

@@ -204,11 +204,16 @@ def term_coefficients(geom, pt):
     return c1, gamma, f * P, f * Q
 
 
-def numerator(coeffs, x, y, chunk: int = 4096):
-    """N(x', y') = int rho_* v_los^2 dz' at the points (x[i], y[i])."""
+def numerator(coeffs, x, y, chunk: Optional[int] = None):
+    """N(x', y') = int rho_* v_los^2 dz' at the points (x[i], y[i]).
+
+    Points are processed in chunks that keep the [terms x points] temporaries
+    near 2^24 elements; the sum over terms of every point is unchanged."""
     c1, gam, C0, C1 = (t.reshape(-1) for t in coeffs)
     x = _t(x).reshape(-1)
     y = _t(y).reshape(-1)
+    if chunk is None:
+        chunk = max(1, min(4096, (1 << 24) // max(1, c1.shape[0])))
     out = []
     for s in range(0, x.shape[0], chunk):
         xx = (x[s:s + chunk] ** 2)[None, :]

@@ -1,0 +1,742 @@
+// Host runtime of the JAM-cyl library: the C ABI of include/jam.h.
+//
+// Responsibilities: validate inputs, build the device description of every
+// geometry once (distinct |x'|/|y'| values of the padded sub-pixel grid, the
+// PSF-and-bin weight matrix in both orientations, Gauss-Legendre nodes),
+// build per-composition work lists ("plans") once, size the caller's
+// workspace, and sequence the kernels on the caller's stream.
+#include "jam.h"
+#include "jam_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+jam_status fail(jam_status s, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return fail(JAM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxNu = 1024;
+constexpr double kPi = 3.14159265358979323846;
+
+// n-node Gauss-Legendre rule on [0, 1]: Newton iteration on P_n from the
+// asymptotic initial guess, in long double; nodes ascending.
+void gauss_legendre01(int n, double *x, double *w) {
+  for (int i = 0; i < n; ++i) {
+    long double z = std::cos(kPi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1.0L; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+      const long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs((double)dz) < 1e-19) break;
+    }
+    // recompute the derivative at the converged node
+    long double p0 = 1.0L, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = (n == 1) ? 1.0L : n * (z * p1 - p0) / (z * z - 1.0L);
+    const long double wi = 2.0L / ((1.0L - z * z) * dp * dp);
+    // z runs from +1 downwards; store ascending on [0, 1]
+    x[i] = (double)(0.5L * (1.0L - z));
+    w[i] = (double)(0.5L * wi);
+  }
+}
+
+// Everything the library keeps about one geometry on the host.
+struct GeomHost {
+  int K = 0, J = 0, J1 = 0, n_u = 0, T = 0;
+  int nx = 0, ny = 0, ss = 1, psf_n = 1, h = 0, n_bins = 0;
+  int nxp = 0, nyp = 0, n_ux = 0, n_uy = 0, n_pix = 0;
+  double bh_sigma = 0, dist = 0, pixsize = 0, xc = 0, yc = 0, s_pc = 0;
+  std::vector<double> lum_sigma, lum_q, lum_I0, mass_sigma, mass_q, mass_S0;
+  std::vector<double> u, w, xs, ys;
+  std::vector<int> ux, uy;
+  std::vector<int> bin_ptr, bin_pix, pix_ptr, pix_bin;
+  std::vector<double> bin_w, pix_w;
+};
+
+jam_status validate(const jam_geometry &g, int gi) {
+  auto bad = [&](const char *what) {
+    return fail(JAM_E_INVALID_ARG, "geometry %d: %s", gi, what);
+  };
+  if (g.n_lum < 1) return bad("n_lum must be >= 1");
+  if (g.n_mass < 0) return bad("n_mass must be >= 0");
+  if (!g.lum_sigma || !g.lum_q || !g.lum_I0) return bad("luminous MGE arrays are NULL");
+  if (g.n_mass > 0 && (!g.mass_sigma || !g.mass_q || !g.mass_S0))
+    return bad("mass MGE arrays are NULL");
+  for (int k = 0; k < g.n_lum; ++k) {
+    if (!(g.lum_sigma[k] > 0) || !std::isfinite(g.lum_sigma[k])) return bad("lum_sigma must be > 0");
+    if (!(g.lum_q[k] > 0 && g.lum_q[k] <= 1)) return bad("lum_q must be in (0, 1]");
+    if (!(g.lum_I0[k] >= 0) || !std::isfinite(g.lum_I0[k])) return bad("lum_I0 must be >= 0");
+  }
+  for (int j = 0; j < g.n_mass; ++j) {
+    if (!(g.mass_sigma[j] > 0) || !std::isfinite(g.mass_sigma[j])) return bad("mass_sigma must be > 0");
+    if (!(g.mass_q[j] > 0 && g.mass_q[j] <= 1)) return bad("mass_q must be in (0, 1]");
+    if (!(g.mass_S0[j] >= 0) || !std::isfinite(g.mass_S0[j])) return bad("mass_S0 must be >= 0");
+  }
+  if (!(g.bh_sigma > 0) || !std::isfinite(g.bh_sigma)) return bad("bh_sigma must be > 0");
+  if (!(g.distance_mpc > 0) || !std::isfinite(g.distance_mpc)) return bad("distance_mpc must be > 0");
+  if (g.nx < 1 || g.ny < 1) return bad("nx, ny must be >= 1");
+  if (!(g.pixsize > 0) || !std::isfinite(g.pixsize)) return bad("pixsize must be > 0");
+  if (!std::isfinite(g.xc) || !std::isfinite(g.yc)) return bad("xc, yc must be finite");
+  if (g.supersample < 1 || g.supersample > 16) return bad("supersample must be in [1, 16]");
+  if (g.psf_n < 1 || g.psf_n % 2 == 0) return bad("psf_n must be odd and >= 1");
+  if (!g.psf) return bad("psf is NULL");
+  for (int i = 0; i < g.psf_n * g.psf_n; ++i)
+    if (!std::isfinite(g.psf[i])) return bad("psf must be finite");
+  if (g.n_bins < 1) return bad("n_bins must be >= 1");
+  if (!g.bin_index) return bad("bin_index is NULL");
+  if (g.n_u < 1 || g.n_u > kMaxNu) return bad("n_u must be in [1, 1024]");
+  const int64_t nsub_x = (int64_t)g.nx * g.supersample + g.psf_n - 1;
+  const int64_t nsub_y = (int64_t)g.ny * g.supersample + g.psf_n - 1;
+  if (nsub_x > 16384 || nsub_y > 16384) return bad("padded sub-pixel grid larger than 16384");
+  std::vector<int> cnt(g.n_bins, 0);
+  for (int64_t i = 0; i < (int64_t)g.nx * g.ny; ++i) {
+    const int b = g.bin_index[i];
+    if (b < -1 || b >= g.n_bins) return bad("bin_index out of range");
+    if (b >= 0) cnt[b]++;
+  }
+  for (int b = 0; b < g.n_bins; ++b)
+    if (cnt[b] == 0) return fail(JAM_E_INVALID_ARG, "geometry %d: bin %d is empty", gi, b);
+  return JAM_OK;
+}
+
+// Distinct |v| of a list, ascending, with the index map.
+void distinct_abs(const std::vector<double> &v, std::vector<double> &vals, std::vector<int> &map) {
+  vals.clear();
+  for (double x : v) vals.push_back(std::fabs(x));
+  std::sort(vals.begin(), vals.end());
+  vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+  map.resize(v.size());
+  for (size_t i = 0; i < v.size(); ++i)
+    map[i] = (int)(std::lower_bound(vals.begin(), vals.end(), std::fabs(v[i])) - vals.begin());
+}
+
+void build_geometry(const jam_geometry &g, GeomHost &o) {
+  o.K = g.n_lum;
+  o.J = g.n_mass;
+  o.J1 = g.n_mass + 1;
+  o.n_u = g.n_u;
+  o.T = o.K * o.J1 * o.n_u;
+  o.nx = g.nx;
+  o.ny = g.ny;
+  o.ss = g.supersample;
+  o.psf_n = g.psf_n;
+  o.h = (g.psf_n - 1) / 2;
+  o.n_bins = g.n_bins;
+  o.bh_sigma = g.bh_sigma;
+  o.dist = g.distance_mpc;
+  o.pixsize = g.pixsize;
+  o.xc = g.xc;
+  o.yc = g.yc;
+  o.s_pc = g.distance_mpc * 1.0e6 * kPi / 648000.0;
+  o.lum_sigma.assign(g.lum_sigma, g.lum_sigma + o.K);
+  o.lum_q.assign(g.lum_q, g.lum_q + o.K);
+  o.lum_I0.assign(g.lum_I0, g.lum_I0 + o.K);
+  if (o.J) {
+    o.mass_sigma.assign(g.mass_sigma, g.mass_sigma + o.J);
+    o.mass_q.assign(g.mass_q, g.mass_q + o.J);
+    o.mass_S0.assign(g.mass_S0, g.mass_S0 + o.J);
+  }
+  o.u.resize(o.n_u);
+  o.w.resize(o.n_u);
+  gauss_legendre01(o.n_u, o.u.data(), o.w.data());
+
+  // padded sub-pixel centres (galaxy at the origin)
+  const int ssx = o.nx * o.ss, ssy = o.ny * o.ss;
+  o.nxp = ssx + 2 * o.h;
+  o.nyp = ssy + 2 * o.h;
+  const double pitch = o.pixsize / o.ss;
+  std::vector<double> xp(o.nxp), yp(o.nyp);
+  for (int c = 0; c < o.nxp; ++c) xp[c] = o.xc + ((double)(c - o.h) - (ssx - 1) / 2.0) * pitch;
+  for (int r = 0; r < o.nyp; ++r) yp[r] = o.yc + ((double)(r - o.h) - (ssy - 1) / 2.0) * pitch;
+  distinct_abs(xp, o.xs, o.ux);
+  distinct_abs(yp, o.ys, o.uy);
+  o.n_ux = (int)o.xs.size();
+  o.n_uy = (int)o.ys.size();
+  o.n_pix = o.n_ux * o.n_uy;
+
+  // W[b, p]: the convolved map at field sub-pixel f is
+  //   C(f) = sum_o psf[o + h] M(f - o),
+  // so bin b's sum of C weights padded sub-pixel (f + h - o) by psf[o + h].
+  std::vector<double> dense((size_t)o.n_bins * o.n_pix, 0.0);
+  const int n = o.psf_n;
+  for (int fy = 0; fy < ssy; ++fy) {
+    for (int fx = 0; fx < ssx; ++fx) {
+      const int b = g.bin_index[(fy / o.ss) * o.nx + fx / o.ss];
+      if (b < 0) continue;
+      double *row = dense.data() + (size_t)b * o.n_pix;
+      for (int oy = -o.h; oy <= o.h; ++oy) {
+        const int iy = o.uy[fy + o.h - oy] * o.n_ux;
+        const double *kr = g.psf + (oy + o.h) * n;
+        for (int ox = -o.h; ox <= o.h; ++ox) row[iy + o.ux[fx + o.h - ox]] += kr[ox + o.h];
+      }
+    }
+  }
+  o.bin_ptr.assign(o.n_bins + 1, 0);
+  std::vector<int> pcount(o.n_pix, 0);
+  for (int b = 0; b < o.n_bins; ++b) {
+    const double *row = dense.data() + (size_t)b * o.n_pix;
+    for (int p = 0; p < o.n_pix; ++p)
+      if (row[p] != 0.0) {
+        o.bin_pix.push_back(p);
+        o.bin_w.push_back(row[p]);
+        pcount[p]++;
+      }
+    o.bin_ptr[b + 1] = (int)o.bin_pix.size();
+  }
+  o.pix_ptr.assign(o.n_pix + 1, 0);
+  for (int p = 0; p < o.n_pix; ++p) o.pix_ptr[p + 1] = o.pix_ptr[p] + pcount[p];
+  o.pix_bin.resize(o.bin_pix.size());
+  o.pix_w.resize(o.bin_pix.size());
+  std::vector<int> fill(o.pix_ptr.begin(), o.pix_ptr.end() - 1);
+  for (int b = 0; b < o.n_bins; ++b)
+    for (int e = o.bin_ptr[b]; e < o.bin_ptr[b + 1]; ++e) {
+      const int p = o.bin_pix[e];
+      o.pix_bin[fill[p]] = b;
+      o.pix_w[fill[p]] = o.bin_w[e];
+      fill[p]++;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// A prepared batch composition.
+struct Plan {
+  std::vector<int32_t> key;
+  int n = 0;
+  void *arena = nullptr;
+  jam::ModelDev *d_models = nullptr;
+  jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
+            *d_maps = nullptr, *d_chain = nullptr;
+  int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0;
+  int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
+  // workspace regions (bytes)
+  size_t off_status = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0, off_bins = 0,
+         off_sens = 0, off_vtmp = 0, ws_fwd = 0, ws_vjp = 0;
+  ~Plan() {
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+}  // namespace
+
+// Event pairs bracketing launches of one kernel, for jam_timing.
+struct KernelTimer {
+  static constexpr int kCap = 4096;
+  std::vector<hipEvent_t> start, stop;
+  int used = 0;
+  bool on = false;
+  void destroy() {
+    for (auto e : start) (void)hipEventDestroy(e);
+    for (auto e : stop) (void)hipEventDestroy(e);
+    start.clear();
+    stop.clear();
+  }
+  bool begin(hipStream_t st) {
+    if (!on || used >= (int)start.size()) return false;
+    return hipEventRecord(start[used], st) == hipSuccess;
+  }
+  void end(hipStream_t st) { (void)hipEventRecord(stop[used++], st); }
+};
+
+struct jam_ctx {
+  int device = 0;
+  jam_options opt{0, 0, nullptr};
+  std::vector<GeomHost> gh;
+  void *arena = nullptr;
+  jam::GeomDev *d_geoms = nullptr;
+  std::list<std::unique_ptr<Plan>> plans;   // most recent first
+  KernelTimer t_num, t_sens;
+  ~jam_ctx() {
+    plans.clear();
+    t_num.destroy();
+    t_sens.destroy();
+    if (arena) (void)hipFree(arena);
+  }
+};
+
+namespace {
+
+constexpr size_t kMaxPlans = 8;
+
+// Split of the (k, j) pair range so that a batch offers enough work items.
+int choose_slices(const GeomHost &g, int n_models) {
+  const int blocks = (g.n_pix + 63) / 64;
+  const int pairs = g.K * g.J1;
+  const int64_t target = std::max<int64_t>(1, 8192 / std::max(1, n_models));
+  int s = (int)std::min<int64_t>((target + blocks - 1) / blocks, std::max(1, pairs / 4));
+  return std::max(1, s);
+}
+
+jam_status make_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
+  auto p = std::make_unique<Plan>();
+  p->key.assign(geom_idx, geom_idx + n);
+  p->n = n;
+  std::vector<jam::ModelDev> md(n);
+  std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain;
+  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0;
+  for (int m = 0; m < n; ++m) {
+    const int gi = geom_idx[m];
+    const GeomHost &g = ctx->gh[gi];
+    jam::ModelDev &d = md[m];
+    d.geom = gi;
+    d.lum_off = (int)p->total_lum;
+    d.mass_off = (int)p->total_mass;
+    d.out_off = (int)p->total_bins;
+    d.n_slices = choose_slices(g, n);
+    d.form = 1;
+    d.n_xt = (g.n_ux + 31) / 32;
+    d.n_yt = (g.n_uy + 31) / 32;
+    d.gauss_off = gauss;
+    d.term_off = terms;
+    d.pix_off = pixd;
+    d.part_off = part;
+    d.map_off = p->total_map;
+    d.sens_off = sens;
+    d.bin_off = bins;
+    gauss += jam::gauss_size(g.K, g.J1);
+    terms += g.T;
+    pixd += 4 * (int64_t)g.n_pix;
+    part += (int64_t)d.n_slices * g.n_pix;
+    bins += 2 * (int64_t)g.n_bins;
+    sens += 3 * (int64_t)g.T + (int64_t)g.K * (3 + g.J1);
+    p->total_lum += g.K;
+    p->total_mass += g.J;
+    p->total_bins += g.n_bins;
+    p->total_map += (int64_t)g.nxp * g.nyp;
+    for (int tb = 0; tb < (g.T + 255) / 256; ++tb) it_terms.push_back({m, tb, 0, 0});
+    for (int pb = 0; pb < (g.n_pix + 255) / 256; ++pb) it_pix.push_back({m, pb, 0, 0});
+    for (int s = 0; s < d.n_slices; ++s)
+      for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_num.push_back({m, pb, s, 0});
+    for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
+    for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
+    for (int k = 0; k < g.K; ++k) it_chain.push_back({m, k, 0, 0});
+  }
+  if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
+    return fail(JAM_E_UNSUPPORTED, "batch too large");
+  const size_t sz_items[6] = {it_terms.size(), it_pix.size(), it_num.size(),
+                              it_bins.size(), it_maps.size(), it_chain.size()};
+  for (size_t s : sz_items)
+    if (s > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
+  // one device arena: models then the item lists
+  size_t off = 0;
+  const size_t o_models = off;
+  off = align256(off + sizeof(jam::ModelDev) * n);
+  size_t o_it[6];
+  std::vector<jam::Item> *lists[6] = {&it_terms, &it_pix, &it_num, &it_bins, &it_maps, &it_chain};
+  for (int i = 0; i < 6; ++i) {
+    o_it[i] = off;
+    off = align256(off + sizeof(jam::Item) * std::max<size_t>(1, lists[i]->size()));
+  }
+  std::vector<char> stage(off, 0);
+  std::memcpy(stage.data() + o_models, md.data(), sizeof(jam::ModelDev) * n);
+  for (int i = 0; i < 6; ++i)
+    if (!lists[i]->empty())
+      std::memcpy(stage.data() + o_it[i], lists[i]->data(), sizeof(jam::Item) * lists[i]->size());
+  HIP_TRY(hipMalloc(&p->arena, off));
+  HIP_TRY(hipMemcpy(p->arena, stage.data(), off, hipMemcpyHostToDevice));
+  char *base = (char *)p->arena;
+  p->d_models = (jam::ModelDev *)(base + o_models);
+  jam::Item **dl[6] = {&p->d_terms, &p->d_pix, &p->d_num, &p->d_bins, &p->d_maps, &p->d_chain};
+  int *cnt[6] = {&p->n_terms, &p->n_pix, &p->n_num, &p->n_bins, &p->n_maps, &p->n_chain};
+  for (int i = 0; i < 6; ++i) {
+    *dl[i] = (jam::Item *)(base + o_it[i]);
+    *cnt[i] = (int)lists[i]->size();
+  }
+  // workspace layout
+  size_t w = 0;
+  p->off_status = w; w = align256(w + sizeof(int) * n);
+  p->off_gauss = w;  w = align256(w + sizeof(double) * gauss);
+  p->off_terms = w;  w = align256(w + sizeof(float4) * terms);
+  p->off_pix = w;    w = align256(w + sizeof(double) * pixd);
+  p->off_part = w;   w = align256(w + sizeof(double) * part);
+  p->off_bins = w;   w = align256(w + sizeof(double) * bins);
+  p->ws_fwd = w;
+  p->off_sens = w;   w = align256(w + sizeof(double) * sens);
+  p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
+  p->ws_vjp = w;
+  out = p.get();
+  ctx->plans.push_front(std::move(p));
+  while (ctx->plans.size() > kMaxPlans) ctx->plans.pop_back();
+  return JAM_OK;
+}
+
+jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  if (n < 1) return fail(JAM_E_INVALID_ARG, "batch size must be >= 1");
+  if (!geom_idx) return fail(JAM_E_INVALID_ARG, "geom_idx is NULL");
+  for (int m = 0; m < n; ++m)
+    if (geom_idx[m] < 0 || geom_idx[m] >= (int)ctx->gh.size())
+      return fail(JAM_E_INVALID_ARG, "geom_idx[%d] = %d out of range", m, geom_idx[m]);
+  for (auto itp = ctx->plans.begin(); itp != ctx->plans.end(); ++itp) {
+    Plan *p = itp->get();
+    if (p->n == n && std::equal(p->key.begin(), p->key.end(), geom_idx)) {
+      if (itp != ctx->plans.begin()) ctx->plans.splice(ctx->plans.begin(), ctx->plans, itp);
+      out = p;
+      return JAM_OK;
+    }
+  }
+  return make_plan(ctx, n, geom_idx, out);
+}
+
+// Switch to the context's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+jam_status check_batch(const jam_batch *b) {
+  if (!b) return fail(JAM_E_INVALID_ARG, "batch is NULL");
+  if (!b->inc || !b->mass_scale || !b->m_bh || !b->beta)
+    return fail(JAM_E_INVALID_ARG, "batch inc, mass_scale, m_bh and beta are required");
+  return JAM_OK;
+}
+
+jam::ParamsDev params_of(const jam_batch *b) {
+  return jam::ParamsDev{b->inc, b->mass_scale, b->m_bh, b->beta, b->lum_I0, b->mass_S0};
+}
+
+// Forward part shared by eval, maps and (recomputing) vjp: set-up, terms,
+// SB map, numerator map.  Leaves N and I in the workspace pix region.
+jam_status forward_maps(jam_ctx *ctx, Plan *p, const jam_batch *b, int32_t *status, char *ws,
+                        hipStream_t st, bool need_numerator) {
+  const jam::ParamsDev pd = params_of(b);
+  int *st_ws = (int *)(ws + p->off_status);
+  double *gauss = (double *)(ws + p->off_gauss);
+  float4 *terms = (float4 *)(ws + p->off_terms);
+  double *pix = (double *)(ws + p->off_pix);
+  double *part = (double *)(ws + p->off_part);
+  jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, st);
+  jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
+  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, pd, pix, st);
+  if (need_numerator) {
+    const bool timed = ctx->t_num.begin(st);
+    jam::launch_num_pix(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part, st);
+    if (timed) ctx->t_num.end(st);
+    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, part, pix, st);
+  }
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (need > ws_bytes) return fail(JAM_E_WORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+  if (!ws) return fail(JAM_E_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(JAM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  return JAM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *jam_last_error(void) { return g_err.c_str(); }
+
+jam_status jam_timing(jam_ctx *ctx, int32_t enable, double *numerator_ms,
+                      int64_t *numerator_launches, double *sens_ms, int64_t *sens_launches) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  KernelTimer *ts[2] = {&ctx->t_num, &ctx->t_sens};
+  if (enable) {
+    for (KernelTimer *t : ts) {
+      if (t->start.empty()) {
+        t->start.resize(KernelTimer::kCap);
+        t->stop.resize(KernelTimer::kCap);
+        for (int i = 0; i < KernelTimer::kCap; ++i) {
+          HIP_TRY(hipEventCreate(&t->start[i]));
+          HIP_TRY(hipEventCreate(&t->stop[i]));
+        }
+      }
+      t->used = 0;
+      t->on = true;
+    }
+    return JAM_OK;
+  }
+  double ms[2] = {0.0, 0.0};
+  for (int k = 0; k < 2; ++k) {
+    KernelTimer *t = ts[k];
+    t->on = false;
+    for (int i = 0; i < t->used; ++i) {
+      HIP_TRY(hipEventSynchronize(t->stop[i]));
+      float e = 0.f;
+      HIP_TRY(hipEventElapsedTime(&e, t->start[i], t->stop[i]));
+      ms[k] += e;
+    }
+  }
+  if (numerator_ms) *numerator_ms = ms[0];
+  if (numerator_launches) *numerator_launches = ctx->t_num.used;
+  if (sens_ms) *sens_ms = ms[1];
+  if (sens_launches) *sens_launches = ctx->t_sens.used;
+  return JAM_OK;
+}
+
+jam_status jam_gauss_legendre(int32_t n, double *nodes, double *weights) {
+  if (n < 1 || n > kMaxNu) return fail(JAM_E_INVALID_ARG, "n must be in [1, 1024]");
+  if (!nodes || !weights) return fail(JAM_E_INVALID_ARG, "output arrays are NULL");
+  gauss_legendre01(n, nodes, weights);
+  return JAM_OK;
+}
+
+jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_options *opt,
+                      jam_ctx **out) {
+  g_err.clear();
+  if (!out) return fail(JAM_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_geom < 1 || !geoms) return fail(JAM_E_INVALID_ARG, "need at least one geometry");
+  for (int i = 0; i < n_geom; ++i) {
+    const jam_status s = validate(geoms[i], i);
+    if (s != JAM_OK) return s;
+  }
+  if (opt && (opt->form < 0 || opt->form > 2))
+    return fail(JAM_E_INVALID_ARG, "options.form must be 0, 1 or 2");
+  auto ctx = std::make_unique<jam_ctx>();
+  if (opt) ctx->opt = *opt;
+  ctx->opt.tune_cache = nullptr;   // not retained
+  HIP_TRY(hipGetDevice(&ctx->device));
+  ctx->gh.resize(n_geom);
+  {
+    const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < nt; ++t)
+      pool.emplace_back([&, t] {
+        for (int i = (int)t; i < n_geom; i += (int)nt) build_geometry(geoms[i], ctx->gh[i]);
+      });
+    for (auto &th : pool) th.join();
+  }
+  // device arena: GeomDev array then every geometry's arrays
+  size_t off = align256(sizeof(jam::GeomDev) * n_geom);
+  struct Offs { size_t ls, lq, li, ms, mq, mS, u, w, xs, ys, ux, uy, bp, bpix, bw, pp, pb, pw; };
+  std::vector<Offs> offs(n_geom);
+  auto take = [&](size_t bytes) { const size_t o = off; off = align256(off + std::max<size_t>(bytes, 8)); return o; };
+  for (int i = 0; i < n_geom; ++i) {
+    const GeomHost &g = ctx->gh[i];
+    Offs &o = offs[i];
+    o.ls = take(8 * g.K); o.lq = take(8 * g.K); o.li = take(8 * g.K);
+    o.ms = take(8 * g.J); o.mq = take(8 * g.J); o.mS = take(8 * g.J);
+    o.u = take(8 * g.n_u); o.w = take(8 * g.n_u);
+    o.xs = take(8 * g.n_ux); o.ys = take(8 * g.n_uy);
+    o.ux = take(4 * g.nxp); o.uy = take(4 * g.nyp);
+    o.bp = take(4 * g.bin_ptr.size()); o.bpix = take(4 * g.bin_pix.size()); o.bw = take(8 * g.bin_w.size());
+    o.pp = take(4 * g.pix_ptr.size()); o.pb = take(4 * g.pix_bin.size()); o.pw = take(8 * g.pix_w.size());
+  }
+  std::vector<char> stage(off, 0);
+  HIP_TRY(hipMalloc(&ctx->arena, off));
+  char *base = (char *)ctx->arena;
+  std::vector<jam::GeomDev> gd(n_geom);
+  auto put = [&](size_t o, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(stage.data() + o, src, bytes);
+    return base + o;
+  };
+  for (int i = 0; i < n_geom; ++i) {
+    const GeomHost &g = ctx->gh[i];
+    const Offs &o = offs[i];
+    jam::GeomDev &d = gd[i];
+    d.K = g.K; d.J1 = g.J1; d.n_u = g.n_u; d.T = g.T;
+    d.n_ux = g.n_ux; d.n_uy = g.n_uy; d.n_pix = g.n_pix; d.n_bins = g.n_bins;
+    d.nxp = g.nxp; d.nyp = g.nyp; d.pad0 = d.pad1 = 0;
+    d.s_pc = g.s_pc; d.bh_sigma = g.bh_sigma;
+    d.lum_sigma = (const double *)put(o.ls, g.lum_sigma.data(), 8 * g.K);
+    d.lum_q = (const double *)put(o.lq, g.lum_q.data(), 8 * g.K);
+    d.lum_I0 = (const double *)put(o.li, g.lum_I0.data(), 8 * g.K);
+    d.mass_sigma = (const double *)put(o.ms, g.mass_sigma.data(), 8 * g.J);
+    d.mass_q = (const double *)put(o.mq, g.mass_q.data(), 8 * g.J);
+    d.mass_S0 = (const double *)put(o.mS, g.mass_S0.data(), 8 * g.J);
+    d.u = (const double *)put(o.u, g.u.data(), 8 * g.n_u);
+    d.w = (const double *)put(o.w, g.w.data(), 8 * g.n_u);
+    d.xs = (const double *)put(o.xs, g.xs.data(), 8 * g.n_ux);
+    d.ys = (const double *)put(o.ys, g.ys.data(), 8 * g.n_uy);
+    d.ux = (const int *)put(o.ux, g.ux.data(), 4 * g.nxp);
+    d.uy = (const int *)put(o.uy, g.uy.data(), 4 * g.nyp);
+    d.bin_ptr = (const int *)put(o.bp, g.bin_ptr.data(), 4 * g.bin_ptr.size());
+    d.bin_pix = (const int *)put(o.bpix, g.bin_pix.data(), 4 * g.bin_pix.size());
+    d.bin_w = (const double *)put(o.bw, g.bin_w.data(), 8 * g.bin_w.size());
+    d.pix_ptr = (const int *)put(o.pp, g.pix_ptr.data(), 4 * g.pix_ptr.size());
+    d.pix_bin = (const int *)put(o.pb, g.pix_bin.data(), 4 * g.pix_bin.size());
+    d.pix_w = (const double *)put(o.pw, g.pix_w.data(), 8 * g.pix_w.size());
+  }
+  std::memcpy(stage.data(), gd.data(), sizeof(jam::GeomDev) * n_geom);
+  HIP_TRY(hipMemcpy(ctx->arena, stage.data(), off, hipMemcpyHostToDevice));
+  ctx->d_geoms = (jam::GeomDev *)ctx->arena;
+  *out = ctx.release();
+  return JAM_OK;
+}
+
+void jam_destroy(jam_ctx *ctx) { delete ctx; }
+
+jam_status jam_batch_sizes(const jam_ctx *ctx, int32_t n, const int32_t *geom_idx,
+                           int64_t *n_bins_total, int64_t *n_lum_total, int64_t *n_mass_total) {
+  if (!ctx || n < 1 || !geom_idx) return fail(JAM_E_INVALID_ARG, "invalid arguments");
+  int64_t b = 0, l = 0, ms = 0;
+  for (int m = 0; m < n; ++m) {
+    if (geom_idx[m] < 0 || geom_idx[m] >= (int)ctx->gh.size())
+      return fail(JAM_E_INVALID_ARG, "geom_idx[%d] out of range", m);
+    const GeomHost &g = ctx->gh[geom_idx[m]];
+    b += g.n_bins;
+    l += g.K;
+    ms += g.J;
+  }
+  if (n_bins_total) *n_bins_total = b;
+  if (n_lum_total) *n_lum_total = l;
+  if (n_mass_total) *n_mass_total = ms;
+  return JAM_OK;
+}
+
+jam_status jam_prepare(jam_ctx *ctx, int32_t n, const int32_t *geom_idx) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  return get_plan(ctx, n, geom_idx, p);
+}
+
+jam_status jam_workspace_size(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t with_vjp,
+                              size_t *bytes) {
+  if (!bytes) return fail(JAM_E_INVALID_ARG, "bytes is NULL");
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  const jam_status s = get_plan(ctx, n, geom_idx, p);
+  if (s != JAM_OK) return s;
+  *bytes = with_vjp ? p->ws_vjp : p->ws_fwd;
+  return JAM_OK;
+}
+
+jam_status jam_eval_batch(jam_ctx *ctx, const jam_batch *batch, double *vrms2, int32_t *status,
+                          void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!vrms2) return fail(JAM_E_INVALID_ARG, "vrms2 is NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, p->ws_fwd)) != JAM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if ((s = forward_maps(ctx, p, batch, status, w, st, true)) != JAM_OK) return s;
+  jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, (const double *)(w + p->off_pix),
+                   (const int *)(w + p->off_status), vrms2, (double *)(w + p->off_bins), st);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_eval(jam_ctx *ctx, const jam_batch *one, double *vrms2, int32_t *status, void *ws,
+                    size_t ws_bytes, void *stream) {
+  if (one && one->n != 1) return fail(JAM_E_INVALID_ARG, "jam_eval takes exactly one model");
+  return jam_eval_batch(ctx, one, vrms2, status, ws, ws_bytes, stream);
+}
+
+jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map, double *I_map,
+                         int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!N_map || !I_map) return fail(JAM_E_INVALID_ARG, "map outputs are NULL");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, p->ws_fwd)) != JAM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if ((s = forward_maps(ctx, p, batch, status, w, st, true)) != JAM_OK) return s;
+  jam::launch_maps(ctx->d_geoms, p->d_models, p->d_maps, p->n_maps, (const double *)(w + p->off_pix),
+                   (const int *)(w + p->off_status), N_map, I_map, st);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, const double *cot,
+                   jam_grads *grads, void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!cot || !grads) return fail(JAM_E_INVALID_ARG, "cot and grads are required");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, p->ws_vjp)) != JAM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  const int *st_ws = (const int *)(w + p->off_status);
+  double *pix = (double *)(w + p->off_pix);
+  double *binws = (double *)(w + p->off_bins);
+  double *sens = (double *)(w + p->off_sens);
+  const bool recompute = (vrms2 == nullptr);
+  if ((s = forward_maps(ctx, p, batch, nullptr, w, st, recompute)) != JAM_OK) return s;
+  // V per bin: the caller's forward output, or recomputed into workspace.
+  const double *V = vrms2;
+  if (recompute) {
+    double *vtmp = (double *)(w + p->off_vtmp);
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, vtmp, binws, st);
+    V = vtmp;
+  } else {
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, nullptr, binws, st);
+  }
+  jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
+  const bool timed = ctx->t_sens.begin(st);
+  jam::launch_sens_pix(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms,
+                       (const float4 *)(w + p->off_terms), pix, st_ws, sens, st);
+  if (timed) ctx->t_sens.end(st);
+  const jam::ParamsDev pd = params_of(batch);
+  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
+  const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
+                         grads->mass_S0};
+  jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, st_ws, gd, st);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal structures shared by the host runtime (jam_host.cpp) and the
+// gfx950 kernels (jam_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace jam {
+
+// Device description of one geometry; every pointer is into the context's
+// device arena.  The sky maps depend on x'^2 and y'^2 only, so the library
+// works on the distinct |x'| values of the padded sub-pixel columns (xs) and
+// the distinct |y'| values of its rows (ys); ux/uy map a padded column/row to
+// its distinct value.  A "unique pixel" is p = iy * n_ux + ix.
+struct GeomDev {
+  int K, J1, n_u, T;          // luminous, mass incl. BH, u-nodes, K*J1*n_u terms
+  int n_ux, n_uy, n_pix;      // distinct |x'|, |y'|, n_ux*n_uy
+  int n_bins;
+  int nxp, nyp;               // padded sub-pixel grid
+  int pad0, pad1;
+  double s_pc;                // pc per arcsec at the geometry's distance
+  double bh_sigma;            // arcsec
+  const double *lum_sigma, *lum_q, *lum_I0;     // [K]
+  const double *mass_sigma, *mass_q, *mass_S0;  // [J1-1]
+  const double *u, *w;                          // Gauss-Legendre on [0,1], [n_u]
+  const double *xs, *ys;                        // [n_ux], [n_uy]
+  const int *ux, *uy;                           // [nxp], [nyp]
+  // Bin weights: v_rms^2_b = sum_p W[b,p] N[p] / sum_p W[b,p] I[p] where
+  // W[b,p] = sum over field sub-pixels q of bin b and padded sub-pixels
+  // mapping to unique pixel p of psf[q - padded]; stored both by bin (for the
+  // forward) and by unique pixel (for the adjoint).
+  const int *bin_ptr, *bin_pix;  const double *bin_w;   // [n_bins+1], [nnz]
+  const int *pix_ptr, *pix_bin;  const double *pix_w;   // [n_pix+1],  [nnz]
+};
+
+// One model of a prepared batch; offsets into packed inputs/outputs and into
+// the caller's workspace regions.
+struct ModelDev {
+  int geom;          // geometry index
+  int lum_off;       // into packed beta / lum_I0
+  int mass_off;      // into packed mass_S0
+  int out_off;       // into packed vrms2 / cot
+  int n_slices;      // split of the term range in the numerator kernels
+  int n_xt, n_yt;    // 32x32 tiles of the unique-pixel map (MFMA form)
+  int form;          // 1 per-pixel VALU, 2 separable MFMA
+  int64_t gauss_off; // doubles, per-Gaussian derived quantities
+  int64_t term_off;  // float4 entries, term table
+  int64_t pix_off;   // doubles, unique-pixel maps (N, I, lambda)
+  int64_t part_off;  // doubles, split-term partial numerators
+  int64_t map_off;   // doubles, padded full maps (jam_eval_maps)
+  int64_t sens_off;  // doubles, per-term adjoint sensitivities + chain rows
+  int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
+};
+
+// A unit of work of one kernel: model m and up to three kernel-specific
+// indices (pixel block, tile, slice, bin, ...).
+struct Item {
+  int m, a, b, c;
+};
+
+// Per-model parameters as the caller passed them (device pointers).
+struct ParamsDev {
+  const double *inc, *mass_scale, *m_bh, *beta, *lum_I0, *mass_S0;
+};
+
+struct GradsDev {
+  double *inc, *mass_scale, *m_bh, *beta, *lum_I0, *mass_S0;
+};
+
+// Layout of the per-model derived table written by the set-up kernel
+// (doubles, at gauss_off): for luminous k: alpha = 1/(2 sigma^2),
+// alphaq = alpha / q^2, nu0 (peak density), b = 1/(1-beta); for mass j
+// (incl. BH): r = 1/(2 sigma^2), e2 = 1 - q^2, Kp = sqrt(2/pi) G M/(s sigma);
+// then sin^2 i, cos^2 i.
+__host__ __device__ inline int64_t gauss_size(int K, int J1) { return 4 * K + 3 * J1 + 2; }
+
+// Kernel launchers (jam_kernels.hip).  All asynchronous on `st`.
+void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *gauss,
+                  int *st_ws, int32_t *st_out, hipStream_t st);
+void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                  const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
+void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+               double *pix, hipStream_t st);
+void launch_num_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                    const float4 *terms, const int *st_ws, double *part, hipStream_t st);
+void launch_num_mfma(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                     const float4 *terms, const int *st_ws, double *part, hipStream_t st);
+void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                   const double *part, double *pix, hipStream_t st);
+void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                 const double *pix, const int *st_ws, double *vrms2, double *binws,
+                 hipStream_t st);
+void launch_maps(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                 const double *pix, const int *st_ws, double *N_map, double *I_map,
+                 hipStream_t st);
+void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                         const double *vrms2, const double *cot, const double *binws,
+                         const int *st_ws, double *pix, hipStream_t st);
+void launch_sens_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                     const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                     hipStream_t st);
+void launch_sens_mfma(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                      const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                      hipStream_t st);
+// sens region per model: [S0 | S1 | Sg] (T doubles each), then the chain
+// rows [K][3 + J1] doubles.
+void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+                  const double *pix, double *sens, const int *st_ws, hipStream_t st);
+void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, const double *sens,
+                  const int *st_ws, GradsDev out, hipStream_t st);
+
+}  // namespace jam

@@ -189,7 +189,7 @@ def _geometry(rng, n_lum, n_mass, n, pixsize, ss, psf_fwhm, psf_n, n_bins, n_u):
 
 
 def _q_min(g: Geometry) -> float:
-    return float(min(g.lum_q.min(), g.mass_q.min()))
+    return float(np.concatenate([g.lum_q, g.mass_q]).min())
 
 
 def _proposal(rng, g: Geometry) -> Params:

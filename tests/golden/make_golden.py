@@ -1,0 +1,107 @@
+"""Write the stored expected values used by the GPU tests and the benchmark.
+
+Every value here comes from the FP64 oracle (``oracle/``) evaluated on the
+seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
+from the GPU library.  Run from the repository root:
+
+    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import jam as ojam                      # noqa: E402
+from paper_2504_01302_amd import inputs              # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _dump(name, obj):
+    path = os.path.join(HERE, name)
+    with open(path, "w") as f:
+        json.dump(obj, f, indent=1)
+    print("wrote", path, flush=True)
+
+
+def cfg2():
+    """IFU-scale model, seed 0: all bins, and N, I at 64 seeded padded
+    sub-pixels."""
+    t = time.time()
+    w = inputs.config2(seed=0)
+    g, p = w.geometries[0], w.params[0]
+    V = ojam.vrms2(g, p).numpy()
+    x, y, _ = ojam.padded_subgrid(g)
+    rng = np.random.default_rng(123)
+    iy = rng.integers(0, len(y), 64)
+    ix = rng.integers(0, len(x), 64)
+    N, I = ojam.point_values(g, p, x[ix], y[iy])
+    _dump("cfg2_seed0.json", dict(
+        source="oracle/jam.py vrms2 and point_values on inputs.config2(seed=0)",
+        vrms2=V.tolist(), pix_iy=iy.tolist(), pix_ix=ix.tolist(),
+        N=N.numpy().tolist(), I=I.numpy().tolist(), seconds=time.time() - t))
+
+
+def cfg3(n_models=4096, n_check=64):
+    """Batched proposals: all bins of a seeded subset of the 4096 models."""
+    w = inputs.config3(n_models=n_models)
+    idx = np.sort(np.random.default_rng(3).choice(n_models, n_check, replace=False))
+    V = [ojam.vrms2(w.geometries[0], w.params[m]).numpy().tolist() for m in idx]
+    _dump("cfg3_subset.json", dict(
+        source="oracle/jam.py vrms2 on inputs.config3(4096), seeded subset",
+        models=idx.tolist(), vrms2=V))
+
+
+def cfg4(n_models=1024, n_check=32, bins_per_model=2):
+    """Uneven batch: a size-stratified seeded subset of 32 models (8 per
+    quartile of work), two seeded bins each (the oracle evaluates only the
+    sub-pixels those bins read)."""
+    w = inputs.config4(n_models=n_models)
+    work = np.array([((g.nx + g.psf_n - 1) ** 2) * g.n_lum * (g.n_mass + 1) * g.n_u
+                     for g in w.geometries], dtype=np.float64)
+    order = np.argsort(work)
+    rng = np.random.default_rng(4)
+    chosen = []
+    for q in range(4):
+        part = order[q * n_models // 4:(q + 1) * n_models // 4]
+        chosen += list(rng.choice(part, n_check // 4, replace=False))
+    chosen = np.sort(np.array(chosen))
+    out = []
+    for m in chosen:
+        g, p = w.geometries[m], w.params[m]
+        bins = np.sort(rng.choice(g.n_bins, min(bins_per_model, g.n_bins), replace=False))
+        V = ojam.vrms2_bins(g, p, bins).numpy()
+        out.append(dict(model=int(m), bins=bins.tolist(), vrms2=V.tolist()))
+        print("cfg4 model", m, flush=True)
+    _dump("cfg4_subset.json", dict(
+        source="oracle/jam.py vrms2_bins on inputs.config4(1024), stratified subset",
+        checks=out))
+
+
+def cfg5(n_models=256, n_check=8):
+    """Gradients: oracle autograd gradients of sum cot * vrms2 for a seeded
+    subset of the 256 config-5 models, cotangent inputs.cotangent(seed 0)."""
+    w = inputs.config5(n_models=n_models)
+    cot = inputs.cotangent(w.geometries[0].n_bins, n_models)
+    idx = np.sort(np.random.default_rng(5).choice(n_models, n_check, replace=False))
+    out = []
+    for m in idx:
+        V, gr = ojam.vrms2_and_grad(w.geometries[0], w.params[m], cot[m])
+        out.append(dict(model=int(m), vrms2=V.numpy().tolist(),
+                        grads={k: np.atleast_1d(v.numpy()).tolist() for k, v in gr.items()}))
+    _dump("cfg5_grads.json", dict(
+        source="oracle/jam.py vrms2_and_grad on inputs.config5(256), seeded subset",
+        checks=out))
+
+
+if __name__ == "__main__":
+    torch.set_num_threads(max(1, os.cpu_count() or 1))
+    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5"]
+    for name in todo:
+        globals()[name]()

@@ -1,0 +1,119 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function include/jam.h declares, its Gauss-Legendre rule matches
+numpy's, and it rejects invalid geometries before touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_01302_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "jam.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jam_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = _declared()
+    assert "jam_eval_batch" in names and "jam_vjp" in names and "jam_create" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.EXPORTED)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 100, 128, 160, 1024])
+def test_gauss_legendre_matches_numpy(n):
+    # numpy's weights carry ~1e-11 (n=128) to ~1e-9 (n=1024) relative error;
+    # the library's are pinned to 40-digit values below.
+    x, w = binding.jam_gauss_legendre(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    assert np.allclose(x, 0.5 * (xr + 1), rtol=0, atol=2e-15)
+    assert np.allclose(w, 0.5 * wr, rtol=3e-9, atol=0)
+    assert abs(w.sum() - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("n", [7, 128])
+def test_gauss_legendre_high_precision(n):
+    import mpmath as mp
+    mp.mp.dps = 40
+    x, w = binding.jam_gauss_legendre(n)
+
+    def legendre(t):
+        p0, p1 = mp.mpf(1), t
+        for k in range(2, n + 1):
+            p0, p1 = p1, ((2 * k - 1) * t * p1 - (k - 1) * p0) / k
+        return p1, p0
+
+    for i in sorted({0, 1, n // 3, n // 2, n - 1}):
+        z = 1 - 2 * mp.mpf(x[i])
+        for _ in range(30):
+            p1, p0 = legendre(z)
+            dp = n * (z * p1 - p0) / (z * z - 1)
+            z = z - p1 / dp
+        p1, p0 = legendre(z)
+        dp = n * (z * p1 - p0) / (z * z - 1)
+        assert abs(float((1 - z) / 2) - x[i]) <= 2e-16
+        assert abs(w[i] / float(1 / ((1 - z * z) * dp * dp)) - 1) < 1e-15
+    # exact on polynomials of degree <= 2n - 1
+    for deg in range(0, min(2 * n, 40)):
+        assert abs(np.sum(w * x ** deg) - 1.0 / (deg + 1)) < 1e-14
+
+
+def test_gauss_legendre_rejects_bad_n():
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_gauss_legendre(0)
+    assert e.value.status == 1
+
+
+def _good():
+    return inputs.small_geometry(seed=1)
+
+
+def _with(**kw):
+    g = _good()
+    return inputs.Geometry(**{**g.__dict__, **kw})
+
+
+BAD = [
+    ("lum_sigma", dict(lum_sigma=np.array([0.1, -1.0, 0.3])), "lum_sigma"),
+    ("lum_q", dict(lum_q=np.array([0.7, 1.2, 0.8])), "lum_q"),
+    ("lum_I0", dict(lum_I0=np.array([1.0, -2.0, 1.0])), "lum_I0"),
+    ("mass_S0", dict(mass_S0=np.array([1.0, np.nan])), "mass_S0"),
+    ("psf even", dict(psf=np.ones((2, 2)) / 4), "psf_n"),
+    ("n_u", dict(n_u=0), "n_u"),
+    ("n_u big", dict(n_u=5000), "n_u"),
+    ("bh_sigma", dict(bh_sigma=0.0), "bh_sigma"),
+    ("distance", dict(distance_mpc=-1.0), "distance"),
+    ("supersample", dict(supersample=0), "supersample"),
+    ("bin range", dict(bin_index=np.full((7, 9), 7, np.int32)), "bin_index"),
+    ("bin empty", dict(bin_index=np.zeros((7, 9), np.int32)), "empty"),
+]
+
+
+@pytest.mark.parametrize("name,kw,msg", BAD, ids=[b[0] for b in BAD])
+def test_invalid_geometry_rejected_on_host(name, kw, msg):
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_create([_good(), _with(**kw)])
+    assert e.value.status == 1
+    assert msg in str(e.value) and "geometry 1" in str(e.value)
+
+
+def test_invalid_form_rejected():
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_create([_good()], form=7)
+    assert e.value.status == 1
+
+
+def test_valid_geometry_needs_a_device_here():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_create([_good()])
+    assert e.value.status == 5
