@@ -33,10 +33,14 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", type=int, default=0)
+    ap.add_argument("--form", type=int, default=2,
+                    help="1 per-pixel VALU kernel, 2 matrix-core kernel (0 = library default)")
     ap.add_argument("--batch", type=int, default=1,
                     help="models per launch (copies of the IFU-scale model)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy three times, the reference "
+                         "kernel for scaling the HBM byte counters of a profile")
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="padded sub-pixels the oracle evaluates for the CPU baseline")
     return ap.parse_args()
@@ -140,7 +144,7 @@ def main():
     n_pix = len(xs) * len(ys)
     T = g.n_lum * (g.n_mass + 1) * g.n_u
     avg_num_s = (num_ms / max(1, num_n)) * 1e-3
-    form_used = a.form if a.form in (1, 2) else 1
+    form_used = 1 if a.form == 1 else 2
     if form_used == 2:
         flops = 2.0 * n_pix * T * n
         roof = dict(bound="mfma", peak=FP32_MFMA_PEAK / 1e12)
@@ -176,6 +180,13 @@ def main():
         "roofline": roof,
         "sens_kernel_avg_ms": sens_ms / max(1, sens_n),
     }
+    if a.copy_calibration:
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = src.numel() * 8
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(g, p, a.cpu_sample)
     print(json.dumps(rec), flush=True)

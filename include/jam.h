@@ -88,14 +88,25 @@ typedef struct {
   int32_t n_u;
 } jam_geometry;
 
-/* form: 0 = automatic (tuned choice), 1 = per-pixel VALU quadrature kernel,
- *       2 = separable matrix-core (MFMA) kernel.
- * autotune: 1 = time the candidate kernel shapes once per shape bucket and
- *       keep the fastest (cached in tune_cache, a JSON path, if not NULL).   */
+/* form: 0 = automatic, 1 = per-pixel VALU quadrature kernels only,
+ *       2 = separable matrix-core (MFMA) kernels.
+ * autotune (form 0 only): 1 = when a batch composition is first prepared,
+ *       time the candidate numerator schedules (kernel variant, 64x64-tile
+ *       threshold, terms per work item, persistent or one workgroup per item)
+ *       on it with fixed valid parameters and keep the fastest; results are
+ *       cached per composition, and in the text file tune_cache if not NULL
+ *       (read at jam_create, rewritten after each tuning).
+ * launch: 0 = persistent grid pulling work items from a device queue
+ *       (largest first), 1 = one workgroup per work item.
+ * graph: 1 = record each prepared composition's evaluation (and adjoint) as
+ *       a HIP graph on first use and replay it while the call's pointers are
+ *       unchanged (re-recorded when they change).                            */
 typedef struct {
   int32_t form;
   int32_t autotune;
   const char *tune_cache;
+  int32_t launch;
+  int32_t graph;
 } jam_options;
 
 /* A batch of n >= 1 models.  geom_idx is HOST memory (n entries, each a
@@ -189,6 +200,12 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
  * 4096 launches of each are recorded; later ones are not timed.            */
 jam_status jam_timing(jam_ctx *ctx, int32_t enable, double *numerator_ms,
                       int64_t *numerator_launches, double *sens_ms, int64_t *sens_launches);
+
+/* Schedule chosen for a batch composition (prepares it if needed):
+ * info[0..7] = numerator rule (0 per-pixel, 1 MFMA), 64x64-tile threshold,
+ * term granularity per item, launch mode, numerator work items, numerator
+ * workgroups launched, adjoint work items, adjoint workgroups launched.     */
+jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t *info);
 
 /* Host utility: the n-node Gauss-Legendre rule on [0, 1] that the library
  * uses (nodes ascending), written to host arrays of n doubles.              */

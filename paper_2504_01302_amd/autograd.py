@@ -1,0 +1,45 @@
+"""torch.autograd.Function over the library: forward = jam_eval_batch,
+backward = jam_vjp.
+
+Only the per-bin output v_rms^2 is saved for the backward pass (a few
+doubles per model); every other forward intermediate is recomputed inside
+jam_vjp, so memory does not grow with the batch beyond the workspace.
+PyTorch provides device memory and streams; all arithmetic runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding
+
+
+class JamVrms2(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0):
+        V, st = jctx.eval_batch(geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+        ctx.jctx = jctx
+        ctx.geom_idx = geom_idx
+        ctx.has_amp = (lum_I0 is not None, mass_S0 is not None)
+        ctx.save_for_backward(inc, mass_scale, m_bh, beta,
+                              lum_I0 if lum_I0 is not None else inc.new_empty(0),
+                              mass_S0 if mass_S0 is not None else inc.new_empty(0), V)
+        ctx.mark_non_differentiable(st)
+        return V, st
+
+    @staticmethod
+    def backward(ctx, gV, _gst):
+        inc, ml, mbh, beta, I0, S0, V = ctx.saved_tensors
+        I0 = I0 if ctx.has_amp[0] else None
+        S0 = S0 if ctx.has_amp[1] else None
+        g = ctx.jctx.vjp(ctx.geom_idx, inc, ml, mbh, beta, I0, S0, V,
+                         gV.contiguous().to(torch.float64))
+        return (None, None, g["inc"], g["mass_scale"], g["m_bh"], g["beta"],
+                g["lum_I0"] if ctx.has_amp[0] else None,
+                g["mass_S0"] if ctx.has_amp[1] else None)
+
+
+def jam_vrms2(jctx: binding.Context, geom_idx, inc, mass_scale, m_bh, beta,
+              lum_I0=None, mass_S0=None):
+    """Differentiable v_rms^2 per bin (packed) and the per-model status."""
+    return JamVrms2.apply(jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "JAM_OK", 1: "JAM_E_INVALID_ARG", 2: "JAM_E_DEPROJECTION",
 
 EXPORTED = ("jam_create", "jam_destroy", "jam_batch_sizes", "jam_workspace_size",
             "jam_prepare", "jam_eval_batch", "jam_eval", "jam_eval_maps", "jam_vjp",
-            "jam_gauss_legendre", "jam_timing", "jam_last_error")
+            "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error")
 
 
 class JamGeometry(ctypes.Structure):
@@ -46,7 +46,8 @@ class JamGeometry(ctypes.Structure):
 
 
 class JamOptions(ctypes.Structure):
-    _fields_ = [("form", c_int32), ("autotune", c_int32), ("tune_cache", ctypes.c_char_p)]
+    _fields_ = [("form", c_int32), ("autotune", c_int32), ("tune_cache", ctypes.c_char_p),
+                ("launch", c_int32), ("graph", c_int32)]
 
 
 class JamBatch(ctypes.Structure):
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.jam_gauss_legendre.argtypes = [c_int32, P_double, P_double]
     lib.jam_timing.argtypes = [c_void_p, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_int64),
                                ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]
+    lib.jam_plan_info.argtypes = [c_void_p, c_int32, P_int32, P_int32]
     lib.jam_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -136,10 +138,10 @@ def _geometry_struct(g, keep: list) -> JamGeometry:
 
 
 def jam_create(geometries: Sequence, form: int = 0, autotune: int = 0,
-               tune_cache: Optional[str] = None) -> int:
+               tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0) -> int:
     keep: list = []
     arr = (JamGeometry * len(geometries))(*[_geometry_struct(g, keep) for g in geometries])
-    opt = JamOptions(form, autotune, tune_cache.encode() if tune_cache else None)
+    opt = JamOptions(form, autotune, tune_cache.encode() if tune_cache else None, launch, graph)
     out = c_void_p()
     _check(load().jam_create(len(geometries), arr, ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -168,6 +170,15 @@ def jam_workspace_size(ctx: int, geom_idx, with_vjp: bool) -> int:
     _check(load().jam_workspace_size(c_void_p(ctx), len(gi), gi.ctypes.data_as(P_int32),
                                      int(with_vjp), ctypes.byref(out)))
     return out.value
+
+
+def jam_plan_info(ctx: int, geom_idx) -> dict:
+    gi = _idx(geom_idx)
+    info = np.zeros(8, np.int32)
+    _check(load().jam_plan_info(c_void_p(ctx), len(gi), gi.ctypes.data_as(P_int32),
+                                info.ctypes.data_as(P_int32)))
+    keys = ("rule", "tau", "gran", "launch", "num_items", "num_grid", "sens_items", "sens_grid")
+    return dict(zip(keys, (int(v) for v in info)))
 
 
 def jam_prepare(ctx: int, geom_idx):
@@ -241,9 +252,9 @@ class Context:
     """
 
     def __init__(self, geometries: Sequence, form: int = 0, autotune: int = 0,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0):
         self.geometries = list(geometries)
-        self.handle = jam_create(self.geometries, form, autotune, tune_cache)
+        self.handle = jam_create(self.geometries, form, autotune, tune_cache, launch, graph)
         self._ws = {}
 
     def close(self):
@@ -270,6 +281,9 @@ class Context:
 
     def sizes(self, geom_idx):
         return jam_batch_sizes(self.handle, geom_idx)
+
+    def plan_info(self, geom_idx) -> dict:
+        return jam_plan_info(self.handle, geom_idx)
 
     def eval_batch(self, geom_idx, inc, mass_scale, m_bh, beta, lum_I0=None, mass_S0=None,
                    stream=None, out=None, status=None):

@@ -237,20 +237,49 @@ void build_geometry(const jam_geometry &g, GeomHost &o) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// How a plan schedules its numerator (what the autotuner varies).
+struct Tune {
+  int rule = 1;     // 0 per-pixel VALU everywhere; 1 matrix cores (64x64 tiles when both
+                    // map sides >= tau, else 32x32 tiles)
+  int tau = 48;
+  int gran = 0;     // term chunks (32 terms) per MFMA item, or (k, j) pairs per per-pixel
+                    // item; 0 = derived from the batch
+  int launch = 0;   // 0 persistent grid pulling items from a device queue; 1 one
+                    // workgroup per item
+};
+
+// Pointers a captured graph was recorded with; replay only on an exact match.
+struct GraphKey {
+  const void *p[10] = {};
+  size_t ws_bytes = 0;
+  bool operator==(const GraphKey &o) const {
+    for (int i = 0; i < 10; ++i)
+      if (p[i] != o.p[i]) return false;
+    return ws_bytes == o.ws_bytes;
+  }
+};
+
 // A prepared batch composition.
 struct Plan {
   std::vector<int32_t> key;
   int n = 0;
+  Tune tune;
   void *arena = nullptr;
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
-            *d_maps = nullptr, *d_chain = nullptr;
-  int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0;
+            *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr;
+  int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0;
+  int grid_num = 1, grid_sens = 1;
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
-  size_t off_status = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0, off_bins = 0,
-         off_sens = 0, off_vtmp = 0, ws_fwd = 0, ws_vjp = 0;
+  size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
+         off_bins = 0, off_sens = 0, off_vtmp = 0, ws_fwd = 0, ws_vjp = 0;
+  // captured evaluations (forward, adjoint)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  GraphKey gkey[2];
   ~Plan() {
+    for (auto &g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
     if (arena) (void)hipFree(arena);
   }
 };
@@ -269,8 +298,8 @@ struct KernelTimer {
     start.clear();
     stop.clear();
   }
-  bool begin(hipStream_t st) {
-    if (!on || used >= (int)start.size()) return false;
+  bool begin(hipStream_t st, bool capturing) {
+    if (!on || capturing || used >= (int)start.size()) return false;
     return hipEventRecord(start[used], st) == hipSuccess;
   }
   void end(hipStream_t st) { (void)hipEventRecord(stop[used++], st); }
@@ -278,16 +307,22 @@ struct KernelTimer {
 
 struct jam_ctx {
   int device = 0;
-  jam_options opt{0, 0, nullptr};
+  int n_cu = 256;
+  int occ_num = 1, occ_sens = 1;
+  jam_options opt{0, 0, nullptr, 0, 0};
+  std::string tune_path;
+  std::vector<std::pair<std::string, Tune>> tuned;   // autotuner cache
   std::vector<GeomHost> gh;
   void *arena = nullptr;
   jam::GeomDev *d_geoms = nullptr;
   std::list<std::unique_ptr<Plan>> plans;   // most recent first
   KernelTimer t_num, t_sens;
+  hipStream_t cap_stream = nullptr;         // graph capture only
   ~jam_ctx() {
     plans.clear();
     t_num.destroy();
     t_sens.destroy();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (arena) (void)hipFree(arena);
   }
 };
@@ -296,32 +331,93 @@ namespace {
 
 constexpr size_t kMaxPlans = 8;
 
-// Split of the (k, j) pair range so that a batch offers enough work items.
-int choose_slices(const GeomHost &g, int n_models) {
-  const int blocks = (g.n_pix + 63) / 64;
-  const int pairs = g.K * g.J1;
-  const int64_t target = std::max<int64_t>(1, 8192 / std::max(1, n_models));
-  int s = (int)std::min<int64_t>((target + blocks - 1) / blocks, std::max(1, pairs / 4));
-  return std::max(1, s);
+// Numerator variant and term-range split of one model under a schedule.
+struct NumChoice {
+  int kind;      // 0 per-pixel VALU, 1 MFMA 64x64 tiles, 2 MFMA 32x32 tiles
+  int n_slices;
+  int tiles;     // work units along the map (pixel blocks or tiles)
+};
+
+NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
+  if (t.rule == 0) {
+    const int pairs = g.K * g.J1;
+    const int per = std::max(1, gran);
+    return {0, std::max(1, (pairs + per - 1) / per), (g.n_pix + 63) / 64};
+  }
+  const int chunks = (g.T + 31) / 32;
+  const bool big = g.n_ux >= t.tau && g.n_uy >= t.tau;
+  const int tw = big ? 64 : 32;
+  const int per = std::max(big ? 4 : 8, gran);
+  return {big ? 1 : 2, std::max(1, (chunks + per - 1) / per),
+          ((g.n_ux + tw - 1) / tw) * ((g.n_uy + tw - 1) / tw)};
 }
 
-jam_status make_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
+// Granularity giving about eight work items per compute unit for the batch.
+int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
+  double work = 0.0;
+  for (int m = 0; m < n; ++m) {
+    const GeomHost &g = ctx->gh[geom_idx[m]];
+    Tune one = t;
+    one.gran = 1;
+    const NumChoice c = choose_numerator(g, one, 1);
+    if (t.rule == 0)
+      work += (double)c.tiles * g.K * g.J1;
+    else
+      work += (double)c.tiles * ((g.T + 31) / 32);
+  }
+  const double target = 8.0 * ctx->n_cu;
+  const double gr = std::ceil(work / target);
+  return (int)std::min(4096.0, std::max(1.0, gr));
+}
+
+// Relative cost of one numerator item, for largest-first ordering.
+double num_item_cost(const GeomHost &g, const NumChoice &c, int slice) {
+  if (c.kind == 0) {
+    const int pairs = g.K * g.J1;
+    const int per = (pairs + c.n_slices - 1) / c.n_slices;
+    const int cnt = std::max(0, std::min(pairs, (slice + 1) * per) - slice * per);
+    return cnt * (double)g.n_u * 64.0 * 5.0 / 32768.0;
+  }
+  const int chunks = (g.T + 31) / 32;
+  const int per = (chunks + c.n_slices - 1) / c.n_slices;
+  const int cnt = std::max(0, std::min(chunks, (slice + 1) * per) - slice * per);
+  return cnt * (c.kind == 1 ? 4.0 : 1.5);
+}
+
+void sort_by_cost(std::vector<jam::Item> &items, std::vector<double> &cost) {
+  std::vector<size_t> idx(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  std::vector<jam::Item> out(items.size());
+  for (size_t i = 0; i < idx.size(); ++i) out[i] = items[idx[i]];
+  items.swap(out);
+}
+
+jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tune &tune_in,
+                      std::unique_ptr<Plan> &out) {
   auto p = std::make_unique<Plan>();
   p->key.assign(geom_idx, geom_idx + n);
   p->n = n;
+  p->tune = tune_in;
+  if (p->tune.gran <= 0) p->tune.gran = default_gran(ctx, n, geom_idx, p->tune);
+  const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
-  std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain;
+  std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens;
+  std::vector<double> c_num, c_sens;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0;
   for (int m = 0; m < n; ++m) {
     const int gi = geom_idx[m];
     const GeomHost &g = ctx->gh[gi];
     jam::ModelDev &d = md[m];
+    std::memset(&d, 0, sizeof d);
     d.geom = gi;
     d.lum_off = (int)p->total_lum;
     d.mass_off = (int)p->total_mass;
     d.out_off = (int)p->total_bins;
-    d.n_slices = choose_slices(g, n);
-    d.form = 1;
+    const NumChoice nc = choose_numerator(g, tune, tune.gran);
+    d.n_slices = nc.n_slices;
+    d.form = nc.kind == 0 ? 1 : 2;
+    d.n_sens_parts = d.form == 1 ? 1 : (g.n_ux + 31) / 32;
     d.n_xt = (g.n_ux + 31) / 32;
     d.n_yt = (g.n_uy + 31) / 32;
     d.gauss_off = gauss;
@@ -336,53 +432,82 @@ jam_status make_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&ou
     pixd += 4 * (int64_t)g.n_pix;
     part += (int64_t)d.n_slices * g.n_pix;
     bins += 2 * (int64_t)g.n_bins;
-    sens += 3 * (int64_t)g.T + (int64_t)g.K * (3 + g.J1);
+    sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 + g.J1);
     p->total_lum += g.K;
     p->total_mass += g.J;
     p->total_bins += g.n_bins;
     p->total_map += (int64_t)g.nxp * g.nyp;
     for (int tb = 0; tb < (g.T + 255) / 256; ++tb) it_terms.push_back({m, tb, 0, 0});
+    if (d.form == 1) {
+      for (int tb = 0; tb < (g.T + 255) / 256; ++tb) {
+        it_sens.push_back({m, tb, 0, 0});
+        c_sens.push_back((double)g.n_pix);
+      }
+    } else {
+      for (int xt = 0; xt < d.n_sens_parts; ++xt)
+        for (int tt = 0; tt < (g.T + 127) / 128; ++tt) {
+          it_sens.push_back({m, xt, tt, 1});
+          c_sens.push_back(4.0 * 32.0 * g.n_uy);
+        }
+    }
     for (int pb = 0; pb < (g.n_pix + 255) / 256; ++pb) it_pix.push_back({m, pb, 0, 0});
-    for (int s = 0; s < d.n_slices; ++s)
-      for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_num.push_back({m, pb, s, 0});
+    for (int s = 0; s < d.n_slices; ++s) {
+      const double c = num_item_cost(g, nc, s);
+      for (int tl = 0; tl < nc.tiles; ++tl) {
+        it_num.push_back({m, tl, s, nc.kind});
+        c_num.push_back(c);
+      }
+    }
     for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
     for (int k = 0; k < g.K; ++k) it_chain.push_back({m, k, 0, 0});
   }
   if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
     return fail(JAM_E_UNSUPPORTED, "batch too large");
-  const size_t sz_items[6] = {it_terms.size(), it_pix.size(), it_num.size(),
-                              it_bins.size(), it_maps.size(), it_chain.size()};
-  for (size_t s : sz_items)
-    if (s > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
+  sort_by_cost(it_num, c_num);
+  sort_by_cost(it_sens, c_sens);
+  constexpr int kLists = 7;
+  std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix,   &it_num, &it_bins,
+                                           &it_maps,  &it_chain, &it_sens};
+  for (auto *l : lists)
+    if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
   size_t off = 0;
   const size_t o_models = off;
   off = align256(off + sizeof(jam::ModelDev) * n);
-  size_t o_it[6];
-  std::vector<jam::Item> *lists[6] = {&it_terms, &it_pix, &it_num, &it_bins, &it_maps, &it_chain};
-  for (int i = 0; i < 6; ++i) {
+  size_t o_it[kLists];
+  for (int i = 0; i < kLists; ++i) {
     o_it[i] = off;
     off = align256(off + sizeof(jam::Item) * std::max<size_t>(1, lists[i]->size()));
   }
   std::vector<char> stage(off, 0);
   std::memcpy(stage.data() + o_models, md.data(), sizeof(jam::ModelDev) * n);
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < kLists; ++i)
     if (!lists[i]->empty())
       std::memcpy(stage.data() + o_it[i], lists[i]->data(), sizeof(jam::Item) * lists[i]->size());
   HIP_TRY(hipMalloc(&p->arena, off));
   HIP_TRY(hipMemcpy(p->arena, stage.data(), off, hipMemcpyHostToDevice));
   char *base = (char *)p->arena;
   p->d_models = (jam::ModelDev *)(base + o_models);
-  jam::Item **dl[6] = {&p->d_terms, &p->d_pix, &p->d_num, &p->d_bins, &p->d_maps, &p->d_chain};
-  int *cnt[6] = {&p->n_terms, &p->n_pix, &p->n_num, &p->n_bins, &p->n_maps, &p->n_chain};
-  for (int i = 0; i < 6; ++i) {
+  jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,   &p->d_num, &p->d_bins,
+                            &p->d_maps,  &p->d_chain, &p->d_sens};
+  int *cnt[kLists] = {&p->n_terms, &p->n_pix,   &p->n_num, &p->n_bins,
+                      &p->n_maps,  &p->n_chain, &p->n_sens};
+  for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
+  }
+  if (tune.launch == 0) {
+    p->grid_num = std::max(1, std::min(p->n_num, ctx->n_cu * ctx->occ_num));
+    p->grid_sens = std::max(1, std::min(p->n_sens, ctx->n_cu * ctx->occ_sens));
+  } else {
+    p->grid_num = std::max(1, p->n_num);
+    p->grid_sens = std::max(1, p->n_sens);
   }
   // workspace layout
   size_t w = 0;
   p->off_status = w; w = align256(w + sizeof(int) * n);
+  p->off_queue = w;  w = align256(w + sizeof(int) * 2);
   p->off_gauss = w;  w = align256(w + sizeof(double) * gauss);
   p->off_terms = w;  w = align256(w + sizeof(float4) * terms);
   p->off_pix = w;    w = align256(w + sizeof(double) * pixd);
@@ -392,9 +517,203 @@ jam_status make_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&ou
   p->off_sens = w;   w = align256(w + sizeof(double) * sens);
   p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->ws_vjp = w;
-  out = p.get();
-  ctx->plans.push_front(std::move(p));
-  while (ctx->plans.size() > kMaxPlans) ctx->plans.pop_back();
+  out = std::move(p);
+  return JAM_OK;
+}
+
+jam::ParamsDev params_of(const jam_batch *b) {
+  return jam::ParamsDev{b->inc, b->mass_scale, b->m_bh, b->beta, b->lum_I0, b->mass_S0};
+}
+
+// Set-up, term table and SB map; optionally the numerator map.  Leaves N and
+// I in the workspace pix region.
+void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_t *status,
+                         char *ws, hipStream_t st, bool need_numerator, bool capturing) {
+  int *st_ws = (int *)(ws + p->off_status);
+  int *queue = (int *)(ws + p->off_queue);
+  double *gauss = (double *)(ws + p->off_gauss);
+  float4 *terms = (float4 *)(ws + p->off_terms);
+  double *pix = (double *)(ws + p->off_pix);
+  double *part = (double *)(ws + p->off_part);
+  jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
+  jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
+  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, pd, pix, st);
+  if (need_numerator) {
+    const bool timed = ctx->t_num.begin(st, capturing);
+    jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
+                    p->tune.launch == 0 ? queue : nullptr, p->grid_num, st);
+    if (timed) ctx->t_num.end(st);
+    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, part, pix, st);
+  }
+}
+
+void launch_eval(jam_ctx *ctx, Plan *p, const jam_batch *b, double *vrms2, int32_t *status,
+                 char *w, hipStream_t st, bool capturing) {
+  launch_forward_maps(ctx, p, params_of(b), status, w, st, true, capturing);
+  jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, (const double *)(w + p->off_pix),
+                   (const int *)(w + p->off_status), vrms2, (double *)(w + p->off_bins), st);
+}
+
+void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, const double *cot,
+                const jam_grads *grads, char *w, hipStream_t st, bool capturing) {
+  const int *st_ws = (const int *)(w + p->off_status);
+  int *queue = (int *)(w + p->off_queue);
+  double *pix = (double *)(w + p->off_pix);
+  double *binws = (double *)(w + p->off_bins);
+  double *sens = (double *)(w + p->off_sens);
+  const jam::ParamsDev pd = params_of(b);
+  const bool recompute = (vrms2 == nullptr);
+  launch_forward_maps(ctx, p, pd, nullptr, w, st, recompute, capturing);
+  // V per bin: the caller's forward output, or recomputed into workspace.
+  const double *V = vrms2;
+  if (recompute) {
+    double *vtmp = (double *)(w + p->off_vtmp);
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, vtmp, binws, st);
+    V = vtmp;
+  } else {
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, nullptr, binws, st);
+  }
+  jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
+  const bool timed = ctx->t_sens.begin(st, capturing);
+  jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
+                   (const float4 *)(w + p->off_terms), pix, st_ws, sens,
+                   p->tune.launch == 0 ? queue + 1 : nullptr, p->grid_sens, st);
+  if (timed) ctx->t_sens.end(st);
+  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
+  const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
+                         grads->mass_S0};
+  jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, st_ws, gd, st);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner.  Candidates differ in the numerator schedule only (variant rule,
+// 64x64-tile threshold, items' term granularity, persistent or one workgroup
+// per item); each is timed on the batch composition with fixed valid
+// parameters (edge-on, isotropic, unit mass scale) in a scratch workspace.
+// Results are cached per composition signature, in memory and optionally in
+// a text file (one "key rule tau gran launch" line per entry).
+// ---------------------------------------------------------------------------
+std::string tune_key(const jam_ctx *ctx, int n, const int32_t *geom_idx) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  for (int m = 0; m < n; ++m) {
+    const GeomHost &g = ctx->gh[geom_idx[m]];
+    mix((uint64_t)g.n_ux | ((uint64_t)g.n_uy << 20) | ((uint64_t)g.T << 40));
+  }
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950/v1/n%d/%016llx", n, (unsigned long long)h);
+  return buf;
+}
+
+void load_tune_file(jam_ctx *ctx) {
+  if (ctx->tune_path.empty()) return;
+  FILE *f = fopen(ctx->tune_path.c_str(), "r");
+  if (!f) return;
+  char key[160];
+  Tune t;
+  while (fscanf(f, "%159s %d %d %d %d", key, &t.rule, &t.tau, &t.gran, &t.launch) == 5)
+    ctx->tuned.push_back({key, t});
+  fclose(f);
+}
+
+void save_tune_file(const jam_ctx *ctx) {
+  if (ctx->tune_path.empty()) return;
+  FILE *f = fopen(ctx->tune_path.c_str(), "w");
+  if (!f) return;
+  for (auto &e : ctx->tuned)
+    fprintf(f, "%s %d %d %d %d\n", e.first.c_str(), e.second.rule, e.second.tau, e.second.gran,
+            e.second.launch);
+  fclose(f);
+}
+
+jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best) {
+  std::vector<Tune> cands;
+  Tune base;
+  const int g0 = default_gran(ctx, n, geom_idx, base);
+  for (int launch = 0; launch < 2; ++launch)
+    for (int tau : {32, 64, 1 << 30})
+      for (double mul : {0.5, 1.0, 2.0}) {
+        Tune t;
+        t.rule = 1;
+        t.tau = tau;
+        t.gran = std::max(1, (int)std::lround(g0 * mul));
+        t.launch = launch;
+        cands.push_back(t);
+      }
+  {
+    Tune t;
+    t.rule = 0;
+    t.gran = 0;
+    cands.push_back(t);
+  }
+  std::vector<std::unique_ptr<Plan>> plans(cands.size());
+  size_t ws_max = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const jam_status s = build_plan(ctx, n, geom_idx, cands[i], plans[i]);
+    if (s != JAM_OK) return s;
+    ws_max = std::max(ws_max, plans[i]->ws_fwd);
+  }
+  int64_t nl = 0;
+  for (int m = 0; m < n; ++m) nl += ctx->gh[geom_idx[m]].K;
+  void *ws = nullptr, *prm = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (prm) (void)hipFree(prm);
+    if (ws) (void)hipFree(ws);
+  };
+  std::vector<double> host(3 * (size_t)n + nl, 0.0);
+  for (int m = 0; m < n; ++m) {
+    host[m] = kPi / 2;                 // inclination
+    host[n + m] = 1.0;                 // mass scale
+    host[2 * n + m] = 1.0e8;           // BH mass
+  }
+  if (hipMalloc(&ws, ws_max) != hipSuccess || hipMalloc(&prm, host.size() * 8) != hipSuccess ||
+      hipStreamCreate(&st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess ||
+      hipMemcpy(prm, host.data(), host.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    cleanup();
+    return fail(JAM_E_DEVICE, "autotune: device allocation failed");
+  }
+  const double *pp = (const double *)prm;
+  const jam::ParamsDev pd{pp, pp + n, pp + 2 * n, pp + 3 * n, nullptr, nullptr};
+  double best_ms = 1e300;
+  size_t best_i = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    Plan *p = plans[i].get();
+    char *w = (char *)ws;
+    float ms = 0.f, tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      launch_forward_maps(ctx, p, pd, nullptr, w, st, false, true);
+      (void)hipEventRecord(e0, st);
+      jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
+                      (const float4 *)(w + p->off_terms), (const int *)(w + p->off_status),
+                      (double *)(w + p->off_part), p->tune.launch == 0 ? (int *)(w + p->off_queue) : nullptr,
+                      p->grid_num, st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        cleanup();
+        return fail(JAM_E_DEVICE, "autotune: timing failed");
+      }
+      if (rep > 0) tot += ms;    // first run warms caches and clocks
+    }
+    if (tot < best_ms) {
+      best_ms = tot;
+      best_i = i;
+    }
+  }
+  const hipError_t e = hipGetLastError();
+  cleanup();
+  if (e != hipSuccess) return fail(JAM_E_DEVICE, "autotune: %s", hipGetErrorString(e));
+  best = plans[best_i]->tune;
   return JAM_OK;
 }
 
@@ -413,7 +732,32 @@ jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out
       return JAM_OK;
     }
   }
-  return make_plan(ctx, n, geom_idx, out);
+  Tune t;
+  if (ctx->opt.form == 1) t.rule = 0;
+  if (ctx->opt.launch == 1) t.launch = 1;
+  if (ctx->opt.form == 0 && ctx->opt.autotune) {
+    const std::string key = tune_key(ctx, n, geom_idx);
+    bool found = false;
+    for (auto &e : ctx->tuned)
+      if (e.first == key) {
+        t = e.second;
+        found = true;
+        break;
+      }
+    if (!found) {
+      const jam_status s = autotune(ctx, n, geom_idx, t);
+      if (s != JAM_OK) return s;
+      ctx->tuned.push_back({key, t});
+      save_tune_file(ctx);
+    }
+  }
+  std::unique_ptr<Plan> p;
+  const jam_status s = build_plan(ctx, n, geom_idx, t, p);
+  if (s != JAM_OK) return s;
+  out = p.get();
+  ctx->plans.push_front(std::move(p));
+  while (ctx->plans.size() > kMaxPlans) ctx->plans.pop_back();
+  return JAM_OK;
 }
 
 // Switch to the context's device for the duration of a call.
@@ -437,37 +781,38 @@ jam_status check_batch(const jam_batch *b) {
   return JAM_OK;
 }
 
-jam::ParamsDev params_of(const jam_batch *b) {
-  return jam::ParamsDev{b->inc, b->mass_scale, b->m_bh, b->beta, b->lum_I0, b->mass_S0};
-}
-
-// Forward part shared by eval, maps and (recomputing) vjp: set-up, terms,
-// SB map, numerator map.  Leaves N and I in the workspace pix region.
-jam_status forward_maps(jam_ctx *ctx, Plan *p, const jam_batch *b, int32_t *status, char *ws,
-                        hipStream_t st, bool need_numerator) {
-  const jam::ParamsDev pd = params_of(b);
-  int *st_ws = (int *)(ws + p->off_status);
-  double *gauss = (double *)(ws + p->off_gauss);
-  float4 *terms = (float4 *)(ws + p->off_terms);
-  double *pix = (double *)(ws + p->off_pix);
-  double *part = (double *)(ws + p->off_part);
-  jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, st);
-  jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
-  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, pd, pix, st);
-  if (need_numerator) {
-    const bool timed = ctx->t_num.begin(st);
-    jam::launch_num_pix(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part, st);
-    if (timed) ctx->t_num.end(st);
-    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, part, pix, st);
-  }
-  HIP_TRY(hipGetLastError());
-  return JAM_OK;
-}
-
 jam_status check_ws(void *ws, size_t ws_bytes, size_t need) {
   if (need > ws_bytes) return fail(JAM_E_WORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need);
   if (!ws) return fail(JAM_E_WORKSPACE, "workspace is NULL");
   if (((uintptr_t)ws & 255) != 0) return fail(JAM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  return JAM_OK;
+}
+
+// Replay the plan's captured graph `which` (0 forward, 1 adjoint) if it was
+// recorded with exactly these pointers; otherwise record it first on the
+// context's capture stream.  `record` launches the sequence on a stream.
+template <typename F>
+jam_status run_graph(jam_ctx *ctx, Plan *p, int which, const GraphKey &key, hipStream_t st,
+                     F record) {
+  if (!p->gexec[which] || !(p->gkey[which] == key)) {
+    if (p->gexec[which]) {
+      HIP_TRY(hipGraphExecDestroy(p->gexec[which]));
+      p->gexec[which] = nullptr;
+    }
+    if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    record(ctx->cap_stream);
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamEndCapture(ctx->cap_stream, &graph));
+    const hipError_t e = hipGraphInstantiate(&p->gexec[which], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      p->gexec[which] = nullptr;
+      return fail(JAM_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    p->gkey[which] = key;
+  }
+  HIP_TRY(hipGraphLaunch(p->gexec[which], st));
   return JAM_OK;
 }
 
@@ -538,10 +883,17 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
   }
   if (opt && (opt->form < 0 || opt->form > 2))
     return fail(JAM_E_INVALID_ARG, "options.form must be 0, 1 or 2");
+  if (opt && (opt->launch < 0 || opt->launch > 1))
+    return fail(JAM_E_INVALID_ARG, "options.launch must be 0 or 1");
   auto ctx = std::make_unique<jam_ctx>();
   if (opt) ctx->opt = *opt;
-  ctx->opt.tune_cache = nullptr;   // not retained
+  if (opt && opt->tune_cache) ctx->tune_path = opt->tune_cache;
+  ctx->opt.tune_cache = nullptr;   // the path is copied
   HIP_TRY(hipGetDevice(&ctx->device));
+  HIP_TRY(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  ctx->occ_num = jam::occupancy_num();
+  ctx->occ_sens = jam::occupancy_sens();
+  load_tune_file(ctx.get());
   ctx->gh.resize(n_geom);
   {
     const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
@@ -664,9 +1016,20 @@ jam_status jam_eval_batch(jam_ctx *ctx, const jam_batch *batch, double *vrms2, i
   if ((s = check_ws(ws, ws_bytes, p->ws_fwd)) != JAM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  if ((s = forward_maps(ctx, p, batch, status, w, st, true)) != JAM_OK) return s;
-  jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, (const double *)(w + p->off_pix),
-                   (const int *)(w + p->off_status), vrms2, (double *)(w + p->off_bins), st);
+  if (ctx->opt.graph) {
+    GraphKey k;
+    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                            batch->mass_S0, vrms2, status, ws, nullptr};
+    std::copy(ptrs, ptrs + 10, k.p);
+    k.ws_bytes = ws_bytes;
+    const jam_batch b = *batch;
+    s = run_graph(ctx, p, 0, k, st, [&](hipStream_t cs) {
+      launch_eval(ctx, p, &b, vrms2, status, w, cs, true);
+    });
+    if (s != JAM_OK) return s;
+  } else {
+    launch_eval(ctx, p, batch, vrms2, status, w, st, false);
+  }
   HIP_TRY(hipGetLastError());
   return JAM_OK;
 }
@@ -690,7 +1053,7 @@ jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map, do
   if ((s = check_ws(ws, ws_bytes, p->ws_fwd)) != JAM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  if ((s = forward_maps(ctx, p, batch, status, w, st, true)) != JAM_OK) return s;
+  launch_forward_maps(ctx, p, params_of(batch), status, w, st, true, false);
   jam::launch_maps(ctx->d_geoms, p->d_models, p->d_maps, p->n_maps, (const double *)(w + p->off_pix),
                    (const int *)(w + p->off_status), N_map, I_map, st);
   HIP_TRY(hipGetLastError());
@@ -710,32 +1073,46 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, co
   if ((s = check_ws(ws, ws_bytes, p->ws_vjp)) != JAM_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
-  const int *st_ws = (const int *)(w + p->off_status);
-  double *pix = (double *)(w + p->off_pix);
-  double *binws = (double *)(w + p->off_bins);
-  double *sens = (double *)(w + p->off_sens);
-  const bool recompute = (vrms2 == nullptr);
-  if ((s = forward_maps(ctx, p, batch, nullptr, w, st, recompute)) != JAM_OK) return s;
-  // V per bin: the caller's forward output, or recomputed into workspace.
-  const double *V = vrms2;
-  if (recompute) {
-    double *vtmp = (double *)(w + p->off_vtmp);
-    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, vtmp, binws, st);
-    V = vtmp;
-  } else {
-    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, nullptr, binws, st);
-  }
-  jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
-  const bool timed = ctx->t_sens.begin(st);
-  jam::launch_sens_pix(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms,
-                       (const float4 *)(w + p->off_terms), pix, st_ws, sens, st);
-  if (timed) ctx->t_sens.end(st);
-  const jam::ParamsDev pd = params_of(batch);
-  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
-  const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
+  if (ctx->opt.graph) {
+    GraphKey k;
+    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta,
+                            batch->lum_I0, batch->mass_S0, vrms2, cot, ws, nullptr};
+    std::copy(ptrs, ptrs + 10, k.p);
+    k.ws_bytes = ws_bytes;
+    // gradient outputs are part of the recorded launches
+    const void *gp[6] = {grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
                          grads->mass_S0};
-  jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, st_ws, gd, st);
+    uintptr_t hsh = 0;
+    for (const void *q : gp) hsh = hsh * 1000003u ^ (uintptr_t)q;
+    k.p[9] = (const void *)hsh;
+    const jam_batch b = *batch;
+    const jam_grads g = *grads;
+    s = run_graph(ctx, p, 1, k, st, [&](hipStream_t cs) {
+      launch_vjp(ctx, p, &b, vrms2, cot, &g, w, cs, true);
+    });
+    if (s != JAM_OK) return s;
+  } else {
+    launch_vjp(ctx, p, batch, vrms2, cot, grads, w, st, false);
+  }
   HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t *info) {
+  if (!ctx || !info) return fail(JAM_E_INVALID_ARG, "invalid arguments");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  const jam_status s = get_plan(ctx, n, geom_idx, p);
+  if (s != JAM_OK) return s;
+  info[0] = p->tune.rule;
+  info[1] = p->tune.tau;
+  info[2] = p->tune.gran;
+  info[3] = p->tune.launch;
+  info[4] = p->n_num;
+  info[5] = p->grid_num;
+  info[6] = p->n_sens;
+  info[7] = p->grid_sens;
   return JAM_OK;
 }
 

@@ -43,6 +43,8 @@ struct ModelDev {
   int n_slices;      // split of the term range in the numerator kernels
   int n_xt, n_yt;    // 32x32 tiles of the unique-pixel map (MFMA form)
   int form;          // 1 per-pixel VALU, 2 separable MFMA
+  int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
+  int pad;
   int64_t gauss_off; // doubles, per-Gaussian derived quantities
   int64_t term_off;  // float4 entries, term table
   int64_t pix_off;   // doubles, unique-pixel maps (N, I, lambda)
@@ -75,16 +77,23 @@ struct GradsDev {
 __host__ __device__ inline int64_t gauss_size(int K, int J1) { return 4 * K + 3 * J1 + 2; }
 
 // Kernel launchers (jam_kernels.hip).  All asynchronous on `st`.
+// Also zeroes the two work-queue counters queues[0..1] (may be NULL).
 void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *gauss,
-                  int *st_ws, int32_t *st_out, hipStream_t st);
+                  int *st_ws, int32_t *st_out, int *queues, hipStream_t st);
 void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
-void launch_num_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                    const float4 *terms, const int *st_ws, double *part, hipStream_t st);
-void launch_num_mfma(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                     const float4 *terms, const int *st_ws, double *part, hipStream_t st);
+// Numerator over a work list whose items carry their variant in Item::c:
+// 0 per-pixel VALU (m, 64-pixel block, slice), 1 MFMA 64x64 tiles and
+// 2 MFMA 32x32 tiles (m, tile, slice).  queue != NULL: persistent grid of
+// `grid` workgroups pulling items from the counter; else `grid` workgroups
+// striding over the list.
+void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
+                hipStream_t st);
+int occupancy_num();    // resident numerator workgroups per CU
+int occupancy_sens();   // resident sensitivity workgroups per CU
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st);
 void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
@@ -96,14 +105,15 @@ void launch_maps(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                          const double *vrms2, const double *cot, const double *binws,
                          const int *st_ws, double *pix, hipStream_t st);
-void launch_sens_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                     const float4 *terms, const double *pix, const int *st_ws, double *sens,
-                     hipStream_t st);
-void launch_sens_mfma(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                      const float4 *terms, const double *pix, const int *st_ws, double *sens,
-                      hipStream_t st);
-// sens region per model: [S0 | S1 | Sg] (T doubles each), then the chain
-// rows [K][3 + J1] doubles.
+// Sensitivities, variant in Item::c: 0 per-pixel VALU (m, 256-term block),
+// 1 MFMA (m, 32-row x tile, 128-term tile); queue as launch_num.
+void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                 const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                 int *queue, int grid, hipStream_t st);
+// sens region per model: n_sens_parts blocks of [S0 | S1 | Sg] (T doubles
+// each), then the chain rows [K][3 + J1] doubles.  The per-pixel kernel
+// writes one block; the MFMA kernel one block per 32-row x tile (items
+// (m, x tile, 128-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, const double *sens,

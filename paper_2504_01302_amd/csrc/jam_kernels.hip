@@ -67,7 +67,10 @@ __device__ inline double wave_sum(double v) {
 __global__ void __launch_bounds__(64) k_setup(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models, int n,
                                               ParamsDev p, double *__restrict__ gauss,
-                                              int *__restrict__ st_ws, int32_t *__restrict__ st_out) {
+                                              int *__restrict__ st_ws, int32_t *__restrict__ st_out,
+                                              int *__restrict__ queues) {
+  // Work-queue counters of the kernels that follow on the stream.
+  if (queues && blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
@@ -213,53 +216,249 @@ __global__ void __launch_bounds__(256) k_sb(const GeomDev *__restrict__ geoms,
 // range of (k, j) pairs, split over the 4 waves; lanes are unique pixels and
 // the term coefficients are wave-uniform (scalar loads).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_num_pix(const GeomDev *__restrict__ geoms,
-                                                 const ModelDev *__restrict__ models,
-                                                 const Item *__restrict__ items, int n_it,
-                                                 const float4 *__restrict__ terms,
-                                                 const int *__restrict__ st_ws,
-                                                 double *__restrict__ part) {
-  __shared__ double red[256];
+__device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
+  double *red = reinterpret_cast<double *>(smem);
+
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
-    const Item it = items[i];
-    const ModelDev md = models[it.m];
-    const GeomDev g = geoms[md.geom];
-    const int q = it.a * 64 + lane;
-    const bool valid = q < g.n_pix;
-    float x2 = 0.f, y2 = 0.f;
-    if (valid) {
-      const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-      x2 = (float)(x * x);
-      y2 = (float)(y * y);
-    }
-    const int n_pairs = g.K * g.J1;
-    const int per = (n_pairs + md.n_slices - 1) / md.n_slices;
-    const int p0 = it.b * per;
-    const int p1 = min(n_pairs, p0 + per);
-    double acc = 0.0;
-    if (st_ws[it.m] == 0) {
-      const float4 *tb = terms + md.term_off;
-      const int nu = g.n_u;
-      for (int pr = p0 + wave; pr < p1; pr += 4) {
-        const float4 *tp = tb + (int64_t)pr * nu;
-        float s = 0.f;
-        for (int n = 0; n < nu; ++n) {
-          const float4 c = tp[n];
-          const float e = fast_exp2(fmaf(c.x, x2, c.y * y2));
-          s = fmaf(e, fmaf(c.w, x2, c.z), s);
-        }
-        acc += (double)s;
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  const int q = it.a * 64 + lane;
+  const bool valid = q < g.n_pix;
+  float x2 = 0.f, y2 = 0.f;
+  if (valid) {
+    const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
+    x2 = (float)(x * x);
+    y2 = (float)(y * y);
+  }
+  const int n_pairs = g.K * g.J1;
+  const int per = (n_pairs + md.n_slices - 1) / md.n_slices;
+  const int p0 = it.b * per;
+  const int p1 = min(n_pairs, p0 + per);
+  double acc = 0.0;
+  if (st_ws[it.m] == 0) {
+    const float4 *tb = terms + md.term_off;
+    const int nu = g.n_u;
+    for (int pr = p0 + wave; pr < p1; pr += 4) {
+      const float4 *tp = tb + (int64_t)pr * nu;
+      float s = 0.f;
+      for (int n = 0; n < nu; ++n) {
+        const float4 c = tp[n];
+        const float e = fast_exp2(fmaf(c.x, x2, c.y * y2));
+        s = fmaf(e, fmaf(c.w, x2, c.z), s);
       }
+      acc += (double)s;
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < 64 && valid) {
-      const double v = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
-      part[md.part_off + (int64_t)it.b * g.n_pix + q] = v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < 64 && valid) {
+    const double v = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
+    part[md.part_off + (int64_t)it.b * g.n_pix + q] = v;
+  }
+  __syncthreads();
+}
+
+
+// ---------------------------------------------------------------------------
+// Separable matrix-core form.  On the unique-pixel map
+//   N[x, y] = sum_t A[x, t] B[y, t],
+//   A[x, t] = 2^(cx_t x^2) (C0_t + C1_t x^2),   B[y, t] = 2^(cy_t y^2),
+// an exact factorisation of the same sum, evaluated as a dense FP32
+// contraction over terms with v_mfma_f32_32x32x2f32.  Each 32x32 output
+// block accumulates a chunk of 32 terms in FP32 and folds it into FP64.
+//
+// Operand layout of v_mfma_f32_32x32x2f32 (lane l): A[l % 32][l / 32],
+// B[l / 32][l % 32]; accumulator r of lane l is D[i][j] with
+// i = (r % 4) + 4 (l / 32) + 8 (r / 4), j = l % 32.
+// ---------------------------------------------------------------------------
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int KC = 32;   // terms per chunk
+
+__device__ inline int mfma_row(int r, int lane) { return (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2); }
+
+// Term range of one slice, in whole chunks.
+__device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int &t1) {
+  const int chunks = (T + KC - 1) / KC;
+  const int per = (chunks + n_slices - 1) / n_slices;
+  t0 = min(T, slice * per * KC);
+  t1 = min(T, t0 + per * KC);
+}
+
+// 64x64 output tile per workgroup, 2x2 waves of 32x32; the A (64 rows) and
+// B (64 columns) operands of each chunk are generated once into LDS (double
+// buffered) and shared by the four waves.  Item (m, tile, slice).
+__device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
+  float (*As)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem);
+  float (*Bs)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem + 2 * KC * 64 * sizeof(float));
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wx = wave & 1, wy = wave >> 1;
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  const int n_xt = (g.n_ux + 63) >> 6;
+  const int x0 = (it.a % n_xt) * 64, y0 = (it.a / n_xt) * 64;
+  const int xi = x0 + lane, yi = y0 + lane;
+  const bool vx = xi < g.n_ux, vy = yi < g.n_uy;
+  float x2 = 0.f, y2 = 0.f;
+  if (vx) { const double x = g.xs[xi]; x2 = (float)(x * x); }
+  if (vy) { const double y = g.ys[yi]; y2 = (float)(y * y); }
+  int t0, t1;
+  slice_range(g.T, md.n_slices, it.b, t0, t1);
+  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC - 1) / KC : 0;
+  const bool active = (x0 + wx * 32 < g.n_ux) && (y0 + wy * 32 < g.n_uy);
+  const float4 *tb = terms + md.term_off;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  auto gen = [&](int buf, int ch) {
+#pragma unroll 2
+    for (int kk = wave; kk < KC; kk += 4) {
+      const int t = t0 + ch * KC + kk;
+      float a = 0.f, b = 0.f;
+      if (t < t1) {
+        const float4 c = tb[t];
+        a = vx ? fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z) : 0.f;
+        b = vy ? fast_exp2(c.y * y2) : 0.f;
+      }
+      As[buf][kk][lane] = a;
+      Bs[buf][kk][lane] = b;
+    }
+  };
+  if (n_ch > 0) gen(0, 0);
+  __syncthreads();
+  for (int ch = 0; ch < n_ch; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < n_ch) gen(cur ^ 1, ch + 1);
+    if (active) {
+      v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const int kh = lane >> 5, c32 = lane & 31;
+#pragma unroll
+      for (int s2 = 0; s2 < KC / 2; ++s2) {
+        const float a = As[cur][2 * s2 + kh][wx * 32 + c32];
+        const float b = Bs[cur][2 * s2 + kh][wy * 32 + c32];
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
     }
     __syncthreads();
+  }
+  if (active) {
+    const int yj = y0 + wy * 32 + (lane & 31);
+    double *out = part + md.part_off + (int64_t)it.b * g.n_pix;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int xr = x0 + wx * 32 + mfma_row(r, lane);
+      if (xr < g.n_ux && yj < g.n_uy) out[(int64_t)yj * g.n_ux + xr] = acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+
+// 32x32 output tile per workgroup for small maps; each of the 4 waves takes
+// every 4th chunk of the slice and generates its own operands in registers
+// (lane l: row/column l % 32, term of its half-wave), then the four FP64
+// partial tiles are summed through LDS in a fixed order.  Item (m, tile, slice).
+__device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
+  double (*red)[16][64] = reinterpret_cast<double (*)[16][64]>(smem);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  const int n_xt = (g.n_ux + 31) >> 5;
+  const int x0 = (it.a % n_xt) * 32, y0 = (it.a / n_xt) * 32;
+  const int c32 = lane & 31, kh = lane >> 5;
+  const int xi = x0 + c32, yi = y0 + c32;
+  const bool vx = xi < g.n_ux, vy = yi < g.n_uy;
+  float x2 = 0.f, y2 = 0.f;
+  if (vx) { const double x = g.xs[xi]; x2 = (float)(x * x); }
+  if (vy) { const double y = g.ys[yi]; y2 = (float)(y * y); }
+  int t0, t1;
+  slice_range(g.T, md.n_slices, it.b, t0, t1);
+  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC - 1) / KC : 0;
+  const float4 *tb = terms + md.term_off;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int ch = wave; ch < n_ch; ch += 4) {
+    v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int tc = t0 + ch * KC;
+#pragma unroll 4
+    for (int s2 = 0; s2 < KC / 2; ++s2) {
+      const int t = tc + 2 * s2 + kh;
+      float a = 0.f, b = 0.f;
+      if (t < t1) {
+        const float4 c = tb[t];
+        a = vx ? fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z) : 0.f;
+        b = vy ? fast_exp2(c.y * y2) : 0.f;
+      }
+      d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave - 1][r][lane] = acc[r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int yj = y0 + c32;
+    double *out = part + md.part_off + (int64_t)it.b * g.n_pix;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+      const int xr = x0 + mfma_row(r, lane);
+      if (xr < g.n_ux && yj < g.n_uy) out[(int64_t)yj * g.n_ux + xr] = v;
+    }
+  }
+  __syncthreads();
+}
+
+
+// Largest LDS user among the numerator variants (the 64x64 MFMA tiles).
+constexpr int kNumSmem = 2 * 2 * KC * 64 * (int)sizeof(float);
+static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double), "32x32 variant LDS");
+static_assert(kNumSmem >= 256 * (int)sizeof(double), "per-pixel variant LDS");
+
+// Numerator over a work list whose items carry their variant in Item::c
+// (0 per-pixel VALU, 1 MFMA 64x64, 2 MFMA 32x32), so one launch serves a
+// batch of uneven models.  With a queue, every workgroup pulls the next item
+// from a device counter (a persistent grid; items are ordered largest first);
+// without one, workgroups stride over the list.
+__global__ void __launch_bounds__(256) k_num(const GeomDev *__restrict__ geoms,
+                                             const ModelDev *__restrict__ models,
+                                             const Item *__restrict__ items, int n_it,
+                                             const float4 *__restrict__ terms,
+                                             const int *__restrict__ st_ws,
+                                             double *__restrict__ part, int *queue) {
+  __shared__ __attribute__((aligned(16))) char smem[kNumSmem];
+  __shared__ int next;
+  int i = blockIdx.x;
+  for (;;) {
+    if (queue) {
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+      __syncthreads();
+      i = next;
+      __syncthreads();
+    }
+    if (i >= n_it) break;
+    const Item it = items[i];
+    if (it.c == 0)
+      num_pix_item(it, geoms, models, terms, st_ws, part, smem);
+    else if (it.c == 1)
+      num_mfma64_item(it, geoms, models, terms, st_ws, part, smem);
+    else
+      num_mfma32_item(it, geoms, models, terms, st_ws, part, smem);
+    if (!queue) i += gridDim.x;
   }
 }
 
@@ -387,57 +586,173 @@ __global__ void __launch_bounds__(256) k_bins_adjoint(const GeomDev *__restrict_
 // with E F = exp(-c1 x^2 - gamma y^2).  Item (m, 256-term block).
 // sens per model: [S0 | S1 | Sg], T doubles each.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_sens_pix(const GeomDev *__restrict__ geoms,
-                                                  const ModelDev *__restrict__ models,
-                                                  const Item *__restrict__ items, int n_it,
-                                                  const float4 *__restrict__ terms,
-                                                  const double *__restrict__ pix,
-                                                  const int *__restrict__ st_ws,
-                                                  double *__restrict__ sens) {
-  __shared__ float sx[256], sy[256], sl[256];
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+__device__ __forceinline__ void sens_pix_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const double *__restrict__ pix, const int *__restrict__ st_ws, double *__restrict__ sens, char *smem) {
+  float *sx = reinterpret_cast<float *>(smem), *sy = sx + 256, *sl = sy + 256;
+
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  if (st_ws[it.m] != 0) return;   // uniform per block
+  const int t = it.a * 256 + threadIdx.x;
+  const bool valid = t < g.T;
+  const float4 c = valid ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const double *lam = pix + md.pix_off + 2 * (int64_t)g.n_pix;
+  double a0 = 0.0, a1 = 0.0, ag = 0.0;
+  for (int base = 0; base < g.n_pix; base += 256) {
+    const int q = base + threadIdx.x;
+    __syncthreads();
+    if (q < g.n_pix) {
+      const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
+      sx[threadIdx.x] = (float)(x * x);
+      sy[threadIdx.x] = (float)(y * y);
+      sl[threadIdx.x] = (float)lam[q];
+    } else {
+      sx[threadIdx.x] = 0.f;
+      sy[threadIdx.x] = 0.f;
+      sl[threadIdx.x] = 0.f;
+    }
+    __syncthreads();
+    const int cnt = min(256, g.n_pix - base);
+    float s0 = 0.f, s1 = 0.f, sg = 0.f;
+    for (int e = 0; e < cnt; ++e) {
+      const float x2 = sx[e], y2 = sy[e];
+      const float le = sl[e] * fast_exp2(fmaf(c.x, x2, c.y * y2));
+      s0 += le;
+      s1 = fmaf(le, x2, s1);
+      sg = fmaf(le * y2, fmaf(c.w, x2, c.z), sg);
+    }
+    a0 += s0;
+    a1 += s1;
+    ag += sg;
+  }
+  if (valid) {
+    double *S = sens + md.sens_off;
+    S[t] = a0;
+    S[g.T + t] = a1;
+    S[2 * (int64_t)g.T + t] = ag;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Per-term adjoint sensitivities, matrix-core form.  With E_t(x) = 2^(cx x^2)
+// and F_t(y) = 2^(cy y^2) on the unique-pixel map,
+//   G[x, t] = sum_y lambda[x, y] F_t(y),   H[x, t] = sum_y lambda[x, y] y^2 F_t(y)
+// are two FP32 contractions over y sharing the lambda operand, and
+//   S0_t = sum_x E G,  S1_t = sum_x x^2 E G,  Sg_t = sum_x E (C0 + C1 x^2) H.
+// Item (m, 32-row x tile, 128-term tile); wave w owns terms 32 w .. 32 w + 31
+// of the tile (lane l: term l % 32, y pair l / 32).  lambda is staged through
+// LDS 256 rows of y at a time; FP32 partial sums over 32 y values are folded
+// into FP64.  Output: per x tile, [S0 | S1 | Sg] (T doubles each).
+// ---------------------------------------------------------------------------
+constexpr int YC = 256;
+
+__device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const double *__restrict__ pix, const int *__restrict__ st_ws, double *__restrict__ sens, char *smem) {
+  float (*lam)[32] = reinterpret_cast<float (*)[32]>(smem);
+  float *ysq = reinterpret_cast<float *>(smem + YC * 32 * sizeof(float));
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c32 = lane & 31, kh = lane >> 5;
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  if (st_ws[it.m] != 0) return;   // uniform per block
+  const int x0 = it.a * 32;
+  const int t = it.b * 128 + wave * 32 + c32;
+  const bool vt = t < g.T;
+  const float4 c = vt ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
+  double gacc[16], hacc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) { gacc[r] = 0.0; hacc[r] = 0.0; }
+  for (int yb = 0; yb < g.n_uy; yb += YC) {
+    const int ny = min(YC, g.n_uy - yb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < YC * 32; e += 256) {
+      const int yy = e >> 5, xx = e & 31;
+      float v = 0.f;
+      if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
+      lam[yy][xx] = v;
+    }
+    for (int e = threadIdx.x; e < YC; e += 256) {
+      float v = 0.f;
+      if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
+      ysq[e] = v;
+    }
+    __syncthreads();
+    for (int y0 = 0; y0 < ny; y0 += 32) {
+      v16f dg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      v16f dh = dg;
+#pragma unroll 4
+      for (int s2 = 0; s2 < 16; ++s2) {
+        const int yy = y0 + 2 * s2 + kh;          // < YC; rows past ny hold zero lambda
+        const float a = lam[yy][c32];
+        const float y2 = ysq[yy];
+        const float b = fast_exp2(c.y * y2);
+        dg = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, dg, 0, 0, 0);
+        dh = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b * y2, dh, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { gacc[r] += (double)dg[r]; hacc[r] += (double)dh[r]; }
+    }
+  }
+  double s0 = 0.0, s1 = 0.0, sg = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int xr = x0 + mfma_row(r, lane);
+    if (xr < g.n_ux) {
+      const double xv = g.xs[xr];
+      const float x2 = (float)(xv * xv);
+      const double e = (double)fast_exp2(c.x * x2);
+      s0 += e * gacc[r];
+      s1 += (double)x2 * e * gacc[r];
+      sg += e * (double)fmaf(c.w, x2, c.z) * hacc[r];
+    }
+  }
+  s0 += __shfl_xor(s0, 32, 64);
+  s1 += __shfl_xor(s1, 32, 64);
+  sg += __shfl_xor(sg, 32, 64);
+  if (kh == 0 && vt) {
+    double *S = sens + md.sens_off + (int64_t)it.a * 3 * g.T;
+    S[t] = s0;
+    S[g.T + t] = s1;
+    S[2 * (int64_t)g.T + t] = sg;
+  }
+}
+
+
+constexpr int kSensSmem = (YC * 32 + YC) * (int)sizeof(float);
+static_assert(kSensSmem >= 3 * 256 * (int)sizeof(float), "per-pixel sensitivity LDS");
+
+// Adjoint sensitivities over a work list, variant in Item::c (0 per-pixel
+// VALU, items (m, 256-term block); 1 MFMA, items (m, x tile, 128-term tile));
+// queue-driven or strided as k_num.
+__global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
+                                              const ModelDev *__restrict__ models,
+                                              const Item *__restrict__ items, int n_it,
+                                              const float4 *__restrict__ terms,
+                                              const double *__restrict__ pix,
+                                              const int *__restrict__ st_ws,
+                                              double *__restrict__ sens, int *queue) {
+  __shared__ __attribute__((aligned(16))) char smem[kSensSmem];
+  __shared__ int next;
+  int i = blockIdx.x;
+  for (;;) {
+    if (queue) {
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+      __syncthreads();
+      i = next;
+      __syncthreads();
+    }
+    if (i >= n_it) break;
     const Item it = items[i];
-    const ModelDev md = models[it.m];
-    const GeomDev g = geoms[md.geom];
-    if (st_ws[it.m] != 0) continue;   // uniform per block
-    const int t = it.a * 256 + threadIdx.x;
-    const bool valid = t < g.T;
-    const float4 c = valid ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const double *lam = pix + md.pix_off + 2 * (int64_t)g.n_pix;
-    double a0 = 0.0, a1 = 0.0, ag = 0.0;
-    for (int base = 0; base < g.n_pix; base += 256) {
-      const int q = base + threadIdx.x;
-      __syncthreads();
-      if (q < g.n_pix) {
-        const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-        sx[threadIdx.x] = (float)(x * x);
-        sy[threadIdx.x] = (float)(y * y);
-        sl[threadIdx.x] = (float)lam[q];
-      } else {
-        sx[threadIdx.x] = 0.f;
-        sy[threadIdx.x] = 0.f;
-        sl[threadIdx.x] = 0.f;
-      }
-      __syncthreads();
-      const int cnt = min(256, g.n_pix - base);
-      float s0 = 0.f, s1 = 0.f, sg = 0.f;
-      for (int e = 0; e < cnt; ++e) {
-        const float x2 = sx[e], y2 = sy[e];
-        const float le = sl[e] * fast_exp2(fmaf(c.x, x2, c.y * y2));
-        s0 += le;
-        s1 = fmaf(le, x2, s1);
-        sg = fmaf(le * y2, fmaf(c.w, x2, c.z), sg);
-      }
-      a0 += s0;
-      a1 += s1;
-      ag += sg;
-    }
-    if (valid) {
-      double *S = sens + md.sens_off;
-      S[t] = a0;
-      S[g.T + t] = a1;
-      S[2 * (int64_t)g.T + t] = ag;
-    }
+    if (it.c == 0)
+      sens_pix_item(it, geoms, models, terms, pix, st_ws, sens, smem);
+    else
+      sens_mfma_item(it, geoms, models, terms, pix, st_ws, sens, smem);
+    __syncthreads();
+    if (!queue) i += gridDim.x;
   }
 }
 
@@ -490,7 +805,8 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
     const GeomDev g = geoms[md.geom];
     const int k = it.a;
     const int J1 = g.J1, J = J1 - 1;
-    double *row = chain + md.sens_off + 3 * (int64_t)g.T + (int64_t)k * (3 + J1);
+    const int np_ = md.n_sens_parts;
+    double *row = chain + md.sens_off + 3 * (int64_t)np_ * g.T + (int64_t)k * (3 + J1);
     if (st_ws[it.m] != 0) {
       for (int c = threadIdx.x; c < 3 + J1; c += 256) row[c] = __builtin_nan("");
       continue;
@@ -552,7 +868,13 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
           const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
           const dual f = wq * dsqrt(kPi / a);
           const dual c0 = f * P, c1u = f * Q;                       // C = I0 M c
-          const double S0 = S0a[t], S1 = S1a[t], Sg = Sga[t];
+          double S0 = 0.0, S1 = 0.0, Sg = 0.0;
+          for (int q = 0; q < np_; ++q) {
+            const int64_t o = (int64_t)q * 3 * g.T + t;
+            S0 += S0a[o];
+            S1 += S1a[o];
+            Sg += Sga[o];
+          }
           const double amp = I0 * Mj;
           acc_i += amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
           // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
@@ -605,7 +927,7 @@ __global__ void __launch_bounds__(64) k_grads(const GeomDev *__restrict__ geoms,
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
     const int K = g.K, J1 = g.J1, J = J1 - 1;
-    const double *cm = sens + md.sens_off + 3 * (int64_t)g.T;
+    const double *cm = sens + md.sens_off + 3 * (int64_t)md.n_sens_parts * g.T;
     const bool ok = st_ws[m] == 0;
     const double nan = __builtin_nan("");
     const double sp = g.s_pc;
@@ -646,8 +968,9 @@ inline int grid_of(int n_it) { return n_it < 1 ? 1 : n_it; }
 // Launchers.
 // ---------------------------------------------------------------------------
 void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *gauss,
-                  int *st_ws, int32_t *st_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(grid_of(n)), dim3(64), 0, st, g, m, n, p, gauss, st_ws, st_out);
+                  int *st_ws, int32_t *st_out, int *queues, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(grid_of(n)), dim3(64), 0, st, g, m, n, p, gauss, st_ws, st_out,
+                     queues);
 }
 void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *gauss, const int *st_ws, float4 *terms, hipStream_t st) {
@@ -658,10 +981,11 @@ void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, Pa
                double *pix, hipStream_t st) {
   hipLaunchKernelGGL(k_sb, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, pix);
 }
-void launch_num_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                    const float4 *terms, const int *st_ws, double *part, hipStream_t st) {
-  hipLaunchKernelGGL(k_num_pix, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, terms,
-                     st_ws, part);
+void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_num, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms, st_ws,
+                     part, queue);
 }
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st) {
@@ -685,11 +1009,21 @@ void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, in
   hipLaunchKernelGGL(k_bins_adjoint, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, vrms2,
                      cot, binws, st_ws, pix);
 }
-void launch_sens_pix(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                     const float4 *terms, const double *pix, const int *st_ws, double *sens,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_sens_pix, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, terms,
-                     pix, st_ws, sens);
+void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                 const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                 int *queue, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_sens, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms, pix,
+                     st_ws, sens, queue);
+}
+int occupancy_num() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_num, 256, 0) != hipSuccess) nb = 1;
+  return nb < 1 ? 1 : nb;
+}
+int occupancy_sens() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sens, 256, 0) != hipSuccess) nb = 1;
+  return nb < 1 ? 1 : nb;
 }
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st) {

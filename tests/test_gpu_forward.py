@@ -42,7 +42,7 @@ def _split(V, w):
 def test_cfg1_forward_parity():
     dev = _dev()
     w = inputs.config1()
-    for form in (1,):
+    for form in (1, 2, 0):
         ctx = binding.Context(w.geometries, form=form)
         V, st = _run(ctx, w, dev)
         ref = ojam.vrms2(w.geometries[0], w.params[0]).numpy()
@@ -69,6 +69,28 @@ def test_small_geometries_parity(seed, kw):
     ref = ojam.vrms2(g, p).numpy()
     rel = np.max(np.abs(V / ref - 1))
     print(f"small seed={seed}: {len(V)} bins, max rel err {rel:.3e}")
+    assert st[0] == 0 and rel <= RTOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("seed,kw", [
+    (11, dict(nx=50, ny=47, ss=2, psf_n=3, n_lum=3, n_mass=2, n_u=24, n_bins=5)),   # 64-tile, ragged
+    (12, dict(nx=35, ny=70, ss=2, psf_n=3, n_lum=2, n_mass=3, n_u=19, n_bins=7)),   # partial waves
+    (13, dict(nx=61, ny=29, ss=1, psf_n=5, n_lum=3, n_mass=2, n_u=21, n_bins=4,
+              xc=0.013, yc=0.021)),                                                 # no mirror dedup
+    (14, dict(nx=7, ny=40, ss=1, psf_n=1, n_lum=2, n_mass=1, n_u=7, n_bins=3)),     # 32-tile, thin
+])
+def test_numerator_variants_parity(seed, kw, form):
+    dev = _dev()
+    g = inputs.small_geometry(seed=seed, pixsize=0.03, **kw)
+    p = inputs.small_params(g, seed=seed)
+    w = inputs.Workload("var", [g], np.zeros(1, np.int32), [p])
+    ctx = binding.Context([g], form=form)
+    V, st = _run(ctx, w, dev)
+    ref = ojam.vrms2(g, p).numpy()
+    rel = np.max(np.abs(V / ref - 1))
+    print(f"variant seed={seed} form={form}: max rel err {rel:.3e}")
     assert st[0] == 0 and rel <= RTOL
     ctx.close()
 
@@ -109,7 +131,8 @@ def test_maps_parity_cfg1():
     ctx.close()
 
 
-def test_batch_mixed_geometries_and_status():
+@pytest.mark.parametrize("form", [1, 2])
+def test_batch_mixed_geometries_and_status(form):
     dev = _dev()
     gs = [inputs.small_geometry(seed=s, nx=6 + s, ny=5 + 2 * s, n_bins=2 + s) for s in range(3)]
     ps = [inputs.small_params(g, seed=s) for s, g in enumerate(gs)]
@@ -119,7 +142,7 @@ def test_batch_mixed_geometries_and_status():
     params[2] = bad
     params[3] = inputs.with_overrides(params[3], beta=np.full(gs[1].n_lum, 1.5))  # b < 0
     w = inputs.Workload("mix", gs, gi, params)
-    ctx = binding.Context(gs)
+    ctx = binding.Context(gs, form=form)
     V, st = _run(ctx, w, dev)
     parts = _split(V, w)
     assert list(st) == [0, 0, 2, 3, 0]
@@ -130,10 +153,11 @@ def test_batch_mixed_geometries_and_status():
     ctx.close()
 
 
-def test_cfg3_batch_subset():
+@pytest.mark.parametrize("form", [1, 2])
+def test_cfg3_batch_subset(form):
     dev = _dev()
     w = inputs.config3(n_models=256)
-    ctx = binding.Context(w.geometries)
+    ctx = binding.Context(w.geometries, form=form)
     V, st = _run(ctx, w, dev)
     assert np.all(st == 0)
     parts = _split(V, w)

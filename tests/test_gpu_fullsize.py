@@ -1,0 +1,148 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times, against stored FP64 oracle values (tests/golden/, written
+by tests/golden/make_golden.py, which calls only oracle/).
+
+Bars: v_rms^2 per bin within 1e-5 relative; sampled N and I map values
+within 1e-5 and 1e-12 relative; gradients as in test_gpu_vjp.py.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_01302_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RTOL = 1e-5
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    return json.load(open(path))
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _offsets(w):
+    o = [0]
+    for i in w.geom_idx:
+        o.append(o[-1] + w.geometries[i].n_bins)
+    return o
+
+
+@pytest.mark.parametrize("form", [2, 1])
+def test_cfg2_all_bins(form):
+    dev = _dev()
+    ref = np.array(_golden("cfg2_seed0.json")["vrms2"])
+    w = inputs.config2(seed=0)
+    ctx = binding.Context(w.geometries, form=form)
+    p = binding.pack_params(w, dev, amplitudes=True)
+    V, st = ctx.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"],
+                           p["lum_I0"], p["mass_S0"])
+    torch.cuda.synchronize()
+    rel = np.abs(V.cpu().numpy() / ref - 1)
+    print(f"cfg2 form={form}: max rel err {rel.max():.3e} over {len(ref)} bins")
+    assert int(st.cpu()[0]) == 0 and rel.max() <= RTOL
+    ctx.close()
+
+
+def test_cfg2_sampled_map_values():
+    dev = _dev()
+    gd = _golden("cfg2_seed0.json")
+    w = inputs.config2(seed=0)
+    g = w.geometries[0]
+    ctx = binding.Context(w.geometries, form=2)
+    p = binding.pack_params(w, dev)
+    N, I, st = ctx.eval_maps(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"])
+    torch.cuda.synchronize()
+    nxp = g.nx * g.supersample + g.psf_n - 1
+    nyp = g.ny * g.supersample + g.psf_n - 1
+    N = N.cpu().numpy().reshape(nyp, nxp)
+    I = I.cpu().numpy().reshape(nyp, nxp)
+    iy, ix = np.array(gd["pix_iy"]), np.array(gd["pix_ix"])
+    rN = np.abs(N[iy, ix] / np.array(gd["N"]) - 1).max()
+    rI = np.abs(I[iy, ix] / np.array(gd["I"]) - 1).max()
+    print(f"cfg2 sampled maps: N {rN:.3e}, I {rI:.3e}")
+    assert rN <= RTOL and rI <= 1e-12
+    ctx.close()
+
+
+def test_cfg3_full_batch():
+    dev = _dev()
+    gd = _golden("cfg3_subset.json")
+    w = inputs.config3(n_models=4096)
+    ctx = binding.Context(w.geometries, form=2)
+    p = binding.pack_params(w, dev)
+    V, st = ctx.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"])
+    torch.cuda.synchronize()
+    V = V.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    o = _offsets(w)
+    worst = 0.0
+    for m, ref in zip(gd["models"], gd["vrms2"]):
+        worst = max(worst, np.abs(V[o[m]:o[m + 1]] / np.array(ref) - 1).max())
+    print(f"cfg3 (4096 models): max rel err {worst:.3e} over {len(gd['models'])} models")
+    assert worst <= RTOL
+    ctx.close()
+
+
+def test_cfg4_uneven_batch():
+    dev = _dev()
+    gd = _golden("cfg4_subset.json")
+    w = inputs.config4(n_models=1024)
+    ctx = binding.Context(w.geometries, form=0)
+    p = binding.pack_params(w, dev)
+    V, st = ctx.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"])
+    torch.cuda.synchronize()
+    V = V.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    o = _offsets(w)
+    worst = 0.0
+    for c in gd["checks"]:
+        m = c["model"]
+        got = V[o[m] + np.array(c["bins"])]
+        worst = max(worst, np.abs(got / np.array(c["vrms2"]) - 1).max())
+    print(f"cfg4 (1024 uneven models): max rel err {worst:.3e} over {len(gd['checks'])} models")
+    assert worst <= RTOL
+    ctx.close()
+
+
+def test_cfg5_gradients():
+    dev = _dev()
+    gd = _golden("cfg5_grads.json")
+    w = inputs.config5(n_models=256)
+    cot = inputs.cotangent(w.geometries[0].n_bins, 256)
+    ctx = binding.Context(w.geometries, form=2)
+    p = binding.pack_params(w, dev, amplitudes=True)
+    V, st = ctx.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"],
+                           p["lum_I0"], p["mass_S0"])
+    g = ctx.vjp(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"], p["lum_I0"],
+                p["mass_S0"], V, torch.as_tensor(cot.reshape(-1), device=dev))
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    K, J = w.geometries[0].n_lum, w.geometries[0].n_mass
+    keys = ("inc", "beta", "mass_scale", "m_bh", "lum_I0", "mass_S0")
+    worst = 0.0
+    for c in gd["checks"]:
+        m = c["model"]
+        got = np.concatenate([np.atleast_1d(g["inc"][m]), g["beta"][m * K:(m + 1) * K],
+                              np.atleast_1d(g["mass_scale"][m]), np.atleast_1d(g["m_bh"][m]),
+                              g["lum_I0"][m * K:(m + 1) * K], g["mass_S0"][m * J:(m + 1) * J]])
+        ref = np.concatenate([np.array(c["grads"][k]) for k in keys])
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        comp = np.abs(got - ref) <= np.maximum(1e-3 * np.abs(ref), 1e-6 * np.abs(ref).max())
+        worst = max(worst, err)
+        assert comp.all(), (m, np.nonzero(~comp))
+    print(f"cfg5 (256 models): worst gradient rel norm err {worst:.3e}")
+    assert worst <= 1e-4
+    ctx.close()

@@ -63,29 +63,46 @@ def _split_grads(g, w):
     return out
 
 
+@pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("recompute", [False, True])
-def test_vjp_small_vs_oracle(recompute):
+def test_vjp_small_vs_oracle(recompute, form):
     dev = _dev()
     g = inputs.small_geometry(seed=21, n_lum=4, n_mass=3, nx=8, ny=7, ss=2, psf_n=3, n_bins=4)
     p = inputs.small_params(g, seed=21)
     w = inputs.Workload("s", [g], np.zeros(1, np.int32), [p])
     cot = [np.random.default_rng(1).standard_normal(g.n_bins)]
-    ctx = binding.Context([g])
+    ctx = binding.Context([g], form=form)
     gg = _split_grads(_gpu_grads(ctx, w, cot, dev, with_forward=not recompute), w)[0]
     _, ref = ojam.vrms2_and_grad(g, p, cot[0])
-    _check(gg, {k: v.numpy() for k, v in ref.items()}, f"small recompute={recompute}")
+    _check(gg, {k: v.numpy() for k, v in ref.items()}, f"small recompute={recompute} form={form}")
     ctx.close()
 
 
-def test_vjp_cfg5_models_vs_oracle():
+@pytest.mark.parametrize("form", [1, 2])
+def test_vjp_cfg5_models_vs_oracle(form):
     dev = _dev()
     w = inputs.config5(n_models=8)
     cot = list(inputs.cotangent(w.geometries[0].n_bins, 8))
-    ctx = binding.Context(w.geometries)
+    ctx = binding.Context(w.geometries, form=form)
     gs = _split_grads(_gpu_grads(ctx, w, cot, dev), w)
     for m in (0, 3, 7):
         _, ref = ojam.vrms2_and_grad(w.geometries[0], w.params[m], cot[m])
-        _check(gs[m], {k: v.numpy() for k, v in ref.items()}, f"cfg5 model {m}")
+        _check(gs[m], {k: v.numpy() for k, v in ref.items()}, f"cfg5 model {m} form={form}")
+    ctx.close()
+
+
+def test_vjp_larger_map_mfma_vs_oracle():
+    """A map with several 32-row x tiles and y chunks of the MFMA adjoint."""
+    dev = _dev()
+    g = inputs.small_geometry(seed=22, n_lum=2, n_mass=2, nx=70, ny=45, ss=2, psf_n=3,
+                              n_bins=5, n_u=12, pixsize=0.02)
+    p = inputs.small_params(g, seed=22)
+    w = inputs.Workload("L", [g], np.zeros(1, np.int32), [p])
+    cot = [np.random.default_rng(2).standard_normal(g.n_bins)]
+    ctx = binding.Context([g], form=2)
+    gg = _split_grads(_gpu_grads(ctx, w, cot, dev), w)[0]
+    _, ref = ojam.vrms2_and_grad(g, p, cot[0])
+    _check(gg, {k: v.numpy() for k, v in ref.items()}, "larger map form=2")
     ctx.close()
 
 
@@ -118,4 +135,23 @@ def test_vjp_vs_gpu_central_differences():
     scale = float(np.sum(np.abs(cot) * 1e5))
     print(f"directional: adjoint {ad:.6e} fd {fd:.6e}")
     assert abs(ad - fd) <= 1e-3 * abs(fd) + 1e-7 * scale
+    ctx.close()
+
+
+def test_autograd_function_matches_vjp_and_oracle():
+    from paper_2504_01302_amd.autograd import jam_vrms2
+    dev = _dev()
+    w = inputs.config5(n_models=3)
+    cot = inputs.cotangent(w.geometries[0].n_bins, 3)
+    ctx = binding.Context(w.geometries, form=2)
+    p = binding.pack_params(w, dev, amplitudes=True)
+    leaves = {k: p[k].clone().requires_grad_(True) for k in KEYS}
+    V, st = jam_vrms2(ctx, w.geom_idx, leaves["inc"], leaves["mass_scale"], leaves["m_bh"],
+                      leaves["beta"], leaves["lum_I0"], leaves["mass_S0"])
+    L = torch.sum(V * torch.as_tensor(cot.reshape(-1), device=dev))
+    L.backward()
+    got = {k: leaves[k].grad.cpu().numpy() for k in KEYS}
+    gs = _split_grads(got, w)
+    _, ref = ojam.vrms2_and_grad(w.geometries[0], w.params[1], cot[1])
+    _check(gs[1], {k: v.numpy() for k, v in ref.items()}, "autograd model 1")
     ctx.close()
