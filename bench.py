@@ -35,13 +35,23 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--form", type=int, default=2,
                     help="1 per-pixel VALU kernel, 2 matrix-core kernel (0 = library default)")
+    ap.add_argument("--launch", type=int, default=0,
+                    help="0 persistent work-queue grid, 1 one workgroup per work item")
+    ap.add_argument("--graph", type=int, default=0, help="1 replay a recorded HIP graph")
+    ap.add_argument("--autotune", type=int, default=0, help="1 autotune the numerator schedule")
+    ap.add_argument("--no-plain-baseline", action="store_true",
+                    help="skip timing the plain per-model forward (per-pixel VALU kernel, "
+                         "one workgroup per item, no graph)")
     ap.add_argument("--batch", type=int, default=1,
                     help="models per launch (copies of the IFU-scale model)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched workloads (4096 proposals on the small geometry, "
+                         "1024 uneven models), reported under 'extra'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, the reference "
                          "kernel for scaling the HBM byte counters of a profile")
-    ap.add_argument("--cpu-sample", type=int, default=256,
+    ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="padded sub-pixels the oracle evaluates for the CPU baseline")
     return ap.parse_args()
 
@@ -66,6 +76,48 @@ def cpu_baseline(g, p, n_sample):
                        f"IFU-scale model ({dt:.1f} s), scaled to one model")
 
 
+def time_batch(torch, binding, w, dev, steps, form, launch, graph):
+    """Forward and forward+adjoint throughput of one whole batch per launch."""
+    ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph)
+    par = binding.pack_params(w, dev, amplitudes=True)
+    nb, _, _ = ctx.sizes(w.geom_idx)
+    V = torch.empty(nb, dtype=torch.float64, device=dev)
+    st = torch.empty(len(w.geom_idx), dtype=torch.int32, device=dev)
+    cot = torch.ones(nb, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def fwd():
+        ctx.eval_batch(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                       par["lum_I0"], par["mass_S0"], out=V, status=st)
+
+    def bwd():
+        ctx.vjp(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                par["lum_I0"], par["mass_S0"], V, cot)
+
+    fwd()
+    bwd()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
+        fwd()
+        bwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / steps
+    n = len(w.geom_idx)
+    ok = bool((st == 0).all().item())
+    ctx.close()
+    return {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
+            "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -81,7 +133,7 @@ def main():
     g, p = w1.geometries[0], w1.params[0]
     n = a.batch
     w = inputs.Workload("cfg2", [g], np.zeros(n, np.int32), [p] * n)
-    ctx = binding.Context([g], form=a.form)
+    ctx = binding.Context([g], form=a.form, launch=a.launch, graph=a.graph, autotune=a.autotune)
     par = binding.pack_params(w, dev, amplitudes=True)
     cot = torch.as_tensor(np.tile(inputs.cotangent(g.n_bins, 1)[0], n), device=dev)
     nb, _, _ = ctx.sizes(w.geom_idx)
@@ -128,6 +180,30 @@ def main():
     ms_fb = e0.elapsed_time(e1) / a.steps
     _, _, sens_ms, sens_n = binding.jam_timing(ctx.handle, False)
 
+    # plain per-model forward on the same GPU: the per-pixel VALU kernel, one
+    # workgroup per work item, no graph, one model per launch
+    plain = None
+    if not a.no_plain_baseline:
+        w_one = inputs.Workload("cfg2", [g], np.zeros(1, np.int32), [p])
+        pc = binding.Context([g], form=1, launch=1)
+        p1 = binding.pack_params(w_one, dev, amplitudes=True)
+        V1 = torch.empty(g.n_bins, dtype=torch.float64, device=dev)
+        s1 = torch.empty(1, dtype=torch.int32, device=dev)
+        run1 = lambda: pc.eval_batch(w_one.geom_idx, p1["inc"], p1["mass_scale"], p1["m_bh"],
+                                     p1["beta"], p1["lum_I0"], p1["mass_S0"], out=V1, status=s1)
+        run1()
+        torch.cuda.synchronize()
+        k1 = max(3, a.steps // 4)
+        e0.record(stream)
+        for _ in range(k1):
+            run1()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / k1
+        plain = {"ms_per_model": ms1, "models_per_s": 1000.0 / ms1,
+                 "speedup_of_value": (n * 1000.0 / ms_f) / (1000.0 / ms1)}
+        pc.close()
+
     # parity of the timed configuration against the stored oracle values
     max_rel = None
     gpath = os.path.join(ROOT, "tests", "golden", "cfg2_seed0.json")
@@ -143,7 +219,8 @@ def main():
                             - (g.ny * g.supersample + g.psf_n - 2) / 2.0))}
     n_pix = len(xs) * len(ys)
     T = g.n_lum * (g.n_mass + 1) * g.n_u
-    avg_num_s = (num_ms / max(1, num_n)) * 1e-3
+    # (graph replays are not bracketed by the kernel timer)
+    avg_num_s = (num_ms / num_n) * 1e-3 if num_n else None
     form_used = 1 if a.form == 1 else 2
     if form_used == 2:
         flops = 2.0 * n_pix * T * n
@@ -151,10 +228,11 @@ def main():
     else:
         flops = PIX_FLOPS_PER_INTEGRAND * n_pix * T * n
         roof = dict(bound="alu", peak=FP32_VECTOR_PEAK / 1e12)
-    achieved = flops / avg_num_s / 1e12
-    roof.update(achieved=achieved, unit="TFLOP/s", frac=achieved / roof["peak"], traffic=None,
-                kernel="k_num_pix" if form_used == 1 else "k_num_mfma",
-                avg_launch_ms=avg_num_s * 1e3, launches=num_n)
+    achieved = flops / avg_num_s / 1e12 if avg_num_s else None
+    roof.update(achieved=achieved, unit="TFLOP/s",
+                frac=achieved / roof["peak"] if achieved else None, traffic=None,
+                kernel="k_num", avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
+                launches=num_n, flops_per_launch=flops)
 
     rec = {
         "metric": "JAM models/sec and fwd+bwd/sec (200² px, 40×40 MGE) at ≤1e-5 rel err vs FP64",
@@ -172,14 +250,24 @@ def main():
         "config": {"workload": "IFU-scale JAM-cyl forward: 40 lum x 40 mass Gaussians + BH, "
                                "200x200 px at 0.025\" with 2x supersampling, 128 u-nodes, "
                                "31x31 PSF, 60 bins",
-                   "models_per_launch": n, "form": form_used},
+                   "models_per_launch": n, "form": form_used, "launch": a.launch,
+                   "graph": a.graph, "autotune": a.autotune,
+                   "schedule": ctx.plan_info(w.geom_idx)},
         "fwd_bwd_per_s": n * 1000.0 / ms_fb,
         "ms_per_fwd_bwd": ms_fb,
         "max_rel_err_vs_oracle": max_rel,
         "wall_s_forward_loop": wall_f,
         "roofline": roof,
         "sens_kernel_avg_ms": sens_ms / max(1, sens_n),
+        "plain_per_model_forward": plain,
     }
+    if not a.no_extra:
+        rec["extra"] = {
+            "batched_4096_small": time_batch(torch, binding, inputs.config3(4096), dev,
+                                             max(3, a.steps // 4), a.form, a.launch, a.graph),
+            "uneven_1024": time_batch(torch, binding, inputs.config4(1024), dev, 2, a.form,
+                                      a.launch, a.graph),
+        }
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB
         dst = torch.empty_like(src)

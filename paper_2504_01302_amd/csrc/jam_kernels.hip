@@ -25,6 +25,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <type_traits>
 
 namespace jam {
 
@@ -289,15 +290,22 @@ __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int 
 
 // 64x64 output tile per workgroup, 2x2 waves of 32x32; the A (64 rows) and
 // B (64 columns) operands of each chunk are generated once into LDS (double
-// buffered) and shared by the four waves.  Item (m, tile, slice).
+// buffered) and shared by the four waves.  Per chunk a wave issues its 16
+// MFMAs on the current buffer first and then generates its quarter of the
+// next chunk's operands, so the exponentials overlap the matrix work; the
+// next chunk's term coefficients (8 per wave, wave-uniform) are loaded at the
+// top of the iteration.  Item (m, tile, slice).
 __device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__restrict__ geoms,
-    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
+                                                const ModelDev *__restrict__ models,
+                                                const float4 *__restrict__ terms,
+                                                const int *__restrict__ st_ws,
+                                                double *__restrict__ part, char *smem) {
   float (*As)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem);
   float (*Bs)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem + 2 * KC * 64 * sizeof(float));
-
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wx = wave & 1, wy = wave >> 1;
+  const int kh = lane >> 5, c32 = lane & 31;
   const ModelDev md = models[it.m];
   const GeomDev g = geoms[md.geom];
   const int n_xt = (g.n_ux + 63) >> 6;
@@ -315,41 +323,85 @@ __device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__
   double acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  // This wave's terms of chunk ch are t0 + ch*KC + wave + 4 i, i < 8; lane i
+  // loads term i's coefficients with a vector load (waited for only when the
+  // exponentials need them, after the MFMAs are issued) and readlane
+  // broadcasts them.
+  float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto load_cf = [&](int ch) {
+    const int tw = t0 + ch * KC + wave;
+    if (lane < KC / 4) cv = tb[min(tw + 4 * lane, t1 - 1)];
+  };
+  auto bcast = [&](float v, int i) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+  };
   auto gen = [&](int buf, int ch) {
-#pragma unroll 2
-    for (int kk = wave; kk < KC; kk += 4) {
-      const int t = t0 + ch * KC + kk;
-      float a = 0.f, b = 0.f;
-      if (t < t1) {
-        const float4 c = tb[t];
-        a = vx ? fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z) : 0.f;
-        b = vy ? fast_exp2(c.y * y2) : 0.f;
-      }
-      As[buf][kk][lane] = a;
-      Bs[buf][kk][lane] = b;
+    const int tw = t0 + ch * KC + wave;
+#pragma unroll
+    for (int i = 0; i < KC / 4; ++i) {
+      const bool vt = tw + 4 * i < t1;
+      const float cx = bcast(cv.x, i), cy = bcast(cv.y, i), c0 = bcast(cv.z, i),
+                  c1 = bcast(cv.w, i);
+      const float a = fast_exp2(cx * x2) * fmaf(c1, x2, c0);
+      const float b = fast_exp2(cy * y2);
+      As[buf][wave + 4 * i][lane] = (vt && vx) ? a : 0.f;
+      Bs[buf][wave + 4 * i][lane] = (vt && vy) ? b : 0.f;
     }
   };
-  if (n_ch > 0) gen(0, 0);
+  if (n_ch > 0) {
+    load_cf(0);
+    gen(0, 0);
+  }
   __syncthreads();
-  for (int ch = 0; ch < n_ch; ++ch) {
-    const int cur = ch & 1;
-    if (ch + 1 < n_ch) gen(cur ^ 1, ch + 1);
-    if (active) {
+  // One basic block per chunk: the MFMAs on the current buffer interleaved
+  // with the generation of the next chunk (past the last chunk the
+  // generation writes an unused buffer from clamped, valid coefficients).
+  // Waves whose 32x32 sub-tile lies outside the map only generate.
+  auto run = [&](auto act) {
+    constexpr bool kActive = decltype(act)::value;
+    for (int ch = 0; ch < n_ch; ++ch) {
+      const int cur = ch & 1, nxt = cur ^ 1;
+      load_cf(ch + 1);
+      const int tw = t0 + (ch + 1) * KC + wave;
       v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      const int kh = lane >> 5, c32 = lane & 31;
+      float ra[KC / 2], rb[KC / 2];
+      if constexpr (kActive) {
 #pragma unroll
-      for (int s2 = 0; s2 < KC / 2; ++s2) {
-        const float a = As[cur][2 * s2 + kh][wx * 32 + c32];
-        const float b = Bs[cur][2 * s2 + kh][wy * 32 + c32];
-        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+        for (int q = 0; q < KC / 2; ++q) {
+          ra[q] = As[cur][2 * q + kh][wx * 32 + c32];
+          rb[q] = Bs[cur][2 * q + kh][wy * 32 + c32];
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
+      for (int q = 0; q < KC / 2; ++q) {
+        if constexpr (kActive) d = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[q], rb[q], d, 0, 0, 0);
+        // half of term i = q / 2 of the next chunk: its A value on even
+        // steps, its B value on odd steps
+        const int i = q >> 1;
+        const bool vt = tw + 4 * i < t1;
+        if ((q & 1) == 0) {
+          const float cx = bcast(cv.x, i), c0 = bcast(cv.z, i), c1 = bcast(cv.w, i);
+          const float av = fast_exp2(cx * x2) * fmaf(c1, x2, c0);
+          As[nxt][wave + 4 * i][lane] = (vt && vx) ? av : 0.f;
+        } else {
+          const float cy = bcast(cv.y, i);
+          const float bv = fast_exp2(cy * y2);
+          Bs[nxt][wave + 4 * i][lane] = (vt && vy) ? bv : 0.f;
+        }
+      }
+      if constexpr (kActive) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
+  };
+  if (active)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
   if (active) {
-    const int yj = y0 + wy * 32 + (lane & 31);
+    const int yj = y0 + wy * 32 + c32;
     double *out = part + md.part_off + (int64_t)it.b * g.n_pix;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -360,15 +412,19 @@ __device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__
   __syncthreads();
 }
 
-
 // 32x32 output tile per workgroup for small maps; each of the 4 waves takes
 // every 4th chunk of the slice and generates its own operands in registers
-// (lane l: row/column l % 32, term of its half-wave), then the four FP64
-// partial tiles are summed through LDS in a fixed order.  Item (m, tile, slice).
+// (lane l: row/column l % 32, term of its half-wave).  A wave's chunk
+// coefficients go through a private 32-entry LDS slot (one vector load per
+// lane, prefetched one chunk ahead); the four FP64 partial tiles are summed
+// through LDS in a fixed order.  Item (m, tile, slice).
 __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__restrict__ geoms,
-    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
+                                                const ModelDev *__restrict__ models,
+                                                const float4 *__restrict__ terms,
+                                                const int *__restrict__ st_ws,
+                                                double *__restrict__ part, char *smem) {
   double (*red)[16][64] = reinterpret_cast<double (*)[16][64]>(smem);
-
+  float4 (*cs)[KC] = reinterpret_cast<float4 (*)[KC]>(smem + 3 * 16 * 64 * sizeof(double));
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const ModelDev md = models[it.m];
@@ -388,20 +444,25 @@ __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__
   double acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  float4 cnext = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (wave < n_ch) cnext = tb[min(t0 + wave * KC + c32, t1 - 1)];
   for (int ch = wave; ch < n_ch; ch += 4) {
-    v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int tc = t0 + ch * KC;
+    if (kh == 0) cs[wave][c32] = cnext;
+    __builtin_amdgcn_wave_barrier();
+    if (ch + 4 < n_ch) cnext = tb[min(tc + 4 * KC + c32, t1 - 1)];
+    v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int s2 = 0; s2 < KC / 2; ++s2) {
-      const int t = tc + 2 * s2 + kh;
-      float a = 0.f, b = 0.f;
-      if (t < t1) {
-        const float4 c = tb[t];
-        a = vx ? fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z) : 0.f;
-        b = vy ? fast_exp2(c.y * y2) : 0.f;
-      }
-      d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+      const int k = 2 * s2 + kh;
+      const float4 c = cs[wave][k];
+      const bool vt = tc + k < t1;
+      const float a = fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z);
+      const float b = fast_exp2(c.y * y2);
+      d = __builtin_amdgcn_mfma_f32_32x32x2f32((vt && vx) ? a : 0.f, (vt && vy) ? b : 0.f, d, 0,
+                                               0, 0);
     }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
   }
@@ -423,10 +484,9 @@ __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__
   __syncthreads();
 }
 
-
 // Largest LDS user among the numerator variants (the 64x64 MFMA tiles).
 constexpr int kNumSmem = 2 * 2 * KC * 64 * (int)sizeof(float);
-static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double), "32x32 variant LDS");
+static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double) + 4 * KC * 16, "32x32 variant LDS");
 static_assert(kNumSmem >= 256 * (int)sizeof(double), "per-pixel variant LDS");
 
 // Numerator over a work list whose items carry their variant in Item::c
