@@ -241,7 +241,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Tune {
   int rule = 1;     // 0 per-pixel VALU everywhere; 1 matrix cores (64x64 tiles when both
                     // map sides >= tau, else 32x32 tiles)
-  int tau = 48;
+  int tau = 1 << 30;
   int gran = 0;     // term chunks (32 terms) per MFMA item, or (k, j) pairs per per-pixel
                     // item; 0 = derived from the batch
   int launch = 0;   // 0 persistent grid pulling items from a device queue; 1 one
@@ -267,8 +267,10 @@ struct Plan {
   void *arena = nullptr;
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
-            *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr;
-  int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0;
+            *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
+            *d_red = nullptr;
+  int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
+      n_sb = 0, n_red = 0;
   int grid_num = 1, grid_sens = 1;
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
@@ -352,7 +354,7 @@ NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
           ((g.n_ux + tw - 1) / tw) * ((g.n_uy + tw - 1) / tw)};
 }
 
-// Granularity giving about eight work items per compute unit for the batch.
+// Granularity giving about four work items per compute unit for the batch.
 int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
   double work = 0.0;
   for (int m = 0; m < n; ++m) {
@@ -365,7 +367,7 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
     else
       work += (double)c.tiles * ((g.T + 31) / 32);
   }
-  const double target = 8.0 * ctx->n_cu;
+  const double target = 4.0 * ctx->n_cu;
   const double gr = std::ceil(work / target);
   return (int)std::min(4096.0, std::max(1.0, gr));
 }
@@ -402,7 +404,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   if (p->tune.gran <= 0) p->tune.gran = default_gran(ctx, n, geom_idx, p->tune);
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
-  std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens;
+  std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
+      it_red;
   std::vector<double> c_num, c_sens;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0;
   for (int m = 0; m < n; ++m) {
@@ -432,7 +435,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     pixd += 4 * (int64_t)g.n_pix;
     part += (int64_t)d.n_slices * g.n_pix;
     bins += 2 * (int64_t)g.n_bins;
-    sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 + g.J1);
+    sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 * g.J1 + 1);
     p->total_lum += g.K;
     p->total_mass += g.J;
     p->total_bins += g.n_bins;
@@ -451,6 +454,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
         }
     }
     for (int pb = 0; pb < (g.n_pix + 255) / 256; ++pb) it_pix.push_back({m, pb, 0, 0});
+    for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_red.push_back({m, pb, 0, 0});
+    for (int rb = 0; rb < (g.n_uy + 7) / 8; ++rb)
+      for (int cb = 0; cb < (g.n_ux + 255) / 256; ++cb) it_sb.push_back({m, rb, cb, 0});
     for (int s = 0; s < d.n_slices; ++s) {
       const double c = num_item_cost(g, nc, s);
       for (int tl = 0; tl < nc.tiles; ++tl) {
@@ -460,15 +466,16 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     }
     for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
-    for (int k = 0; k < g.K; ++k) it_chain.push_back({m, k, 0, 0});
+    for (int k = 0; k < g.K; ++k)
+      for (int jb = 0; jb <= (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
   }
   if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
     return fail(JAM_E_UNSUPPORTED, "batch too large");
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 7;
-  std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix,   &it_num, &it_bins,
-                                           &it_maps,  &it_chain, &it_sens};
+  constexpr int kLists = 9;
+  std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix,  &it_num, &it_bins, &it_maps,
+                                           &it_chain, &it_sens, &it_sb,  &it_red};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -489,10 +496,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   HIP_TRY(hipMemcpy(p->arena, stage.data(), off, hipMemcpyHostToDevice));
   char *base = (char *)p->arena;
   p->d_models = (jam::ModelDev *)(base + o_models);
-  jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,   &p->d_num, &p->d_bins,
-                            &p->d_maps,  &p->d_chain, &p->d_sens};
-  int *cnt[kLists] = {&p->n_terms, &p->n_pix,   &p->n_num, &p->n_bins,
-                      &p->n_maps,  &p->n_chain, &p->n_sens};
+  jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins, &p->d_maps,
+                            &p->d_chain, &p->d_sens, &p->d_sb,  &p->d_red};
+  int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins, &p->n_maps,
+                      &p->n_chain, &p->n_sens, &p->n_sb,  &p->n_red};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -537,13 +544,13 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   double *part = (double *)(ws + p->off_part);
   jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
   jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
-  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, pd, pix, st);
+  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, pd, pix, st);
   if (need_numerator) {
     const bool timed = ctx->t_num.begin(st, capturing);
     jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
                     p->tune.launch == 0 ? queue : nullptr, p->grid_num, st);
     if (timed) ctx->t_num.end(st);
-    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, part, pix, st);
+    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_red, p->n_red, part, pix, st);
   }
 }
 

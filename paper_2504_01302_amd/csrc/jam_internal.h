@@ -82,6 +82,7 @@ void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
                   int *st_ws, int32_t *st_out, int *queues, hipStream_t st);
 void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
+// Items (m, block of 8 unique-pixel rows, block of 256 columns).
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
 // Numerator over a work list whose items carry their variant in Item::c:
@@ -94,6 +95,7 @@ void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                 hipStream_t st);
 int occupancy_num();    // resident numerator workgroups per CU
 int occupancy_sens();   // resident sensitivity workgroups per CU
+// Items (m, 64-pixel block).
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st);
 void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
@@ -111,12 +113,14 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const float4 *terms, const double *pix, const int *st_ws, double *sens,
                  int *queue, int grid, hipStream_t st);
 // sens region per model: n_sens_parts blocks of [S0 | S1 | Sg] (T doubles
-// each), then the chain rows [K][3 + J1] doubles.  The per-pixel kernel
+// each), then the chain rows: [K][J1][3] doubles and [K] doubles.  Chain
+// items (m, k, jb) for jb <= ceil(J1 / 4) (the last one per k is the
+// surface-brightness path).  The per-pixel kernel
 // writes one block; the MFMA kernel one block per 32-row x tile (items
 // (m, x tile, 128-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
-void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, const double *sens,
+void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st);
 
 }  // namespace jam

@@ -188,27 +188,56 @@ __global__ void __launch_bounds__(256) k_terms(const GeomDev *__restrict__ geoms
 }
 
 // ---------------------------------------------------------------------------
-// Surface brightness, eq. (sb_mge_2D), FP64, on the unique-pixel map.
+// Surface brightness, eq. (sb_mge_2D), FP64, on the unique-pixel map, using
+// its separability: I(x, y) = sum_k I0_k exp(-x^2/2s_k^2) exp(-y^2/2s_k^2q_k^2).
+// Item (m, block of 8 rows, block of 256 columns): the row factors are
+// computed once per workgroup, the column factor once per thread and k.
 // pix region per model: [N | I | lambda_N | lambda_I], n_pix doubles each.
 // ---------------------------------------------------------------------------
+constexpr int kSbRows = 8;
+constexpr int kSbK = 32;   // luminous Gaussians per LDS pass
+
 __global__ void __launch_bounds__(256) k_sb(const GeomDev *__restrict__ geoms,
                                             const ModelDev *__restrict__ models,
                                             const Item *__restrict__ items, int n_it, ParamsDev p,
                                             double *__restrict__ pix) {
+  __shared__ double fy[kSbK][kSbRows];
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const int q = it.a * 256 + threadIdx.x;
-    if (q >= g.n_pix) continue;
-    const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-    double acc = 0.0;
-    for (int k = 0; k < g.K; ++k) {
-      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-      const double qo = g.lum_q[k], sig = g.lum_sigma[k];
-      acc += I0 * exp(-(x * x + y * y / (qo * qo)) / (2.0 * sig * sig));
+    const int y0 = it.a * kSbRows;
+    const int ix = it.b * 256 + threadIdx.x;
+    const bool vx = ix < g.n_ux;
+    const double x = vx ? g.xs[ix] : 0.0;
+    double acc[kSbRows];
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r) acc[r] = 0.0;
+    for (int k0 = 0; k0 < g.K; k0 += kSbK) {
+      const int nk = min(kSbK, g.K - k0);
+      __syncthreads();
+      if (threadIdx.x < nk * kSbRows) {
+        const int kk = threadIdx.x / kSbRows, r = threadIdx.x % kSbRows;
+        const int iy = y0 + r;
+        const double qo = g.lum_q[k0 + kk], sig = g.lum_sigma[k0 + kk];
+        const double y = iy < g.n_uy ? g.ys[iy] : 0.0;
+        fy[kk][r] = exp(-(y * y) / (2.0 * sig * sig * qo * qo));
+      }
+      __syncthreads();
+      for (int kk = 0; kk < nk; ++kk) {
+        const int k = k0 + kk;
+        const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+        const double sig = g.lum_sigma[k];
+        const double fx = I0 * exp(-(x * x) / (2.0 * sig * sig));
+#pragma unroll
+        for (int r = 0; r < kSbRows; ++r) acc[r] += fx * fy[kk][r];
+      }
     }
-    pix[md.pix_off + g.n_pix + q] = acc;
+    if (vx) {
+#pragma unroll
+      for (int r = 0; r < kSbRows; ++r)
+        if (y0 + r < g.n_uy) pix[md.pix_off + g.n_pix + (int64_t)(y0 + r) * g.n_ux + ix] = acc[r];
+    }
   }
 }
 
@@ -522,21 +551,32 @@ __global__ void __launch_bounds__(256) k_num(const GeomDev *__restrict__ geoms,
   }
 }
 
-// Sum the split-term partials in a fixed order into the N map.
+// Sum the split-term partials in a fixed order into the N map.  Item
+// (m, 64-pixel block); the four waves take every fourth slice and their sums
+// are combined in a fixed order.
 __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geoms,
                                                 const ModelDev *__restrict__ models,
                                                 const Item *__restrict__ items, int n_it,
                                                 const double *__restrict__ part,
                                                 double *__restrict__ pix) {
+  __shared__ double red[3][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const int q = it.a * 256 + threadIdx.x;
-    if (q >= g.n_pix) continue;
+    const int q = it.a * 64 + lane;
     double acc = 0.0;
-    for (int s = 0; s < md.n_slices; ++s) acc += part[md.part_off + (int64_t)s * g.n_pix + q];
-    pix[md.pix_off + q] = acc;
+    if (q < g.n_pix) {
+      const double *pp = part + md.part_off + q;
+      for (int s = wave; s < md.n_slices; s += 4) acc += pp[(int64_t)s * g.n_pix];
+    }
+    if (wave > 0) red[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && q < g.n_pix)
+      pix[md.pix_off + q] = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+    __syncthreads();
   }
 }
 
@@ -560,15 +600,29 @@ __global__ void __launch_bounds__(256) k_bins(const GeomDev *__restrict__ geoms,
     const double *Nm = pix + md.pix_off;
     const double *Im = Nm + g.n_pix;
     const bool want_n = vrms2 != nullptr;
-    double an = 0.0, ai = 0.0;
-    for (int e = g.bin_ptr[b] + threadIdx.x; e < g.bin_ptr[b + 1]; e += 256) {
+    // four independent accumulators keep four gathers in flight per thread
+    double an[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+    const int e1 = g.bin_ptr[b + 1];
+    int e = g.bin_ptr[b] + threadIdx.x;
+    for (; e + 3 * 256 < e1; e += 4 * 256) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double wv = g.bin_w[e + u * 256];
+        const int q = g.bin_pix[e + u * 256];
+        if (want_n) an[u] += wv * Nm[q];
+        ai[u] += wv * Im[q];
+      }
+    }
+    for (int u = 0; e < e1; e += 256, ++u) {
       const double wv = g.bin_w[e];
       const int q = g.bin_pix[e];
-      if (want_n) an += wv * Nm[q];
-      ai += wv * Im[q];
+      if (want_n) an[u] += wv * Nm[q];
+      ai[u] += wv * Im[q];
     }
-    const double sn = want_n ? block_sum256(an, sh) : 0.0;
-    const double si = block_sum256(ai, sh);
+    const double an_t = (an[0] + an[1]) + (an[2] + an[3]);
+    const double ai_t = (ai[0] + ai[1]) + (ai[2] + ai[3]);
+    const double sn = want_n ? block_sum256(an_t, sh) : 0.0;
+    const double si = block_sum256(ai_t, sh);
     if (threadIdx.x == 0) {
       const bool ok = st_ws[it.m] == 0;
       if (binws) {
@@ -819,9 +873,14 @@ __global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
 // ---------------------------------------------------------------------------
 // FP64 chain from per-term sensitivities to the parameters.  Forward-mode
 // dual numbers carry d/d(inclination) through the deprojection and the term
-// coefficients.  Item (m, k): all terms of luminous Gaussian k.
-// chain per model: [K][3 + J1] doubles: d/di, d/dbeta_k, d/dI0_k (N and I
-// paths), then d/dM_j (j < J1, BH last) partial sums over k.
+// coefficients.  Items (m, k, jb): wave w of the workgroup takes mass
+// Gaussian j = 4 jb + w (BH last) and its lanes the u-nodes; with
+// jb = ceil(J1 / 4) the item instead computes the surface-brightness path of
+// luminous Gaussian k.  Chain rows per model (doubles, after the
+// sensitivity blocks): [K][J1][3] = (d/di, d/db_k, H_kj) for the terms of
+// (k, j), with H_kj = sum_n (S0 c0 + S1 c1) the derivative with respect to
+// the amplitude product I0_k M_j; then [K] surface-brightness terms
+// sum_p lambda_I[p] exp(-(x^2 + y^2/q'^2)/(2 sigma'^2)).
 // ---------------------------------------------------------------------------
 struct dual {
   double v, d;
@@ -846,174 +905,174 @@ __device__ inline dual dsqrt(dual a) {
 }
 __device__ inline dual dconst(double v) { return {v, 0.0}; }
 
+__device__ inline double *chain_rows(double *sens, const ModelDev &md, const GeomDev &g) {
+  return sens + md.sens_off + 3 * (int64_t)md.n_sens_parts * g.T;
+}
+
 __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms,
                                                const ModelDev *__restrict__ models,
                                                const Item *__restrict__ items, int n_it,
                                                ParamsDev p, const double *__restrict__ pix,
-                                               const double *__restrict__ sens,
-                                               const int *__restrict__ st_ws,
-                                               double *__restrict__ chain) {
-  // chain rows live in the sens region after the three sensitivity arrays:
-  // per model [K][3 + J1] doubles at sens_off + 3 T.
+                                               double *__restrict__ sens,
+                                               const int *__restrict__ st_ws) {
   __shared__ double sh[256];
-  __shared__ double shj[4][2];
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;   // uniform per block; k_grads writes NaN
     const int k = it.a;
     const int J1 = g.J1, J = J1 - 1;
-    const int np_ = md.n_sens_parts;
-    double *row = chain + md.sens_off + 3 * (int64_t)np_ * g.T + (int64_t)k * (3 + J1);
-    if (st_ws[it.m] != 0) {
-      for (int c = threadIdx.x; c < 3 + J1; c += 256) row[c] = __builtin_nan("");
+    double *rows = chain_rows(sens, md, g);
+    const double qok = g.lum_q[k], sk = g.lum_sigma[k];
+    if (it.b * 4 >= J1) {
+      // surface-brightness path of I0_k, separable in x and y
+      const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
+      const double ax = 0.5 / (sk * sk), ay = ax / (qok * qok);
+      double acc = 0.0;
+      for (int iy = 0; iy < g.n_uy; ++iy) {
+        const double yv = g.ys[iy];
+        const double fy = exp(-ay * yv * yv);
+        double row = 0.0;
+        for (int ix = threadIdx.x; ix < g.n_ux; ix += 256) {
+          const double xv = g.xs[ix];
+          row += lamI[(int64_t)iy * g.n_ux + ix] * exp(-ax * xv * xv);
+        }
+        acc += fy * row;
+      }
+      const double t = block_sum256(acc, sh);
+      if (threadIdx.x == 0) rows[(int64_t)g.K * J1 * 3 + k] = t;
       continue;
     }
+    const int j = it.b * 4 + wave;
+    if (j >= J1) continue;            // uniform per wave; no block barrier follows
     const double inc = p.inc[it.m];
     const dual s = {sin(inc), cos(inc)};
     const dual c = {cos(inc), -sin(inc)};
     const dual si2 = s * s, ci2 = c * c;
     const double G = grav_const();
     const double sp = g.s_pc;
-    // luminous Gaussian k
-    const double qok = g.lum_q[k], sk = g.lum_sigma[k];
     const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-    const double beta = p.beta[md.lum_off + k];
-    const double b = 1.0 / (1.0 - beta);
+    const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
     const dual qk = dsqrt(qok * qok - ci2) / s;
     const double alpha = 0.5 / (sk * sk);
     const dual alphaq = dconst(alpha) / (qk * qk);
     const dual nu1 = dconst(qok / (sqrt(2.0 * kPi) * sk)) / qk;   // nu0 / I0
+    dual e2;
+    double r, Kt, Mj;
+    if (j < J) {
+      const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+      const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+      const dual qj = dsqrt(qo * qo - ci2) / s;
+      e2 = 1.0 - qj * qj;
+      r = 0.5 / (sj * sj);
+      Kt = sqrt(2.0 / kPi) * G / (sp * sj);
+      Mj = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
+    } else {
+      e2 = dconst(0.0);
+      r = 0.5 / (g.bh_sigma * g.bh_sigma);
+      Kt = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
+      Mj = p.m_bh[it.m];
+    }
+    const double amp = I0 * Mj;
     const double *S0a = sens + md.sens_off;
-    const double *S1a = S0a + g.T;
-    const double *Sga = S1a + g.T;
-    double acc_i = 0.0, acc_b = 0.0, acc_I = 0.0;
-    for (int j0 = 0; j0 < J1; j0 += 4) {
-      const int j = j0 + wave;
-      double hj = 0.0;
-      double Mj = 0.0;
-      if (j < J1) {
-        dual e2;
-        double r, Kt;
-        if (j < J) {
-          const double qo = g.mass_q[j], sj = g.mass_sigma[j];
-          const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
-          const dual qj = dsqrt(qo * qo - ci2) / s;
-          e2 = 1.0 - qj * qj;
-          r = 0.5 / (sj * sj);
-          Kt = sqrt(2.0 / kPi) * G / (sp * sj);
-          Mj = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
-        } else {
-          e2 = dconst(0.0);
-          r = 0.5 / (g.bh_sigma * g.bh_sigma);
-          Kt = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
-          Mj = p.m_bh[it.m];
-        }
-        for (int n = lane; n < g.n_u; n += 64) {
-          const int64_t t = ((int64_t)k * J1 + j) * g.n_u + n;
-          const double u = g.u[n], wq = g.w[n];
-          const double u2 = u * u;
-          const dual h = 1.0 - u2 * e2;
-          const double c1 = alpha + r * u2;
-          const dual A = alphaq + (r * u2) * (dconst(1.0) / h);
-          const dual a = c1 * si2 + A * ci2;
-          const dual gam = c1 * A / a;
-          const dual sh_ = dsqrt(h);
-          const dual base = (Kt * r * u2) * nu1;                    // per unit I0 M
-          const dual gg = base / (A * h * sh_);
-          const dual ww = 2.0 * base / sh_;
-          const dual P = (ci2 + b * si2) * gg;
-          const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
-          const dual f = wq * dsqrt(kPi / a);
-          const dual c0 = f * P, c1u = f * Q;                       // C = I0 M c
-          double S0 = 0.0, S1 = 0.0, Sg = 0.0;
-          for (int q = 0; q < np_; ++q) {
-            const int64_t o = (int64_t)q * 3 * g.T + t;
-            S0 += S0a[o];
-            S1 += S1a[o];
-            Sg += Sga[o];
-          }
-          const double amp = I0 * Mj;
-          acc_i += amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
-          // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
-          acc_b += amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
-          hj += S0 * c0.v + S1 * c1u.v;
-        }
+    const int np_ = md.n_sens_parts;
+    double acc_i = 0.0, acc_b = 0.0, hj = 0.0;
+    for (int n = lane; n < g.n_u; n += 64) {
+      const int64_t t = ((int64_t)k * J1 + j) * g.n_u + n;
+      double S0 = 0.0, S1 = 0.0, Sg = 0.0;
+      for (int q = 0; q < np_; ++q) {
+        const double *blk = S0a + (int64_t)q * 3 * g.T;
+        S0 += blk[t];
+        S1 += blk[g.T + t];
+        Sg += blk[2 * (int64_t)g.T + t];
       }
-      hj = wave_sum(hj);
-      if (lane == 0) {
-        shj[wave][0] = hj;
-        shj[wave][1] = Mj;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int w4 = 0; w4 < 4; ++w4) {
-          const int jj = j0 + w4;
-          if (jj < J1) {
-            row[3 + jj] = I0 * shj[w4][0];     // d/dM_j
-            acc_I += shj[w4][1] * shj[w4][0];  // d/dI0_k, N path
-          }
-        }
-      }
-      __syncthreads();
+      const double u = g.u[n], wq = g.w[n];
+      const double u2 = u * u;
+      const dual h = 1.0 - u2 * e2;
+      const double c1 = alpha + r * u2;
+      const dual A = alphaq + (r * u2) * (dconst(1.0) / h);
+      const dual a = c1 * si2 + A * ci2;
+      const dual gam = c1 * A / a;
+      const dual sh_ = dsqrt(h);
+      const dual base = (Kt * r * u2) * nu1;                    // per unit I0 M
+      const dual gg = base / (A * h * sh_);
+      const dual ww = 2.0 * base / sh_;
+      const dual P = (ci2 + b * si2) * gg;
+      const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
+      const dual f = wq * dsqrt(kPi / a);
+      const dual c0 = f * P, c1u = f * Q;                       // C = I0 M c
+      acc_i += amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
+      // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
+      acc_b += amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
+      hj += S0 * c0.v + S1 * c1u.v;
     }
-    // I path: d/dI0_k += sum_p lambda_I[p] exp(-(x^2 + y^2/q'^2)/(2 sigma'^2))
-    const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
-    double acc_l = 0.0;
-    for (int q = threadIdx.x; q < g.n_pix; q += 256) {
-      const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-      acc_l += lamI[q] * exp(-(x * x + y * y / (qok * qok)) / (2.0 * sk * sk));
+    acc_i = wave_sum(acc_i);
+    acc_b = wave_sum(acc_b);
+    hj = wave_sum(hj);
+    if (lane == 0) {
+      double *o = rows + ((int64_t)k * J1 + j) * 3;
+      o[0] = acc_i;
+      o[1] = acc_b;
+      o[2] = hj;
     }
-    const double ti = block_sum256(acc_i, sh);
-    const double tb = block_sum256(acc_b, sh);
-    const double tl = block_sum256(acc_l, sh);
-    if (threadIdx.x == 0) {
-      row[0] = ti;
-      row[1] = tb * b * b;           // db/dbeta = b^2
-      row[2] = acc_I + tl;
-    }
-    __syncthreads();
   }
 }
 
-// Final per-model gradients from the per-k chain rows.  One block per model.
+// Final per-model gradients from the chain rows.  One block per model.
 __global__ void __launch_bounds__(64) k_grads(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models, int n,
-                                              ParamsDev p, const double *__restrict__ sens,
+                                              ParamsDev p, double *__restrict__ sens,
                                               const int *__restrict__ st_ws, GradsDev out) {
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
     const int K = g.K, J1 = g.J1, J = J1 - 1;
-    const double *cm = sens + md.sens_off + 3 * (int64_t)md.n_sens_parts * g.T;
+    const double *rows = chain_rows(sens, md, g);
     const bool ok = st_ws[m] == 0;
     const double nan = __builtin_nan("");
     const double sp = g.s_pc;
+    const double ml = p.mass_scale[m];
+    auto mass = [&](int j) {
+      if (j == J) return p.m_bh[m];
+      const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+      return ml * 2.0 * kPi * S0 * (sp * g.mass_sigma[j]) * (sp * g.mass_sigma[j]) * g.mass_q[j];
+    };
+    double di = 0.0;
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
-      const double *row = cm + (int64_t)k * (3 + J1);
-      if (out.beta) out.beta[md.lum_off + k] = ok ? row[1] : nan;
-      if (out.lum_I0) out.lum_I0[md.lum_off + k] = ok ? row[2] : nan;
+      double db = 0.0, dI = rows[(int64_t)K * J1 * 3 + k];
+      for (int j = 0; j < J1; ++j) {
+        const double *o = rows + ((int64_t)k * J1 + j) * 3;
+        di += o[0];
+        db += o[1];
+        dI += mass(j) * o[2];
+      }
+      const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
+      if (out.beta) out.beta[md.lum_off + k] = ok ? db * b * b : nan;     // db/dbeta = b^2
+      if (out.lum_I0) out.lum_I0[md.lum_off + k] = ok ? dI : nan;
     }
     double dml = 0.0;
     for (int j = threadIdx.x; j < J1; j += blockDim.x) {
       double dM = 0.0;
-      for (int k = 0; k < K; ++k) dM += cm[(int64_t)k * (3 + J1) + 3 + j];
+      for (int k = 0; k < K; ++k) {
+        const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+        dM += I0 * rows[((int64_t)k * J1 + j) * 3 + 2];
+      }
       if (j < J) {
         const double qo = g.mass_q[j], sj = g.mass_sigma[j];
         const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
         const double unit = 2.0 * kPi * (sp * sj) * (sp * sj) * qo;   // dM/d(ml S0)
-        if (out.mass_S0) out.mass_S0[md.mass_off + j] = ok ? dM * p.mass_scale[m] * unit : nan;
+        if (out.mass_S0) out.mass_S0[md.mass_off + j] = ok ? dM * ml * unit : nan;
         dml += dM * S0 * unit;
       } else {
         if (out.m_bh) out.m_bh[m] = ok ? dM : nan;
       }
     }
+    di = wave_sum(di);
     dml = wave_sum(dml);
     if (threadIdx.x == 0) {
-      double di = 0.0;
-      for (int k = 0; k < K; ++k) di += cm[(int64_t)k * (3 + J1)];
       if (out.inc) out.inc[m] = ok ? di : nan;
       if (out.mass_scale) out.mass_scale[m] = ok ? dml : nan;
     }
@@ -1088,9 +1147,9 @@ int occupancy_sens() {
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st) {
   hipLaunchKernelGGL(k_chain, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, pix, sens,
-                     st_ws, sens);
+                     st_ws);
 }
-void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, const double *sens,
+void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(64), 0, st, g, m, n, p, sens, st_ws, out);
 }
