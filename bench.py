@@ -76,6 +76,25 @@ def cpu_baseline(g, p, n_sample):
                        f"IFU-scale model ({dt:.1f} s), scaled to one model")
 
 
+def profiled_traffic():
+    """HBM bytes per k_num launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel source has changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_num_ifu_scale_hbm.md")
+    src = os.path.join(ROOT, "paper_2504_01302_amd", "csrc", "jam_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = re.search(r"Kernel source sha256: ([0-9a-f]{64})", text)
+    b = re.search(r"k_num_traffic_bytes_per_launch: ([0-9.]+)", text)
+    if not h or not b:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(b.group(1))
+
+
 def time_batch(torch, binding, w, dev, steps, form, launch, graph):
     """Forward and forward+adjoint throughput of one whole batch per launch."""
     ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph)
@@ -229,8 +248,10 @@ def main():
         flops = PIX_FLOPS_PER_INTEGRAND * n_pix * T * n
         roof = dict(bound="alu", peak=FP32_VECTOR_PEAK / 1e12)
     achieved = flops / avg_num_s / 1e12 if avg_num_s else None
+    traffic = profiled_traffic() if (form_used == 2 and n == 1 and a.launch == 0
+                                     and not a.autotune) else None
     roof.update(achieved=achieved, unit="TFLOP/s",
-                frac=achieved / roof["peak"] if achieved else None, traffic=None,
+                frac=achieved / roof["peak"] if achieved else None, traffic=traffic,
                 kernel="k_num", avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
                 launches=num_n, flops_per_launch=flops)
 

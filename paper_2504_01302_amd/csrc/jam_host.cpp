@@ -448,15 +448,15 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       }
     } else {
       for (int xt = 0; xt < d.n_sens_parts; ++xt)
-        for (int tt = 0; tt < (g.T + 127) / 128; ++tt) {
+        for (int tt = 0; tt < (g.T + 255) / 256; ++tt) {
           it_sens.push_back({m, xt, tt, 1});
-          c_sens.push_back(4.0 * 32.0 * g.n_uy);
+          c_sens.push_back(8.0 * 32.0 * g.n_uy);
         }
     }
     for (int pb = 0; pb < (g.n_pix + 255) / 256; ++pb) it_pix.push_back({m, pb, 0, 0});
     for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_red.push_back({m, pb, 0, 0});
     for (int rb = 0; rb < (g.n_uy + 7) / 8; ++rb)
-      for (int cb = 0; cb < (g.n_ux + 255) / 256; ++cb) it_sb.push_back({m, rb, cb, 0});
+      for (int cb = 0; cb < (g.n_ux + 63) / 64; ++cb) it_sb.push_back({m, rb, cb, 0});
     for (int s = 0; s < d.n_slices; ++s) {
       const double c = num_item_cost(g, nc, s);
       for (int tl = 0; tl < nc.tiles; ++tl) {

@@ -82,7 +82,7 @@ void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
                   int *st_ws, int32_t *st_out, int *queues, hipStream_t st);
 void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
-// Items (m, block of 8 unique-pixel rows, block of 256 columns).
+// Items (m, block of 8 unique-pixel rows, block of 64 columns).
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
 // Numerator over a work list whose items carry their variant in Item::c:
@@ -108,7 +108,7 @@ void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, in
                          const double *vrms2, const double *cot, const double *binws,
                          const int *st_ws, double *pix, hipStream_t st);
 // Sensitivities, variant in Item::c: 0 per-pixel VALU (m, 256-term block),
-// 1 MFMA (m, 32-row x tile, 128-term tile); queue as launch_num.
+// 1 MFMA (m, 32-row x tile, 256-term tile); queue as launch_num.
 void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const float4 *terms, const double *pix, const int *st_ws, double *sens,
                  int *queue, int grid, hipStream_t st);
@@ -117,7 +117,7 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // items (m, k, jb) for jb <= ceil(J1 / 4) (the last one per k is the
 // surface-brightness path).  The per-pixel kernel
 // writes one block; the MFMA kernel one block per 32-row x tile (items
-// (m, x tile, 128-term tile)).
+// (m, x tile, 256-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,

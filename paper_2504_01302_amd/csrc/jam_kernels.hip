@@ -56,6 +56,20 @@ __device__ double block_sum256(double v, double *sh) {
   return r;
 }
 
+// Deterministic block sum of one double over a 1024-thread block.
+__device__ double block_sum1024(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -195,49 +209,55 @@ __global__ void __launch_bounds__(256) k_terms(const GeomDev *__restrict__ geoms
 // pix region per model: [N | I | lambda_N | lambda_I], n_pix doubles each.
 // ---------------------------------------------------------------------------
 constexpr int kSbRows = 8;
-constexpr int kSbK = 32;   // luminous Gaussians per LDS pass
 
+// Item (m, block of 8 rows, block of 64 columns); lane = column, wave w takes
+// luminous Gaussians k = w, w + 4, ...; the four partial sums are combined in
+// a fixed order.
 __global__ void __launch_bounds__(256) k_sb(const GeomDev *__restrict__ geoms,
                                             const ModelDev *__restrict__ models,
                                             const Item *__restrict__ items, int n_it, ParamsDev p,
                                             double *__restrict__ pix) {
-  __shared__ double fy[kSbK][kSbRows];
+  __shared__ double red[3][kSbRows][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
     const int y0 = it.a * kSbRows;
-    const int ix = it.b * 256 + threadIdx.x;
+    const int ix = it.b * 64 + lane;
     const bool vx = ix < g.n_ux;
     const double x = vx ? g.xs[ix] : 0.0;
+    double yy[kSbRows];
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r) {
+      const double y = y0 + r < g.n_uy ? g.ys[y0 + r] : 0.0;
+      yy[r] = y * y;
+    }
     double acc[kSbRows];
 #pragma unroll
     for (int r = 0; r < kSbRows; ++r) acc[r] = 0.0;
-    for (int k0 = 0; k0 < g.K; k0 += kSbK) {
-      const int nk = min(kSbK, g.K - k0);
-      __syncthreads();
-      if (threadIdx.x < nk * kSbRows) {
-        const int kk = threadIdx.x / kSbRows, r = threadIdx.x % kSbRows;
-        const int iy = y0 + r;
-        const double qo = g.lum_q[k0 + kk], sig = g.lum_sigma[k0 + kk];
-        const double y = iy < g.n_uy ? g.ys[iy] : 0.0;
-        fy[kk][r] = exp(-(y * y) / (2.0 * sig * sig * qo * qo));
-      }
-      __syncthreads();
-      for (int kk = 0; kk < nk; ++kk) {
-        const int k = k0 + kk;
-        const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-        const double sig = g.lum_sigma[k];
-        const double fx = I0 * exp(-(x * x) / (2.0 * sig * sig));
+    for (int k = wave; k < g.K; k += 4) {
+      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+      const double sig = g.lum_sigma[k], qo = g.lum_q[k];
+      const double a = 1.0 / (2.0 * sig * sig);
+      const double fx = I0 * exp(-a * x * x);
+      const double ay = a / (qo * qo);
 #pragma unroll
-        for (int r = 0; r < kSbRows; ++r) acc[r] += fx * fy[kk][r];
-      }
+      for (int r = 0; r < kSbRows; ++r) acc[r] += fx * exp(-ay * yy[r]);
     }
-    if (vx) {
+    if (wave > 0)
+#pragma unroll
+      for (int r = 0; r < kSbRows; ++r) red[wave - 1][r][lane] = acc[r];
+    __syncthreads();
+    if (wave == 0 && vx) {
 #pragma unroll
       for (int r = 0; r < kSbRows; ++r)
-        if (y0 + r < g.n_uy) pix[md.pix_off + g.n_pix + (int64_t)(y0 + r) * g.n_ux + ix] = acc[r];
+        if (y0 + r < g.n_uy)
+          pix[md.pix_off + g.n_pix + (int64_t)(y0 + r) * g.n_ux + ix] =
+              ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
     }
+    __syncthreads();
   }
 }
 
@@ -584,14 +604,14 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
 // Bins: sums of the PSF-weighted maps per bin and their FP64 ratio.
 // Item (m, bin).  binws per model: [Nb | Ib], n_bins doubles each.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bins(const GeomDev *__restrict__ geoms,
+__global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models,
                                               const Item *__restrict__ items, int n_it,
                                               const double *__restrict__ pix,
                                               const int *__restrict__ st_ws,
                                               double *__restrict__ vrms2,
                                               double *__restrict__ binws) {
-  __shared__ double sh[256];
+  __shared__ double sh[1024];
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
@@ -604,16 +624,16 @@ __global__ void __launch_bounds__(256) k_bins(const GeomDev *__restrict__ geoms,
     double an[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
     const int e1 = g.bin_ptr[b + 1];
     int e = g.bin_ptr[b] + threadIdx.x;
-    for (; e + 3 * 256 < e1; e += 4 * 256) {
+    for (; e + 3 * 1024 < e1; e += 4 * 1024) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double wv = g.bin_w[e + u * 256];
-        const int q = g.bin_pix[e + u * 256];
+        const double wv = g.bin_w[e + u * 1024];
+        const int q = g.bin_pix[e + u * 1024];
         if (want_n) an[u] += wv * Nm[q];
         ai[u] += wv * Im[q];
       }
     }
-    for (int u = 0; e < e1; e += 256, ++u) {
+    for (int u = 0; e < e1; e += 1024, ++u) {
       const double wv = g.bin_w[e];
       const int q = g.bin_pix[e];
       if (want_n) an[u] += wv * Nm[q];
@@ -621,8 +641,8 @@ __global__ void __launch_bounds__(256) k_bins(const GeomDev *__restrict__ geoms,
     }
     const double an_t = (an[0] + an[1]) + (an[2] + an[3]);
     const double ai_t = (ai[0] + ai[1]) + (ai[2] + ai[3]);
-    const double sn = want_n ? block_sum256(an_t, sh) : 0.0;
-    const double si = block_sum256(ai_t, sh);
+    const double sn = want_n ? block_sum1024(an_t, sh) : 0.0;
+    const double si = block_sum1024(ai_t, sh);
     if (threadIdx.x == 0) {
       const bool ok = st_ws[it.m] == 0;
       if (binws) {
@@ -754,18 +774,23 @@ __device__ __forceinline__ void sens_pix_item(const Item it, const GeomDev *__re
 //   G[x, t] = sum_y lambda[x, y] F_t(y),   H[x, t] = sum_y lambda[x, y] y^2 F_t(y)
 // are two FP32 contractions over y sharing the lambda operand, and
 //   S0_t = sum_x E G,  S1_t = sum_x x^2 E G,  Sg_t = sum_x E (C0 + C1 x^2) H.
-// Item (m, 32-row x tile, 128-term tile); wave w owns terms 32 w .. 32 w + 31
-// of the tile (lane l: term l % 32, y pair l / 32).  lambda is staged through
+// Item (m, 32-row x tile, 256-term tile); wave w owns terms 64 w .. 64 w + 63
+// of the tile, as two 32-term column blocks (lane l: term l % 32, y pair
+// l / 32).  lambda is staged through
 // LDS 256 rows of y at a time; FP32 partial sums over 32 y values are folded
 // into FP64.  Output: per x tile, [S0 | S1 | Sg] (T doubles each).
 // ---------------------------------------------------------------------------
 constexpr int YC = 256;
+constexpr int kSensTerms = 256;   // terms per MFMA sensitivity item (64 per wave)
 
 __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__restrict__ geoms,
-    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const double *__restrict__ pix, const int *__restrict__ st_ws, double *__restrict__ sens, char *smem) {
+                                               const ModelDev *__restrict__ models,
+                                               const float4 *__restrict__ terms,
+                                               const double *__restrict__ pix,
+                                               const int *__restrict__ st_ws,
+                                               double *__restrict__ sens, char *smem) {
   float (*lam)[32] = reinterpret_cast<float (*)[32]>(smem);
   float *ysq = reinterpret_cast<float *>(smem + YC * 32 * sizeof(float));
-
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c32 = lane & 31, kh = lane >> 5;
@@ -773,13 +798,21 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
   const GeomDev g = geoms[md.geom];
   if (st_ws[it.m] != 0) return;   // uniform per block
   const int x0 = it.a * 32;
-  const int t = it.b * 128 + wave * 32 + c32;
-  const bool vt = t < g.T;
-  const float4 c = vt ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
   const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
-  double gacc[16], hacc[16];
+  // wave w owns terms it.b*kSensTerms + w*64 + h*32 + (0..31), h = 0, 1
+  float4 c[2];
+  bool vt[2];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) { gacc[r] = 0.0; hacc[r] = 0.0; }
+  for (int h = 0; h < 2; ++h) {
+    const int t = it.b * kSensTerms + wave * 64 + h * 32 + c32;
+    vt[h] = t < g.T;
+    c[h] = vt[h] ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  double gacc[2][16], hacc[2][16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { gacc[h][r] = 0.0; hacc[h][r] = 0.0; }
   for (int yb = 0; yb < g.n_uy; yb += YC) {
     const int ny = min(YC, g.n_uy - yb);
     __syncthreads();
@@ -796,51 +829,65 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
     }
     __syncthreads();
     for (int y0 = 0; y0 < ny; y0 += 32) {
-      v16f dg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      v16f dh = dg;
-#pragma unroll 4
+      // this chunk's operands: lambda[x0 + c32][y0 + 2 s + kh] and y^2
+      float ra[16], ry[16];
+#pragma unroll
       for (int s2 = 0; s2 < 16; ++s2) {
         const int yy = y0 + 2 * s2 + kh;          // < YC; rows past ny hold zero lambda
-        const float a = lam[yy][c32];
-        const float y2 = ysq[yy];
-        const float b = fast_exp2(c.y * y2);
-        dg = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, dg, 0, 0, 0);
-        dh = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b * y2, dh, 0, 0, 0);
+        ra[s2] = lam[yy][c32];
+        ry[s2] = ysq[yy];
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { gacc[r] += (double)dg[r]; hacc[r] += (double)dh[r]; }
-    }
-  }
-  double s0 = 0.0, s1 = 0.0, sg = 0.0;
+      for (int h = 0; h < 2; ++h) {
+        v16f dg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        v16f dh = dg;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int xr = x0 + mfma_row(r, lane);
-    if (xr < g.n_ux) {
-      const double xv = g.xs[xr];
-      const float x2 = (float)(xv * xv);
-      const double e = (double)fast_exp2(c.x * x2);
-      s0 += e * gacc[r];
-      s1 += (double)x2 * e * gacc[r];
-      sg += e * (double)fmaf(c.w, x2, c.z) * hacc[r];
+        for (int s2 = 0; s2 < 16; ++s2) {
+          const float b = fast_exp2(c[h].y * ry[s2]);
+          dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b, dg, 0, 0, 0);
+          dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b * ry[s2], dh, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          gacc[h][r] += (double)dg[r];
+          hacc[h][r] += (double)dh[r];
+        }
+      }
     }
   }
-  s0 += __shfl_xor(s0, 32, 64);
-  s1 += __shfl_xor(s1, 32, 64);
-  sg += __shfl_xor(sg, 32, 64);
-  if (kh == 0 && vt) {
-    double *S = sens + md.sens_off + (int64_t)it.a * 3 * g.T;
-    S[t] = s0;
-    S[g.T + t] = s1;
-    S[2 * (int64_t)g.T + t] = sg;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double s0 = 0.0, s1 = 0.0, sg = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int xr = x0 + mfma_row(r, lane);
+      if (xr < g.n_ux) {
+        const double xv = g.xs[xr];
+        const float x2 = (float)(xv * xv);
+        const double e = (double)fast_exp2(c[h].x * x2);
+        s0 += e * gacc[h][r];
+        s1 += (double)x2 * e * gacc[h][r];
+        sg += e * (double)fmaf(c[h].w, x2, c[h].z) * hacc[h][r];
+      }
+    }
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    sg += __shfl_xor(sg, 32, 64);
+    const int t = it.b * kSensTerms + wave * 64 + h * 32 + c32;
+    if (kh == 0 && vt[h]) {
+      double *S = sens + md.sens_off + (int64_t)it.a * 3 * g.T;
+      S[t] = s0;
+      S[g.T + t] = s1;
+      S[2 * (int64_t)g.T + t] = sg;
+    }
   }
 }
-
 
 constexpr int kSensSmem = (YC * 32 + YC) * (int)sizeof(float);
 static_assert(kSensSmem >= 3 * 256 * (int)sizeof(float), "per-pixel sensitivity LDS");
 
 // Adjoint sensitivities over a work list, variant in Item::c (0 per-pixel
-// VALU, items (m, 256-term block); 1 MFMA, items (m, x tile, 128-term tile));
+// VALU, items (m, 256-term block); 1 MFMA, items (m, x tile, 256-term tile));
 // queue-driven or strided as k_num.
 __global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models,
@@ -928,20 +975,29 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
     double *rows = chain_rows(sens, md, g);
     const double qok = g.lum_q[k], sk = g.lum_sigma[k];
     if (it.b * 4 >= J1) {
-      // surface-brightness path of I0_k, separable in x and y
+      // surface-brightness path of I0_k, separable in x and y: the row
+      // factors of up to 256 rows go through LDS, the column factor is
+      // computed once per column and row chunk.
       const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
       const double ax = 0.5 / (sk * sk), ay = ax / (qok * qok);
       double acc = 0.0;
-      for (int iy = 0; iy < g.n_uy; ++iy) {
-        const double yv = g.ys[iy];
-        const double fy = exp(-ay * yv * yv);
-        double row = 0.0;
+      for (int y0 = 0; y0 < g.n_uy; y0 += 256) {
+        const int ny = min(256, g.n_uy - y0);
+        __syncthreads();
+        if (threadIdx.x < ny) {
+          const double yv = g.ys[y0 + threadIdx.x];
+          sh[threadIdx.x] = exp(-ay * yv * yv);
+        }
+        __syncthreads();
         for (int ix = threadIdx.x; ix < g.n_ux; ix += 256) {
           const double xv = g.xs[ix];
-          row += lamI[(int64_t)iy * g.n_ux + ix] * exp(-ax * xv * xv);
+          const double *col = lamI + (int64_t)y0 * g.n_ux + ix;
+          double cs = 0.0;
+          for (int r = 0; r < ny; ++r) cs += col[(int64_t)r * g.n_ux] * sh[r];
+          acc += exp(-ax * xv * xv) * cs;
         }
-        acc += fy * row;
       }
+      __syncthreads();   // row factors in sh are still being read
       const double t = block_sum256(acc, sh);
       if (threadIdx.x == 0) rows[(int64_t)g.K * J1 * 3 + k] = t;
       continue;
@@ -1021,11 +1077,18 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
   }
 }
 
-// Final per-model gradients from the chain rows.  One block per model.
-__global__ void __launch_bounds__(64) k_grads(const GeomDev *__restrict__ geoms,
-                                              const ModelDev *__restrict__ models, int n,
-                                              ParamsDev p, double *__restrict__ sens,
-                                              const int *__restrict__ st_ws, GradsDev out) {
+// Final per-model gradients from the chain rows.  One 256-thread block per
+// model: each wave reduces one luminous Gaussian's row at a time over the
+// mass Gaussians (lanes), then the waves reduce the mass derivatives over
+// the luminous Gaussians; partial sums are combined in a fixed order.
+__global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms,
+                                               const ModelDev *__restrict__ models, int n,
+                                               ParamsDev p, double *__restrict__ sens,
+                                               const int *__restrict__ st_ws, GradsDev out) {
+  __shared__ double part[4][2];
+  __shared__ double mpart[4][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
@@ -1040,42 +1103,62 @@ __global__ void __launch_bounds__(64) k_grads(const GeomDev *__restrict__ geoms,
       const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
       return ml * 2.0 * kPi * S0 * (sp * g.mass_sigma[j]) * (sp * g.mass_sigma[j]) * g.mass_q[j];
     };
+    // d/di, d/dbeta_k, d/dI0_k
     double di = 0.0;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-      double db = 0.0, dI = rows[(int64_t)K * J1 * 3 + k];
-      for (int j = 0; j < J1; ++j) {
+    for (int k = wave; k < K; k += 4) {
+      double a = 0.0, db = 0.0, dI = 0.0;
+      for (int j = lane; j < J1; j += 64) {
         const double *o = rows + ((int64_t)k * J1 + j) * 3;
-        di += o[0];
+        a += o[0];
         db += o[1];
         dI += mass(j) * o[2];
       }
-      const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
-      if (out.beta) out.beta[md.lum_off + k] = ok ? db * b * b : nan;     // db/dbeta = b^2
-      if (out.lum_I0) out.lum_I0[md.lum_off + k] = ok ? dI : nan;
+      a = wave_sum(a);
+      db = wave_sum(db);
+      dI = wave_sum(dI);
+      di += a;
+      if (lane == 0) {
+        const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
+        if (out.beta) out.beta[md.lum_off + k] = ok ? db * b * b : nan;   // db/dbeta = b^2
+        if (out.lum_I0)
+          out.lum_I0[md.lum_off + k] = ok ? dI + rows[(int64_t)K * J1 * 3 + k] : nan;
+      }
     }
+    // d/dM_j = sum_k I0_k H_kj; then the mass scale, Sigma0_j and the BH
     double dml = 0.0;
-    for (int j = threadIdx.x; j < J1; j += blockDim.x) {
+    for (int j0 = 0; j0 < J1; j0 += 64) {
+      const int j = j0 + lane;
       double dM = 0.0;
-      for (int k = 0; k < K; ++k) {
-        const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-        dM += I0 * rows[((int64_t)k * J1 + j) * 3 + 2];
-      }
-      if (j < J) {
-        const double qo = g.mass_q[j], sj = g.mass_sigma[j];
-        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
-        const double unit = 2.0 * kPi * (sp * sj) * (sp * sj) * qo;   // dM/d(ml S0)
-        if (out.mass_S0) out.mass_S0[md.mass_off + j] = ok ? dM * ml * unit : nan;
-        dml += dM * S0 * unit;
-      } else {
-        if (out.m_bh) out.m_bh[m] = ok ? dM : nan;
+      if (j < J1)
+        for (int k = wave; k < K; k += 4) {
+          const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+          dM += I0 * rows[((int64_t)k * J1 + j) * 3 + 2];
+        }
+      __syncthreads();
+      mpart[wave][lane] = dM;
+      __syncthreads();
+      if (wave == 0 && j < J1) {
+        dM = ((mpart[0][lane] + mpart[1][lane]) + mpart[2][lane]) + mpart[3][lane];
+        if (j < J) {
+          const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+          const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+          const double unit = 2.0 * kPi * (sp * sj) * (sp * sj) * qo;   // dM/d(ml S0)
+          if (out.mass_S0) out.mass_S0[md.mass_off + j] = ok ? dM * ml * unit : nan;
+          dml += dM * S0 * unit;
+        } else {
+          if (out.m_bh) out.m_bh[m] = ok ? dM : nan;
+        }
       }
     }
-    di = wave_sum(di);
-    dml = wave_sum(dml);
+    if (wave == 0) dml = wave_sum(dml);
+    if (lane == 0) part[wave][0] = di;
+    __syncthreads();
     if (threadIdx.x == 0) {
-      if (out.inc) out.inc[m] = ok ? di : nan;
+      const double dsum = ((part[0][0] + part[1][0]) + part[2][0]) + part[3][0];
+      if (out.inc) out.inc[m] = ok ? dsum : nan;
       if (out.mass_scale) out.mass_scale[m] = ok ? dml : nan;
     }
+    __syncthreads();
   }
 }
 
@@ -1113,7 +1196,7 @@ void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it
 void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const double *pix, const int *st_ws, double *vrms2, double *binws,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_bins, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, pix, st_ws,
+  hipLaunchKernelGGL(k_bins, dim3(grid_of(n_it)), dim3(1024), 0, st, g, m, it, n_it, pix, st_ws,
                      vrms2, binws);
 }
 void launch_maps(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
@@ -1151,7 +1234,7 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 }
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st) {
-  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(64), 0, st, g, m, n, p, sens, st_ws, out);
+  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
 }
 
 }  // namespace jam
