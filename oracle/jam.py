@@ -355,3 +355,29 @@ def point_values(geom, params, x, y):
     pt = _param_tensors(geom, params)
     coeffs = term_coefficients(geom, pt)
     return numerator(coeffs, x, y), surface_brightness(geom, pt["lum_I0"], x, y)
+
+
+# ---------------------------------------------------------------------------
+# Goodness of fit of the dynamical model, eq. (chi2_dyn).
+# ---------------------------------------------------------------------------
+
+def chi2_dyn(V, vrms_obs, cov):
+    """chi^2 = (v_obs - v_pre)^T Sigma_kin^-1 (v_obs - v_pre), eq. (chi2_dyn),
+    with the predicted v_rms = sqrt of the binned second moment, eq. (Vrms).
+    ``cov`` is the covariance of the measured v_rms [(km/s)^2]; the product
+    with its inverse is a linear solve."""
+    V = torch.as_tensor(V, dtype=DT)
+    r = _t(vrms_obs) - torch.sqrt(V)
+    return torch.dot(r, torch.linalg.solve(_t(cov), r))
+
+
+def chi2_and_grad(geom, params, vrms_obs, cov):
+    """chi^2 of one model (eq. chi2_dyn on eq. Vrms of the binned moments) and
+    its gradient with respect to the parameters of ``GRAD_KEYS`` (exact
+    autograd of the FP64 arithmetic)."""
+    pt0 = _param_tensors(geom, params)
+    leaves = {k: pt0[k].detach().clone().requires_grad_(True) for k in GRAD_KEYS}
+    V = vrms2(geom, params, overrides=leaves)
+    c2 = chi2_dyn(V, vrms_obs, cov)
+    grads = torch.autograd.grad(c2, [leaves[k] for k in GRAD_KEYS])
+    return float(c2.detach()), {k: g.detach() for k, g in zip(GRAD_KEYS, grads)}

@@ -268,6 +268,25 @@ def cotangent(n_bins: int, n_models: int, seed: int = 0) -> np.ndarray:
     return _rng(5, seed).standard_normal((n_models, n_bins))
 
 
+# Synthetic kinematic data for the goodness of fit of eq. (chi2_dyn); the
+# measured v_rms of the paper's lens and their covariance are not available.
+VRMS_OBS_RANGE = (200.0, 400.0)    # km/s, uniform per bin
+VRMS_REL_ERR = (0.04, 0.06)        # 1-sigma error per bin, relative, uniform
+VRMS_SYS_REL = 0.02                # error common to all bins, relative
+
+
+def kinematic_data(n_bins: int, seed: int = 0):
+    """Observed v_rms per bin [km/s] and the covariance of their errors
+    [(km/s)^2]: independent per-bin errors of 4-6 % plus a 2 % error shared
+    by all bins, cov = diag(e_b^2) + 0.02^2 v v^T (symmetric positive
+    definite)."""
+    rng = _rng(11, seed)
+    v = rng.uniform(*VRMS_OBS_RANGE, n_bins)
+    e = rng.uniform(*VRMS_REL_ERR, n_bins) * v
+    cov = np.diag(e ** 2) + VRMS_SYS_REL ** 2 * np.outer(v, v)
+    return v, cov
+
+
 def with_overrides(p: Params, **kw) -> Params:
     return replace(p, **kw)
 

@@ -15,7 +15,7 @@ import math
 import numpy as np
 import pytest
 import torch
-from scipy import integrate, signal, special
+from scipy import integrate, linalg, signal, special
 
 from oracle import jam
 from paper_2504_01302_amd import inputs
@@ -450,3 +450,70 @@ def test_gradient_central_differences():
         gv = grads[key] if idx is None else grads[key][idx]
         ref, noise = fd(setter, x0)
         assert abs(float(gv) - ref) <= 1e-7 * abs(ref) + noise, (key, idx, float(gv), ref)
+
+
+# --------------------------------------------------------------------------
+# Goodness of fit, eq. (chi2_dyn) on eq. (Vrms).
+# --------------------------------------------------------------------------
+
+def test_chi2_worked_examples():
+    # uncorrelated: r = (3 - 2, 5 - 3) = (1, 2); chi^2 = 1/1 + 4/4 = 2
+    assert float(jam.chi2_dyn([4.0, 9.0], [3.0, 5.0], np.diag([1.0, 4.0]))) == pytest.approx(2.0, rel=1e-15)
+    # correlated: cov = [[2, 1], [1, 2]], cov^-1 = [[2, -1], [-1, 2]] / 3, r = (1, 1): 2/3
+    cov = np.array([[2.0, 1.0], [1.0, 2.0]])
+    assert float(jam.chi2_dyn([1.0, 1.0], [2.0, 2.0], cov)) == pytest.approx(2.0 / 3.0, rel=1e-15)
+    # correlated, r = (1, -1): (2 + 1 + 1 + 2) / 3 = 2
+    assert float(jam.chi2_dyn([1.0, 9.0], [2.0, 2.0], cov)) == pytest.approx(2.0, rel=1e-15)
+    # a perfect fit
+    assert float(jam.chi2_dyn([4.0, 9.0], [2.0, 3.0], cov)) == 0.0
+
+
+def test_chi2_whitened_and_scaled():
+    """chi^2 = |L^-1 r|^2 for cov = L L^T (a triangular solve instead of the
+    general solve), and cov -> c cov scales chi^2 by 1/c."""
+    rng = np.random.default_rng(4)
+    n = 17
+    A = rng.standard_normal((n, n))
+    cov = A @ A.T + n * np.eye(n)
+    V = rng.uniform(1e4, 1.5e5, n)
+    v = rng.uniform(150.0, 400.0, n)
+    r = v - np.sqrt(V)
+    L = np.linalg.cholesky(cov)
+    z = linalg.solve_triangular(L, r, lower=True)
+    c2 = float(jam.chi2_dyn(V, v, cov))
+    assert c2 == pytest.approx(float(z @ z), rel=1e-12)
+    assert float(jam.chi2_dyn(V, v, 3.0 * cov)) == pytest.approx(c2 / 3.0, rel=1e-12)
+    # the synthetic covariance recipe is symmetric positive definite
+    vo, cv = inputs.kinematic_data(60, seed=3)
+    assert np.array_equal(cv, cv.T) and np.linalg.eigvalsh(cv).min() > 0
+    assert vo.shape == (60,) and np.all((vo >= 200.0) & (vo <= 400.0))
+
+
+def test_chi2_gradient_central_differences():
+    g = inputs.small_geometry(seed=13, n_lum=2, n_mass=2, nx=6, ny=5, psf_n=3, n_bins=3)
+    p = inputs.small_params(g, seed=13)
+    V0 = jam.vrms2(g, p).numpy()
+    # observed values near the model, so chi^2 depends on the fit, not the offset
+    rng = np.random.default_rng(8)
+    vo = np.sqrt(V0) * (1.0 + 0.05 * rng.standard_normal(g.n_bins))
+    cov = np.diag((0.05 * vo) ** 2) + 0.02 ** 2 * np.outer(vo, vo)
+    c2, grads = jam.chi2_and_grad(g, p, vo, cov)
+    assert c2 == pytest.approx(float(jam.chi2_dyn(V0, vo, cov)), rel=1e-14)
+
+    def C(pp):
+        return float(jam.chi2_dyn(jam.vrms2(g, pp), vo, cov))
+
+    def fd(setter, x0):
+        h = 1e-3 * max(abs(x0), 1.0)
+        d1 = (C(setter(x0 + h)) - C(setter(x0 - h))) / (2 * h)
+        d2 = (C(setter(x0 + h / 2)) - C(setter(x0 - h / 2))) / h
+        return (4 * d2 - d1) / 3, 1e-13 * max(c2, 1.0) / h
+
+    b1 = lambda v: inputs.with_overrides(p, beta=np.r_[v, p.beta[1:]])
+    checks = [("inc", None, lambda v: inputs.with_overrides(p, inc=v), p.inc),
+              ("mass_scale", None, lambda v: inputs.with_overrides(p, mass_scale=v), p.mass_scale),
+              ("beta", 0, b1, p.beta[0])]
+    for key, idx, setter, x0 in checks:
+        gv = float(grads[key] if idx is None else grads[key][idx])
+        ref, noise = fd(setter, x0)
+        assert abs(gv - ref) <= 1e-7 * abs(ref) + noise, (key, gv, ref)
