@@ -137,6 +137,54 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph):
             "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok}
 
 
+def time_chi2(torch, binding, w, dev, steps, form, launch, graph):
+    """chi^2 per proposal (eq. chi2_dyn) fused after the forward, and its
+    adjoint, for a whole batch per launch (one scalar and one gradient per
+    proposal for a gradient sampler)."""
+    from paper_2504_01302_amd import inputs
+    ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph)
+    for gi, g in enumerate(w.geometries):
+        ctx.set_kinematics(gi, *inputs.kinematic_data(g.n_bins, seed=gi))
+    par = binding.pack_params(w, dev, amplitudes=True)
+    n = len(w.geom_idx)
+    cot = torch.ones(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    args = (w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"], par["lum_I0"],
+            par["mass_S0"])
+
+    state = {}
+
+    def fwd():
+        state["out"] = ctx.eval_chi2(*args, keep_vrms2=True)
+        return state["out"]
+
+    def bwd():
+        ctx.vjp_chi2(*args, cot, vrms2=state["out"][1])
+
+    c2, _, st = fwd()
+    bwd()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
+        fwd()
+        bwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / steps
+    ok = bool((st == 0).all().item()) and bool(torch.isfinite(c2).all().item())
+    ctx.close()
+    return {"models": n, "ms_chi2": ms_f, "chi2_per_s": n * 1000.0 / ms_f,
+            "ms_chi2_and_grad": ms_fb, "chi2_and_grad_per_s": n * 1000.0 / ms_fb,
+            "all_finite": ok}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -288,6 +336,8 @@ def main():
                                              max(3, a.steps // 4), a.form, a.launch, a.graph),
             "uneven_1024": time_batch(torch, binding, inputs.config4(1024), dev, 2, a.form,
                                       a.launch, a.graph),
+            "chi2_4096_small": time_chi2(torch, binding, inputs.config3(4096), dev,
+                                         max(3, a.steps // 4), a.form, a.launch, a.graph),
         }
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB

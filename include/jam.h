@@ -192,6 +192,44 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
                    const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
                    void *stream);
 
+/* Observed kinematics of geometry `geom` for the goodness of fit of eq.
+ * (chi2_dyn): vrms_obs (HOST, n_bins doubles, km/s) and the covariance of
+ * their measurement errors, cov (HOST, n_bins x n_bins doubles, row-major,
+ * (km/s)^2, symmetric positive definite).  The library factors cov (FP64
+ * Cholesky), keeps vrms_obs and cov^-1 on the device and owns them until
+ * jam_destroy or the next call for the same geometry.  A set-up call: it
+ * allocates and waits for the device, so it must not overlap evaluations.
+ * JAM_E_INVALID_ARG for a bad index, NULL arrays, non-finite values, an
+ * asymmetric or non-positive-definite cov; JAM_E_UNSUPPORTED above 4096
+ * bins.                                                                      */
+jam_status jam_set_kinematics(jam_ctx *ctx, int32_t geom, const double *vrms_obs,
+                              const double *cov);
+
+/* chi^2 of eq. (chi2_dyn) per model from v_rms^2 per bin (eq. (Vrms)):
+ * chi2_m = r^T cov^-1 r with r_b = vrms_obs_b - sqrt(vrms2_b), in FP64.
+ * vrms2: DEVICE, packed as jam_eval_batch writes it; chi2: DEVICE double[n];
+ * dchi2 (DEVICE, packed like vrms2, may be NULL) receives d chi2_m / d
+ * vrms2_b = -(cov^-1 r)_b / sqrt(vrms2_b).  A model with any vrms2_b <= 0 or
+ * NaN gets NaN in chi2 and dchi2.  Every model's geometry needs kinematics
+ * (jam_set_kinematics), else JAM_E_INVALID_ARG before any launch.           */
+jam_status jam_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
+                    double *chi2, double *dchi2, void *stream);
+
+/* Forward model and chi^2 in one call: chi2 (DEVICE double[n]); vrms2
+ * (DEVICE, packed, may be NULL to keep it in the workspace) and status as in
+ * jam_eval_batch.  ws_bytes >= jam_workspace_size(..., 0).                  */
+jam_status jam_eval_chi2(jam_ctx *ctx, const jam_batch *batch, double *chi2, double *vrms2,
+                         int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of the chi^2: gradients of sum_m cot_m chi2_m (cot: DEVICE
+ * double[n]) with respect to the parameters of jam_vjp.  vrms2 is the
+ * forward output for the same batch (DEVICE, packed), or NULL to have the
+ * forward recomputed; d chi2 / d vrms2 is formed in the workspace and fed to
+ * the adjoint of jam_vjp.  ws_bytes >= jam_workspace_size(..., 1).          */
+jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
+                        const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
+                        void *stream);
+
 /* Kernel timing, for measurement.  enable = 1 clears the record and starts
  * bracketing every launch of the quadrature (numerator) kernel and of the
  * adjoint sensitivity kernel with HIP events on the caller's stream;
@@ -203,8 +241,9 @@ jam_status jam_timing(jam_ctx *ctx, int32_t enable, double *numerator_ms,
 
 /* Schedule chosen for a batch composition (prepares it if needed):
  * info[0..7] = numerator rule (0 per-pixel, 1 MFMA), 64x64-tile threshold,
- * term granularity per item, launch mode, numerator work items, numerator
- * workgroups launched, adjoint work items, adjoint workgroups launched.     */
+ * slice length per item ((k, j) pairs, or units of 64 terms), launch mode,
+ * numerator work items, numerator workgroups launched, adjoint work items,
+ * adjoint workgroups launched.                                               */
 jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t *info);
 
 /* Host utility: the n-node Gauss-Legendre rule on [0, 1] that the library

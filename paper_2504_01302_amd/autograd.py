@@ -1,5 +1,6 @@
-"""torch.autograd.Function over the library: forward = jam_eval_batch,
-backward = jam_vjp.
+"""torch.autograd.Functions over the library: forward = jam_eval_batch,
+backward = jam_vjp; and the chi^2 of eq. (chi2_dyn), forward =
+jam_eval_chi2, backward = jam_vjp_chi2.
 
 Only the per-bin output v_rms^2 is saved for the backward pass (a few
 doubles per model); every other forward intermediate is recomputed inside
@@ -43,3 +44,36 @@ def jam_vrms2(jctx: binding.Context, geom_idx, inc, mass_scale, m_bh, beta,
               lum_I0=None, mass_S0=None):
     """Differentiable v_rms^2 per bin (packed) and the per-model status."""
     return JamVrms2.apply(jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+
+
+class JamChi2(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0):
+        c2, V, st = jctx.eval_chi2(geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
+                                   keep_vrms2=True)
+        ctx.jctx = jctx
+        ctx.geom_idx = geom_idx
+        ctx.has_amp = (lum_I0 is not None, mass_S0 is not None)
+        ctx.save_for_backward(inc, mass_scale, m_bh, beta,
+                              lum_I0 if lum_I0 is not None else inc.new_empty(0),
+                              mass_S0 if mass_S0 is not None else inc.new_empty(0), V)
+        ctx.mark_non_differentiable(st)
+        return c2, st
+
+    @staticmethod
+    def backward(ctx, gc, _gst):
+        inc, ml, mbh, beta, I0, S0, V = ctx.saved_tensors
+        I0 = I0 if ctx.has_amp[0] else None
+        S0 = S0 if ctx.has_amp[1] else None
+        g = ctx.jctx.vjp_chi2(ctx.geom_idx, inc, ml, mbh, beta, I0, S0,
+                              gc.contiguous().to(torch.float64), vrms2=V)
+        return (None, None, g["inc"], g["mass_scale"], g["m_bh"], g["beta"],
+                g["lum_I0"] if ctx.has_amp[0] else None,
+                g["mass_S0"] if ctx.has_amp[1] else None)
+
+
+def jam_chi2(jctx: binding.Context, geom_idx, inc, mass_scale, m_bh, beta,
+             lum_I0=None, mass_S0=None):
+    """Differentiable chi^2 per model (eq. chi2_dyn; kinematics set on the
+    context with ``set_kinematics``) and the per-model status."""
+    return JamChi2.apply(jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)

@@ -32,7 +32,8 @@ STATUS_NAMES = {0: "JAM_OK", 1: "JAM_E_INVALID_ARG", 2: "JAM_E_DEPROJECTION",
 
 EXPORTED = ("jam_create", "jam_destroy", "jam_batch_sizes", "jam_workspace_size",
             "jam_prepare", "jam_eval_batch", "jam_eval", "jam_eval_maps", "jam_vjp",
-            "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error")
+            "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error",
+            "jam_set_kinematics", "jam_chi2", "jam_eval_chi2", "jam_vjp_chi2")
 
 
 class JamGeometry(ctypes.Structure):
@@ -99,6 +100,13 @@ def load(path: str = LIB_PATH):
     lib.jam_timing.argtypes = [c_void_p, c_int32, ctypes.POINTER(c_double), ctypes.POINTER(c_int64),
                                ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]
     lib.jam_plan_info.argtypes = [c_void_p, c_int32, P_int32, P_int32]
+    lib.jam_set_kinematics.argtypes = [c_void_p, c_int32, P_double, P_double]
+    lib.jam_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p, c_void_p,
+                             c_void_p]
+    lib.jam_eval_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.jam_vjp_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
+                                 ctypes.POINTER(JamGrads), c_void_p, c_size_t, c_void_p]
     lib.jam_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         f = getattr(lib, name)
@@ -240,6 +248,42 @@ def jam_vjp(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, vrms2, 
                           c_void_p(stream)))
 
 
+def jam_set_kinematics(ctx: int, geom: int, vrms_obs, cov):
+    v = np.ascontiguousarray(vrms_obs, dtype=np.float64)
+    c = np.ascontiguousarray(cov, dtype=np.float64)
+    if c.size != v.size * v.size:
+        raise ValueError("cov must be n_bins x n_bins")
+    _check(load().jam_set_kinematics(c_void_p(ctx), int(geom), v.ctypes.data_as(P_double),
+                                      c.ctypes.data_as(P_double)))
+
+
+def jam_chi2(ctx, geom_idx, vrms2, chi2, dchi2, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, None, None, None, None, None, None)
+    _check(load().jam_chi2(c_void_p(ctx), ctypes.byref(b), _ptr(vrms2), _ptr(chi2), _ptr(dchi2),
+                           c_void_p(stream)))
+
+
+def jam_eval_chi2(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
+                  chi2, vrms2, status, ws, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+    _check(load().jam_eval_chi2(c_void_p(ctx), ctypes.byref(b), _ptr(chi2), _ptr(vrms2),
+                                _ptr(status), _ptr(ws), ws.numel() * ws.element_size(),
+                                c_void_p(stream)))
+
+
+def jam_vjp_chi2(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, vrms2, cot,
+                 g_inc, g_mass_scale, g_m_bh, g_beta, g_lum_I0, g_mass_S0, ws, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+    gr = JamGrads(_ptr(g_inc), _ptr(g_mass_scale), _ptr(g_m_bh), _ptr(g_beta),
+                  _ptr(g_lum_I0), _ptr(g_mass_S0))
+    _check(load().jam_vjp_chi2(c_void_p(ctx), ctypes.byref(b), _ptr(vrms2), _ptr(cot),
+                               ctypes.byref(gr), _ptr(ws), ws.numel() * ws.element_size(),
+                               c_void_p(stream)))
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper for torch device tensors.
 # ---------------------------------------------------------------------------
@@ -328,6 +372,49 @@ class Context:
         s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
         jam_vjp(self.handle, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, vrms2, cot,
                 g["inc"], g["mass_scale"], g["m_bh"], g["beta"], g["lum_I0"], g["mass_S0"], ws, s)
+        return g
+
+
+    def set_kinematics(self, geom: int, vrms_obs, cov):
+        jam_set_kinematics(self.handle, geom, vrms_obs, cov)
+
+    def chi2(self, geom_idx, vrms2, want_grad: bool = False, stream=None):
+        """chi^2 per model from packed v_rms^2 (and d chi^2 / d v_rms^2)."""
+        import torch
+        dev = vrms2.device
+        c = torch.empty(len(geom_idx), dtype=torch.float64, device=dev)
+        d = torch.empty_like(vrms2) if want_grad else None
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        jam_chi2(self.handle, geom_idx, vrms2, c, d, s)
+        return c, d
+
+    def eval_chi2(self, geom_idx, inc, mass_scale, m_bh, beta, lum_I0=None, mass_S0=None,
+                  stream=None, keep_vrms2: bool = False):
+        import torch
+        dev = inc.device
+        nb, _, _ = self.sizes(geom_idx)
+        c = torch.empty(len(geom_idx), dtype=torch.float64, device=dev)
+        vr = torch.empty(nb, dtype=torch.float64, device=dev) if keep_vrms2 else None
+        st = torch.empty(len(geom_idx), dtype=torch.int32, device=dev)
+        ws = self.workspace(geom_idx, False, dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        jam_eval_chi2(self.handle, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
+                      c, vr, st, ws, s)
+        return c, vr, st
+
+    def vjp_chi2(self, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, cot,
+                 vrms2=None, stream=None):
+        import torch
+        dev = inc.device
+        n = len(geom_idx)
+        _, nl, nm = self.sizes(geom_idx)
+        z = lambda k: torch.empty(k, dtype=torch.float64, device=dev)
+        g = dict(inc=z(n), mass_scale=z(n), m_bh=z(n), beta=z(nl), lum_I0=z(nl), mass_S0=z(nm))
+        ws = self.workspace(geom_idx, True, dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+        jam_vjp_chi2(self.handle, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
+                     vrms2, cot, g["inc"], g["mass_scale"], g["m_bh"], g["beta"], g["lum_I0"],
+                     g["mass_S0"], ws, s)
         return g
 
 

@@ -15,7 +15,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <list>
+#include <queue>
 #include <memory>
 #include <string>
 #include <thread>
@@ -242,8 +244,8 @@ struct Tune {
   int rule = 1;     // 0 per-pixel VALU everywhere; 1 matrix cores (64x64 tiles when both
                     // map sides >= tau, else 32x32 tiles)
   int tau = 1 << 30;
-  int gran = 0;     // term chunks (32 terms) per MFMA item, or (k, j) pairs per per-pixel
-                    // item; 0 = derived from the batch
+  int gran = 0;     // slice length: units of 64 terms per MFMA item, or (k, j) pairs per
+                    // per-pixel item; 0 = derived from the batch
   int launch = 0;   // 0 persistent grid pulling items from a device queue; 1 one
                     // workgroup per item
 };
@@ -275,10 +277,11 @@ struct Plan {
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
-         off_bins = 0, off_sens = 0, off_vtmp = 0, ws_fwd = 0, ws_vjp = 0;
-  // captured evaluations (forward, adjoint)
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  GraphKey gkey[2];
+         off_bins = 0, off_vfwd = 0, off_sens = 0, off_vtmp = 0, off_cot = 0, ws_fwd = 0,
+         ws_vjp = 0;
+  // captured evaluations (forward, adjoint, forward + chi^2, adjoint of chi^2)
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  GraphKey gkey[4];
   ~Plan() {
     for (auto &g : gexec)
       if (g) (void)hipGraphExecDestroy(g);
@@ -320,11 +323,19 @@ struct jam_ctx {
   std::list<std::unique_ptr<Plan>> plans;   // most recent first
   KernelTimer t_num, t_sens;
   hipStream_t cap_stream = nullptr;         // graph capture only
+  // observed kinematics per geometry (chi^2): one device buffer each holding
+  // [vrms_obs | inverse covariance], and the device table of pointers
+  std::vector<void *> kin_buf;
+  std::vector<jam::KinDev> kin_host;
+  jam::KinDev *d_kin = nullptr;
   ~jam_ctx() {
     plans.clear();
     t_num.destroy();
     t_sens.destroy();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (void *b : kin_buf)
+      if (b) (void)hipFree(b);
+    if (d_kin) (void)hipFree(d_kin);
     if (arena) (void)hipFree(arena);
   }
 };
@@ -334,56 +345,122 @@ namespace {
 constexpr size_t kMaxPlans = 8;
 
 // Numerator variant and term-range split of one model under a schedule.
+// `gran` is the slice length in units: (k, j) pairs for the per-pixel
+// variant, 64 terms for the MFMA variants (the 64x64 variant slices in
+// 32-term chunks, two per unit).
 struct NumChoice {
   int kind;      // 0 per-pixel VALU, 1 MFMA 64x64 tiles, 2 MFMA 32x32 tiles
   int n_slices;
   int tiles;     // work units along the map (pixel blocks or tiles)
+  int units;     // slice units of the whole term range
 };
 
 NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
   if (t.rule == 0) {
     const int pairs = g.K * g.J1;
     const int per = std::max(1, gran);
-    return {0, std::max(1, (pairs + per - 1) / per), (g.n_pix + 63) / 64};
+    return {0, std::max(1, (pairs + per - 1) / per), (g.n_pix + 63) / 64, pairs};
   }
-  const int chunks = (g.T + 31) / 32;
   const bool big = g.n_ux >= t.tau && g.n_uy >= t.tau;
   const int tw = big ? 64 : 32;
-  const int per = std::max(big ? 4 : 8, gran);
-  return {big ? 1 : 2, std::max(1, (chunks + per - 1) / per),
-          ((g.n_ux + tw - 1) / tw) * ((g.n_uy + tw - 1) / tw)};
-}
-
-// Granularity giving about four work items per compute unit for the batch.
-int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
-  double work = 0.0;
-  for (int m = 0; m < n; ++m) {
-    const GeomHost &g = ctx->gh[geom_idx[m]];
-    Tune one = t;
-    one.gran = 1;
-    const NumChoice c = choose_numerator(g, one, 1);
-    if (t.rule == 0)
-      work += (double)c.tiles * g.K * g.J1;
-    else
-      work += (double)c.tiles * ((g.T + 31) / 32);
+  const int tiles = ((g.n_ux + tw - 1) / tw) * ((g.n_uy + tw - 1) / tw);
+  if (big) {
+    const int chunks = (g.T + 31) / 32;
+    const int per = std::max(8, 2 * gran);
+    return {1, std::max(1, (chunks + per - 1) / per), tiles, (g.T + 63) / 64};
   }
-  const double target = 4.0 * ctx->n_cu;
-  const double gr = std::ceil(work / target);
-  return (int)std::min(4096.0, std::max(1.0, gr));
+  const int chunks = (g.T + 63) / 64;
+  const int per = std::max(4, gran);
+  return {2, std::max(1, (chunks + per - 1) / per), tiles, chunks};
 }
 
-// Relative cost of one numerator item, for largest-first ordering.
+// Relative cost of one numerator item, for largest-first ordering and the
+// schedule model: the kernels' chunk loop plus a fixed per-item cost (the
+// partial-tile store and its reduction).
 double num_item_cost(const GeomHost &g, const NumChoice &c, int slice) {
   if (c.kind == 0) {
     const int pairs = g.K * g.J1;
     const int per = (pairs + c.n_slices - 1) / c.n_slices;
     const int cnt = std::max(0, std::min(pairs, (slice + 1) * per) - slice * per);
-    return cnt * (double)g.n_u * 64.0 * 5.0 / 32768.0;
+    return cnt * (double)g.n_u * 64.0 * 5.0 / 32768.0 + 1.0;
   }
-  const int chunks = (g.T + 31) / 32;
+  const int unit = c.kind == 1 ? 32 : 64;
+  const int chunks = (g.T + unit - 1) / unit;
   const int per = (chunks + c.n_slices - 1) / c.n_slices;
   const int cnt = std::max(0, std::min(chunks, (slice + 1) * per) - slice * per);
-  return cnt * (c.kind == 1 ? 4.0 : 1.5);
+  return cnt * (c.kind == 1 ? 4.0 : 3.0) + 3.0;
+}
+
+// Completion time of the numerator launch as modelled: every resident
+// workgroup pulls the next item, largest first, from the queue, i.e. list
+// scheduling in cost order on `slots` identical workers.
+double list_schedule_makespan(std::vector<double> &cost, int slots) {
+  std::sort(cost.begin(), cost.end(), std::greater<double>());
+  if (cost.empty()) return 0.0;
+  if ((int)cost.size() <= slots) return cost[0];
+  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+  for (int i = 0; i < slots; ++i) q.push(0.0);
+  double mk = 0.0;
+  for (double c : cost) {
+    const double t = q.top() + c;
+    q.pop();
+    mk = std::max(mk, t);
+    q.push(t);
+  }
+  return mk;
+}
+
+// Default slice length: the one whose item list the resident workgroups
+// finish first under the list-scheduling model.  Candidates are geometric
+// around one item per resident workgroup, plus the exact splits of the
+// largest model, so a uniform item list can fill whole rounds of workgroups.
+int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
+  const int slots = std::max(1, ctx->n_cu * ctx->occ_num);
+  double work = 0.0, big_work = -1.0;
+  int big_units = 1, big_tiles = 1;
+  std::vector<NumChoice> whole(n);
+  for (int m = 0; m < n; ++m) {
+    const GeomHost &g = ctx->gh[geom_idx[m]];
+    whole[m] = choose_numerator(g, t, 1 << 29);
+    const double w = (double)whole[m].tiles * whole[m].units;
+    work += w;
+    if (w > big_work) {
+      big_work = w;
+      big_units = whole[m].units;
+      big_tiles = whole[m].tiles;
+    }
+  }
+  const double g0 = std::max(1.0, std::ceil(work / slots));
+  std::vector<int> cands;
+  for (int k = -8; k <= 16; ++k)
+    cands.push_back((int)std::min(1.0e9, std::max(1.0, std::round(g0 * std::pow(2.0, k / 8.0)))));
+  if (big_work >= 0.25 * work) {
+    const int s_max = std::min(4096, 4 * slots / std::max(1, big_tiles) + 1);
+    for (int sl = 1; sl <= s_max; ++sl) cands.push_back((big_units + sl - 1) / sl);
+  }
+  std::sort(cands.begin(), cands.end());
+  cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+  double best = 1e300;
+  int best_g = (int)g0;
+  std::vector<double> cost;
+  for (int gr : cands) {
+    cost.clear();
+    for (int m = 0; m < n; ++m) {
+      const GeomHost &g = ctx->gh[geom_idx[m]];
+      const NumChoice c = choose_numerator(g, t, gr);
+      for (int sl = 0; sl < c.n_slices; ++sl) {
+        const double ci = num_item_cost(g, c, sl);
+        for (int tl = 0; tl < c.tiles; ++tl) cost.push_back(ci);
+      }
+    }
+    if (cost.size() > (size_t)64 * slots + (size_t)4 * n) continue;   // far too fine
+    const double mk = list_schedule_makespan(cost, slots);
+    if (mk < best * (1.0 - 1e-9) || (mk <= best * (1.0 + 1e-9) && gr > best_g)) {
+      best = mk;
+      best_g = gr;
+    }
+  }
+  return std::min(1 << 29, std::max(1, best_g));
 }
 
 void sort_by_cost(std::vector<jam::Item> &items, std::vector<double> &cost) {
@@ -520,9 +597,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_pix = w;    w = align256(w + sizeof(double) * pixd);
   p->off_part = w;   w = align256(w + sizeof(double) * part);
   p->off_bins = w;   w = align256(w + sizeof(double) * bins);
+  p->off_vfwd = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->ws_fwd = w;
   p->off_sens = w;   w = align256(w + sizeof(double) * sens);
   p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
+  p->off_cot = w;    w = align256(w + sizeof(double) * p->total_bins);
   p->ws_vjp = w;
   out = std::move(p);
   return JAM_OK;
@@ -561,8 +640,12 @@ void launch_eval(jam_ctx *ctx, Plan *p, const jam_batch *b, double *vrms2, int32
                    (const int *)(w + p->off_status), vrms2, (double *)(w + p->off_bins), st);
 }
 
+// Adjoint of sum_b cot_b V_b; with chi2_cot != NULL the cotangent is instead
+// chi2_cot[m] * d chi^2_m / dV_b, formed in the workspace from V (given or
+// recomputed).
 void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, const double *cot,
-                const jam_grads *grads, char *w, hipStream_t st, bool capturing) {
+                const jam_grads *grads, char *w, hipStream_t st, bool capturing,
+                const double *chi2_cot = nullptr) {
   const int *st_ws = (const int *)(w + p->off_status);
   int *queue = (int *)(w + p->off_queue);
   double *pix = (double *)(w + p->off_pix);
@@ -579,6 +662,12 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     V = vtmp;
   } else {
     jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, nullptr, binws, st);
+  }
+  if (chi2_cot) {
+    double *c = (double *)(w + p->off_cot);
+    jam::launch_chi2(ctx->d_geoms, p->d_models, p->n, ctx->d_kin, V, st_ws, nullptr, chi2_cot, c,
+                     st);
+    cot = c;
   }
   jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
   const bool timed = ctx->t_sens.begin(st, capturing);
@@ -613,7 +702,7 @@ std::string tune_key(const jam_ctx *ctx, int n, const int32_t *geom_idx) {
     mix((uint64_t)g.n_ux | ((uint64_t)g.n_uy << 20) | ((uint64_t)g.T << 40));
   }
   char buf[128];
-  snprintf(buf, sizeof buf, "gfx950/v1/n%d/%016llx", n, (unsigned long long)h);
+  snprintf(buf, sizeof buf, "gfx950/v2/n%d/%016llx", n, (unsigned long long)h);
   return buf;
 }
 
@@ -823,6 +912,52 @@ jam_status run_graph(jam_ctx *ctx, Plan *p, int which, const GraphKey &key, hipS
   return JAM_OK;
 }
 
+// Inverse of a symmetric positive definite n x n matrix (row-major) by its
+// Cholesky factor C = L L^T: L^-1 by forward substitution, then
+// C^-1 = L^-T L^-1, written symmetric.  False if C is not positive definite.
+bool spd_inverse(int n, const double *c, std::vector<double> &inv) {
+  std::vector<long double> L((size_t)n * n, 0.0L), Li((size_t)n * n, 0.0L);
+  for (int j = 0; j < n; ++j) {
+    long double d = c[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0L)) return false;
+    const long double ljj = std::sqrt(d);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      long double v = c[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / ljj;
+    }
+  }
+  for (int j = 0; j < n; ++j) {          // column j of L^-1
+    Li[(size_t)j * n + j] = 1.0L / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      long double v = 0.0L;
+      for (int k = j; k < i; ++k) v += L[(size_t)i * n + k] * Li[(size_t)k * n + j];
+      Li[(size_t)i * n + j] = -v / L[(size_t)i * n + i];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      long double v = 0.0L;
+      for (int k = j; k < n; ++k) v += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+      inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = (double)v;
+    }
+  return true;
+}
+
+jam_status check_kinematics(const jam_ctx *ctx, const jam_batch *b) {
+  for (int m = 0; m < b->n; ++m) {
+    const int gi = b->geom_idx[m];
+    if (gi < 0 || gi >= (int)ctx->kin_host.size())
+      return fail(JAM_E_INVALID_ARG, "geom_idx[%d] out of range", m);
+    if (!ctx->kin_host[gi].prec)
+      return fail(JAM_E_INVALID_ARG, "no kinematics set for geometry %d (model %d)", gi, m);
+  }
+  return JAM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -965,6 +1100,11 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
   std::memcpy(stage.data(), gd.data(), sizeof(jam::GeomDev) * n_geom);
   HIP_TRY(hipMemcpy(ctx->arena, stage.data(), off, hipMemcpyHostToDevice));
   ctx->d_geoms = (jam::GeomDev *)ctx->arena;
+  ctx->kin_buf.assign(n_geom, nullptr);
+  ctx->kin_host.assign(n_geom, jam::KinDev{nullptr, nullptr});
+  HIP_TRY(hipMalloc(&ctx->d_kin, sizeof(jam::KinDev) * n_geom));
+  HIP_TRY(hipMemcpy(ctx->d_kin, ctx->kin_host.data(), sizeof(jam::KinDev) * n_geom,
+                    hipMemcpyHostToDevice));
   *out = ctx.release();
   return JAM_OK;
 }
@@ -1100,6 +1240,145 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, co
     if (s != JAM_OK) return s;
   } else {
     launch_vjp(ctx, p, batch, vrms2, cot, grads, w, st, false);
+  }
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_set_kinematics(jam_ctx *ctx, int32_t geom, const double *vrms_obs,
+                              const double *cov) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  if (geom < 0 || geom >= (int)ctx->gh.size()) return fail(JAM_E_INVALID_ARG, "geometry %d out of range", geom);
+  if (!vrms_obs || !cov) return fail(JAM_E_INVALID_ARG, "vrms_obs and cov are required");
+  const int nb = ctx->gh[geom].n_bins;
+  if (nb > jam::kChi2MaxBins)
+    return fail(JAM_E_UNSUPPORTED, "chi^2 supports at most %d bins (geometry %d has %d)",
+                jam::kChi2MaxBins, geom, nb);
+  double cmax = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    if (!std::isfinite(vrms_obs[i])) return fail(JAM_E_INVALID_ARG, "vrms_obs[%d] is not finite", i);
+    for (int j = 0; j < nb; ++j) {
+      const double v = cov[(size_t)i * nb + j];
+      if (!std::isfinite(v)) return fail(JAM_E_INVALID_ARG, "cov[%d][%d] is not finite", i, j);
+      cmax = std::max(cmax, std::fabs(v));
+    }
+  }
+  for (int i = 0; i < nb; ++i)
+    for (int j = i + 1; j < nb; ++j)
+      if (std::fabs(cov[(size_t)i * nb + j] - cov[(size_t)j * nb + i]) > 1e-12 * cmax)
+        return fail(JAM_E_INVALID_ARG, "cov is not symmetric at (%d, %d)", i, j);
+  std::vector<double> host((size_t)nb + (size_t)nb * nb);
+  std::vector<double> inv;
+  if (!spd_inverse(nb, cov, inv)) return fail(JAM_E_INVALID_ARG, "cov is not positive definite");
+  std::copy(vrms_obs, vrms_obs + nb, host.begin());
+  std::copy(inv.begin(), inv.end(), host.begin() + nb);
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  HIP_TRY(hipDeviceSynchronize());      // no evaluation may still read the old buffer
+  void *buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, host.size() * sizeof(double)));
+  if (hipMemcpy(buf, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(buf);
+    return fail(JAM_E_DEVICE, "copy of the kinematics failed");
+  }
+  const jam::KinDev kd{(const double *)buf, (const double *)buf + nb};
+  if (hipMemcpy(ctx->d_kin + geom, &kd, sizeof kd, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(buf);
+    return fail(JAM_E_DEVICE, "copy of the kinematics table failed");
+  }
+  if (ctx->kin_buf[geom]) HIP_TRY(hipFree(ctx->kin_buf[geom]));
+  ctx->kin_buf[geom] = buf;
+  ctx->kin_host[geom] = kd;
+  return JAM_OK;
+}
+
+jam_status jam_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, double *chi2,
+                    double *dchi2, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  if (!batch || batch->n < 1 || !batch->geom_idx) return fail(JAM_E_INVALID_ARG, "invalid batch");
+  if (!vrms2 || !chi2) return fail(JAM_E_INVALID_ARG, "vrms2 and chi2 are required");
+  jam_status s = check_kinematics(ctx, batch);
+  if (s != JAM_OK) return s;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  jam::launch_chi2(ctx->d_geoms, p->d_models, p->n, ctx->d_kin, vrms2, nullptr, chi2, nullptr,
+                   dchi2, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_eval_chi2(jam_ctx *ctx, const jam_batch *batch, double *chi2, double *vrms2,
+                         int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!chi2) return fail(JAM_E_INVALID_ARG, "chi2 is NULL");
+  if ((s = check_kinematics(ctx, batch)) != JAM_OK) return s;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, p->ws_fwd)) != JAM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  double *V = vrms2 ? vrms2 : (double *)(w + p->off_vfwd);
+  auto record = [&](const jam_batch *b, hipStream_t cs, bool capturing) {
+    launch_eval(ctx, p, b, V, status, w, cs, capturing);
+    jam::launch_chi2(ctx->d_geoms, p->d_models, p->n, ctx->d_kin, V,
+                     (const int *)(w + p->off_status), chi2, nullptr, nullptr, cs);
+  };
+  if (ctx->opt.graph) {
+    GraphKey k;
+    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                            batch->mass_S0, V, status, ws, chi2};
+    std::copy(ptrs, ptrs + 10, k.p);
+    k.ws_bytes = ws_bytes;
+    const jam_batch b = *batch;
+    s = run_graph(ctx, p, 2, k, st, [&](hipStream_t cs) { record(&b, cs, true); });
+    if (s != JAM_OK) return s;
+  } else {
+    record(batch, st, false);
+  }
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
+                        const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
+                        void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!cot || !grads) return fail(JAM_E_INVALID_ARG, "cot and grads are required");
+  if ((s = check_kinematics(ctx, batch)) != JAM_OK) return s;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  if ((s = get_plan(ctx, batch->n, batch->geom_idx, p)) != JAM_OK) return s;
+  if ((s = check_ws(ws, ws_bytes, p->ws_vjp)) != JAM_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char *w = (char *)ws;
+  if (ctx->opt.graph) {
+    GraphKey k;
+    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta,
+                            batch->lum_I0, batch->mass_S0, vrms2, cot, ws, nullptr};
+    std::copy(ptrs, ptrs + 10, k.p);
+    k.ws_bytes = ws_bytes;
+    const void *gp[6] = {grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
+                         grads->mass_S0};
+    uintptr_t hsh = 0;
+    for (const void *q : gp) hsh = hsh * 1000003u ^ (uintptr_t)q;
+    k.p[9] = (const void *)hsh;
+    const jam_batch b = *batch;
+    const jam_grads g = *grads;
+    s = run_graph(ctx, p, 3, k, st, [&](hipStream_t cs) {
+      launch_vjp(ctx, p, &b, vrms2, nullptr, &g, w, cs, true, cot);
+    });
+    if (s != JAM_OK) return s;
+  } else {
+    launch_vjp(ctx, p, batch, vrms2, nullptr, grads, w, st, false, cot);
   }
   HIP_TRY(hipGetLastError());
   return JAM_OK;

@@ -54,6 +54,14 @@ struct ModelDev {
   int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
 };
 
+// Observed kinematics of one geometry for the chi^2 of eq. (chi2_dyn):
+// v_rms per bin and the inverse covariance of their errors (row-major,
+// n_bins x n_bins).  Both NULL until set.
+struct KinDev {
+  const double *vobs, *prec;
+};
+constexpr int kChi2MaxBins = 4096;
+
 // A unit of work of one kernel: model m and up to three kernel-specific
 // indices (pixel block, tile, slice, bin, ...).
 struct Item {
@@ -122,5 +130,9 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st);
+// chi^2 per model from V (packed per bin); chi2 and dV may be NULL.  dV gets
+// cot[m] * d chi^2_m / dV_b (cot NULL: 1).  st_ws may be NULL.
+void launch_chi2(const GeomDev *g, const ModelDev *m, int n, const KinDev *kin, const double *V,
+                 const int *st_ws, double *chi2, const double *cot, double *dV, hipStream_t st);
 
 }  // namespace jam

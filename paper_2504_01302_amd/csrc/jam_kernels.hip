@@ -24,6 +24,7 @@
 #include "jam_internal.h"
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -329,12 +330,15 @@ constexpr int KC = 32;   // terms per chunk
 
 __device__ inline int mfma_row(int r, int lane) { return (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2); }
 
-// Term range of one slice, in whole chunks.
-__device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int &t1) {
-  const int chunks = (T + KC - 1) / KC;
+constexpr int KC2 = 64;  // terms per chunk of the 32x32 variant
+
+// Term range of one slice, in whole chunks of `unit` terms.
+__device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int &t1,
+                                   int unit = KC) {
+  const int chunks = (T + unit - 1) / unit;
   const int per = (chunks + n_slices - 1) / n_slices;
-  t0 = min(T, slice * per * KC);
-  t1 = min(T, t0 + per * KC);
+  t0 = min(T, slice * per * unit);
+  t1 = min(T, t0 + per * unit);
 }
 
 // 64x64 output tile per workgroup, 2x2 waves of 32x32; the A (64 rows) and
@@ -461,19 +465,21 @@ __device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__
   __syncthreads();
 }
 
-// 32x32 output tile per workgroup for small maps; each of the 4 waves takes
-// every 4th chunk of the slice and generates its own operands in registers
+// 32x32 output tile per workgroup; each of the 4 waves takes every 4th chunk
+// of 64 terms of the slice and generates its own operands in registers
 // (lane l: row/column l % 32, term of its half-wave).  A wave's chunk
-// coefficients go through a private 32-entry LDS slot (one vector load per
-// lane, prefetched one chunk ahead); the four FP64 partial tiles are summed
-// through LDS in a fixed order.  Item (m, tile, slice).
+// coefficients go through a private 64-entry LDS slot (one vector load per
+// lane, prefetched one chunk ahead).  Each chunk is summed by 32 MFMAs into a
+// fresh FP32 tile that is then folded into the FP64 accumulators; the four
+// FP64 partial tiles are summed through LDS in a fixed order.
+// Item (m, tile, slice); slices are in whole 64-term chunks.
 __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__restrict__ geoms,
                                                 const ModelDev *__restrict__ models,
                                                 const float4 *__restrict__ terms,
                                                 const int *__restrict__ st_ws,
                                                 double *__restrict__ part, char *smem) {
   double (*red)[16][64] = reinterpret_cast<double (*)[16][64]>(smem);
-  float4 (*cs)[KC] = reinterpret_cast<float4 (*)[KC]>(smem + 3 * 16 * 64 * sizeof(double));
+  float4 (*cs)[KC2] = reinterpret_cast<float4 (*)[KC2]>(smem + 3 * 16 * 64 * sizeof(double));
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const ModelDev md = models[it.m];
@@ -482,34 +488,53 @@ __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__
   const int x0 = (it.a % n_xt) * 32, y0 = (it.a / n_xt) * 32;
   const int c32 = lane & 31, kh = lane >> 5;
   const int xi = x0 + c32, yi = y0 + c32;
-  const bool vx = xi < g.n_ux, vy = yi < g.n_uy;
-  float x2 = 0.f, y2 = 0.f;
-  if (vx) { const double x = g.xs[xi]; x2 = (float)(x * x); }
-  if (vy) { const double y = g.ys[yi]; y2 = (float)(y * y); }
+  // Rows/columns outside the map get an exponent offset of -inf (and x^2 = 0),
+  // so their operands are exactly 0 without a per-element select; inside the
+  // map the offset is 0 and fma(c, x^2, 0) rounds exactly like c * x^2.
+  float x2 = 0.f, y2 = 0.f, xoff = -__builtin_inff(), yoff = -__builtin_inff();
+  if (xi < g.n_ux) { const double x = g.xs[xi]; x2 = (float)(x * x); xoff = 0.f; }
+  if (yi < g.n_uy) { const double y = g.ys[yi]; y2 = (float)(y * y); yoff = 0.f; }
   int t0, t1;
-  slice_range(g.T, md.n_slices, it.b, t0, t1);
-  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC - 1) / KC : 0;
+  slice_range(g.T, md.n_slices, it.b, t0, t1, KC2);
+  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC2 - 1) / KC2 : 0;
   const float4 *tb = terms + md.term_off;
   double acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0;
   float4 cnext = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (wave < n_ch) cnext = tb[min(t0 + wave * KC + c32, t1 - 1)];
+  if (wave < n_ch) cnext = tb[min(t0 + wave * KC2 + lane, t1 - 1)];
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int ch = wave; ch < n_ch; ch += 4) {
-    const int tc = t0 + ch * KC;
-    if (kh == 0) cs[wave][c32] = cnext;
+    const int tc = t0 + ch * KC2;
+    cs[wave][lane] = cnext;
     __builtin_amdgcn_wave_barrier();
-    if (ch + 4 < n_ch) cnext = tb[min(tc + 4 * KC + c32, t1 - 1)];
-    v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (ch + 4 < n_ch) cnext = tb[min(tc + 4 * KC2 + lane, t1 - 1)];
+    v16f d;
+    if (tc + KC2 <= t1) {          // whole chunk (wave-uniform)
+      {
+        const float4 c = cs[wave][kh];
+        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
+        const float b = fast_exp2(fmaf(c.y, y2, yoff));
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, zero, 0, 0, 0);
+      }
 #pragma unroll 4
-    for (int s2 = 0; s2 < KC / 2; ++s2) {
-      const int k = 2 * s2 + kh;
-      const float4 c = cs[wave][k];
-      const bool vt = tc + k < t1;
-      const float a = fast_exp2(c.x * x2) * fmaf(c.w, x2, c.z);
-      const float b = fast_exp2(c.y * y2);
-      d = __builtin_amdgcn_mfma_f32_32x32x2f32((vt && vx) ? a : 0.f, (vt && vy) ? b : 0.f, d, 0,
-                                               0, 0);
+      for (int s2 = 1; s2 < KC2 / 2; ++s2) {
+        const float4 c = cs[wave][2 * s2 + kh];
+        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
+        const float b = fast_exp2(fmaf(c.y, y2, yoff));
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+      }
+    } else {                      // last, partial chunk of the slice
+      d = zero;
+#pragma unroll 4
+      for (int s2 = 0; s2 < KC2 / 2; ++s2) {
+        const int k = 2 * s2 + kh;
+        const float4 c = cs[wave][k];
+        const bool vt = tc + k < t1;
+        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
+        const float b = fast_exp2(fmaf(c.y, y2, yoff));
+        d = __builtin_amdgcn_mfma_f32_32x32x2f32(vt ? a : 0.f, vt ? b : 0.f, d, 0, 0, 0);
+      }
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -535,7 +560,7 @@ __device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__
 
 // Largest LDS user among the numerator variants (the 64x64 MFMA tiles).
 constexpr int kNumSmem = 2 * 2 * KC * 64 * (int)sizeof(float);
-static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double) + 4 * KC * 16, "32x32 variant LDS");
+static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double) + 4 * KC2 * 16, "32x32 variant LDS");
 static_assert(kNumSmem >= 256 * (int)sizeof(double), "per-pixel variant LDS");
 
 // Numerator over a work list whose items carry their variant in Item::c
@@ -775,10 +800,12 @@ __device__ __forceinline__ void sens_pix_item(const Item it, const GeomDev *__re
 // are two FP32 contractions over y sharing the lambda operand, and
 //   S0_t = sum_x E G,  S1_t = sum_x x^2 E G,  Sg_t = sum_x E (C0 + C1 x^2) H.
 // Item (m, 32-row x tile, 256-term tile); wave w owns terms 64 w .. 64 w + 63
-// of the tile, as two 32-term column blocks (lane l: term l % 32, y pair
-// l / 32).  lambda is staged through
-// LDS 256 rows of y at a time; FP32 partial sums over 32 y values are folded
-// into FP64.  Output: per x tile, [S0 | S1 | Sg] (T doubles each).
+// of the tile and takes them as two 32-term column blocks one after the
+// other (lane l: term l % 32, y pair l / 32), so only one block's FP64
+// accumulators are live.  lambda is staged through LDS 256 rows of y at a
+// time (once per item when the map has at most 256 distinct |y|); FP32
+// partial sums over 64 y values are folded into FP64.  Output: per x tile,
+// [S0 | S1 | Sg] (T doubles each).
 // ---------------------------------------------------------------------------
 constexpr int YC = 256;
 constexpr int kSensTerms = 256;   // terms per MFMA sensitivity item (64 per wave)
@@ -799,64 +826,61 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
   if (st_ws[it.m] != 0) return;   // uniform per block
   const int x0 = it.a * 32;
   const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
-  // wave w owns terms it.b*kSensTerms + w*64 + h*32 + (0..31), h = 0, 1
-  float4 c[2];
-  bool vt[2];
-#pragma unroll
+  const int n_yb = (g.n_uy + YC - 1) / YC;
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int h = 0; h < 2; ++h) {
+    // this block's terms: it.b*kSensTerms + w*64 + h*32 + (0..31)
     const int t = it.b * kSensTerms + wave * 64 + h * 32 + c32;
-    vt[h] = t < g.T;
-    c[h] = vt[h] ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  double gacc[2][16], hacc[2][16];
+    const bool vt = t < g.T;
+    const float4 c = vt ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double gacc[16], hacc[16];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) { gacc[h][r] = 0.0; hacc[h][r] = 0.0; }
-  for (int yb = 0; yb < g.n_uy; yb += YC) {
-    const int ny = min(YC, g.n_uy - yb);
-    __syncthreads();
-    for (int e = threadIdx.x; e < YC * 32; e += 256) {
-      const int yy = e >> 5, xx = e & 31;
-      float v = 0.f;
-      if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
-      lam[yy][xx] = v;
-    }
-    for (int e = threadIdx.x; e < YC; e += 256) {
-      float v = 0.f;
-      if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
-      ysq[e] = v;
-    }
-    __syncthreads();
-    for (int y0 = 0; y0 < ny; y0 += 32) {
-      // this chunk's operands: lambda[x0 + c32][y0 + 2 s + kh] and y^2
-      float ra[16], ry[16];
-#pragma unroll
-      for (int s2 = 0; s2 < 16; ++s2) {
-        const int yy = y0 + 2 * s2 + kh;          // < YC; rows past ny hold zero lambda
-        ra[s2] = lam[yy][c32];
-        ry[s2] = ysq[yy];
+    for (int r = 0; r < 16; ++r) { gacc[r] = 0.0; hacc[r] = 0.0; }
+    for (int ybi = 0; ybi < n_yb; ++ybi) {
+      const int yb = ybi * YC;
+      const int ny = min(YC, g.n_uy - yb);
+      if (h == 0 || n_yb > 1) {         // uniform per block
+        __syncthreads();
+        for (int e = threadIdx.x; e < YC * 32; e += 256) {
+          const int yy = e >> 5, xx = e & 31;
+          float v = 0.f;
+          if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
+          lam[yy][xx] = v;
+        }
+        for (int e = threadIdx.x; e < YC; e += 256) {
+          float v = 0.f;
+          if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
+          ysq[e] = v;
+        }
+        __syncthreads();
       }
+      for (int y0 = 0; y0 < ny; y0 += 64) {
+        // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2, 64 y values (rows
+        // past ny hold zero lambda; y0 + 63 < YC)
+        v16f dg = zero, dh = zero;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        v16f dg = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        v16f dh = dg;
+        for (int half = 0; half < 2; ++half) {
+          float ra[16], ry[16];
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) {
-          const float b = fast_exp2(c[h].y * ry[s2]);
-          dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b, dg, 0, 0, 0);
-          dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b * ry[s2], dh, 0, 0, 0);
+          for (int s2 = 0; s2 < 16; ++s2) {
+            const int yy = y0 + 32 * half + 2 * s2 + kh;
+            ra[s2] = lam[yy][c32];
+            ry[s2] = ysq[yy];
+          }
+#pragma unroll
+          for (int s2 = 0; s2 < 16; ++s2) {
+            const float b = fast_exp2(c.y * ry[s2]);
+            dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b, dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b * ry[s2], dh, 0, 0, 0);
+          }
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          gacc[h][r] += (double)dg[r];
-          hacc[h][r] += (double)dh[r];
+          gacc[r] += (double)dg[r];
+          hacc[r] += (double)dh[r];
         }
       }
     }
-  }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
     double s0 = 0.0, s1 = 0.0, sg = 0.0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -864,17 +888,16 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
       if (xr < g.n_ux) {
         const double xv = g.xs[xr];
         const float x2 = (float)(xv * xv);
-        const double e = (double)fast_exp2(c[h].x * x2);
-        s0 += e * gacc[h][r];
-        s1 += (double)x2 * e * gacc[h][r];
-        sg += e * (double)fmaf(c[h].w, x2, c[h].z) * hacc[h][r];
+        const double e = (double)fast_exp2(c.x * x2);
+        s0 += e * gacc[r];
+        s1 += (double)x2 * e * gacc[r];
+        sg += e * (double)fmaf(c.w, x2, c.z) * hacc[r];
       }
     }
     s0 += __shfl_xor(s0, 32, 64);
     s1 += __shfl_xor(s1, 32, 64);
     sg += __shfl_xor(sg, 32, 64);
-    const int t = it.b * kSensTerms + wave * 64 + h * 32 + c32;
-    if (kh == 0 && vt[h]) {
+    if (kh == 0 && vt) {
       double *S = sens + md.sens_off + (int64_t)it.a * 3 * g.T;
       S[t] = s0;
       S[g.T + t] = s1;
@@ -1162,6 +1185,59 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
   }
 }
 
+// ---------------------------------------------------------------------------
+// Goodness of fit, eq. (chi2_dyn): chi^2 = r^T P r with r_b = v_obs,b -
+// sqrt(V_b) (eq. (Vrms)) and P the inverse covariance of the measured v_rms.
+// One workgroup per model: r in LDS; s = P r by rows, one row per wave at a
+// time with the lanes along the row and a fixed-order wave sum; chi^2 = r.s
+// summed in a fixed order.  dV (optional) receives cot_m * d chi^2 / dV_b =
+// -cot_m s_b / sqrt(V_b).  All FP64; NaN for a model whose status is not OK
+// or with any V_b <= 0 (v_rms undefined).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_chi2(const GeomDev *__restrict__ geoms,
+                                              const ModelDev *__restrict__ models, int n,
+                                              const KinDev *__restrict__ kin,
+                                              const double *__restrict__ V,
+                                              const int *__restrict__ st_ws,
+                                              double *__restrict__ chi2,
+                                              const double *__restrict__ cot,
+                                              double *__restrict__ dV) {
+  __shared__ double r[kChi2MaxBins];
+  __shared__ double part[4];
+  __shared__ int bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double nan = __builtin_nan("");
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const ModelDev md = models[m];
+    const int nb = geoms[md.geom].n_bins;
+    const KinDev kd = kin[md.geom];
+    const double *Vm = V + md.out_off;
+    if (tid == 0) bad = (st_ws && st_ws[m] != 0) ? 1 : 0;
+    __syncthreads();
+    for (int b = tid; b < nb; b += 256) {
+      const double v = Vm[b];
+      if (!(v > 0.0)) bad = 1;       // every writer stores the same value
+      r[b] = kd.vobs[b] - sqrt(v);
+    }
+    __syncthreads();
+    const bool ok = bad == 0;
+    const double scale = cot ? cot[m] : 1.0;
+    double acc = 0.0;
+    for (int b = wave; b < nb; b += 4) {
+      const double *row = kd.prec + (int64_t)b * nb;
+      double sb = 0.0;
+      for (int c = lane; c < nb; c += 64) sb = fma(row[c], r[c], sb);
+      sb = wave_sum(sb);
+      acc = fma(r[b], sb, acc);
+      if (dV && lane == 0) dV[md.out_off + b] = ok ? -scale * sb / sqrt(Vm[b]) : nan;
+    }
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (tid == 0 && chi2) chi2[m] = ok ? ((part[0] + part[1]) + part[2]) + part[3] : nan;
+    __syncthreads();
+  }
+}
+
 inline int grid_of(int n_it) { return n_it < 1 ? 1 : n_it; }
 
 }  // namespace
@@ -1235,6 +1311,11 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
+}
+void launch_chi2(const GeomDev *g, const ModelDev *m, int n, const KinDev *kin, const double *V,
+                 const int *st_ws, double *chi2, const double *cot, double *dV, hipStream_t st) {
+  hipLaunchKernelGGL(k_chi2, dim3(grid_of(std::min(n, 65536))), dim3(256), 0, st, g, m, n, kin, V,
+                     st_ws, chi2, cot, dV);
 }
 
 }  // namespace jam
