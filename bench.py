@@ -36,7 +36,7 @@ def _args():
     ap.add_argument("--form", type=int, default=2,
                     help="1 per-pixel VALU kernel, 2 matrix-core kernel (0 = library default)")
     ap.add_argument("--launch", type=int, default=0,
-                    help="0 persistent work-queue grid, 1 one workgroup per work item")
+                    help="0 one worker per work item, 1 persistent work-queue grid")
     ap.add_argument("--graph", type=int, default=0, help="1 replay a recorded HIP graph")
     ap.add_argument("--autotune", type=int, default=0, help="1 autotune the numerator schedule")
     ap.add_argument("--no-plain-baseline", action="store_true",
@@ -77,17 +77,18 @@ def cpu_baseline(g, p, n_sample):
 
 
 def profiled_traffic():
-    """HBM bytes per k_num launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel source has changed since."""
+    """HBM bytes per launch of the matrix-core quadrature kernel (k_num_mfma)
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None
+    when the kernel source has changed since."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_num_ifu_scale_hbm.md")
+    path = os.path.join(ROOT, "profiles", "k_num_mfma_ifu_scale_hbm.md")
     src = os.path.join(ROOT, "paper_2504_01302_amd", "csrc", "jam_kernels.hip")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     h = re.search(r"Kernel source sha256: ([0-9a-f]{64})", text)
-    b = re.search(r"k_num_traffic_bytes_per_launch: ([0-9.]+)", text)
+    b = re.search(r"k_num_mfma_traffic_bytes_per_launch: ([0-9.]+)", text)
     if not h or not b:
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
@@ -252,7 +253,7 @@ def main():
     plain = None
     if not a.no_plain_baseline:
         w_one = inputs.Workload("cfg2", [g], np.zeros(1, np.int32), [p])
-        pc = binding.Context([g], form=1, launch=1)
+        pc = binding.Context([g], form=1, launch=0)
         p1 = binding.pack_params(w_one, dev, amplitudes=True)
         V1 = torch.empty(g.n_bins, dtype=torch.float64, device=dev)
         s1 = torch.empty(1, dtype=torch.int32, device=dev)
@@ -300,7 +301,7 @@ def main():
                                      and not a.autotune) else None
     roof.update(achieved=achieved, unit="TFLOP/s",
                 frac=achieved / roof["peak"] if achieved else None, traffic=traffic,
-                kernel="k_num", avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
+                kernel="k_num_mfma" if form_used == 2 else "k_num_pix", avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
                 launches=num_n, flops_per_launch=flops)
 
     rec = {

@@ -92,12 +92,14 @@ typedef struct {
  *       2 = separable matrix-core (MFMA) kernels.
  * autotune (form 0 only): 1 = when a batch composition is first prepared,
  *       time the candidate numerator schedules (kernel variant, 64x64-tile
- *       threshold, terms per work item, persistent or one workgroup per item)
+ *       pairing threshold, terms per work item, per-item or persistent launch)
  *       on it with fixed valid parameters and keep the fastest; results are
  *       cached per composition, and in the text file tune_cache if not NULL
  *       (read at jam_create, rewritten after each tuning).
- * launch: 0 = persistent grid pulling work items from a device queue
- *       (largest first), 1 = one workgroup per work item.
+ * launch: 0 = one worker per work item (a workgroup, or a wave for the
+ *       matrix-core numerator), dispatched by the hardware; 1 = persistent
+ *       grid whose workers pull work items from a device queue (largest
+ *       first).
  * graph: 1 = record each prepared composition's evaluation (and adjoint) as
  *       a HIP graph on first use and replay it while the call's pointers are
  *       unchanged (re-recorded when they change).                            */

@@ -241,13 +241,14 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // How a plan schedules its numerator (what the autotuner varies).
 struct Tune {
-  int rule = 1;     // 0 per-pixel VALU everywhere; 1 matrix cores (64x64 tiles when both
-                    // map sides >= tau, else 32x32 tiles)
-  int tau = 1 << 30;
+  int rule = 1;     // 0 per-pixel VALU everywhere; 1 matrix cores, one wave per tile of
+                    // 32x32 blocks
+  int tau = 0;      // a map axis with at least tau distinct values pairs its 32-blocks
+                    // into 64-wide tiles
   int gran = 0;     // slice length: units of 64 terms per MFMA item, or (k, j) pairs per
                     // per-pixel item; 0 = derived from the batch
-  int launch = 0;   // 0 persistent grid pulling items from a device queue; 1 one
-                    // workgroup per item
+  int launch = 0;   // 0 one worker per item (a workgroup, or a wave for the matrix-core
+                    // numerator); 1 persistent grid pulling items from a device queue
 };
 
 // Pointers a captured graph was recorded with; replay only on an exact match.
@@ -313,7 +314,7 @@ struct KernelTimer {
 struct jam_ctx {
   int device = 0;
   int n_cu = 256;
-  int occ_num = 1, occ_sens = 1;
+  int occ_num_pix = 1, occ_num_mfma = 1, occ_sens = 1;
   jam_options opt{0, 0, nullptr, 0, 0};
   std::string tune_path;
   std::vector<std::pair<std::string, Tune>> tuned;   // autotuner cache
@@ -346,49 +347,75 @@ constexpr size_t kMaxPlans = 8;
 
 // Numerator variant and term-range split of one model under a schedule.
 // `gran` is the slice length in units: (k, j) pairs for the per-pixel
-// variant, 64 terms for the MFMA variants (the 64x64 variant slices in
-// 32-term chunks, two per unit).
-struct NumChoice {
-  int kind;      // 0 per-pixel VALU, 1 MFMA 64x64 tiles, 2 MFMA 32x32 tiles
-  int n_slices;
-  int tiles;     // work units along the map (pixel blocks or tiles)
-  int units;     // slice units of the whole term range
+// variant, 64 terms for the matrix-core variant.  The matrix-core variant
+// covers the unique-pixel map with wave tiles of BX x BY blocks of 32x32:
+// along an axis with at least tau distinct values the blocks pair up into
+// 64-wide tiles (an odd last block stays 32 wide).
+struct WaveTile {
+  int bx, by, BX, BY;   // origin in 32-blocks, extent in blocks (1 or 2)
 };
 
+struct NumChoice {
+  int kind;      // 0 per-pixel VALU, 2 matrix-core wave tiles
+  int n_slices;
+  int units;     // slice units of the whole term range
+  std::vector<WaveTile> tiles;   // matrix core
+  int pix_blocks = 0;            // per-pixel: 64-pixel blocks
+  int n_tiles() const { return kind == 0 ? pix_blocks : (int)tiles.size(); }
+  double tile_units(int i) const { return kind == 0 ? 1.0 : tiles[i].BX * tiles[i].BY; }
+};
+
+std::vector<std::pair<int, int>> axis_tiles(int n, int tau) {
+  const int nb = (n + 31) / 32;
+  std::vector<std::pair<int, int>> out;   // (first block, blocks)
+  for (int b = 0; b < nb;) {
+    const int w = (n >= tau && b + 1 < nb) ? 2 : 1;
+    out.push_back({b, w});
+    b += w;
+  }
+  return out;
+}
+
 NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
+  NumChoice c;
   if (t.rule == 0) {
     const int pairs = g.K * g.J1;
     const int per = std::max(1, gran);
-    return {0, std::max(1, (pairs + per - 1) / per), (g.n_pix + 63) / 64, pairs};
-  }
-  const bool big = g.n_ux >= t.tau && g.n_uy >= t.tau;
-  const int tw = big ? 64 : 32;
-  const int tiles = ((g.n_ux + tw - 1) / tw) * ((g.n_uy + tw - 1) / tw);
-  if (big) {
-    const int chunks = (g.T + 31) / 32;
-    const int per = std::max(8, 2 * gran);
-    return {1, std::max(1, (chunks + per - 1) / per), tiles, (g.T + 63) / 64};
+    c.kind = 0;
+    c.n_slices = std::max(1, (pairs + per - 1) / per);
+    c.units = pairs;
+    c.pix_blocks = (g.n_pix + 63) / 64;
+    return c;
   }
   const int chunks = (g.T + 63) / 64;
   const int per = std::max(4, gran);
-  return {2, std::max(1, (chunks + per - 1) / per), tiles, chunks};
+  c.kind = 2;
+  c.n_slices = std::max(1, (chunks + per - 1) / per);
+  c.units = chunks;
+  for (const auto &ty : axis_tiles(g.n_uy, t.tau))
+    for (const auto &tx : axis_tiles(g.n_ux, t.tau))
+      c.tiles.push_back({tx.first, ty.first, tx.second, ty.second});
+  return c;
 }
 
 // Relative cost of one numerator item, for largest-first ordering and the
 // schedule model: the kernels' chunk loop plus a fixed per-item cost (the
-// partial-tile store and its reduction).
-double num_item_cost(const GeomHost &g, const NumChoice &c, int slice) {
+// partial-tile store and its reduction).  `tile` indexes c's tiles.
+double num_item_cost(const GeomHost &g, const NumChoice &c, int slice, int tile) {
   if (c.kind == 0) {
     const int pairs = g.K * g.J1;
     const int per = (pairs + c.n_slices - 1) / c.n_slices;
     const int cnt = std::max(0, std::min(pairs, (slice + 1) * per) - slice * per);
     return cnt * (double)g.n_u * 64.0 * 5.0 / 32768.0 + 1.0;
   }
-  const int unit = c.kind == 1 ? 32 : 64;
-  const int chunks = (g.T + unit - 1) / unit;
+  const int chunks = (g.T + 63) / 64;
   const int per = (chunks + c.n_slices - 1) / c.n_slices;
   const int cnt = std::max(0, std::min(chunks, (slice + 1) * per) - slice * per);
-  return cnt * (c.kind == 1 ? 4.0 : 3.0) + 3.0;
+  // per chunk: 32 MFMAs per block and operand generation per row / column
+  // block; per item: the wave's start (dependent descriptor and coordinate
+  // loads, first chunk) and its tile store
+  const WaveTile &w = c.tiles[tile];
+  return cnt * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY)) + 8.0;
 }
 
 // Completion time of the numerator launch as modelled: every resident
@@ -410,24 +437,29 @@ double list_schedule_makespan(std::vector<double> &cost, int slots) {
   return mk;
 }
 
-// Default slice length: the one whose item list the resident workgroups
-// finish first under the list-scheduling model.  Candidates are geometric
-// around one item per resident workgroup, plus the exact splits of the
-// largest model, so a uniform item list can fill whole rounds of workgroups.
+// Workers pulling numerator items: workgroups (per-pixel form) or waves
+// (matrix-core form) resident on the device.
+int num_slots(const jam_ctx *ctx, const Tune &t) {
+  return std::max(1, t.rule == 0 ? ctx->n_cu * ctx->occ_num_pix : 4 * ctx->n_cu * ctx->occ_num_mfma);
+}
+
+// Default slice length: the one whose item list the resident workers finish
+// first under the list-scheduling model.  Candidates are geometric around one
+// item per worker, plus the exact splits of the largest model, so a uniform
+// item list can fill whole rounds of workers.
 int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
-  const int slots = std::max(1, ctx->n_cu * ctx->occ_num);
+  const int slots = num_slots(ctx, t);
   double work = 0.0, big_work = -1.0;
   int big_units = 1, big_tiles = 1;
-  std::vector<NumChoice> whole(n);
   for (int m = 0; m < n; ++m) {
     const GeomHost &g = ctx->gh[geom_idx[m]];
-    whole[m] = choose_numerator(g, t, 1 << 29);
-    const double w = (double)whole[m].tiles * whole[m].units;
+    const NumChoice c = choose_numerator(g, t, 1 << 29);
+    const double w = (double)c.n_tiles() * c.units;
     work += w;
     if (w > big_work) {
       big_work = w;
-      big_units = whole[m].units;
-      big_tiles = whole[m].tiles;
+      big_units = c.units;
+      big_tiles = c.n_tiles();
     }
   }
   const double g0 = std::max(1.0, std::ceil(work / slots));
@@ -448,10 +480,8 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
     for (int m = 0; m < n; ++m) {
       const GeomHost &g = ctx->gh[geom_idx[m]];
       const NumChoice c = choose_numerator(g, t, gr);
-      for (int sl = 0; sl < c.n_slices; ++sl) {
-        const double ci = num_item_cost(g, c, sl);
-        for (int tl = 0; tl < c.tiles; ++tl) cost.push_back(ci);
-      }
+      for (int sl = 0; sl < c.n_slices; ++sl)
+        for (int tl = 0; tl < c.n_tiles(); ++tl) cost.push_back(num_item_cost(g, c, sl, tl));
     }
     if (cost.size() > (size_t)64 * slots + (size_t)4 * n) continue;   // far too fine
     const double mk = list_schedule_makespan(cost, slots);
@@ -510,7 +540,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     gauss += jam::gauss_size(g.K, g.J1);
     terms += g.T;
     pixd += 4 * (int64_t)g.n_pix;
-    part += (int64_t)d.n_slices * g.n_pix;
+    part += (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);   // padded to whole blocks
     bins += 2 * (int64_t)g.n_bins;
     sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 * g.J1 + 1);
     p->total_lum += g.K;
@@ -534,13 +564,16 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_red.push_back({m, pb, 0, 0});
     for (int rb = 0; rb < (g.n_uy + 7) / 8; ++rb)
       for (int cb = 0; cb < (g.n_ux + 63) / 64; ++cb) it_sb.push_back({m, rb, cb, 0});
-    for (int s = 0; s < d.n_slices; ++s) {
-      const double c = num_item_cost(g, nc, s);
-      for (int tl = 0; tl < nc.tiles; ++tl) {
-        it_num.push_back({m, tl, s, nc.kind});
-        c_num.push_back(c);
+    for (int s = 0; s < d.n_slices; ++s)
+      for (int tl = 0; tl < nc.n_tiles(); ++tl) {
+        if (nc.kind == 0) {
+          it_num.push_back({m, tl, s, 0});
+        } else {
+          const WaveTile &w = nc.tiles[tl];
+          it_num.push_back({m, w.bx | (w.by << 16), s, 2 + (w.BX - 1) + 2 * (w.BY - 1)});
+        }
+        c_num.push_back(num_item_cost(g, nc, s, tl));
       }
-    }
     for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
     for (int k = 0; k < g.K; ++k)
@@ -581,11 +614,14 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
   }
-  if (tune.launch == 0) {
-    p->grid_num = std::max(1, std::min(p->n_num, ctx->n_cu * ctx->occ_num));
+  // numerator workers: workgroups (per-pixel) or waves, 4 per workgroup (matrix core)
+  const int num_wg = tune.rule == 0 ? p->n_num : (p->n_num + 3) / 4;
+  if (tune.launch == 1) {
+    const int occ = tune.rule == 0 ? ctx->occ_num_pix : ctx->occ_num_mfma;
+    p->grid_num = std::max(1, std::min(num_wg, ctx->n_cu * occ));
     p->grid_sens = std::max(1, std::min(p->n_sens, ctx->n_cu * ctx->occ_sens));
   } else {
-    p->grid_num = std::max(1, p->n_num);
+    p->grid_num = std::max(1, num_wg);
     p->grid_sens = std::max(1, p->n_sens);
   }
   // workspace layout
@@ -627,7 +663,7 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   if (need_numerator) {
     const bool timed = ctx->t_num.begin(st, capturing);
     jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
-                    p->tune.launch == 0 ? queue : nullptr, p->grid_num, st);
+                    p->tune.launch == 1 ? queue : nullptr, p->grid_num, p->tune.rule == 1, st);
     if (timed) ctx->t_num.end(st);
     jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_red, p->n_red, part, pix, st);
   }
@@ -673,7 +709,7 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   const bool timed = ctx->t_sens.begin(st, capturing);
   jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
                    (const float4 *)(w + p->off_terms), pix, st_ws, sens,
-                   p->tune.launch == 0 ? queue + 1 : nullptr, p->grid_sens, st);
+                   p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
   if (timed) ctx->t_sens.end(st);
   jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
   const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
@@ -732,8 +768,8 @@ jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best
   Tune base;
   const int g0 = default_gran(ctx, n, geom_idx, base);
   for (int launch = 0; launch < 2; ++launch)
-    for (int tau : {32, 64, 1 << 30})
-      for (double mul : {0.5, 1.0, 2.0}) {
+    for (int tau : {0, 1 << 30})
+      for (double mul : {0.5, 0.75, 1.0, 1.5, 2.0}) {
         Tune t;
         t.rule = 1;
         t.tau = tau;
@@ -792,8 +828,8 @@ jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best
       (void)hipEventRecord(e0, st);
       jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
                       (const float4 *)(w + p->off_terms), (const int *)(w + p->off_status),
-                      (double *)(w + p->off_part), p->tune.launch == 0 ? (int *)(w + p->off_queue) : nullptr,
-                      p->grid_num, st);
+                      (double *)(w + p->off_part), p->tune.launch == 1 ? (int *)(w + p->off_queue) : nullptr,
+                      p->grid_num, p->tune.rule == 1, st);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         cleanup();
@@ -1033,7 +1069,8 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
   ctx->opt.tune_cache = nullptr;   // the path is copied
   HIP_TRY(hipGetDevice(&ctx->device));
   HIP_TRY(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-  ctx->occ_num = jam::occupancy_num();
+  ctx->occ_num_pix = jam::occupancy_num(false);
+  ctx->occ_num_mfma = jam::occupancy_num(true);
   ctx->occ_sens = jam::occupancy_sens();
   load_tune_file(ctx.get());
   ctx->gh.resize(n_geom);

@@ -41,7 +41,8 @@ struct ModelDev {
   int mass_off;      // into packed mass_S0
   int out_off;       // into packed vrms2 / cot
   int n_slices;      // split of the term range in the numerator kernels
-  int n_xt, n_yt;    // 32x32 tiles of the unique-pixel map (MFMA form)
+  int n_xt, n_yt;    // 32x32 blocks covering the unique-pixel map (partial maps are
+                     // stored padded to 32 n_xt x 32 n_yt per slice)
   int form;          // 1 per-pixel VALU, 2 separable MFMA
   int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
   int pad;
@@ -93,15 +94,17 @@ void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // Items (m, block of 8 unique-pixel rows, block of 64 columns).
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
-// Numerator over a work list whose items carry their variant in Item::c:
-// 0 per-pixel VALU (m, 64-pixel block, slice), 1 MFMA 64x64 tiles and
-// 2 MFMA 32x32 tiles (m, tile, slice).  queue != NULL: persistent grid of
-// `grid` workgroups pulling items from the counter; else `grid` workgroups
-// striding over the list.
+// Numerator over a work list.  mfma = false: per-pixel VALU form, one
+// workgroup per item (m, 64-pixel block, slice).  mfma = true: matrix-core
+// form, one wave per item (m, tile origin in 32-blocks x | y << 16, slice,
+// variant 2..5 = tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32).
+// queue != NULL: persistent grid of `grid` workgroups whose workgroups (per-
+// pixel) or waves (matrix core) pull items from the counter; else `grid`
+// workgroups striding over the list.
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                 const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
-                hipStream_t st);
-int occupancy_num();    // resident numerator workgroups per CU
+                bool mfma, hipStream_t st);
+int occupancy_num(bool mfma);   // resident numerator workgroups per CU
 int occupancy_sens();   // resident sensitivity workgroups per CU
 // Items (m, 64-pixel block).
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,

@@ -43,6 +43,17 @@ __device__ inline double grav_const() { return kGMsun / (kAu * 648000.0 / kPi * 
 
 __device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Split-term partial maps are stored per slice on the unique-pixel map padded
+// to whole 32x32 blocks and transposed (y fastest): element (x, y) at
+// x * 32 n_yt + y, 32 n_xt * 32 n_yt doubles per slice.  A wave's MFMA tile
+// then stores 32 consecutive y values per instruction.
+__device__ inline int64_t part_slice_size(const ModelDev &md) {
+  return (int64_t)(32 * md.n_xt) * (32 * md.n_yt);
+}
+__device__ inline int64_t part_index(const ModelDev &md, const GeomDev &g, int q) {
+  return (int64_t)(q % g.n_ux) * (32 * md.n_yt) + q / g.n_ux;
+}
+
 // Deterministic block sum of one double over a 256-thread block.
 __device__ double block_sum256(double v, double *sh) {
   const int t = threadIdx.x;
@@ -306,7 +317,7 @@ __device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__res
   __syncthreads();
   if (threadIdx.x < 64 && valid) {
     const double v = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
-    part[md.part_off + (int64_t)it.b * g.n_pix + q] = v;
+    part[md.part_off + it.b * part_slice_size(md) + part_index(md, g, q)] = v;
   }
   __syncthreads();
 }
@@ -330,7 +341,8 @@ constexpr int KC = 32;   // terms per chunk
 
 __device__ inline int mfma_row(int r, int lane) { return (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2); }
 
-constexpr int KC2 = 64;  // terms per chunk of the 32x32 variant
+constexpr int KC2 = 64;  // terms per chunk of the matrix-core numerator
+
 
 // Term range of one slice, in whole chunks of `unit` terms.
 __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int &t1,
@@ -341,240 +353,143 @@ __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int 
   t1 = min(T, t0 + per * unit);
 }
 
-// 64x64 output tile per workgroup, 2x2 waves of 32x32; the A (64 rows) and
-// B (64 columns) operands of each chunk are generated once into LDS (double
-// buffered) and shared by the four waves.  Per chunk a wave issues its 16
-// MFMAs on the current buffer first and then generates its quarter of the
-// next chunk's operands, so the exponentials overlap the matrix work; the
-// next chunk's term coefficients (8 per wave, wave-uniform) are loaded at the
-// top of the iteration.  Item (m, tile, slice).
-__device__ __forceinline__ void num_mfma64_item(const Item it, const GeomDev *__restrict__ geoms,
-                                                const ModelDev *__restrict__ models,
-                                                const float4 *__restrict__ terms,
-                                                const int *__restrict__ st_ws,
-                                                double *__restrict__ part, char *smem) {
-  float (*As)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem);
-  float (*Bs)[KC][64] = reinterpret_cast<float (*)[KC][64]>(smem + 2 * KC * 64 * sizeof(float));
+// One wave, one item: an output tile of BX x BY blocks of 32x32 unique
+// pixels (BX along x, BY along y) over one slice of the terms, in chunks of
+// 64 terms.  Lane l generates the operands of its row / column l % 32 of
+// every block for the term of its half-wave (A for BX rows, B for BY
+// columns), so each generated value feeds BY (resp. BX) MFMAs.  A chunk's
+// coefficients go through the wave's private 64-entry LDS slot (one vector
+// load per lane, prefetched a chunk ahead); each chunk is summed into fresh
+// FP32 blocks that are then folded into FP64 accumulators.  No cross-wave
+// reduction: the wave writes its tile of the slice's partial map.
+// Item (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 for
+// (BX, BY) = (1,1), (2,1), (1,2), (2,2)); slices are whole 64-term chunks.
+template <int BX, int BY>
+__device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__restrict__ geoms,
+                                              const ModelDev *__restrict__ models,
+                                              const float4 *__restrict__ terms,
+                                              const int *__restrict__ st_ws,
+                                              double *__restrict__ part, float4 *cs) {
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wx = wave & 1, wy = wave >> 1;
-  const int kh = lane >> 5, c32 = lane & 31;
   const ModelDev md = models[it.m];
   const GeomDev g = geoms[md.geom];
-  const int n_xt = (g.n_ux + 63) >> 6;
-  const int x0 = (it.a % n_xt) * 64, y0 = (it.a / n_xt) * 64;
-  const int xi = x0 + lane, yi = y0 + lane;
-  const bool vx = xi < g.n_ux, vy = yi < g.n_uy;
-  float x2 = 0.f, y2 = 0.f;
-  if (vx) { const double x = g.xs[xi]; x2 = (float)(x * x); }
-  if (vy) { const double y = g.ys[yi]; y2 = (float)(y * y); }
-  int t0, t1;
-  slice_range(g.T, md.n_slices, it.b, t0, t1);
-  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC - 1) / KC : 0;
-  const bool active = (x0 + wx * 32 < g.n_ux) && (y0 + wy * 32 < g.n_uy);
-  const float4 *tb = terms + md.term_off;
-  double acc[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-  // This wave's terms of chunk ch are t0 + ch*KC + wave + 4 i, i < 8; lane i
-  // loads term i's coefficients with a vector load (waited for only when the
-  // exponentials need them, after the MFMAs are issued) and readlane
-  // broadcasts them.
-  float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto load_cf = [&](int ch) {
-    const int tw = t0 + ch * KC + wave;
-    if (lane < KC / 4) cv = tb[min(tw + 4 * lane, t1 - 1)];
-  };
-  auto bcast = [&](float v, int i) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-  };
-  auto gen = [&](int buf, int ch) {
-    const int tw = t0 + ch * KC + wave;
-#pragma unroll
-    for (int i = 0; i < KC / 4; ++i) {
-      const bool vt = tw + 4 * i < t1;
-      const float cx = bcast(cv.x, i), cy = bcast(cv.y, i), c0 = bcast(cv.z, i),
-                  c1 = bcast(cv.w, i);
-      const float a = fast_exp2(cx * x2) * fmaf(c1, x2, c0);
-      const float b = fast_exp2(cy * y2);
-      As[buf][wave + 4 * i][lane] = (vt && vx) ? a : 0.f;
-      Bs[buf][wave + 4 * i][lane] = (vt && vy) ? b : 0.f;
-    }
-  };
-  if (n_ch > 0) {
-    load_cf(0);
-    gen(0, 0);
-  }
-  __syncthreads();
-  // One basic block per chunk: the MFMAs on the current buffer interleaved
-  // with the generation of the next chunk (past the last chunk the
-  // generation writes an unused buffer from clamped, valid coefficients).
-  // Waves whose 32x32 sub-tile lies outside the map only generate.
-  auto run = [&](auto act) {
-    constexpr bool kActive = decltype(act)::value;
-    for (int ch = 0; ch < n_ch; ++ch) {
-      const int cur = ch & 1, nxt = cur ^ 1;
-      load_cf(ch + 1);
-      const int tw = t0 + (ch + 1) * KC + wave;
-      v16f d = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float ra[KC / 2], rb[KC / 2];
-      if constexpr (kActive) {
-#pragma unroll
-        for (int q = 0; q < KC / 2; ++q) {
-          ra[q] = As[cur][2 * q + kh][wx * 32 + c32];
-          rb[q] = Bs[cur][2 * q + kh][wy * 32 + c32];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < KC / 2; ++q) {
-        if constexpr (kActive) d = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[q], rb[q], d, 0, 0, 0);
-        // half of term i = q / 2 of the next chunk: its A value on even
-        // steps, its B value on odd steps
-        const int i = q >> 1;
-        const bool vt = tw + 4 * i < t1;
-        if ((q & 1) == 0) {
-          const float cx = bcast(cv.x, i), c0 = bcast(cv.z, i), c1 = bcast(cv.w, i);
-          const float av = fast_exp2(cx * x2) * fmaf(c1, x2, c0);
-          As[nxt][wave + 4 * i][lane] = (vt && vx) ? av : 0.f;
-        } else {
-          const float cy = bcast(cv.y, i);
-          const float bv = fast_exp2(cy * y2);
-          Bs[nxt][wave + 4 * i][lane] = (vt && vy) ? bv : 0.f;
-        }
-      }
-      if constexpr (kActive) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
-      }
-      __syncthreads();
-    }
-  };
-  if (active)
-    run(std::true_type{});
-  else
-    run(std::false_type{});
-  if (active) {
-    const int yj = y0 + wy * 32 + c32;
-    double *out = part + md.part_off + (int64_t)it.b * g.n_pix;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int xr = x0 + wx * 32 + mfma_row(r, lane);
-      if (xr < g.n_ux && yj < g.n_uy) out[(int64_t)yj * g.n_ux + xr] = acc[r];
-    }
-  }
-  __syncthreads();
-}
-
-// 32x32 output tile per workgroup; each of the 4 waves takes every 4th chunk
-// of 64 terms of the slice and generates its own operands in registers
-// (lane l: row/column l % 32, term of its half-wave).  A wave's chunk
-// coefficients go through a private 64-entry LDS slot (one vector load per
-// lane, prefetched one chunk ahead).  Each chunk is summed by 32 MFMAs into a
-// fresh FP32 tile that is then folded into the FP64 accumulators; the four
-// FP64 partial tiles are summed through LDS in a fixed order.
-// Item (m, tile, slice); slices are in whole 64-term chunks.
-__device__ __forceinline__ void num_mfma32_item(const Item it, const GeomDev *__restrict__ geoms,
-                                                const ModelDev *__restrict__ models,
-                                                const float4 *__restrict__ terms,
-                                                const int *__restrict__ st_ws,
-                                                double *__restrict__ part, char *smem) {
-  double (*red)[16][64] = reinterpret_cast<double (*)[16][64]>(smem);
-  float4 (*cs)[KC2] = reinterpret_cast<float4 (*)[KC2]>(smem + 3 * 16 * 64 * sizeof(double));
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const ModelDev md = models[it.m];
-  const GeomDev g = geoms[md.geom];
-  const int n_xt = (g.n_ux + 31) >> 5;
-  const int x0 = (it.a % n_xt) * 32, y0 = (it.a / n_xt) * 32;
+  const int x0 = (it.a & 0xffff) * 32, y0 = (it.a >> 16) * 32;
   const int c32 = lane & 31, kh = lane >> 5;
-  const int xi = x0 + c32, yi = y0 + c32;
   // Rows/columns outside the map get an exponent offset of -inf (and x^2 = 0),
   // so their operands are exactly 0 without a per-element select; inside the
   // map the offset is 0 and fma(c, x^2, 0) rounds exactly like c * x^2.
-  float x2 = 0.f, y2 = 0.f, xoff = -__builtin_inff(), yoff = -__builtin_inff();
-  if (xi < g.n_ux) { const double x = g.xs[xi]; x2 = (float)(x * x); xoff = 0.f; }
-  if (yi < g.n_uy) { const double y = g.ys[yi]; y2 = (float)(y * y); yoff = 0.f; }
+  float x2[BX], xoff[BX], y2[BY], yoff[BY];
+#pragma unroll
+  for (int bx = 0; bx < BX; ++bx) {
+    const int xi = x0 + 32 * bx + c32;
+    x2[bx] = 0.f;
+    xoff[bx] = -__builtin_inff();
+    if (xi < g.n_ux) { const double x = g.xs[xi]; x2[bx] = (float)(x * x); xoff[bx] = 0.f; }
+  }
+#pragma unroll
+  for (int by = 0; by < BY; ++by) {
+    const int yi = y0 + 32 * by + c32;
+    y2[by] = 0.f;
+    yoff[by] = -__builtin_inff();
+    if (yi < g.n_uy) { const double y = g.ys[yi]; y2[by] = (float)(y * y); yoff[by] = 0.f; }
+  }
   int t0, t1;
   slice_range(g.T, md.n_slices, it.b, t0, t1, KC2);
   const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC2 - 1) / KC2 : 0;
   const float4 *tb = terms + md.term_off;
-  double acc[16];
+  double acc[BX][BY][16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+    for (int by = 0; by < BY; ++by)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[bx][by][r] = 0.0;
   float4 cnext = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (wave < n_ch) cnext = tb[min(t0 + wave * KC2 + lane, t1 - 1)];
+  if (n_ch > 0) cnext = tb[min(t0 + lane, t1 - 1)];
   const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int ch = wave; ch < n_ch; ch += 4) {
+  for (int ch = 0; ch < n_ch; ++ch) {
     const int tc = t0 + ch * KC2;
-    cs[wave][lane] = cnext;
+    cs[lane] = cnext;
     __builtin_amdgcn_wave_barrier();
-    if (ch + 4 < n_ch) cnext = tb[min(tc + 4 * KC2 + lane, t1 - 1)];
-    v16f d;
+    if (ch + 1 < n_ch) cnext = tb[min(tc + KC2 + lane, t1 - 1)];
+    v16f d[BX][BY];
+#pragma unroll
+    for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+      for (int by = 0; by < BY; ++by) d[bx][by] = zero;
     if (tc + KC2 <= t1) {          // whole chunk (wave-uniform)
-      {
-        const float4 c = cs[wave][kh];
-        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
-        const float b = fast_exp2(fmaf(c.y, y2, yoff));
-        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, zero, 0, 0, 0);
-      }
-#pragma unroll 4
-      for (int s2 = 1; s2 < KC2 / 2; ++s2) {
-        const float4 c = cs[wave][2 * s2 + kh];
-        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
-        const float b = fast_exp2(fmaf(c.y, y2, yoff));
-        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d, 0, 0, 0);
+#pragma unroll 2
+      for (int s2 = 0; s2 < KC2 / 2; ++s2) {
+        const float4 c = cs[2 * s2 + kh];
+        float a[BX], b[BY];
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx)
+          a[bx] = fast_exp2(fmaf(c.x, x2[bx], xoff[bx])) * fmaf(c.w, x2[bx], c.z);
+#pragma unroll
+        for (int by = 0; by < BY; ++by) b[by] = fast_exp2(fmaf(c.y, y2[by], yoff[by]));
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+          for (int by = 0; by < BY; ++by)
+            d[bx][by] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bx], b[by], d[bx][by], 0, 0, 0);
       }
     } else {                      // last, partial chunk of the slice
-      d = zero;
-#pragma unroll 4
       for (int s2 = 0; s2 < KC2 / 2; ++s2) {
         const int k = 2 * s2 + kh;
-        const float4 c = cs[wave][k];
+        const float4 c = cs[k];
         const bool vt = tc + k < t1;
-        const float a = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
-        const float b = fast_exp2(fmaf(c.y, y2, yoff));
-        d = __builtin_amdgcn_mfma_f32_32x32x2f32(vt ? a : 0.f, vt ? b : 0.f, d, 0, 0, 0);
+        float a[BX], b[BY];
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+          const float v = fast_exp2(fmaf(c.x, x2[bx], xoff[bx])) * fmaf(c.w, x2[bx], c.z);
+          a[bx] = vt ? v : 0.f;
+        }
+#pragma unroll
+        for (int by = 0; by < BY; ++by) {
+          const float v = fast_exp2(fmaf(c.y, y2[by], yoff[by]));
+          b[by] = vt ? v : 0.f;
+        }
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+          for (int by = 0; by < BY; ++by)
+            d[bx][by] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bx], b[by], d[bx][by], 0, 0, 0);
       }
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] += (double)d[r];
-  }
-  if (wave > 0) {
+    for (int bx = 0; bx < BX; ++bx)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) red[wave - 1][r][lane] = acc[r];
+      for (int by = 0; by < BY; ++by)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[bx][by][r] += (double)d[bx][by][r];
   }
-  __syncthreads();
-  if (wave == 0) {
-    const int yj = y0 + c32;
-    double *out = part + md.part_off + (int64_t)it.b * g.n_pix;
+  // padded, transposed partial map: every row and column of the tile exists,
+  // so the stores need no bounds checks; lanes store consecutive y
+  const int ldh = 32 * md.n_yt;
+  double *out = part + md.part_off + it.b * part_slice_size(md) +
+                (int64_t)(x0 + 4 * kh) * ldh + y0 + c32;
+#pragma unroll
+  for (int bx = 0; bx < BX; ++bx)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
-      const int xr = x0 + mfma_row(r, lane);
-      if (xr < g.n_ux && yj < g.n_uy) out[(int64_t)yj * g.n_ux + xr] = v;
+      double *o = out + (int64_t)(32 * bx + (r & 3) + 8 * (r >> 2)) * ldh;
+#pragma unroll
+      for (int by = 0; by < BY; ++by) o[32 * by] = acc[bx][by][r];
     }
-  }
-  __syncthreads();
 }
 
-// Largest LDS user among the numerator variants (the 64x64 MFMA tiles).
-constexpr int kNumSmem = 2 * 2 * KC * 64 * (int)sizeof(float);
-static_assert(kNumSmem >= 3 * 16 * 64 * (int)sizeof(double) + 4 * KC2 * 16, "32x32 variant LDS");
-static_assert(kNumSmem >= 256 * (int)sizeof(double), "per-pixel variant LDS");
-
-// Numerator over a work list whose items carry their variant in Item::c
-// (0 per-pixel VALU, 1 MFMA 64x64, 2 MFMA 32x32), so one launch serves a
-// batch of uneven models.  With a queue, every workgroup pulls the next item
-// from a device counter (a persistent grid; items are ordered largest first);
+// Numerator, per-pixel VALU form, over a work list of items (m, 64-pixel
+// block, slice).  With a queue, every workgroup pulls the next item from a
+// device counter (a persistent grid; items are ordered largest first);
 // without one, workgroups stride over the list.
-__global__ void __launch_bounds__(256) k_num(const GeomDev *__restrict__ geoms,
-                                             const ModelDev *__restrict__ models,
-                                             const Item *__restrict__ items, int n_it,
-                                             const float4 *__restrict__ terms,
-                                             const int *__restrict__ st_ws,
-                                             double *__restrict__ part, int *queue) {
-  __shared__ __attribute__((aligned(16))) char smem[kNumSmem];
+__global__ void __launch_bounds__(256) k_num_pix(const GeomDev *__restrict__ geoms,
+                                                 const ModelDev *__restrict__ models,
+                                                 const Item *__restrict__ items, int n_it,
+                                                 const float4 *__restrict__ terms,
+                                                 const int *__restrict__ st_ws,
+                                                 double *__restrict__ part, int *queue) {
+  __shared__ double smem[256];
   __shared__ int next;
   int i = blockIdx.x;
   for (;;) {
@@ -585,20 +500,48 @@ __global__ void __launch_bounds__(256) k_num(const GeomDev *__restrict__ geoms,
       __syncthreads();
     }
     if (i >= n_it) break;
-    const Item it = items[i];
-    if (it.c == 0)
-      num_pix_item(it, geoms, models, terms, st_ws, part, smem);
-    else if (it.c == 1)
-      num_mfma64_item(it, geoms, models, terms, st_ws, part, smem);
-    else
-      num_mfma32_item(it, geoms, models, terms, st_ws, part, smem);
+    num_pix_item(items[i], geoms, models, terms, st_ws, part, reinterpret_cast<char *>(smem));
     if (!queue) i += gridDim.x;
   }
 }
 
+// Numerator, matrix-core form: every wave is a worker of its own.  With a
+// queue, each wave pulls the next item (largest first) from a device
+// counter; without one, wave w of workgroup b takes items 4 b + w, striding
+// by the grid.  Variants of different tile shapes share one launch; the
+// register budget is that of the 2x2 tile (two waves per SIMD, with the
+// MFMA accumulators in ordinary VGPRs).
+__global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__ geoms,
+                                                  const ModelDev *__restrict__ models,
+                                                  const Item *__restrict__ items, int n_it,
+                                                  const float4 *__restrict__ terms,
+                                                  const int *__restrict__ st_ws,
+                                                  double *__restrict__ part, int *queue) {
+  __shared__ __attribute__((aligned(16))) float4 cs[4][KC2];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int i = blockIdx.x * 4 + wave;
+  for (;;) {
+    if (queue) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1);
+      i = __shfl(v, 0, 64);
+    }
+    if (i >= n_it) break;
+    const Item it = items[i];
+    switch (it.c) {
+      case 2: num_tile_item<1, 1>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
+      case 3: num_tile_item<2, 1>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
+      case 4: num_tile_item<1, 2>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
+      default: num_tile_item<2, 2>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
+    }
+    if (!queue) i += gridDim.x * 4;
+  }
+}
+
 // Sum the split-term partials in a fixed order into the N map.  Item
-// (m, 64-pixel block); the four waves take every fourth slice and their sums
-// are combined in a fixed order.
+// (m, block of 64 pixels in the partial maps' order, y fastest); the four
+// waves take every fourth slice and their sums are combined in a fixed order.
 __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geoms,
                                                 const ModelDev *__restrict__ models,
                                                 const Item *__restrict__ items, int n_it,
@@ -611,16 +554,19 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const int q = it.a * 64 + lane;
+    // u walks the map with y fastest, as the partial maps are laid out
+    const int u = it.a * 64 + lane;
+    const int x = u / g.n_uy, y = u % g.n_uy;
     double acc = 0.0;
-    if (q < g.n_pix) {
-      const double *pp = part + md.part_off + q;
-      for (int s = wave; s < md.n_slices; s += 4) acc += pp[(int64_t)s * g.n_pix];
+    if (u < g.n_pix) {
+      const double *pp = part + md.part_off + (int64_t)x * (32 * md.n_yt) + y;
+      const int64_t stride = part_slice_size(md);
+      for (int s = wave; s < md.n_slices; s += 4) acc += pp[s * stride];
     }
     if (wave > 0) red[wave - 1][lane] = acc;
     __syncthreads();
-    if (wave == 0 && q < g.n_pix)
-      pix[md.pix_off + q] = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+    if (wave == 0 && u < g.n_pix)
+      pix[md.pix_off + (int64_t)y * g.n_ux + x] = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
     __syncthreads();
   }
 }
@@ -858,8 +804,10 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
         // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2, 64 y values (rows
         // past ny hold zero lambda; y0 + 63 < YC)
         v16f dg = zero, dh = zero;
+        const int halves = (ny - y0 > 32) ? 2 : 1;   // uniform per block
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
+          if (half >= halves) break;
           float ra[16], ry[16];
 #pragma unroll
           for (int s2 = 0; s2 < 16; ++s2) {
@@ -1261,9 +1209,13 @@ void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, Pa
 }
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                 const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
-                hipStream_t st) {
-  hipLaunchKernelGGL(k_num, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms, st_ws,
-                     part, queue);
+                bool mfma, hipStream_t st) {
+  if (mfma)
+    hipLaunchKernelGGL(k_num_mfma, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
+                       st_ws, part, queue);
+  else
+    hipLaunchKernelGGL(k_num_pix, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
+                       st_ws, part, queue);
 }
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st) {
@@ -1293,9 +1245,11 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
   hipLaunchKernelGGL(k_sens, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms, pix,
                      st_ws, sens, queue);
 }
-int occupancy_num() {
+int occupancy_num(bool mfma) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_num, 256, 0) != hipSuccess) nb = 1;
+  const hipError_t e = mfma ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_num_mfma, 256, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_num_pix, 256, 0);
+  if (e != hipSuccess) nb = 1;
   return nb < 1 ? 1 : nb;
 }
 int occupancy_sens() {
