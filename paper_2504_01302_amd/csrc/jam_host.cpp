@@ -411,11 +411,12 @@ double num_item_cost(const GeomHost &g, const NumChoice &c, int slice, int tile)
   const int chunks = (g.T + 63) / 64;
   const int per = (chunks + c.n_slices - 1) / c.n_slices;
   const int cnt = std::max(0, std::min(chunks, (slice + 1) * per) - slice * per);
-  // per chunk: 32 MFMAs per block and operand generation per row / column
-  // block; per item: the wave's start (dependent descriptor and coordinate
-  // loads, first chunk) and its tile store
+  // per chunk of a wave (a quarter of the item's chunks): 32 MFMAs per block
+  // and operand generation per row / column block; per item: the start
+  // (dependent descriptor and coordinate loads, first chunk), the four-wave
+  // sum and the tile store
   const WaveTile &w = c.tiles[tile];
-  return cnt * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY)) + 8.0;
+  return ((cnt + 3) / 4) * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY)) + 8.0;
 }
 
 // Completion time of the numerator launch as modelled: every resident
@@ -437,15 +438,15 @@ double list_schedule_makespan(std::vector<double> &cost, int slots) {
   return mk;
 }
 
-// Workers pulling numerator items: workgroups (per-pixel form) or waves
-// (matrix-core form) resident on the device.
-int num_slots(const jam_ctx *ctx, const Tune &t) {
-  return std::max(1, t.rule == 0 ? ctx->n_cu * ctx->occ_num_pix : 4 * ctx->n_cu * ctx->occ_num_mfma);
-}
+// Workers of the schedule model.  A compute unit processes the workgroups
+// resident on it at its full rate however many there are (co-resident
+// workgroups share its SIMDs), so the model's workers are the compute units
+// and its jobs the workgroup items.
+int num_slots(const jam_ctx *ctx, const Tune &) { return std::max(1, ctx->n_cu); }
 
-// Default slice length: the one whose item list the resident workers finish
-// first under the list-scheduling model.  Candidates are geometric around one
-// item per worker, plus the exact splits of the largest model, so a uniform
+// Default slice length: the one whose item list the workers finish first
+// under the list-scheduling model.  Candidates are geometric around a few
+// jobs per worker, plus the exact splits of the largest model, so a uniform
 // item list can fill whole rounds of workers.
 int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune &t) {
   const int slots = num_slots(ctx, t);
@@ -462,12 +463,14 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
       big_tiles = c.n_tiles();
     }
   }
-  const double g0 = std::max(1.0, std::ceil(work / slots));
+  // jobs a worker holds at once
+  const double per_slot = t.rule == 0 ? ctx->occ_num_pix : ctx->occ_num_mfma;
+  const double g0 = std::max(1.0, std::ceil(work / (slots * per_slot)));
   std::vector<int> cands;
   for (int k = -8; k <= 16; ++k)
     cands.push_back((int)std::min(1.0e9, std::max(1.0, std::round(g0 * std::pow(2.0, k / 8.0)))));
   if (big_work >= 0.25 * work) {
-    const int s_max = std::min(4096, 4 * slots / std::max(1, big_tiles) + 1);
+    const int s_max = std::min(4096, (int)(4 * per_slot) * slots / std::max(1, big_tiles) + 1);
     for (int sl = 1; sl <= s_max; ++sl) cands.push_back((big_units + sl - 1) / sl);
   }
   std::sort(cands.begin(), cands.end());
@@ -483,7 +486,7 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
       for (int sl = 0; sl < c.n_slices; ++sl)
         for (int tl = 0; tl < c.n_tiles(); ++tl) cost.push_back(num_item_cost(g, c, sl, tl));
     }
-    if (cost.size() > (size_t)64 * slots + (size_t)4 * n) continue;   // far too fine
+    if (cost.size() > (size_t)(64 * per_slot) * slots + (size_t)4 * n) continue;   // too fine
     const double mk = list_schedule_makespan(cost, slots);
     if (mk < best * (1.0 - 1e-9) || (mk <= best * (1.0 + 1e-9) && gr > best_g)) {
       best = mk;
@@ -614,8 +617,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
   }
-  // numerator workers: workgroups (per-pixel) or waves, 4 per workgroup (matrix core)
-  const int num_wg = tune.rule == 0 ? p->n_num : (p->n_num + 3) / 4;
+  const int num_wg = p->n_num;   // one workgroup per numerator item
   if (tune.launch == 1) {
     const int occ = tune.rule == 0 ? ctx->occ_num_pix : ctx->occ_num_mfma;
     p->grid_num = std::max(1, std::min(num_wg, ctx->n_cu * occ));

@@ -94,13 +94,12 @@ void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // Items (m, block of 8 unique-pixel rows, block of 64 columns).
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
-// Numerator over a work list.  mfma = false: per-pixel VALU form, one
-// workgroup per item (m, 64-pixel block, slice).  mfma = true: matrix-core
-// form, one wave per item (m, tile origin in 32-blocks x | y << 16, slice,
-// variant 2..5 = tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32).
-// queue != NULL: persistent grid of `grid` workgroups whose workgroups (per-
-// pixel) or waves (matrix core) pull items from the counter; else `grid`
-// workgroups striding over the list.
+// Numerator over a work list of workgroup items.  mfma = false: per-pixel
+// VALU form, items (m, 64-pixel block, slice).  mfma = true: matrix-core
+// form, items (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 =
+// tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32).  queue != NULL:
+// persistent grid of `grid` workgroups pulling items from the counter; else
+// `grid` workgroups striding over the list.
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                 const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
                 bool mfma, hipStream_t st);

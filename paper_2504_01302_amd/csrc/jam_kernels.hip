@@ -353,15 +353,16 @@ __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int 
   t1 = min(T, t0 + per * unit);
 }
 
-// One wave, one item: an output tile of BX x BY blocks of 32x32 unique
-// pixels (BX along x, BY along y) over one slice of the terms, in chunks of
-// 64 terms.  Lane l generates the operands of its row / column l % 32 of
-// every block for the term of its half-wave (A for BX rows, B for BY
-// columns), so each generated value feeds BY (resp. BX) MFMAs.  A chunk's
-// coefficients go through the wave's private 64-entry LDS slot (one vector
-// load per lane, prefetched a chunk ahead); each chunk is summed into fresh
-// FP32 blocks that are then folded into FP64 accumulators.  No cross-wave
-// reduction: the wave writes its tile of the slice's partial map.
+// One workgroup, one item: an output tile of BX x BY blocks of 32x32 unique
+// pixels (BX along x, BY along y) over one slice of the terms; the four
+// waves take contiguous quarters of the slice in chunks of 64 terms.  Lane l
+// generates the operands of its row / column l % 32 of every block for the
+// term of its half-wave (A for BX rows, B for BY columns), so each generated
+// value feeds BY (resp. BX) MFMAs.  A chunk's coefficients go through the
+// wave's private 64-entry LDS slot (one vector load per lane, prefetched a
+// chunk ahead); each chunk is summed into fresh FP32 blocks that are then
+// folded into FP64 accumulators.  The four FP64 tiles are summed through LDS
+// in a fixed order and wave 0 writes the slice's partial tile.
 // Item (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 for
 // (BX, BY) = (1,1), (2,1), (1,2), (2,2)); slices are whole 64-term chunks.
 template <int BX, int BY>
@@ -369,7 +370,8 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
                                               const ModelDev *__restrict__ models,
                                               const float4 *__restrict__ terms,
                                               const int *__restrict__ st_ws,
-                                              double *__restrict__ part, float4 *cs) {
+                                              double *__restrict__ part, float4 *cs, int wave,
+                                              double *red) {
   const int lane = threadIdx.x & 63;
   const ModelDev md = models[it.m];
   const GeomDev g = geoms[md.geom];
@@ -393,9 +395,14 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
     yoff[by] = -__builtin_inff();
     if (yi < g.n_uy) { const double y = g.ys[yi]; y2[by] = (float)(y * y); yoff[by] = 0.f; }
   }
-  int t0, t1;
-  slice_range(g.T, md.n_slices, it.b, t0, t1, KC2);
-  const int n_ch = (st_ws[it.m] == 0) ? (t1 - t0 + KC2 - 1) / KC2 : 0;
+  int ts, te;
+  slice_range(g.T, md.n_slices, it.b, ts, te, KC2);
+  // this wave's quarter of the slice, in whole chunks
+  const int n_all = (st_ws[it.m] == 0) ? (te - ts + KC2 - 1) / KC2 : 0;
+  const int qn = (n_all + 3) / 4;
+  const int cb = min(n_all, wave * qn), ce = min(n_all, cb + qn);
+  const int n_ch = ce - cb;
+  const int t0 = ts + cb * KC2, t1 = min(te, ts + ce * KC2);
   const float4 *tb = terms + md.term_off;
   double acc[BX][BY][16];
 #pragma unroll
@@ -464,6 +471,29 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[bx][by][r] += (double)d[bx][by][r];
   }
+  // fixed-order sum of the four waves' tiles: wave 0 adds those of waves
+  // 3, 2 and 1 in turn through one LDS tile
+  for (int src = 3; src >= 1; --src) {
+    __syncthreads();
+    if (wave == src) {
+#pragma unroll
+      for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+        for (int by = 0; by < BY; ++by)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) red[((bx * BY + by) * 16 + r) * 64 + lane] = acc[bx][by][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int bx = 0; bx < BX; ++bx)
+#pragma unroll
+        for (int by = 0; by < BY; ++by)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[bx][by][r] += red[((bx * BY + by) * 16 + r) * 64 + lane];
+    }
+  }
+  if (wave != 0) return;
   // padded, transposed partial map: every row and column of the tile exists,
   // so the stores need no bounds checks; lanes store consecutive y
   const int ldh = 32 * md.n_yt;
@@ -505,12 +535,12 @@ __global__ void __launch_bounds__(256) k_num_pix(const GeomDev *__restrict__ geo
   }
 }
 
-// Numerator, matrix-core form: every wave is a worker of its own.  With a
-// queue, each wave pulls the next item (largest first) from a device
-// counter; without one, wave w of workgroup b takes items 4 b + w, striding
-// by the grid.  Variants of different tile shapes share one launch; the
-// register budget is that of the 2x2 tile (two waves per SIMD, with the
-// MFMA accumulators in ordinary VGPRs).
+// Numerator, matrix-core form, over a work list of workgroup items.  With a
+// queue, every workgroup pulls the next item (largest first) from a device
+// counter (a persistent grid); without one, workgroups stride over the list.
+// Variants of different tile shapes share one launch; the register budget is
+// that of the 2x2 tile (two waves per SIMD, with the MFMA accumulators in
+// ordinary VGPRs).
 __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__ geoms,
                                                   const ModelDev *__restrict__ models,
                                                   const Item *__restrict__ items, int n_it,
@@ -518,24 +548,26 @@ __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__
                                                   const int *__restrict__ st_ws,
                                                   double *__restrict__ part, int *queue) {
   __shared__ __attribute__((aligned(16))) float4 cs[4][KC2];
-  const int lane = threadIdx.x & 63;
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int next;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int i = blockIdx.x * 4 + wave;
+  int i = blockIdx.x;
   for (;;) {
     if (queue) {
-      int v = 0;
-      if (lane == 0) v = atomicAdd(queue, 1);
-      i = __shfl(v, 0, 64);
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+      __syncthreads();
+      i = next;
+      __syncthreads();
     }
     if (i >= n_it) break;
     const Item it = items[i];
     switch (it.c) {
-      case 2: num_tile_item<1, 1>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
-      case 3: num_tile_item<2, 1>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
-      case 4: num_tile_item<1, 2>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
-      default: num_tile_item<2, 2>(it, geoms, models, terms, st_ws, part, cs[wave]); break;
+      case 2: num_tile_item<1, 1>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
+      case 3: num_tile_item<2, 1>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
+      case 4: num_tile_item<1, 2>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
+      default: num_tile_item<2, 2>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
     }
-    if (!queue) i += gridDim.x * 4;
+    if (!queue) i += gridDim.x;
   }
 }
 

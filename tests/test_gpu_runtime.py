@@ -55,11 +55,8 @@ def test_persistent_equals_one_workgroup_per_item(form):
     Vb, sb = _eval(b, w, p)
     assert np.all(sa == 0) and np.array_equal(Va, Vb)
     ia, ib = a.plan_info(w.geom_idx), b.plan_info(w.geom_idx)
-    # one worker per item: a workgroup (per-pixel form) or a wave, four per
-    # workgroup (matrix-core form)
-    per_wg = 1 if form == 1 else 4
-    assert ia["num_grid"] * per_wg <= ia["num_items"] + per_wg - 1
-    assert ib["num_grid"] == (ib["num_items"] + per_wg - 1) // per_wg
+    # one workgroup per item, or a persistent grid of at most as many
+    assert ia["num_grid"] <= ia["num_items"] and ib["num_grid"] == ib["num_items"]
     o = np.cumsum([0] + [w.geometries[i].n_bins for i in w.geom_idx])
     for m in (0, 7, 23):
         ref = ojam.vrms2(w.geometries[w.geom_idx[m]], w.params[m]).numpy()
