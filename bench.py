@@ -186,6 +186,71 @@ def time_chi2(torch, binding, w, dev, steps, form, launch, graph):
             "all_finite": ok}
 
 
+def time_mge_pipeline(torch, binding, dev, steps, n=4096):
+    """Per-proposal pipeline from profile parameters to chi^2 and its
+    gradient: 1-D MGE of a Chameleon light profile (21 Gaussians, Euler
+    order 10) -> lum_I0 of a small geometry -> v_rms^2 and chi^2 -> adjoint
+    -> gradient with respect to the profile components; n proposals per
+    launch.  Also the MGE kernels alone."""
+    import numpy as np
+    from paper_2504_01302_amd import inputs
+    sig = np.exp(np.linspace(np.log(0.02), np.log(20.0), 21))
+    base = inputs.config3(n).geometries[0]
+    K = len(sig)
+    g = inputs.Geometry(sig, np.full(K, 0.8), np.ones(K), base.mass_sigma, base.mass_q,
+                        base.mass_S0, base.bh_sigma, base.distance_mpc, base.nx, base.ny,
+                        base.pixsize, base.xc, base.yc, base.supersample, base.psf, base.n_bins,
+                        base.bin_index, base.n_u)
+    w = inputs.config3(n)
+    params = [inputs.Params(p.inc, np.full(K, float(np.mean(p.beta))), p.mass_scale, p.m_bh)
+              for p in w.params]
+    w = inputs.Workload("mge", [g], np.zeros(n, np.int32), params)
+    ctx = binding.Context([g])
+    ctx.set_kinematics(0, *inputs.kinematic_data(g.n_bins, seed=0))
+    par = binding.pack_params(w, dev, amplitudes=True)
+    rng = np.random.default_rng(7)
+    comp = np.zeros((n, 2, 3))
+    comp[:, 0] = np.c_[np.full(n, 1.0), rng.uniform(0.03, 0.08, n), np.full(n, 0.5)]
+    comp[:, 1] = np.c_[np.full(n, -1.0), rng.uniform(1.5, 3.0, n), np.full(n, 0.5)]
+    comp = torch.as_tensor(comp, device=dev)
+    ones = torch.ones(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    args = lambda amp: (w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                        amp.reshape(-1), par["mass_S0"])
+
+    def mge_only():
+        amp = binding.jam_mge1d(comp, sig, 10)
+        binding.jam_mge1d_vjp(comp, sig, amp, 10)
+
+    def pipeline():
+        amp = binding.jam_mge1d(comp, sig, 10)
+        c2, V, st = ctx.eval_chi2(*args(amp), keep_vrms2=True)
+        gr = ctx.vjp_chi2(*args(amp), ones, vrms2=V)
+        return c2, st, binding.jam_mge1d_vjp(comp, sig, gr["lum_I0"].reshape(n, K), 10)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_mge = timed(mge_only, steps)
+    ms_pipe = timed(pipeline, steps)
+    c2, st, gcomp = pipeline()
+    torch.cuda.synchronize()
+    ok = bool((st == 0).all().item()) and bool(torch.isfinite(c2).all().item()) and \
+        bool(torch.isfinite(gcomp).all().item())
+    ctx.close()
+    return {"proposals": n, "gaussians": K, "ms_mge_fwd_bwd": ms_mge,
+            "ms_profile_to_chi2_and_grad": ms_pipe,
+            "proposals_per_s": n * 1000.0 / ms_pipe, "all_finite": ok}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -339,6 +404,7 @@ def main():
                                       a.launch, a.graph),
             "chi2_4096_small": time_chi2(torch, binding, inputs.config3(4096), dev,
                                          max(3, a.steps // 4), a.form, a.launch, a.graph),
+            "mge_chi2_4096_small": time_mge_pipeline(torch, binding, dev, max(3, a.steps // 4)),
         }
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB

@@ -232,6 +232,33 @@ jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms
                         const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* One-dimensional multi-Gaussian expansion of radial profiles by the
+ * integral transform of Sect. 3.2 (eq. integral_transfer) evaluated with the
+ * Euler algorithm.  Each of n_prof profiles is a sum of n_comp cored power
+ * laws F(R) = sum_c a_c (R^2 + c_c^2)^(-p_c) of the elliptical radius R
+ * (this covers the paper's Chameleon and dPIE profiles, p = 1/2 pairs, its
+ * softened power law, p = (gamma - 1) / 2, and the p = 3/2 basis of its
+ * eNFW); comp is DEVICE double[n_prof][n_comp][3] = (a, c, p) with c >= 0.
+ * sigma (HOST, n_sigma strictly increasing positive values, equally spaced
+ * in log) are the Gaussians' dispersions; euler_p is the Euler order P
+ * (2P + 1 profile evaluations per Gaussian).  amp (DEVICE
+ * double[n_prof][n_sigma]) receives the peak amplitudes A_n of
+ * F(R) ~ sum_n A_n exp(-R^2 / (2 sigma_n^2)) (trapezoid weights in
+ * log sigma).  Used as lum_I0 / mass_S0 of a geometry whose Gaussians have
+ * these dispersions and a common axis ratio.  Limits: n_comp <= 64,
+ * n_sigma <= 64, 1 <= euler_p <= 20, n_prof <= 2^24; JAM_E_INVALID_ARG
+ * otherwise.  Asynchronous on `stream`; no allocation.                     */
+jam_status jam_mge1d(int32_t n_prof, int32_t n_comp, const double *comp, int32_t n_sigma,
+                     const double *sigma, int32_t euler_p, double *amp, void *stream);
+
+/* Adjoint of jam_mge1d: grad (DEVICE double[n_prof][n_comp][3]) receives
+ * sum_n cot[prof][n] d amp[prof][n] / d (a, c, p) for cot (DEVICE
+ * double[n_prof][n_sigma]), e.g. the lum_I0 / mass_S0 gradients of jam_vjp.
+ * Same arguments and limits as jam_mge1d.                                   */
+jam_status jam_mge1d_vjp(int32_t n_prof, int32_t n_comp, const double *comp, int32_t n_sigma,
+                         const double *sigma, int32_t euler_p, const double *cot, double *grad,
+                         void *stream);
+
 /* Kernel timing, for measurement.  enable = 1 clears the record and starts
  * bracketing every launch of the quadrature (numerator) kernel and of the
  * adjoint sensitivity kernel with HIP events on the caller's stream;

@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "JAM_OK", 1: "JAM_E_INVALID_ARG", 2: "JAM_E_DEPROJECTION",
 EXPORTED = ("jam_create", "jam_destroy", "jam_batch_sizes", "jam_workspace_size",
             "jam_prepare", "jam_eval_batch", "jam_eval", "jam_eval_maps", "jam_vjp",
             "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error",
-            "jam_set_kinematics", "jam_chi2", "jam_eval_chi2", "jam_vjp_chi2")
+            "jam_set_kinematics", "jam_chi2", "jam_eval_chi2", "jam_vjp_chi2", "jam_mge1d",
+            "jam_mge1d_vjp")
 
 
 class JamGeometry(ctypes.Structure):
@@ -101,6 +102,10 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]
     lib.jam_plan_info.argtypes = [c_void_p, c_int32, P_int32, P_int32]
     lib.jam_set_kinematics.argtypes = [c_void_p, c_int32, P_double, P_double]
+    lib.jam_mge1d.argtypes = [c_int32, c_int32, c_void_p, c_int32, P_double, c_int32, c_void_p,
+                              c_void_p]
+    lib.jam_mge1d_vjp.argtypes = [c_int32, c_int32, c_void_p, c_int32, P_double, c_int32,
+                                  c_void_p, c_void_p, c_void_p]
     lib.jam_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p, c_void_p,
                              c_void_p]
     lib.jam_eval_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
@@ -282,6 +287,34 @@ def jam_vjp_chi2(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, vr
     _check(load().jam_vjp_chi2(c_void_p(ctx), ctypes.byref(b), _ptr(vrms2), _ptr(cot),
                                ctypes.byref(gr), _ptr(ws), ws.numel() * ws.element_size(),
                                c_void_p(stream)))
+
+
+def jam_mge1d(comp, sigma, euler_p: int = 10, out=None, stream=None):
+    """Peak amplitudes [n_prof, n_sigma] of the 1-D MGE of cored power-law
+    profiles; comp is a float64 device tensor [n_prof, n_comp, 3]."""
+    import torch
+    comp = comp.contiguous()
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    amp = out if out is not None else torch.empty(comp.shape[0], len(sig), dtype=torch.float64,
+                                                  device=comp.device)
+    s = stream if stream is not None else torch.cuda.current_stream(comp.device).cuda_stream
+    _check(load().jam_mge1d(comp.shape[0], comp.shape[1], _ptr(comp), len(sig),
+                            sig.ctypes.data_as(P_double), int(euler_p), _ptr(amp), c_void_p(s)))
+    return amp
+
+
+def jam_mge1d_vjp(comp, sigma, cot, euler_p: int = 10, stream=None):
+    """Gradient [n_prof, n_comp, 3] of sum(cot * amp) with respect to comp."""
+    import torch
+    comp = comp.contiguous()
+    cot = cot.contiguous()
+    sig = np.ascontiguousarray(sigma, dtype=np.float64)
+    grad = torch.empty_like(comp)
+    s = stream if stream is not None else torch.cuda.current_stream(comp.device).cuda_stream
+    _check(load().jam_mge1d_vjp(comp.shape[0], comp.shape[1], _ptr(comp), len(sig),
+                                sig.ctypes.data_as(P_double), int(euler_p), _ptr(cot),
+                                _ptr(grad), c_void_p(s)))
+    return grad
 
 
 # ---------------------------------------------------------------------------

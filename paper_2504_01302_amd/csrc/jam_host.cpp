@@ -558,7 +558,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       }
     } else {
       for (int xt = 0; xt < d.n_sens_parts; ++xt)
-        for (int tt = 0; tt < (g.T + 255) / 256; ++tt) {
+        for (int tt = 0; tt < (g.T + jam::kSensTerms - 1) / jam::kSensTerms; ++tt) {
           it_sens.push_back({m, xt, tt, 1});
           c_sens.push_back(8.0 * 32.0 * g.n_uy);
         }
@@ -983,6 +983,58 @@ bool spd_inverse(int n, const double *c, std::vector<double> &inv) {
       inv[(size_t)i * n + j] = inv[(size_t)j * n + i] = (double)v;
     }
   return true;
+}
+
+// Constants of the one-dimensional MGE transform: Euler nodes
+// beta_k = P ln(10)/3 + i pi k and signed binomial weights (-1)^k xi_k,
+// k = 0..2P, and per Gaussian the factor w_n dlog(sigma) 2 10^(P/3) that,
+// with the transform's 2 sqrt(2 pi) and the expansion's 1/sqrt(2 pi), turns
+// sum_k (-1)^k xi_k Re F(sigma_n chi_k) into the peak amplitude.
+jam_status mge_constants(int32_t n_comp, int32_t n_sigma, const double *sigma, int32_t P,
+                         jam::MgeConst &k) {
+  if (n_comp < 1 || n_comp > jam::kMgeMaxComp)
+    return fail(JAM_E_INVALID_ARG, "n_comp must be in [1, %d]", jam::kMgeMaxComp);
+  if (n_sigma < 1 || n_sigma > jam::kMgeMaxSigma)
+    return fail(JAM_E_INVALID_ARG, "n_sigma must be in [1, %d]", jam::kMgeMaxSigma);
+  if (P < 1 || 2 * P + 1 > jam::kMgeMaxTerms)
+    return fail(JAM_E_INVALID_ARG, "euler_p must be in [1, %d]", (jam::kMgeMaxTerms - 1) / 2);
+  if (!sigma) return fail(JAM_E_INVALID_ARG, "sigma is NULL");
+  for (int n = 0; n < n_sigma; ++n) {
+    if (!(sigma[n] > 0.0) || !std::isfinite(sigma[n]))
+      return fail(JAM_E_INVALID_ARG, "sigma[%d] must be positive and finite", n);
+    if (n > 0 && !(sigma[n] > sigma[n - 1]))
+      return fail(JAM_E_INVALID_ARG, "sigma must be strictly increasing");
+  }
+  std::memset(&k, 0, sizeof k);
+  k.n_terms = 2 * P + 1;
+  k.n_sigma = n_sigma;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  k.beta_re = (double)(P * std::log(10.0L) / 3.0L);
+  long double xi[jam::kMgeMaxTerms] = {};
+  xi[0] = 0.5L;
+  for (int j = 1; j <= P; ++j) xi[j] = 1.0L;
+  const long double pw = std::ldexp(1.0L, -P);
+  xi[2 * P] = pw;
+  long double binom = 1.0L;   // binom(P, j), built up with j
+  for (int j = 1; j < P; ++j) {
+    binom = binom * (P - j + 1) / j;
+    xi[2 * P - j] = xi[2 * P - j + 1] + pw * binom;
+  }
+  for (int j = 0; j <= 2 * P; ++j) {
+    k.beta_im[j] = (double)(pi * j);
+    k.eta[j] = (double)((j % 2 ? -xi[j] : xi[j]));
+  }
+  const long double dlog =
+      n_sigma > 1 ? (std::log((long double)sigma[n_sigma - 1]) - std::log((long double)sigma[0])) /
+                        (n_sigma - 1)
+                  : 1.0L;
+  const long double f = 2.0L * std::pow(10.0L, P / 3.0L) * dlog;
+  for (int n = 0; n < n_sigma; ++n) {
+    k.sigma2[n] = sigma[n] * sigma[n];
+    const long double w = (n_sigma > 1 && (n == 0 || n == n_sigma - 1)) ? 0.5L : 1.0L;
+    k.scale[n] = (double)(w * f);
+  }
+  return JAM_OK;
 }
 
 jam_status check_kinematics(const jam_ctx *ctx, const jam_batch *b) {
@@ -1419,6 +1471,31 @@ jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms
   } else {
     launch_vjp(ctx, p, batch, vrms2, nullptr, grads, w, st, false, cot);
   }
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_mge1d(int32_t n_prof, int32_t n_comp, const double *comp, int32_t n_sigma,
+                     const double *sigma, int32_t euler_p, double *amp, void *stream) {
+  if (n_prof < 1 || n_prof > (1 << 24)) return fail(JAM_E_INVALID_ARG, "n_prof must be in [1, 2^24]");
+  if (!comp || !amp) return fail(JAM_E_INVALID_ARG, "comp and amp are required");
+  jam::MgeConst k;
+  const jam_status s = mge_constants(n_comp, n_sigma, sigma, euler_p, k);
+  if (s != JAM_OK) return s;
+  jam::launch_mge1d(n_prof, n_comp, comp, k, amp, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_mge1d_vjp(int32_t n_prof, int32_t n_comp, const double *comp, int32_t n_sigma,
+                         const double *sigma, int32_t euler_p, const double *cot, double *grad,
+                         void *stream) {
+  if (n_prof < 1 || n_prof > (1 << 24)) return fail(JAM_E_INVALID_ARG, "n_prof must be in [1, 2^24]");
+  if (!comp || !cot || !grad) return fail(JAM_E_INVALID_ARG, "comp, cot and grad are required");
+  jam::MgeConst k;
+  const jam_status s = mge_constants(n_comp, n_sigma, sigma, euler_p, k);
+  if (s != JAM_OK) return s;
+  jam::launch_mge1d_vjp(n_prof, n_comp, comp, k, cot, grad, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return JAM_OK;
 }

@@ -62,6 +62,23 @@ struct KinDev {
   const double *vobs, *prec;
 };
 constexpr int kChi2MaxBins = 4096;
+constexpr int kSensTerms = 512;   // terms per matrix-core sensitivity item
+
+// Constants of the one-dimensional MGE transform (Euler inversion), passed
+// by value: nodes beta_k = beta_re + i beta_im[k] and signed weights eta[k]
+// (k < n_terms = 2P + 1); per Gaussian n < n_sigma its sigma^2 and the
+// factor turning sum_k eta_k Re F(sigma chi_k) into its peak amplitude.
+constexpr int kMgeMaxTerms = 41;
+constexpr int kMgeMaxSigma = 64;
+constexpr int kMgeMaxComp = 64;
+struct MgeConst {
+  int n_terms, n_sigma;
+  double beta_re;
+  double beta_im[kMgeMaxTerms];
+  double eta[kMgeMaxTerms];
+  double sigma2[kMgeMaxSigma];
+  double scale[kMgeMaxSigma];
+};
 
 // A unit of work of one kernel: model m and up to three kernel-specific
 // indices (pixel block, tile, slice, bin, ...).
@@ -118,7 +135,7 @@ void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, in
                          const double *vrms2, const double *cot, const double *binws,
                          const int *st_ws, double *pix, hipStream_t st);
 // Sensitivities, variant in Item::c: 0 per-pixel VALU (m, 256-term block),
-// 1 MFMA (m, 32-row x tile, 256-term tile); queue as launch_num.
+// 1 MFMA (m, 32-row x tile, tile of kSensTerms terms); queue as launch_num.
 void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const float4 *terms, const double *pix, const int *st_ws, double *sens,
                  int *queue, int grid, hipStream_t st);
@@ -132,6 +149,13 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st);
+// One-dimensional MGE of n_prof profiles, each a sum of n_comp cored power
+// laws (a, c, p) = comp[prof][comp][0..2]: amp[prof][n] (device).
+void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,
+                  hipStream_t st);
+// grad[prof][comp][0..2] = sum_n cot[prof][n] d amp[prof][n] / d (a, c, p).
+void launch_mge1d_vjp(int n_prof, int n_comp, const double *comp, const MgeConst &k,
+                      const double *cot, double *grad, hipStream_t st);
 // chi^2 per model from V (packed per bin); chi2 and dV may be NULL.  dV gets
 // cot[m] * d chi^2_m / dV_b (cot NULL: 1).  st_ws may be NULL.
 void launch_chi2(const GeomDev *g, const ModelDev *m, int n, const KinDev *kin, const double *V,

@@ -777,16 +777,16 @@ __device__ __forceinline__ void sens_pix_item(const Item it, const GeomDev *__re
 //   G[x, t] = sum_y lambda[x, y] F_t(y),   H[x, t] = sum_y lambda[x, y] y^2 F_t(y)
 // are two FP32 contractions over y sharing the lambda operand, and
 //   S0_t = sum_x E G,  S1_t = sum_x x^2 E G,  Sg_t = sum_x E (C0 + C1 x^2) H.
-// Item (m, 32-row x tile, 256-term tile); wave w owns terms 64 w .. 64 w + 63
-// of the tile and takes them as two 32-term column blocks one after the
+// Item (m, 32-row x tile, tile of kSensTerms terms); wave w owns a quarter
+// of the tile's terms and takes them as 32-term column blocks one after the
 // other (lane l: term l % 32, y pair l / 32), so only one block's FP64
 // accumulators are live.  lambda is staged through LDS 256 rows of y at a
 // time (once per item when the map has at most 256 distinct |y|); FP32
-// partial sums over 64 y values are folded into FP64.  Output: per x tile,
+// partial sums over 128 y values are folded into FP64.  Output: per x tile,
 // [S0 | S1 | Sg] (T doubles each).
 // ---------------------------------------------------------------------------
 constexpr int YC = 256;
-constexpr int kSensTerms = 256;   // terms per MFMA sensitivity item (64 per wave)
+constexpr int kSensWave = kSensTerms / 4;   // terms per wave of an item
 
 __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__restrict__ geoms,
                                                const ModelDev *__restrict__ models,
@@ -806,9 +806,9 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
   const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
   const int n_yb = (g.n_uy + YC - 1) / YC;
   const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int h = 0; h < 2; ++h) {
-    // this block's terms: it.b*kSensTerms + w*64 + h*32 + (0..31)
-    const int t = it.b * kSensTerms + wave * 64 + h * 32 + c32;
+  for (int h = 0; h < kSensWave / 32; ++h) {
+    // this block's terms: it.b*kSensTerms + w*kSensWave + h*32 + (0..31)
+    const int t = it.b * kSensTerms + wave * kSensWave + h * 32 + c32;
     const bool vt = t < g.T;
     const float4 c = vt ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double gacc[16], hacc[16];
@@ -832,18 +832,18 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
         }
         __syncthreads();
       }
-      for (int y0 = 0; y0 < ny; y0 += 64) {
-        // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2, 64 y values (rows
-        // past ny hold zero lambda; y0 + 63 < YC)
+      for (int y0 = 0; y0 < ny; y0 += 128) {
+        // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2, up to 128 y values
+        // in quarters of 32 (rows past ny hold zero lambda; y0 + 127 < YC)
         v16f dg = zero, dh = zero;
-        const int halves = (ny - y0 > 32) ? 2 : 1;   // uniform per block
+        const int quarters = min(4, (ny - y0 + 31) / 32);   // uniform per block
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          if (half >= halves) break;
+        for (int qy = 0; qy < 4; ++qy) {
+          if (qy >= quarters) break;
           float ra[16], ry[16];
 #pragma unroll
           for (int s2 = 0; s2 < 16; ++s2) {
-            const int yy = y0 + 32 * half + 2 * s2 + kh;
+            const int yy = y0 + 32 * qy + 2 * s2 + kh;
             ra[s2] = lam[yy][c32];
             ry[s2] = ysq[yy];
           }
@@ -1218,6 +1218,89 @@ __global__ void __launch_bounds__(256) k_chi2(const GeomDev *__restrict__ geoms,
   }
 }
 
+// ---------------------------------------------------------------------------
+// One-dimensional MGE of radial profiles (Sect. 3.2, eq. integral_transfer
+// and the Euler approximation after it).  A profile F(R) = sum_c a_c
+// (R^2 + c_c^2)^(-p_c) is expanded as F(R) ~ sum_n A_n exp(-R^2/(2 sigma_n^2))
+// with A_n = scale_n sum_k eta_k Re F(sigma_n chi_k), chi_k^2 = 2 beta_k, so
+// F is needed at R^2 = 2 sigma_n^2 beta_k, where Re(R^2) > 0 and the
+// principal logarithm of R^2 + c^2 is analytic.  FP64 throughout.
+// ---------------------------------------------------------------------------
+struct cplx {
+  double re, im;
+};
+__device__ inline cplx c_log(cplx z) { return {log(hypot(z.re, z.im)), atan2(z.im, z.re)}; }
+__device__ inline cplx c_exp(cplx z) {
+  double sn, cs;
+  sincos(z.im, &sn, &cs);
+  const double e = exp(z.re);
+  return {e * cs, e * sn};
+}
+__device__ inline cplx c_mul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ inline cplx c_div(cplx a, cplx b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Thread per (profile, Gaussian n); the terms k and components c are summed
+// in a fixed order.
+__global__ void __launch_bounds__(256) k_mge1d(int n_prof, int n_comp,
+                                               const double *__restrict__ comp, MgeConst kc,
+                                               double *__restrict__ amp) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n_prof * kc.n_sigma) return;
+  const int prof = (int)(id / kc.n_sigma), n = (int)(id % kc.n_sigma);
+  const double *cp = comp + (int64_t)prof * n_comp * 3;
+  double f = 0.0;
+  for (int k = 0; k < kc.n_terms; ++k) {
+    const cplx r2 = {2.0 * kc.sigma2[n] * kc.beta_re, 2.0 * kc.sigma2[n] * kc.beta_im[k]};
+    double fr = 0.0;   // Re F(R)
+    for (int c = 0; c < n_comp; ++c) {
+      const double a = cp[3 * c], cc = cp[3 * c + 1], p = cp[3 * c + 2];
+      const cplx L = c_log({r2.re + cc * cc, r2.im});
+      fr += a * c_exp({-p * L.re, -p * L.im}).re;
+    }
+    f += kc.eta[k] * fr;
+  }
+  amp[id] = kc.scale[n] * f;
+}
+
+// Thread per (profile, component): its three derivatives summed over the
+// Gaussians n (weighted by the cotangent) and the terms k in a fixed order.
+__global__ void __launch_bounds__(256) k_mge1d_vjp(int n_prof, int n_comp,
+                                                   const double *__restrict__ comp, MgeConst kc,
+                                                   const double *__restrict__ cot,
+                                                   double *__restrict__ grad) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n_prof * n_comp) return;
+  const int prof = (int)(id / n_comp);
+  const double *cp = comp + id * 3;
+  const double a = cp[0], cc = cp[1], p = cp[2];
+  double ga = 0.0, gc = 0.0, gp = 0.0;
+  for (int n = 0; n < kc.n_sigma; ++n) {
+    double da = 0.0, dc = 0.0, dp = 0.0;
+    for (int k = 0; k < kc.n_terms; ++k) {
+      const cplx w = {2.0 * kc.sigma2[n] * kc.beta_re + cc * cc, 2.0 * kc.sigma2[n] * kc.beta_im[k]};
+      const cplx L = c_log(w);
+      const cplx E = c_exp({-p * L.re, -p * L.im});          // w^-p
+      const cplx Ew = c_div(E, w);                            // w^-(p+1)
+      const double eta = kc.eta[k];
+      da += eta * E.re;
+      dc += eta * (-2.0 * p * cc * a) * Ew.re;
+      dp += eta * (-a) * c_mul(L, E).re;
+    }
+    const double s = kc.scale[n] * cot[(int64_t)prof * kc.n_sigma + n];
+    ga += s * da;
+    gc += s * dc;
+    gp += s * dp;
+  }
+  grad[id * 3] = ga;
+  grad[id * 3 + 1] = gc;
+  grad[id * 3 + 2] = gp;
+}
+
 inline int grid_of(int n_it) { return n_it < 1 ? 1 : n_it; }
 
 }  // namespace
@@ -1297,6 +1380,18 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
+}
+void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,
+                  hipStream_t st) {
+  const int64_t n = (int64_t)n_prof * k.n_sigma;
+  hipLaunchKernelGGL(k_mge1d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_prof, n_comp,
+                     comp, k, amp);
+}
+void launch_mge1d_vjp(int n_prof, int n_comp, const double *comp, const MgeConst &k,
+                      const double *cot, double *grad, hipStream_t st) {
+  const int64_t n = (int64_t)n_prof * n_comp;
+  hipLaunchKernelGGL(k_mge1d_vjp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_prof,
+                     n_comp, comp, k, cot, grad);
 }
 void launch_chi2(const GeomDev *g, const ModelDev *m, int n, const KinDev *kin, const double *V,
                  const int *st_ws, double *chi2, const double *cot, double *dV, hipStream_t st) {

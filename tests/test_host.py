@@ -117,3 +117,21 @@ def test_valid_geometry_needs_a_device_here():
     with pytest.raises(binding.JamError) as e:
         binding.jam_create([_good()])
     assert e.value.status == 5
+
+
+def test_mge1d_rejects_bad_arguments_before_any_launch():
+    """Argument errors of the 1-D MGE come back before the device is touched."""
+    import ctypes
+    lib = binding.load()
+    P = ctypes.POINTER(ctypes.c_double)
+    fake = ctypes.c_void_p(16)            # never dereferenced: the call fails first
+    def call(sig, n_sigma, p=10, n_comp=1, n_prof=1):
+        s = np.ascontiguousarray(sig, dtype=np.float64)
+        return lib.jam_mge1d(n_prof, n_comp, fake, n_sigma, s.ctypes.data_as(P), p, fake, None)
+    assert call([1.0, 0.5], 2) == 1                # not increasing
+    assert call([0.0, 0.5], 2) == 1                # not positive
+    assert call([0.1, 0.5], 2, p=0) == 1           # Euler order
+    assert call([0.1, 0.5], 2, p=21) == 1
+    assert call([0.1, 0.5], 2, n_comp=0) == 1
+    assert call([0.1, 0.5], 2, n_prof=0) == 1
+    assert call(np.linspace(0.1, 1, 65), 65) == 1  # too many Gaussians
