@@ -138,6 +138,36 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph):
             "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok}
 
 
+def time_spherical(torch, binding, w, dev, steps):
+    """Forward throughput of the spherically aligned model (eqs. J1, J2) on
+    one whole batch per launch (the adjoint is not built for it)."""
+    ctx = binding.Context(w.geometries, alignment=1)
+    par = binding.pack_params(w, dev)
+    nb, _, _ = ctx.sizes(w.geom_idx)
+    V = torch.empty(nb, dtype=torch.float64, device=dev)
+    st = torch.empty(len(w.geom_idx), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def fwd():
+        ctx.eval_batch(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                       out=V, status=st)
+
+    fwd()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fwd()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / steps
+    n = len(w.geom_idx)
+    ok = bool((st == 0).all().item())
+    ctx.close()
+    return {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
+            "all_status_ok": ok}
+
+
 def time_chi2(torch, binding, w, dev, steps, form, launch, graph):
     """chi^2 per proposal (eq. chi2_dyn) fused after the forward, and its
     adjoint, for a whole batch per launch (one scalar and one gradient per
@@ -405,6 +435,9 @@ def main():
             "chi2_4096_small": time_chi2(torch, binding, inputs.config3(4096), dev,
                                          max(3, a.steps // 4), a.form, a.launch, a.graph),
             "mge_chi2_4096_small": time_mge_pipeline(torch, binding, dev, max(3, a.steps // 4)),
+            "spherical_ifu_scale": time_spherical(torch, binding, w1, dev, max(3, a.steps // 4)),
+            "spherical_4096_small": time_spherical(torch, binding, inputs.config3(4096), dev,
+                                                   max(3, a.steps // 4)),
         }
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB

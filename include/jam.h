@@ -102,13 +102,22 @@ typedef struct {
  *       first).
  * graph: 1 = record each prepared composition's evaluation (and adjoint) as
  *       a HIP graph on first use and replay it while the call's pointers are
- *       unchanged (re-recorded when they change).                            */
+ *       unchanged (re-recorded when they change).
+ * alignment: 0 = cylindrically aligned velocity ellipsoid (beta_k = 1 -
+ *       v_z^2 / v_R^2 per luminous Gaussian; closed-form line-of-sight
+ *       integral); 1 = spherically aligned (eqs. J1, J2 of Sect. 2.4; beta_k
+ *       = 1 - v_theta^2 / v_r^2), solved along the characteristics of the
+ *       Jeans equations into a 128 x 24 polar table of the intrinsic moments
+ *       per model and integrated along the line of sight (64 nodes); forward
+ *       only (jam_vjp and jam_vjp_chi2 return JAM_E_UNSUPPORTED), form and
+ *       autotune do not apply.                                              */
 typedef struct {
   int32_t form;
   int32_t autotune;
   const char *tune_cache;
   int32_t launch;
   int32_t graph;
+  int32_t alignment;
 } jam_options;
 
 /* A batch of n >= 1 models.  geom_idx is HOST memory (n entries, each a

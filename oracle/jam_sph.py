@@ -251,7 +251,7 @@ def vrms2(geom, params):
     X, Y = np.meshgrid(x, y)
     N = numerator_table(geom, params, X.ravel(), Y.ravel(), table).reshape(X.shape)
     pt = ojam._param_tensors(geom, params)
-    I = ojam.surface_brightness(geom, pt["lum_I0"], torch.as_tensor(X), torch.as_tensor(Y))
+    I = ojam.surface_brightness(geom, pt["lum_I0"], X.ravel(), Y.ravel()).reshape(X.shape)
     Nb = ojam.bin_sums(ojam.convolve_valid(torch.as_tensor(N), geom.psf, h), geom)
     Ib = ojam.bin_sums(ojam.convolve_valid(I, geom.psf, h), geom)
     return (Nb / Ib).numpy()

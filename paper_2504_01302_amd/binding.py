@@ -49,7 +49,7 @@ class JamGeometry(ctypes.Structure):
 
 class JamOptions(ctypes.Structure):
     _fields_ = [("form", c_int32), ("autotune", c_int32), ("tune_cache", ctypes.c_char_p),
-                ("launch", c_int32), ("graph", c_int32)]
+                ("launch", c_int32), ("graph", c_int32), ("alignment", c_int32)]
 
 
 class JamBatch(ctypes.Structure):
@@ -151,10 +151,12 @@ def _geometry_struct(g, keep: list) -> JamGeometry:
 
 
 def jam_create(geometries: Sequence, form: int = 0, autotune: int = 0,
-               tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0) -> int:
+               tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0,
+               alignment: int = 0) -> int:
     keep: list = []
     arr = (JamGeometry * len(geometries))(*[_geometry_struct(g, keep) for g in geometries])
-    opt = JamOptions(form, autotune, tune_cache.encode() if tune_cache else None, launch, graph)
+    opt = JamOptions(form, autotune, tune_cache.encode() if tune_cache else None, launch, graph,
+                     alignment)
     out = c_void_p()
     _check(load().jam_create(len(geometries), arr, ctypes.byref(opt), ctypes.byref(out)))
     return out.value
@@ -329,9 +331,11 @@ class Context:
     """
 
     def __init__(self, geometries: Sequence, form: int = 0, autotune: int = 0,
-                 tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0):
+                 tune_cache: Optional[str] = None, launch: int = 0, graph: int = 0,
+                 alignment: int = 0):
         self.geometries = list(geometries)
-        self.handle = jam_create(self.geometries, form, autotune, tune_cache, launch, graph)
+        self.handle = jam_create(self.geometries, form, autotune, tune_cache, launch, graph,
+                                 alignment)
         self._ws = {}
 
     def close(self):

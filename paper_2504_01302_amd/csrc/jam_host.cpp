@@ -91,6 +91,9 @@ struct GeomHost {
   std::vector<int> ux, uy;
   std::vector<int> bin_ptr, bin_pix, pix_ptr, pix_bin;
   std::vector<double> bin_w, pix_w;
+  // spherically aligned model: polar table radii and the 8-node rule
+  double sph_lnr0 = 0, sph_dlnr = 0, sph_sig_max = 0;
+  double gl8_x[8] = {}, gl8_w[8] = {};
 };
 
 jam_status validate(const jam_geometry &g, int gi) {
@@ -237,6 +240,34 @@ void build_geometry(const jam_geometry &g, GeomHost &o) {
     }
 }
 
+// Polar table of the spherically aligned model: radii log-spaced from half
+// the smallest distance of a padded sub-pixel centre from the centre to
+// 12 max sigma'_k / min q'_k; and the 8-node Gauss-Legendre rule on [-1, 1].
+void build_spherical(GeomHost &o) {
+  double rmin = 0.0;
+  for (double x : o.xs)
+    for (double y : o.ys) {
+      const double r = std::sqrt(x * x + y * y);
+      if (r > 0.0 && (rmin == 0.0 || r < rmin)) rmin = r;
+    }
+  const double r_lo = rmin > 0.0 ? 0.5 * rmin : 1e-3;
+  double smax = 0.0, qmin = 1.0;
+  for (int k = 0; k < o.K; ++k) {
+    smax = std::max(smax, o.lum_sigma[k]);
+    qmin = std::min(qmin, o.lum_q[k]);
+  }
+  const double r_hi = 12.0 * smax / qmin;
+  o.sph_lnr0 = std::log(r_lo);
+  o.sph_dlnr = (std::log(r_hi) - std::log(r_lo)) / (jam::kSphNR - 1);
+  o.sph_sig_max = smax;
+  double u[8], w[8];
+  gauss_legendre01(8, u, w);
+  for (int i = 0; i < 8; ++i) {
+    o.gl8_x[i] = 2.0 * u[i] - 1.0;
+    o.gl8_w[i] = 2.0 * w[i];
+  }
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // How a plan schedules its numerator (what the autotuner varies).
@@ -271,15 +302,16 @@ struct Plan {
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
-            *d_red = nullptr;
+            *d_red = nullptr, *d_sph = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0;
+      n_sb = 0, n_red = 0, n_sph = 0;
+  bool spherical = false;
   int grid_num = 1, grid_sens = 1;
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
-         off_bins = 0, off_vfwd = 0, off_sens = 0, off_vtmp = 0, off_cot = 0, ws_fwd = 0,
-         ws_vjp = 0;
+         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sens = 0, off_vtmp = 0, off_cot = 0,
+         ws_fwd = 0, ws_vjp = 0;
   // captured evaluations (forward, adjoint, forward + chi^2, adjoint of chi^2)
   hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   GraphKey gkey[4];
@@ -315,7 +347,7 @@ struct jam_ctx {
   int device = 0;
   int n_cu = 256;
   int occ_num_pix = 1, occ_num_mfma = 1, occ_sens = 1;
-  jam_options opt{0, 0, nullptr, 0, 0};
+  jam_options opt{0, 0, nullptr, 0, 0, 0};
   std::string tune_path;
   std::vector<std::pair<std::string, Tune>> tuned;   // autotuner cache
   std::vector<GeomHost> gh;
@@ -515,9 +547,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red;
+      it_red, it_sph;
   std::vector<double> c_num, c_sens;
-  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0;
+  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0;
+  const bool spherical = ctx->opt.alignment == 1;
   for (int m = 0; m < n; ++m) {
     const int gi = geom_idx[m];
     const GeomHost &g = ctx->gh[gi];
@@ -540,6 +573,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     d.map_off = p->total_map;
     d.sens_off = sens;
     d.bin_off = bins;
+    d.sph_off = sph;
+    if (spherical) {
+      sph += (int64_t)jam::kSphNR * jam::kSphNT * 3;
+      for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
+    }
     gauss += jam::gauss_size(g.K, g.J1);
     terms += g.T;
     pixd += 4 * (int64_t)g.n_pix;
@@ -586,9 +624,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     return fail(JAM_E_UNSUPPORTED, "batch too large");
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 9;
+  constexpr int kLists = 10;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix,  &it_num, &it_bins, &it_maps,
-                                           &it_chain, &it_sens, &it_sb,  &it_red};
+                                           &it_chain, &it_sens, &it_sb,  &it_red,  &it_sph};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -610,9 +648,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   char *base = (char *)p->arena;
   p->d_models = (jam::ModelDev *)(base + o_models);
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins, &p->d_maps,
-                            &p->d_chain, &p->d_sens, &p->d_sb,  &p->d_red};
+                            &p->d_chain, &p->d_sens, &p->d_sb,  &p->d_red,  &p->d_sph};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins, &p->n_maps,
-                      &p->n_chain, &p->n_sens, &p->n_sb,  &p->n_red};
+                      &p->n_chain, &p->n_sens, &p->n_sb,  &p->n_red,  &p->n_sph};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -636,7 +674,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_part = w;   w = align256(w + sizeof(double) * part);
   p->off_bins = w;   w = align256(w + sizeof(double) * bins);
   p->off_vfwd = w;   w = align256(w + sizeof(double) * p->total_bins);
+  p->off_sph = w;    w = align256(w + sizeof(double) * sph);
   p->ws_fwd = w;
+  p->spherical = spherical;
   p->off_sens = w;   w = align256(w + sizeof(double) * sens);
   p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->off_cot = w;    w = align256(w + sizeof(double) * p->total_bins);
@@ -660,8 +700,18 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   double *pix = (double *)(ws + p->off_pix);
   double *part = (double *)(ws + p->off_part);
   jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
-  jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
+  if (!p->spherical)
+    jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
   jam::launch_sb(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, pd, pix, st);
+  if (p->spherical) {
+    if (!need_numerator) return;
+    double *tabs = (double *)(ws + p->off_sph);
+    const bool timed = ctx->t_num.begin(st, capturing);
+    jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, st_ws, tabs, st);
+    if (timed) ctx->t_num.end(st);
+    jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix, st);
+    return;
+  }
   if (need_numerator) {
     const bool timed = ctx->t_num.begin(st, capturing);
     jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
@@ -1117,6 +1167,8 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
     return fail(JAM_E_INVALID_ARG, "options.form must be 0, 1 or 2");
   if (opt && (opt->launch < 0 || opt->launch > 1))
     return fail(JAM_E_INVALID_ARG, "options.launch must be 0 or 1");
+  if (opt && (opt->alignment < 0 || opt->alignment > 1))
+    return fail(JAM_E_INVALID_ARG, "options.alignment must be 0 or 1");
   auto ctx = std::make_unique<jam_ctx>();
   if (opt) ctx->opt = *opt;
   if (opt && opt->tune_cache) ctx->tune_path = opt->tune_cache;
@@ -1133,7 +1185,10 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
     std::vector<std::thread> pool;
     for (unsigned t = 0; t < nt; ++t)
       pool.emplace_back([&, t] {
-        for (int i = (int)t; i < n_geom; i += (int)nt) build_geometry(geoms[i], ctx->gh[i]);
+        for (int i = (int)t; i < n_geom; i += (int)nt) {
+          build_geometry(geoms[i], ctx->gh[i]);
+          build_spherical(ctx->gh[i]);
+        }
       });
     for (auto &th : pool) th.join();
   }
@@ -1187,6 +1242,13 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
     d.pix_ptr = (const int *)put(o.pp, g.pix_ptr.data(), 4 * g.pix_ptr.size());
     d.pix_bin = (const int *)put(o.pb, g.pix_bin.data(), 4 * g.pix_bin.size());
     d.pix_w = (const double *)put(o.pw, g.pix_w.data(), 8 * g.pix_w.size());
+    d.sph_lnr0 = g.sph_lnr0;
+    d.sph_dlnr = g.sph_dlnr;
+    d.sph_sig_max = g.sph_sig_max;
+    for (int q = 0; q < 8; ++q) {
+      d.gl8_x[q] = g.gl8_x[q];
+      d.gl8_w[q] = g.gl8_w[q];
+    }
   }
   std::memcpy(stage.data(), gd.data(), sizeof(jam::GeomDev) * n_geom);
   HIP_TRY(hipMemcpy(ctx->arena, stage.data(), off, hipMemcpyHostToDevice));
@@ -1300,6 +1362,8 @@ jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map, do
 
 jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, const double *cot,
                    jam_grads *grads, void *ws, size_t ws_bytes, void *stream) {
+  if (ctx && ctx->opt.alignment == 1)
+    return fail(JAM_E_UNSUPPORTED, "the adjoint of the spherically aligned model is not built");
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   jam_status s = check_batch(batch);
   if (s != JAM_OK) return s;
@@ -1439,6 +1503,8 @@ jam_status jam_eval_chi2(jam_ctx *ctx, const jam_batch *batch, double *chi2, dou
 jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
                         const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
                         void *stream) {
+  if (ctx && ctx->opt.alignment == 1)
+    return fail(JAM_E_UNSUPPORTED, "the adjoint of the spherically aligned model is not built");
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   jam_status s = check_batch(batch);
   if (s != JAM_OK) return s;

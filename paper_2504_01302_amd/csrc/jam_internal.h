@@ -31,7 +31,20 @@ struct GeomDev {
   // forward) and by unique pixel (for the adjoint).
   const int *bin_ptr, *bin_pix;  const double *bin_w;   // [n_bins+1], [nnz]
   const int *pix_ptr, *pix_bin;  const double *pix_w;   // [n_pix+1],  [nnz]
+  // Spherically aligned model: polar table radii r_i = exp(sph_lnr0 + i
+  // sph_dlnr), i < kSphNR; the 8-node Gauss-Legendre rule on [-1, 1] of the
+  // composite quadratures.
+  double sph_lnr0, sph_dlnr, sph_sig_max;
+  double gl8_x[8], gl8_w[8];
 };
+
+// Spherically aligned model: polar table of kSphNR radii x kSphNT angles on
+// [0, pi/2] of (A_r, A_theta, A_phi); composite rules of kSphSeg segments of
+// 8 Gauss-Legendre nodes for the r' and line-of-sight integrals.
+constexpr int kSphNR = 128;
+constexpr int kSphNT = 24;
+constexpr int kSphSeg = 8;
+constexpr int kSphNodes = 8 * kSphSeg;   // 64
 
 // One model of a prepared batch; offsets into packed inputs/outputs and into
 // the caller's workspace regions.
@@ -53,6 +66,7 @@ struct ModelDev {
   int64_t map_off;   // doubles, padded full maps (jam_eval_maps)
   int64_t sens_off;  // doubles, per-term adjoint sensitivities + chain rows
   int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
+  int64_t sph_off;   // doubles, spherical moment table [kSphNR][kSphNT][3]
 };
 
 // Observed kinematics of one geometry for the chi^2 of eq. (chi2_dyn):
@@ -149,6 +163,15 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st);
+// Spherically aligned model.  Moments: items (m, table point i_r * kSphNT +
+// i_theta), one workgroup each, writing A_r, A_theta, A_phi into the model's
+// table.  Numerator: items (m, 64-pixel block), the line-of-sight integral of
+// the projected table into the unique-pixel N map.
+void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                        const double *gauss, const int *st_ws, double *table, hipStream_t st);
+void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                    const double *gauss, const int *st_ws, const double *table, double *pix,
+                    hipStream_t st);
 // One-dimensional MGE of n_prof profiles, each a sum of n_comp cored power
 // laws (a, c, p) = comp[prof][comp][0..2]: amp[prof][n] (device).
 void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,

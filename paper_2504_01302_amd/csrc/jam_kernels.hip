@@ -1301,6 +1301,225 @@ __global__ void __launch_bounds__(256) k_mge1d_vjp(int n_prof, int n_comp,
   grad[id * 3 + 2] = gp;
 }
 
+// ---------------------------------------------------------------------------
+// Spherically aligned model (eqs. J1, J2).  For tracer Gaussian k with
+// constant beta the Jeans equations integrate along the characteristics
+// r^(1-beta) sin(theta) = const:
+//   P_k = nu v_r^2 = r^(-2 beta) int_r^inf r'^(2 beta) nu (d_z Phi) / cos(theta') dr',
+//   d_theta P_k = r^(1 - 3 beta) cos(theta) I_D,
+//   I_D = int_r^inf r'^(3 beta + 1) R' nu [G_theta + G (1/q^2 - 1) / sigma^2] dr',
+//   nu v_phi^2 = (1 - beta) P + (1 - beta) sin(theta) r^(1 - 3 beta) I_D - nu R^2 G_phi,
+// with G = (d_z Phi) / z, G_theta and G_phi u-integrals over the mass
+// Gaussians (each term w K exp(-r_j u^2 (R^2 + z^2 / h)) times a polynomial
+// in u).  The moments summed over the tracers, A_r = sum P_k, A_theta =
+// sum (1 - beta_k) P_k and A_phi = sum nu v_phi^2_k, are tabulated on a polar
+// grid and interpolated along the line of sight.
+// ---------------------------------------------------------------------------
+constexpr int kSphChunk = 1024;   // (j, u) terms staged in LDS at a time
+
+// Item (m, table point).  In round q wave w takes tracer k = 4 q + w; lane l
+// is node l of the composite Gauss-Legendre rule in tau = ln(r'/r) on
+// [0, ln(r_max / r)], r_max^2 = r^2 + 50 sigma_k^2.  The terms' coefficients
+// go through LDS in chunks (FP32: exponent factors with -log2 e folded in,
+// and the G, G_theta, G_phi weights); the exps and sums over up to 64 terms
+// are FP32, everything else FP64; all sums run in a fixed order.
+__global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__ geoms,
+                                                     const ModelDev *__restrict__ models,
+                                                     const Item *__restrict__ items, int n_it,
+                                                     const double *__restrict__ gauss,
+                                                     const int *__restrict__ st_ws,
+                                                     double *__restrict__ table) {
+  __shared__ float4 tc[kSphChunk];   // (-c log2e, -d log2e, gP, gT)
+  __shared__ float tf[kSphChunk];    // gF
+  __shared__ double sh[256];
+  __shared__ double wred[3][4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr double kLog2e = 1.4426950408889634;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    double *out = table + md.sph_off + (int64_t)it.a * 3;
+    if (st_ws[it.m] != 0) {                 // uniform per block
+      if (threadIdx.x < 3) out[threadIdx.x] = 0.0;
+      continue;
+    }
+    const int K = g.K, J1 = g.J1, nu_n = g.n_u, T = J1 * nu_n;
+    const double *tab = gauss + md.gauss_off;
+    const double *mt = tab + 4 * K;
+    const int ir = it.a / kSphNT, ith = it.a % kSphNT;
+    const double r = exp(g.sph_lnr0 + ir * g.sph_dlnr);
+    const double th = ith * (0.5 * kPi / (kSphNT - 1));
+    const double sth = sin(th), cth = cos(th);
+    const double Rp0 = r * sth, zp0 = r * cth;
+    const float R20 = (float)(Rp0 * Rp0), Z20 = (float)(zp0 * zp0);
+    const int seg = lane >> 3, gi = lane & 7;
+    // the rule's node and weight of this lane, read from global memory (a
+    // lane-dependent index into the by-value descriptor would go to scratch)
+    const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
+    double Ar = 0.0, At = 0.0, Ap = 0.0;   // this wave's tracers (lane 0)
+    double accF = 0.0;                      // this thread's share of G_phi
+    const int rounds = (K + 3) / 4;
+    for (int q = 0; q < rounds; ++q) {
+      const int k = 4 * q + wave;
+      const bool on = k < K;                // uniform per wave
+      double alpha = 1.0, alphaq = 1.0, beta = 0.0, wn = 0.0, nuv = 0.0, rp = r, Rp = 0.0;
+      float R2 = 0.f, Z2 = 0.f;
+      if (on) {
+        alpha = tab[k];
+        alphaq = tab[K + k];
+        beta = 1.0 - 1.0 / tab[3 * K + k];
+        const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r));
+        const double hs = tmax / kSphSeg;
+        const double tau = (seg + 0.5 + 0.5 * glx) * hs;
+        rp = r * exp(tau);
+        const double st = fmin(1.0, sth * pow(r / rp, 1.0 - beta));
+        const double ct = sqrt(fmax(0.0, 1.0 - st * st));
+        Rp = rp * st;
+        const double zp = rp * ct;
+        R2 = (float)(Rp * Rp);
+        Z2 = (float)(zp * zp);
+        wn = 0.5 * glw * hs * rp;                  // dr' = r' dtau
+        nuv = tab[2 * K + k] * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
+      }
+      double accG = 0.0, accT = 0.0;
+      for (int c0 = 0; c0 < T; c0 += kSphChunk) {
+        const int cn = min(kSphChunk, T - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += 256) {
+          const int j = (c0 + t) / nu_n, n = (c0 + t) % nu_n;
+          const double rj = mt[j], e2 = mt[J1 + j], Kp = mt[2 * J1 + j];
+          const double u = g.u[n], u2 = u * u, wK = g.w[n] * Kp;
+          const double hh = 1.0 - e2 * u2, h15 = hh * sqrt(hh);
+          tc[t] = make_float4((float)(-rj * u2 * kLog2e), (float)(-rj * u2 / hh * kLog2e),
+                              (float)(wK * 2.0 * rj * u2 / h15),
+                              (float)(wK * e2 * 4.0 * rj * rj * u2 * u2 * u2 / (h15 * hh)));
+          tf[t] = (float)(wK * e2 * 2.0 * rj * u2 * u2 / h15);
+        }
+        __syncthreads();
+        if (on) {
+          for (int t0 = 0; t0 < cn; t0 += 64) {
+            const int t1 = min(cn, t0 + 64);
+            float sg = 0.f, sd = 0.f;
+            for (int t = t0; t < t1; ++t) {
+              const float4 c = tc[t];
+              const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
+              sg = fmaf(c.z, e, sg);
+              sd = fmaf(c.w, e, sd);
+            }
+            accG += (double)sg;
+            accT += (double)sd;
+          }
+        }
+        if (q == 0) {
+          for (int t = threadIdx.x; t < cn; t += 256) {
+            const float4 c = tc[t];
+            accF += (double)(tf[t] * fast_exp2(fmaf(c.x, R20, c.y * Z20)));
+          }
+        }
+      }
+      if (on) {
+        const double sk2 = 0.5 / alpha, qk2 = alpha / alphaq;
+        double fP = wn * pow(rp, 2.0 * beta + 1.0) * nuv * accG;
+        double fD = wn * pow(rp, 3.0 * beta + 1.0) * Rp * nuv *
+                    (accT + accG * (1.0 / qk2 - 1.0) / sk2);
+        fP = wave_sum(fP);
+        fD = wave_sum(fD);
+        const double P = pow(r, -2.0 * beta) * fP;
+        Ar += P;
+        At += (1.0 - beta) * P;
+        Ap += (1.0 - beta) * P + (1.0 - beta) * sth * pow(r, 1.0 - 3.0 * beta) * fD;
+      }
+    }
+    if (lane == 0) {
+      wred[0][wave] = Ar;
+      wred[1][wave] = At;
+      wred[2][wave] = Ap;
+    }
+    const double Gphi = block_sum256(accF, sh);   // synchronises the block
+    if (threadIdx.x == 0) {
+      double nus = 0.0;
+      for (int k = 0; k < K; ++k)
+        nus += tab[2 * K + k] * exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
+      out[0] = ((wred[0][0] + wred[0][1]) + wred[0][2]) + wred[0][3];
+      out[1] = ((wred[1][0] + wred[1][1]) + wred[1][2]) + wred[1][3];
+      out[2] = (((wred[2][0] + wred[2][1]) + wred[2][2]) + wred[2][3]) - nus * Rp0 * Rp0 * Gphi;
+    }
+    __syncthreads();
+  }
+}
+
+// Line-of-sight integral of the projected moment table into the unique-pixel
+// N map.  Item (m, 64-pixel block); thread = pixel.  Nodes z' = a sinh(w), w
+// on [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
+// a sinh(W) = 12 max_k sigma_k; the table is interpolated bilinearly in
+// (ln r, theta), the first radius standing for smaller ones and zero beyond
+// the last.  FP64.
+__global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geoms,
+                                                 const ModelDev *__restrict__ models,
+                                                 const Item *__restrict__ items, int n_it,
+                                                 const double *__restrict__ gauss,
+                                                 const int *__restrict__ st_ws,
+                                                 const double *__restrict__ table,
+                                                 double *__restrict__ pix) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)n_it * 64) return;
+  const Item it = items[gid >> 6];
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  const int q = it.a * 64 + (int)(gid & 63);
+  if (q >= g.n_pix) return;
+  double *Nout = pix + md.pix_off + q;
+  if (st_ws[it.m] != 0) {
+    *Nout = 0.0;
+    return;
+  }
+  const int K = g.K;
+  const double *tab = gauss + md.gauss_off;
+  const double *mt = tab + 4 * K;
+  const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
+  double smin = 1e300, smax = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
+    smin = fmin(smin, sk * qk);
+    smax = fmax(smax, sk);
+  }
+  const double a = 0.25 * smin, W = asinh(12.0 * smax / a);
+  const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
+  const double *T = table + md.sph_off;
+  const double dth = 0.5 * kPi / (kSphNT - 1);
+  const double hw = 2.0 * W / kSphSeg;
+  const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
+  double acc = 0.0;
+  for (int nd = 0; nd < kSphNodes; ++nd) {
+    const int seg = nd >> 3, gi = nd & 7;
+    const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
+    const double zp = a * sinh(w), wz = 0.5 * glw[gi] * hw * a * cosh(w);
+    const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
+    const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
+    const double ct = Z / r, st = R / r;
+    const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
+    const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
+    if (xf > kSphNR - 1) continue;
+    const double yf = acos(fmin(1.0, fabs(ct))) / dth;
+    const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
+    const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
+    const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
+    const double *c00 = T + ((int64_t)xi * kSphNT + yi) * 3;
+    const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
+    double A[3];
+    for (int f = 0; f < 3; ++f)
+      A[f] = (1 - fx) * (1 - fy) * c00[f] + fx * (1 - fy) * c10[f] + (1 - fx) * fy * c01[f] +
+             fx * fy * c11[f];
+    const double ner = si * st * sp + ci * ct;
+    const double net = si * ct * sp - ci * st;
+    const double nep = si * cp;
+    acc += wz * (ner * ner * A[0] + net * net * A[1] + nep * nep * A[2]);
+  }
+  *Nout = acc;
+}
+
 inline int grid_of(int n_it) { return n_it < 1 ? 1 : n_it; }
 
 }  // namespace
@@ -1380,6 +1599,17 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
+}
+void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                        const double *gauss, const int *st_ws, double *table, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_moments, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
+                     st_ws, table);
+}
+void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                    const double *gauss, const int *st_ws, const double *table, double *pix,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_num, dim3(grid_of((n_it + 3) / 4)), dim3(256), 0, st, g, m, it, n_it,
+                     gauss, st_ws, table, pix);
 }
 void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,
                   hipStream_t st) {

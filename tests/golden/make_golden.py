@@ -4,7 +4,7 @@ Every value here comes from the FP64 oracle (``oracle/``) evaluated on the
 seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
 from the GPU library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5]
+    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5] [sph1]
 """
 import json
 import os
@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import jam as ojam                      # noqa: E402
+from oracle import jam_sph as osph                  # noqa: E402
 from paper_2504_01302_amd import inputs              # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,8 +101,22 @@ def cfg5(n_models=256, n_check=8):
         checks=out))
 
 
+def sph1(n_models=3):
+    """Spherically aligned model on the config-1 geometry: all bins of the
+    config-1 model and of two seeded config-3 proposals (anisotropic)."""
+    t = time.time()
+    w1 = inputs.config1()
+    w3 = inputs.config3(n_models=8)
+    params = [w1.params[0]] + [w3.params[m] for m in (2, 5)][:n_models - 1]
+    V = [osph.vrms2(w1.geometries[0], p).tolist() for p in params]
+    _dump("sph_cfg1.json", dict(
+        source="oracle/jam_sph.py vrms2 on inputs.config1() model 0 and "
+               "inputs.config3(8) models 2 and 5 (config-1 geometry)",
+        config3_models=[2, 5], vrms2=V, seconds=time.time() - t))
+
+
 if __name__ == "__main__":
     torch.set_num_threads(max(1, os.cpu_count() or 1))
-    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5"]
+    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5", "sph1"]
     for name in todo:
         globals()[name]()
