@@ -48,6 +48,8 @@ def _args():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched workloads (4096 proposals on the small geometry, "
                          "1024 uneven models), reported under 'extra'")
+    ap.add_argument("--extra", default="",
+                    help="comma-separated names of the extra workloads to run (default all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, the reference "
                          "kernel for scaling the HBM byte counters of a profile")
@@ -427,18 +429,24 @@ def main():
         "plain_per_model_forward": plain,
     }
     if not a.no_extra:
-        rec["extra"] = {
-            "batched_4096_small": time_batch(torch, binding, inputs.config3(4096), dev,
-                                             max(3, a.steps // 4), a.form, a.launch, a.graph),
-            "uneven_1024": time_batch(torch, binding, inputs.config4(1024), dev, 2, a.form,
-                                      a.launch, a.graph),
-            "chi2_4096_small": time_chi2(torch, binding, inputs.config3(4096), dev,
-                                         max(3, a.steps // 4), a.form, a.launch, a.graph),
-            "mge_chi2_4096_small": time_mge_pipeline(torch, binding, dev, max(3, a.steps // 4)),
-            "spherical_ifu_scale": time_spherical(torch, binding, w1, dev, max(3, a.steps // 4)),
-            "spherical_4096_small": time_spherical(torch, binding, inputs.config3(4096), dev,
-                                                   max(3, a.steps // 4)),
+        k = max(3, a.steps // 4)
+        extras = {
+            "batched_4096_small": lambda: time_batch(torch, binding, inputs.config3(4096), dev,
+                                                     k, a.form, a.launch, a.graph),
+            "uneven_1024": lambda: time_batch(torch, binding, inputs.config4(1024), dev, 2,
+                                              a.form, a.launch, a.graph),
+            "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,
+                                                 a.form, a.launch, a.graph),
+            "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
+            "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
+            "spherical_4096_small": lambda: time_spherical(torch, binding, inputs.config3(4096),
+                                                           dev, k),
         }
+        names = [x for x in a.extra.split(",") if x] or list(extras)
+        unknown = [x for x in names if x not in extras]
+        if unknown:
+            sys.exit(f"unknown extra workload(s) {unknown}; known: {list(extras)}")
+        rec["extra"] = {x: extras[x]() for x in names}
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB
         dst = torch.empty_like(src)

@@ -579,7 +579,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
     }
     gauss += jam::gauss_size(g.K, g.J1);
-    terms += g.T;
+    const int tsph = jam::sph_terms_padded(g.J1, g.n_u);
+    terms += spherical ? tsph + tsph / 4 : g.T;   // spherical: float4 terms, then floats
     pixd += 4 * (int64_t)g.n_pix;
     part += (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);   // padded to whole blocks
     bins += 2 * (int64_t)g.n_bins;
@@ -588,7 +589,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     p->total_mass += g.J;
     p->total_bins += g.n_bins;
     p->total_map += (int64_t)g.nxp * g.nyp;
-    for (int tb = 0; tb < (g.T + 255) / 256; ++tb) it_terms.push_back({m, tb, 0, 0});
+    for (int tb = 0; tb < ((spherical ? tsph : g.T) + 255) / 256; ++tb)
+      it_terms.push_back({m, tb, 0, 0});
     if (d.form == 1) {
       for (int tb = 0; tb < (g.T + 255) / 256; ++tb) {
         it_sens.push_back({m, tb, 0, 0});
@@ -700,14 +702,18 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   double *pix = (double *)(ws + p->off_pix);
   double *part = (double *)(ws + p->off_part);
   jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
-  if (!p->spherical)
+  if (p->spherical)
+    jam::launch_sph_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms,
+                          st);
+  else
     jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
   jam::launch_sb(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, pd, pix, st);
   if (p->spherical) {
     if (!need_numerator) return;
     double *tabs = (double *)(ws + p->off_sph);
     const bool timed = ctx->t_num.begin(st, capturing);
-    jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, st_ws, tabs, st);
+    jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, terms, st_ws,
+                            tabs, st);
     if (timed) ctx->t_num.end(st);
     jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix, st);
     return;

@@ -45,6 +45,11 @@ constexpr int kSphNR = 128;
 constexpr int kSphNT = 24;
 constexpr int kSphSeg = 8;
 constexpr int kSphNodes = 8 * kSphSeg;   // 64
+// (j, u) terms of the spherical potential integrals, padded to whole groups
+// of 64; the per-model term region holds that many float4 plus as many floats.
+__host__ __device__ inline int sph_terms_padded(int J1, int n_u) {
+  return (J1 * n_u + 63) / 64 * 64;
+}
 
 // One model of a prepared batch; offsets into packed inputs/outputs and into
 // the caller's workspace regions.
@@ -163,12 +168,17 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const int *st_ws, GradsDev out, hipStream_t st);
-// Spherically aligned model.  Moments: items (m, table point i_r * kSphNT +
-// i_theta), one workgroup each, writing A_r, A_theta, A_phi into the model's
-// table.  Numerator: items (m, 64-pixel block), the line-of-sight integral of
-// the projected table into the unique-pixel N map.
+// Spherically aligned model.  Terms: items (m, block of 256 terms), the
+// model's FP32 (j, u) coefficients into its term region.  Moments: items (m,
+// table point i_r * kSphNT + i_theta), one workgroup each, writing A_r,
+// A_theta, A_phi into the model's table.  Numerator: items (m, 64-pixel
+// block), the line-of-sight integral of the projected table into the
+// unique-pixel N map.
+void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                      const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                        const double *gauss, const int *st_ws, double *table, hipStream_t st);
+                        const double *gauss, const float4 *terms, const int *st_ws, double *table,
+                        hipStream_t st);
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);

@@ -1317,16 +1317,54 @@ __global__ void __launch_bounds__(256) k_mge1d_vjp(int n_prof, int n_comp,
 // ---------------------------------------------------------------------------
 constexpr int kSphChunk = 1024;   // (j, u) terms staged in LDS at a time
 
+// FP32 coefficients of the (j, u) terms of G, G_theta and G_phi, once per
+// model: (-r_j u^2 log2e, -r_j u^2 / h log2e, gP, gT) and gF, zero-padded to
+// a whole number of 64-term groups (a zero term adds exactly nothing).
+// Item (m, block of 256 terms); thread = term.
+__global__ void __launch_bounds__(256) k_sph_terms(const GeomDev *__restrict__ geoms,
+                                                   const ModelDev *__restrict__ models,
+                                                   const Item *__restrict__ items, int n_it,
+                                                   const double *__restrict__ gauss,
+                                                   const int *__restrict__ st_ws,
+                                                   float4 *__restrict__ terms) {
+  constexpr double kLog2e = 1.4426950408889634;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const int nu_n = g.n_u, T = g.J1 * nu_n, Tp = sph_terms_padded(g.J1, nu_n);
+    const int t = it.a * 256 + threadIdx.x;
+    if (t >= Tp) continue;
+    float4 *tc = terms + md.term_off;
+    float *tf = (float *)(tc + Tp);
+    if (t >= T || st_ws[it.m] != 0) {
+      tc[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      tf[t] = 0.f;
+      continue;
+    }
+    const double *mt = gauss + md.gauss_off + 4 * g.K;
+    const int j = t / nu_n, n = t % nu_n;
+    const double rj = mt[j], e2 = mt[g.J1 + j], Kp = mt[2 * g.J1 + j];
+    const double u = g.u[n], u2 = u * u, wK = g.w[n] * Kp;
+    const double hh = 1.0 - e2 * u2, h15 = hh * sqrt(hh);
+    tc[t] = make_float4((float)(-rj * u2 * kLog2e), (float)(-rj * u2 / hh * kLog2e),
+                        (float)(wK * 2.0 * rj * u2 / h15),
+                        (float)(wK * e2 * 4.0 * rj * rj * u2 * u2 * u2 / (h15 * hh)));
+    tf[t] = (float)(wK * e2 * 2.0 * rj * u2 * u2 / h15);
+  }
+}
+
 // Item (m, table point).  In round q wave w takes tracer k = 4 q + w; lane l
 // is node l of the composite Gauss-Legendre rule in tau = ln(r'/r) on
-// [0, ln(r_max / r)], r_max^2 = r^2 + 50 sigma_k^2.  The terms' coefficients
-// go through LDS in chunks (FP32: exponent factors with -log2 e folded in,
-// and the G, G_theta, G_phi weights); the exps and sums over up to 64 terms
-// are FP32, everything else FP64; all sums run in a fixed order.
+// [0, ln(r_max / r)], r_max^2 = r^2 + 50 sigma_k^2.  The per-model term
+// coefficients go through LDS in chunks; each group of 64 terms is summed in
+// FP32 (fully unrolled, the coefficient reads are wave-wide broadcasts) and
+// folded into FP64; everything else is FP64; all sums run in a fixed order.
 __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
                                                      const Item *__restrict__ items, int n_it,
                                                      const double *__restrict__ gauss,
+                                                     const float4 *__restrict__ terms,
                                                      const int *__restrict__ st_ws,
                                                      double *__restrict__ table) {
   __shared__ float4 tc[kSphChunk];   // (-c log2e, -d log2e, gP, gT)
@@ -1335,7 +1373,6 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
   __shared__ double wred[3][4];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  constexpr double kLog2e = 1.4426950408889634;
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
@@ -1345,9 +1382,10 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       if (threadIdx.x < 3) out[threadIdx.x] = 0.0;
       continue;
     }
-    const int K = g.K, J1 = g.J1, nu_n = g.n_u, T = J1 * nu_n;
+    const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
+    const float4 *gtc = terms + md.term_off;
+    const float *gtf = (const float *)(gtc + Tp);
     const double *tab = gauss + md.gauss_off;
-    const double *mt = tab + 4 * K;
     const int ir = it.a / kSphNT, ith = it.a % kSphNT;
     const double r = exp(g.sph_lnr0 + ir * g.sph_dlnr);
     const double th = ith * (0.5 * kPi / (kSphNT - 1));
@@ -1384,26 +1422,20 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
         nuv = tab[2 * K + k] * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
       }
       double accG = 0.0, accT = 0.0;
-      for (int c0 = 0; c0 < T; c0 += kSphChunk) {
-        const int cn = min(kSphChunk, T - c0);
+      for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
+        const int cn = min(kSphChunk, Tp - c0);   // a multiple of 64
         __syncthreads();
         for (int t = threadIdx.x; t < cn; t += 256) {
-          const int j = (c0 + t) / nu_n, n = (c0 + t) % nu_n;
-          const double rj = mt[j], e2 = mt[J1 + j], Kp = mt[2 * J1 + j];
-          const double u = g.u[n], u2 = u * u, wK = g.w[n] * Kp;
-          const double hh = 1.0 - e2 * u2, h15 = hh * sqrt(hh);
-          tc[t] = make_float4((float)(-rj * u2 * kLog2e), (float)(-rj * u2 / hh * kLog2e),
-                              (float)(wK * 2.0 * rj * u2 / h15),
-                              (float)(wK * e2 * 4.0 * rj * rj * u2 * u2 * u2 / (h15 * hh)));
-          tf[t] = (float)(wK * e2 * 2.0 * rj * u2 * u2 / h15);
+          tc[t] = gtc[c0 + t];
+          tf[t] = gtf[c0 + t];
         }
         __syncthreads();
         if (on) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
-            const int t1 = min(cn, t0 + 64);
             float sg = 0.f, sd = 0.f;
-            for (int t = t0; t < t1; ++t) {
-              const float4 c = tc[t];
+#pragma unroll
+            for (int t = 0; t < 64; ++t) {
+              const float4 c = tc[t0 + t];
               const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
               sg = fmaf(c.z, e, sg);
               sd = fmaf(c.w, e, sd);
@@ -1600,10 +1632,16 @@ void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
                   const int *st_ws, GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
 }
+void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                      const double *gauss, const int *st_ws, float4 *terms, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_terms, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
+                     st_ws, terms);
+}
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                        const double *gauss, const int *st_ws, double *table, hipStream_t st) {
+                        const double *gauss, const float4 *terms, const int *st_ws, double *table,
+                        hipStream_t st) {
   hipLaunchKernelGGL(k_sph_moments, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
-                     st_ws, table);
+                     terms, st_ws, table);
 }
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
