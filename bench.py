@@ -218,6 +218,49 @@ def time_chi2(torch, binding, w, dev, steps, form, launch, graph):
             "all_finite": ok}
 
 
+def time_beta_profile(torch, binding, w, dev, steps):
+    """Radial anisotropy profile per proposal (4 numbers) sampled into the
+    per-Gaussian beta_k, chi^2 and its gradient back to the profile, for a
+    whole batch per launch."""
+    from paper_2504_01302_amd import inputs
+    ctx = binding.Context(w.geometries)
+    for gi, g in enumerate(w.geometries):
+        ctx.set_kinematics(gi, *inputs.kinematic_data(g.n_bins, seed=gi))
+    par = binding.pack_params(w, dev, amplitudes=True)
+    n = len(w.geom_idx)
+    rng = np.random.default_rng(7)
+    prof = torch.as_tensor(np.stack([rng.uniform(-0.4, 0.0, n), rng.uniform(0.0, 0.4, n),
+                                     10.0 ** rng.uniform(-1.5, 0.5, n), rng.uniform(1.0, 3.0, n)],
+                                    axis=1), device=dev)
+    cot = torch.ones(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    state = {}
+
+    def step():
+        beta = ctx.beta_logistic(w.geom_idx, prof)
+        args = (w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], beta, par["lum_I0"],
+                par["mass_S0"])
+        c2, V, st = ctx.eval_chi2(*args, keep_vrms2=True)
+        g = ctx.vjp_chi2(*args, cot, vrms2=V)
+        state["gp"] = ctx.beta_logistic_vjp(w.geom_idx, prof, g["beta"])
+        state["ok"] = (st, c2)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st, c2 = state["ok"]
+    ok = bool((st == 0).all().item()) and bool(torch.isfinite(state["gp"]).all().item())
+    ctx.close()
+    return {"models": n, "ms_profile_to_chi2_and_grad": ms, "per_s": n * 1000.0 / ms,
+            "all_finite": ok}
+
+
 def time_mge_pipeline(torch, binding, dev, steps, n=4096):
     """Per-proposal pipeline from profile parameters to chi^2 and its
     gradient: 1-D MGE of a Chameleon light profile (21 Gaussians, Euler
@@ -438,6 +481,8 @@ def main():
             "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,
                                                  a.form, a.launch, a.graph),
             "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
+            "beta_profile_chi2_4096_small": lambda: time_beta_profile(
+                torch, binding, inputs.config3(4096), dev, k),
             "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
             "spherical_4096_small": lambda: time_spherical(torch, binding, inputs.config3(4096),
                                                            dev, k),

@@ -268,6 +268,27 @@ jam_status jam_mge1d_vjp(int32_t n_prof, int32_t n_comp, const double *comp, int
                          const double *sigma, int32_t euler_p, const double *cot, double *grad,
                          void *stream);
 
+/* Radially varying orbital anisotropy (Sect. 6: tangential near the centre,
+ * radial outside).  For each model m of the batch (only batch->n and
+ * batch->geom_idx are read) prof (DEVICE double[n][4]) holds a logistic
+ * profile in log r, (beta_0, beta_inf, r_a [arcsec], alpha):
+ *   beta(r) = beta_0 + (beta_inf - beta_0) / (1 + (r_a / r)^alpha),
+ * and beta (DEVICE, packed like jam_batch.beta) receives it sampled at every
+ * tracer Gaussian's dispersion, beta_k = beta(sigma'_k) (the Jeans solutions
+ * take one constant anisotropy per Gaussian).  A model whose r_a or alpha is
+ * not positive and finite gets NaN, which jam_eval_batch reports as
+ * JAM_E_NONPHYSICAL.  Prepares the batch composition's plan if needed;
+ * asynchronous on `stream`; no other allocation.                            */
+jam_status jam_beta_logistic(jam_ctx *ctx, const jam_batch *batch, const double *prof, double *beta,
+                             void *stream);
+
+/* Adjoint of jam_beta_logistic: grad (DEVICE double[n][4]) receives
+ * sum_k cot_k d beta_k / d (beta_0, beta_inf, r_a, alpha) for cot (DEVICE,
+ * packed like beta; e.g. the beta gradient of jam_vjp); NaN for an invalid
+ * profile.  Fixed-order sums.                                               */
+jam_status jam_beta_logistic_vjp(jam_ctx *ctx, const jam_batch *batch, const double *prof,
+                                 const double *cot, double *grad, void *stream);
+
 /* Kernel timing, for measurement.  enable = 1 clears the record and starts
  * bracketing every launch of the quadrature (numerator) kernel and of the
  * adjoint sensitivity kernel with HIP events on the caller's stream;

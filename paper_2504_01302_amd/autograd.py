@@ -1,6 +1,7 @@
 """torch.autograd.Functions over the library: forward = jam_eval_batch,
-backward = jam_vjp; and the chi^2 of eq. (chi2_dyn), forward =
-jam_eval_chi2, backward = jam_vjp_chi2.
+backward = jam_vjp; the chi^2 of eq. (chi2_dyn), forward = jam_eval_chi2,
+backward = jam_vjp_chi2; and the radial anisotropy profile, forward =
+jam_beta_logistic, backward = jam_beta_logistic_vjp.
 
 Only the per-bin output v_rms^2 is saved for the backward pass (a few
 doubles per model); every other forward intermediate is recomputed inside
@@ -77,3 +78,24 @@ def jam_chi2(jctx: binding.Context, geom_idx, inc, mass_scale, m_bh, beta,
     """Differentiable chi^2 per model (eq. chi2_dyn; kinematics set on the
     context with ``set_kinematics``) and the per-model status."""
     return JamChi2.apply(jctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+
+
+class BetaLogistic(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, jctx, geom_idx, prof):
+        ctx.jctx = jctx
+        ctx.geom_idx = geom_idx
+        ctx.save_for_backward(prof)
+        return jctx.beta_logistic(geom_idx, prof)
+
+    @staticmethod
+    def backward(ctx, gbeta):
+        (prof,) = ctx.saved_tensors
+        return None, None, ctx.jctx.beta_logistic_vjp(ctx.geom_idx, prof,
+                                                      gbeta.contiguous().to(torch.float64))
+
+
+def beta_logistic(jctx: binding.Context, geom_idx, prof):
+    """Differentiable packed beta_k of logistic anisotropy profiles
+    prof [n, 4] = (beta_0, beta_inf, r_a, alpha), one per model."""
+    return BetaLogistic.apply(jctx, geom_idx, prof)

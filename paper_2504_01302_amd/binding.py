@@ -34,7 +34,7 @@ EXPORTED = ("jam_create", "jam_destroy", "jam_batch_sizes", "jam_workspace_size"
             "jam_prepare", "jam_eval_batch", "jam_eval", "jam_eval_maps", "jam_vjp",
             "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error",
             "jam_set_kinematics", "jam_chi2", "jam_eval_chi2", "jam_vjp_chi2", "jam_mge1d",
-            "jam_mge1d_vjp")
+            "jam_mge1d_vjp", "jam_beta_logistic", "jam_beta_logistic_vjp")
 
 
 class JamGeometry(ctypes.Structure):
@@ -108,6 +108,10 @@ def load(path: str = LIB_PATH):
                                   c_void_p, c_void_p, c_void_p]
     lib.jam_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p, c_void_p,
                              c_void_p]
+    lib.jam_beta_logistic.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
+                                      c_void_p]
+    lib.jam_beta_logistic_vjp.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
+                                          c_void_p, c_void_p]
     lib.jam_eval_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]
     lib.jam_vjp_chi2.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
@@ -291,6 +295,20 @@ def jam_vjp_chi2(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0, vr
                                c_void_p(stream)))
 
 
+def jam_beta_logistic(ctx, geom_idx, prof, beta, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, None, None, None, None, None, None)
+    _check(load().jam_beta_logistic(c_void_p(ctx), ctypes.byref(b), _ptr(prof), _ptr(beta),
+                                    c_void_p(stream)))
+
+
+def jam_beta_logistic_vjp(ctx, geom_idx, prof, cot, grad, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, None, None, None, None, None, None)
+    _check(load().jam_beta_logistic_vjp(c_void_p(ctx), ctypes.byref(b), _ptr(prof), _ptr(cot),
+                                        _ptr(grad), c_void_p(stream)))
+
+
 def jam_mge1d(comp, sigma, euler_p: int = 10, out=None, stream=None):
     """Peak amplitudes [n_prof, n_sigma] of the 1-D MGE of cored power-law
     profiles; comp is a float64 device tensor [n_prof, n_comp, 3]."""
@@ -411,6 +429,26 @@ class Context:
                 g["inc"], g["mass_scale"], g["m_bh"], g["beta"], g["lum_I0"], g["mass_S0"], ws, s)
         return g
 
+
+    def beta_logistic(self, geom_idx, prof, out=None, stream=None):
+        """Packed beta_k from logistic anisotropy profiles prof [n, 4] =
+        (beta_0, beta_inf, r_a, alpha), sampled at each tracer sigma."""
+        import torch
+        prof = prof.contiguous()
+        _, nl, _ = self.sizes(geom_idx)
+        beta = out if out is not None else torch.empty(nl, dtype=torch.float64, device=prof.device)
+        s = stream if stream is not None else torch.cuda.current_stream(prof.device).cuda_stream
+        jam_beta_logistic(self.handle, geom_idx, prof, beta, s)
+        return beta
+
+    def beta_logistic_vjp(self, geom_idx, prof, cot, stream=None):
+        """Gradient [n, 4] of sum(cot * beta) with respect to the profiles."""
+        import torch
+        prof = prof.contiguous()
+        grad = torch.empty_like(prof)
+        s = stream if stream is not None else torch.cuda.current_stream(prof.device).cuda_stream
+        jam_beta_logistic_vjp(self.handle, geom_idx, prof, cot.contiguous(), grad, s)
+        return grad
 
     def set_kinematics(self, geom: int, vrms_obs, cov):
         jam_set_kinematics(self.handle, geom, vrms_obs, cov)

@@ -1572,6 +1572,37 @@ jam_status jam_mge1d_vjp(int32_t n_prof, int32_t n_comp, const double *comp, int
   return JAM_OK;
 }
 
+jam_status jam_beta_logistic(jam_ctx *ctx, const jam_batch *batch, const double *prof, double *beta,
+                             void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  if (!batch || batch->n < 1 || !batch->geom_idx) return fail(JAM_E_INVALID_ARG, "invalid batch");
+  if (!prof || !beta) return fail(JAM_E_INVALID_ARG, "prof and beta are required");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  const jam_status s = get_plan(ctx, batch->n, batch->geom_idx, p);
+  if (s != JAM_OK) return s;
+  jam::launch_beta_logistic(ctx->d_geoms, p->d_models, p->n, prof, beta, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
+jam_status jam_beta_logistic_vjp(jam_ctx *ctx, const jam_batch *batch, const double *prof,
+                                 const double *cot, double *grad, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  if (!batch || batch->n < 1 || !batch->geom_idx) return fail(JAM_E_INVALID_ARG, "invalid batch");
+  if (!prof || !cot || !grad) return fail(JAM_E_INVALID_ARG, "prof, cot and grad are required");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = nullptr;
+  const jam_status s = get_plan(ctx, batch->n, batch->geom_idx, p);
+  if (s != JAM_OK) return s;
+  jam::launch_beta_logistic_vjp(ctx->d_geoms, p->d_models, p->n, prof, cot, grad,
+                                (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
+}
+
 jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t *info) {
   if (!ctx || !info) return fail(JAM_E_INVALID_ARG, "invalid arguments");
   DeviceGuard dg(ctx->device);

@@ -182,6 +182,13 @@ void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);
+// Logistic radial anisotropy profile prof[m][0..3] = (beta_0, beta_inf, r_a,
+// alpha) sampled at every tracer Gaussian's sigma into the packed beta, and
+// its adjoint grad[m][0..3] from the packed cotangent of beta.
+void launch_beta_logistic(const GeomDev *g, const ModelDev *m, int n, const double *prof,
+                          double *beta, hipStream_t st);
+void launch_beta_logistic_vjp(const GeomDev *g, const ModelDev *m, int n, const double *prof,
+                              const double *cot, double *grad, hipStream_t st);
 // One-dimensional MGE of n_prof profiles, each a sum of n_comp cored power
 // laws (a, c, p) = comp[prof][comp][0..2]: amp[prof][n] (device).
 void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,

@@ -1482,6 +1482,66 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Radial anisotropy profile sampled per tracer Gaussian (Sect. 6):
+// beta_k = beta_0 + (beta_inf - beta_0) / (1 + (r_a / sigma_k)^alpha).
+// Block per model, thread per Gaussian; an invalid profile (r_a or alpha not
+// positive and finite) gives NaN, which the forward's set-up reports.
+// ---------------------------------------------------------------------------
+__device__ inline bool logistic_ok(const double *pf) {
+  return pf[2] > 0.0 && pf[3] > 0.0 && isfinite(pf[2]) && isfinite(pf[3]) && isfinite(pf[0]) &&
+         isfinite(pf[1]);
+}
+
+__global__ void __launch_bounds__(256) k_beta_logistic(const GeomDev *__restrict__ geoms,
+                                                       const ModelDev *__restrict__ models, int n,
+                                                       const double *__restrict__ prof,
+                                                       double *__restrict__ beta) {
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const ModelDev md = models[m];
+    const GeomDev g = geoms[md.geom];
+    const double *pf = prof + 4 * (int64_t)m;
+    const bool ok = logistic_ok(pf);
+    for (int k = threadIdx.x; k < g.K; k += blockDim.x) {
+      const double x = pow(pf[2] / g.lum_sigma[k], pf[3]);
+      beta[md.lum_off + k] = ok ? pf[0] + (pf[1] - pf[0]) / (1.0 + x) : __builtin_nan("");
+    }
+  }
+}
+
+// grad[m][0..3] = sum_k cot_k d beta_k / d (beta_0, beta_inf, r_a, alpha); the
+// sum over k runs in a fixed order (thread strides, then the block sum).
+__global__ void __launch_bounds__(256) k_beta_logistic_vjp(const GeomDev *__restrict__ geoms,
+                                                           const ModelDev *__restrict__ models,
+                                                           int n, const double *__restrict__ prof,
+                                                           const double *__restrict__ cot,
+                                                           double *__restrict__ grad) {
+  __shared__ double sh[256];
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const ModelDev md = models[m];
+    const GeomDev g = geoms[md.geom];
+    const double *pf = prof + 4 * (int64_t)m;
+    const bool ok = logistic_ok(pf);
+    const double d = pf[1] - pf[0];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < g.K; k += blockDim.x) {
+      const double lr = log(pf[2] / g.lum_sigma[k]);
+      const double x = exp(pf[3] * lr), f = 1.0 / (1.0 + x);
+      const double c = cot[md.lum_off + k];
+      const double dfx = -f * f * x;                  // x df/dx
+      a[0] += c * (1.0 - f);
+      a[1] += c * f;
+      a[2] += c * d * dfx * pf[3] / pf[2];
+      a[3] += c * d * dfx * lr;
+    }
+    for (int i = 0; i < 4; ++i) {
+      const double s = block_sum256(a[i], sh);
+      if (threadIdx.x == 0) grad[4 * (int64_t)m + i] = ok ? s : __builtin_nan("");
+      __syncthreads();
+    }
+  }
+}
+
 // Line-of-sight integral of the projected moment table into the unique-pixel
 // N map.  Item (m, 64-pixel block); thread = pixel.  Nodes z' = a sinh(w), w
 // on [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
@@ -1648,6 +1708,15 @@ void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_i
                     hipStream_t st) {
   hipLaunchKernelGGL(k_sph_num, dim3(grid_of((n_it + 3) / 4)), dim3(256), 0, st, g, m, it, n_it,
                      gauss, st_ws, table, pix);
+}
+void launch_beta_logistic(const GeomDev *g, const ModelDev *m, int n, const double *prof,
+                          double *beta, hipStream_t st) {
+  hipLaunchKernelGGL(k_beta_logistic, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, prof, beta);
+}
+void launch_beta_logistic_vjp(const GeomDev *g, const ModelDev *m, int n, const double *prof,
+                              const double *cot, double *grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_beta_logistic_vjp, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, prof, cot,
+                     grad);
 }
 void launch_mge1d(int n_prof, int n_comp, const double *comp, const MgeConst &k, double *amp,
                   hipStream_t st) {
