@@ -140,21 +140,28 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph):
             "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok}
 
 
-def time_spherical(torch, binding, w, dev, steps):
-    """Forward throughput of the spherically aligned model (eqs. J1, J2) on
-    one whole batch per launch (the adjoint is not built for it)."""
+def time_spherical(torch, binding, w, dev, steps, backward=True):
+    """Forward and forward+adjoint throughput of the spherically aligned
+    model (eqs. J1, J2) on one whole batch per launch."""
     ctx = binding.Context(w.geometries, alignment=1)
-    par = binding.pack_params(w, dev)
+    par = binding.pack_params(w, dev, amplitudes=True)
     nb, _, _ = ctx.sizes(w.geom_idx)
     V = torch.empty(nb, dtype=torch.float64, device=dev)
     st = torch.empty(len(w.geom_idx), dtype=torch.int32, device=dev)
+    cot = torch.ones(nb, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
     def fwd():
         ctx.eval_batch(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
-                       out=V, status=st)
+                       par["lum_I0"], par["mass_S0"], out=V, status=st)
+
+    def bwd():
+        return ctx.vjp(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                       par["lum_I0"], par["mass_S0"], V, cot)
 
     fwd()
+    if backward:
+        g = bwd()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -164,10 +171,20 @@ def time_spherical(torch, binding, w, dev, steps):
     torch.cuda.synchronize()
     ms_f = e0.elapsed_time(e1) / steps
     n = len(w.geom_idx)
-    ok = bool((st == 0).all().item())
+    rec = {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f}
+    if backward:
+        e0.record(stream)
+        for _ in range(steps):
+            fwd()
+            g = bwd()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_fb = e0.elapsed_time(e1) / steps
+        rec.update(ms_fwd_bwd=ms_fb, fwd_bwd_per_s=n * 1000.0 / ms_fb,
+                   grads_finite=bool(torch.isfinite(g["inc"]).all().item()))
+    rec["all_status_ok"] = bool((st == 0).all().item())
     ctx.close()
-    return {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
-            "all_status_ok": ok}
+    return rec
 
 
 def time_chi2(torch, binding, w, dev, steps, form, launch, graph):

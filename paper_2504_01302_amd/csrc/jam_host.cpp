@@ -584,14 +584,25 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     pixd += 4 * (int64_t)g.n_pix;
     part += (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);   // padded to whole blocks
     bins += 2 * (int64_t)g.n_bins;
-    sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 * g.J1 + 1);
+    if (spherical) {
+      d.n_sens_parts = jam::sph_ranges(g.K);
+      sens += jam::sph_adj_size(g.K, g.n_pix, tsph, d.n_sens_parts);
+    } else {
+      sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 * g.J1 + 1);
+    }
     p->total_lum += g.K;
     p->total_mass += g.J;
     p->total_bins += g.n_bins;
     p->total_map += (int64_t)g.nxp * g.nyp;
     for (int tb = 0; tb < ((spherical ? tsph : g.T) + 255) / 256; ++tb)
       it_terms.push_back({m, tb, 0, 0});
-    if (d.form == 1) {
+    if (spherical) {
+      for (int tt = 0; tt < (tsph + 255) / 256; ++tt)
+        for (int r = 0; r < d.n_sens_parts; ++r) {
+          it_sens.push_back({m, tt, r, 0});
+          c_sens.push_back((double)jam::sph_range_len(g.K, d.n_sens_parts));
+        }
+    } else if (d.form == 1) {
       for (int tb = 0; tb < (g.T + 255) / 256; ++tb) {
         it_sens.push_back({m, tb, 0, 0});
         c_sens.push_back((double)g.n_pix);
@@ -620,7 +631,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
     for (int k = 0; k < g.K; ++k)
-      for (int jb = 0; jb <= (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
+      if (spherical)
+        it_chain.push_back({m, k, 0, 0});
+      else
+        for (int jb = 0; jb <= (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
   }
   if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
     return fail(JAM_E_UNSUPPORTED, "batch too large");
@@ -747,7 +761,8 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   double *sens = (double *)(w + p->off_sens);
   const jam::ParamsDev pd = params_of(b);
   const bool recompute = (vrms2 == nullptr);
-  launch_forward_maps(ctx, p, pd, nullptr, w, st, recompute, capturing);
+  // the spherical adjoint needs the moment table, so it always recomputes it
+  launch_forward_maps(ctx, p, pd, nullptr, w, st, recompute || p->spherical, capturing);
   // V per bin: the caller's forward output, or recomputed into workspace.
   const double *V = vrms2;
   if (recompute) {
@@ -764,14 +779,24 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     cot = c;
   }
   jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
+  const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
+                         grads->mass_S0};
+  if (p->spherical) {
+    const bool ts = ctx->t_sens.begin(st, capturing);
+    jam::launch_sph_adjoint(ctx->d_geoms, p->d_models, p->n, p->d_red, p->n_red, p->d_sph,
+                            p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, p->d_chain,
+                            p->n_chain, pd, (const double *)(w + p->off_gauss),
+                            (const float4 *)(w + p->off_terms), st_ws,
+                            (const double *)(w + p->off_sph), pix, sens, gd, st);
+    if (ts) ctx->t_sens.end(st);
+    return;
+  }
   const bool timed = ctx->t_sens.begin(st, capturing);
   jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
                    (const float4 *)(w + p->off_terms), pix, st_ws, sens,
                    p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
   if (timed) ctx->t_sens.end(st);
   jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
-  const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
-                         grads->mass_S0};
   jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, st_ws, gd, st);
 }
 
@@ -1368,8 +1393,6 @@ jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map, do
 
 jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, const double *cot,
                    jam_grads *grads, void *ws, size_t ws_bytes, void *stream) {
-  if (ctx && ctx->opt.alignment == 1)
-    return fail(JAM_E_UNSUPPORTED, "the adjoint of the spherically aligned model is not built");
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   jam_status s = check_batch(batch);
   if (s != JAM_OK) return s;
@@ -1509,8 +1532,6 @@ jam_status jam_eval_chi2(jam_ctx *ctx, const jam_batch *batch, double *chi2, dou
 jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
                         const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
                         void *stream) {
-  if (ctx && ctx->opt.alignment == 1)
-    return fail(JAM_E_UNSUPPORTED, "the adjoint of the spherically aligned model is not built");
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   jam_status s = check_batch(batch);
   if (s != JAM_OK) return s;

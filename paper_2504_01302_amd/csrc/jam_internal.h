@@ -182,6 +182,60 @@ void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);
+// Adjoint of the spherically aligned model, after the bin adjoint has filled
+// lambda_N and lambda_I: zero the table cotangents (block per model), the
+// line-of-sight adjoint (items as launch_sph_num), the characteristic
+// integrals' adjoint (items as launch_sph_moments), the term-major
+// sensitivities over point ranges (items (m, 256-term tile, range)) and over
+// the table points (items (m, 256-term tile)), the per-term chain (items (m,
+// 256-term tile)), the surface-brightness rows (items (m, k)), and the
+// per-model gradients (block per model).
+void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
+                        int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
+                        int n_sens, const Item *it_tile, int n_tile, const Item *it_k, int n_k,
+                        ParamsDev p, const double *gauss, const float4 *terms,
+                        const int *st_ws, const double *table, const double *pix, double *sens,
+                        GradsDev out, hipStream_t st);
+// Adjoint of the spherically aligned model.  Per model, in the sensitivity
+// region (doubles): the table cotangent [kSphNR*kSphNT][3], per (cell,
+// tracer) rows (d/dbeta, d/dalphaq, d/dnu0) [cells][K][3], line-of-sight
+// partials (d/di at fixed node scale, d/d node scale) per 64-pixel block,
+// per-term sensitivities per point range [n_rng][Tp][6] and of the cell
+// points [Tp][3], per-term chain values (d/de2, d/dKp) [Tp][2], and the
+// surface-brightness rows [K].  n_rng is ModelDev::n_sens_parts.
+constexpr int kSphCells = kSphNR * kSphNT;
+struct SphAdj {
+  double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *sbrow;
+};
+__host__ __device__ inline int64_t sph_adj_size(int K, int n_pix, int Tp, int n_rng) {
+  return 3LL * kSphCells + 3LL * kSphCells * K + 2LL * ((n_pix + 63) / 64) +
+         6LL * n_rng * Tp + 5LL * Tp + K;
+}
+__host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix, int Tp,
+                                                 int n_rng) {
+  SphAdj a;
+  a.dtab = base;
+  a.rows = a.dtab + 3LL * kSphCells;
+  a.losp = a.rows + 3LL * kSphCells * K;
+  a.sparts = a.losp + 2LL * ((n_pix + 63) / 64);
+  a.cparts = a.sparts + 6LL * n_rng * Tp;
+  a.tchain = a.cparts + 3LL * Tp;
+  a.sbrow = a.tchain + 2LL * Tp;
+  return a;
+}
+// Points of one model's characteristic integrals: (cell, tracer, node).
+__host__ __device__ inline int64_t sph_points(int K) { return (int64_t)kSphCells * K * kSphNodes; }
+// Point ranges of the term-major sensitivity pass: about 2^17 points each,
+// at most 64, each a whole number of 256-point chunks.
+__host__ __device__ inline int sph_ranges(int K) {
+  const int64_t r = (sph_points(K) + 131071) / 131072;
+  return (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
+}
+__host__ __device__ inline int64_t sph_range_len(int K, int n_rng) {
+  const int64_t per = (sph_points(K) + n_rng - 1) / n_rng;
+  return (per + 255) / 256 * 256;
+}
+
 // Logistic radial anisotropy profile prof[m][0..3] = (beta_0, beta_inf, r_a,
 // alpha) sampled at every tracer Gaussian's sigma into the packed beta, and
 // its adjoint grad[m][0..3] from the packed cotangent of beta.

@@ -1483,6 +1483,670 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the spherically aligned model.  With lambda_N per unique pixel
+// (bin adjoint) the chain runs back through the line-of-sight rule (to the
+// table and, at fixed table, to i and the node scale a), through the
+// characteristic integrals (to beta_k, alphaq_k, nu0_k per table cell and
+// tracer, and to the (j, u) term coefficients by term-major sums over all
+// (cell, tracer, node) points), through the term coefficients (to e_j^2 and
+// K_j), and through the set-up to the parameters.  FP64 except the FP32
+// exponentials and their sums over 64 or 256 points, as in the forward.
+// ---------------------------------------------------------------------------
+
+// Node of tracer k's characteristic through table point (r, theta): the same
+// FP64 operations as the forward moment kernel.
+struct SphNode {
+  double rp, st, ct, Rp, zp, wn, en, tau;
+  bool clamped;
+};
+__device__ inline SphNode sph_node(double r, double sth, double alpha, double alphaq, double beta,
+                                   int seg, double glx, double glw) {
+  SphNode o;
+  const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r));
+  const double hs = tmax / kSphSeg;
+  o.tau = (seg + 0.5 + 0.5 * glx) * hs;
+  o.rp = r * exp(o.tau);
+  const double sraw = sth * pow(r / o.rp, 1.0 - beta);
+  o.clamped = !(sraw < 1.0);
+  o.st = fmin(1.0, sraw);
+  o.ct = sqrt(fmax(0.0, 1.0 - o.st * o.st));
+  o.Rp = o.rp * o.st;
+  o.zp = o.rp * o.ct;
+  o.wn = 0.5 * glw * hs * o.rp;
+  o.en = exp(-(alpha * o.Rp * o.Rp + alphaq * o.zp * o.zp));
+  return o;
+}
+
+__device__ inline void sph_cell(const GeomDev &g, int cell, double &r, double &sth, double &cth) {
+  const int ir = cell / kSphNT, ith = cell % kSphNT;
+  r = exp(g.sph_lnr0 + ir * g.sph_dlnr);
+  const double th = ith * (0.5 * kPi / (kSphNT - 1));
+  sth = sin(th);
+  cth = cos(th);
+}
+
+__device__ inline SphAdj sph_adj_of(double *sens, const ModelDev &md, const GeomDev &g) {
+  return sph_adj_layout(sens + md.sens_off, g.K, g.n_pix, sph_terms_padded(g.J1, g.n_u),
+                        md.n_sens_parts);
+}
+
+__global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ geoms,
+                                                  const ModelDev *__restrict__ models, int n,
+                                                  double *__restrict__ sens) {
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const ModelDev md = models[m];
+    const GeomDev g = geoms[md.geom];
+    double *d = sph_adj_of(sens, md, g).dtab;
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) d[i] = 0.0;
+  }
+}
+
+// Line-of-sight adjoint.  Item (m, 64-pixel block), thread = pixel, as the
+// forward.  The table cotangent receives lambda_N w_z (n.e_f)^2 times the
+// bilinear weights (atomic FP64 adds); the derivatives of the node's
+// integrand at fixed table with respect to i (line of sight and node
+// position) and to the node scale a are summed per item (wave sums).
+__global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__ geoms,
+                                                     const ModelDev *__restrict__ models,
+                                                     const Item *__restrict__ items, int n_it,
+                                                     const double *__restrict__ gauss,
+                                                     const int *__restrict__ st_ws,
+                                                     const double *__restrict__ table,
+                                                     const double *__restrict__ pix,
+                                                     double *__restrict__ sens) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t iw = gid >> 6;                 // item of this wave
+  if (iw >= n_it) return;                      // whole waves only
+  const Item it = items[iw];
+  const ModelDev md = models[it.m];
+  const GeomDev g = geoms[md.geom];
+  if (st_ws[it.m] != 0) return;                // uniform per wave
+  const SphAdj adj = sph_adj_of(sens, md, g);
+  const int q = it.a * 64 + (int)(gid & 63);
+  const bool on = q < g.n_pix;
+  const int K = g.K;
+  const double *tab = gauss + md.gauss_off;
+  const double *mt = tab + 4 * K;
+  const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
+  double smin = 1e300, smax = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
+    smin = fmin(smin, sk * qk);
+    smax = fmax(smax, sk);
+  }
+  const double a = 0.25 * smin, cW = 12.0 * smax, W = asinh(cW / a);
+  const double Wa = -(cW / (a * a)) / sqrt(1.0 + (cW / a) * (cW / a));   // dW/da
+  const double x = on ? g.xs[q % g.n_ux] : 0.0, y = on ? g.ys[q / g.n_ux] : 0.0;
+  const double lamN = on ? pix[md.pix_off + 2 * (int64_t)g.n_pix + q] : 0.0;
+  const double *T = table + md.sph_off;
+  const double dth = 0.5 * kPi / (kSphNT - 1);
+  const double hw = 2.0 * W / kSphSeg;
+  const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
+  double acc_i = 0.0, acc_a = 0.0;
+  for (int nd = 0; on && nd < kSphNodes; ++nd) {
+    const int seg = nd >> 3, gi = nd & 7;
+    const double om = -1.0 + (seg + 0.5 + 0.5 * glx[gi]) / 4.0;   // w = W om
+    const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
+    const double shw = sinh(w), chw = cosh(w);
+    const double zp = a * shw, wz = 0.5 * glw[gi] * hw * a * chw;
+    const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
+    const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
+    const double ct = Z / r, st = R / r;
+    const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
+    const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
+    if (xf > kSphNR - 1) continue;
+    const double yf = acos(fmin(1.0, fabs(ct))) / dth;
+    const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
+    const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
+    const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
+    const int64_t i00 = ((int64_t)xi * kSphNT + yi) * 3;
+    const double *c00 = T + i00;
+    const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
+    const double ner = si * st * sp + ci * ct;
+    const double net = si * ct * sp - ci * st;
+    const double nep = si * cp;
+    const double nf[3] = {ner, net, nep};
+    // table cotangent
+    const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+    double *d00 = adj.dtab + i00;
+    double *d10 = d00 + kSphNT * 3, *d01 = d00 + 3, *d11 = d10 + 3;
+    double A[3], AL[3], AT[3];
+    const bool xin = xf >= 0.0;          // below the first radius the table is constant
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const double cf = lamN * wz * nf[f] * nf[f];
+      atomicAdd(d00 + f, cf * w00);
+      atomicAdd(d10 + f, cf * w10);
+      atomicAdd(d01 + f, cf * w01);
+      atomicAdd(d11 + f, cf * w11);
+      A[f] = w00 * c00[f] + w10 * c10[f] + w01 * c01[f] + w11 * c11[f];
+      AL[f] = xin ? ((1 - fy) * (c10[f] - c00[f]) + fy * (c11[f] - c01[f])) / g.sph_dlnr : 0.0;
+      AT[f] = ((1 - fx) * (c01[f] - c00[f]) + fx * (c11[f] - c10[f])) / dth;
+    }
+    // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
+    const double r2 = r * r, sz = Z < 0.0 ? -1.0 : 1.0;
+    const double lY = Y / r2, lZ = Z / r2;
+    const double tY = R > 0.0 ? fabs(Z) * (Y / R) / r2 : 0.0, tZ = -R * sz / r2;
+    // line-of-sight components and their derivatives (Y, Z; explicit i)
+    double nY[3] = {0.0, 0.0, 0.0}, nZ[3] = {0.0, 0.0, 0.0}, ni[3] = {0.0, 0.0, 0.0};
+    nY[0] = (si - ner * Y / r) / r;
+    nZ[0] = (ci - ner * Z / r) / r;
+    ni[0] = (ci * Y - si * Z) / r;
+    if (R > 0.0) {
+      const double rR = r * R;
+      nY[1] = ((si * Z - 2.0 * ci * Y) - net * (Y / r * R + r * Y / R)) / rR;
+      nZ[1] = (si * Y - net * (Z / r) * R) / rR;
+      ni[1] = (ci * Z * Y + si * R * R) / rR;
+      nY[2] = -si * X * Y / (R * R * R);
+      ni[2] = ci * X / R;
+    }
+    double F = 0.0, FY = 0.0, FZ = 0.0, Fi = 0.0;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const double dAY = AL[f] * lY + AT[f] * tY, dAZ = AL[f] * lZ + AT[f] * tZ;
+      F += nf[f] * nf[f] * A[f];
+      FY += 2.0 * nf[f] * nY[f] * A[f] + nf[f] * nf[f] * dAY;
+      FZ += 2.0 * nf[f] * nZ[f] * A[f] + nf[f] * nf[f] * dAZ;
+      Fi += 2.0 * nf[f] * ni[f] * A[f];
+    }
+    const double Yi = zp * ci + y * si, Zi = y * ci - zp * si;
+    acc_i += lamN * wz * (Fi + FY * Yi + FZ * Zi);
+    const double dzp = shw + a * chw * om * Wa;
+    const double dwz = 0.5 * glw[gi] * (2.0 / kSphSeg) *
+                       (Wa * a * chw + W * chw + W * a * shw * om * Wa);
+    acc_a += lamN * (dwz * F + wz * (FY * si + FZ * ci) * dzp);
+  }
+  acc_i = wave_sum(acc_i);
+  acc_a = wave_sum(acc_a);
+  if ((gid & 63) == 0) {
+    adj.losp[2 * it.a] = acc_i;
+    adj.losp[2 * it.a + 1] = acc_a;
+  }
+}
+
+// Characteristic integrals' adjoint.  Item (m, table cell), the forward's
+// layout: wave w takes tracer k = 4 q + w, lane = node.  Per node the term
+// sums G, G_theta and their derivatives in R'^2 and z'^2; per (cell,
+// tracer) the derivatives of the cell's L = lambda . (A_r, A_theta, A_phi)
+// with respect to beta_k, alphaq_k and nu0_k go to rows; the A_phi term
+// -nu R^2 G_phi adds its alphaq_k, nu0_k derivatives after.
+__global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restrict__ geoms,
+                                                         const ModelDev *__restrict__ models,
+                                                         const Item *__restrict__ items, int n_it,
+                                                         const double *__restrict__ gauss,
+                                                         const float4 *__restrict__ terms,
+                                                         const int *__restrict__ st_ws,
+                                                         double *__restrict__ sens) {
+  __shared__ float4 tc[kSphChunk];
+  __shared__ float tf[kSphChunk];
+  __shared__ double sh[256];
+  constexpr double kLn2 = 0.6931471805599453;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
+    const float4 *gtc = terms + md.term_off;
+    const float *gtf = (const float *)(gtc + Tp);
+    const double *tab = gauss + md.gauss_off;
+    const int cell = it.a;
+    double r, sth, cth;
+    sph_cell(g, cell, r, sth, cth);
+    const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1], lp = adj.dtab[3 * cell + 2];
+    const double Rp0 = r * sth, zp0 = r * cth;
+    const float R20 = (float)(Rp0 * Rp0), Z20 = (float)(zp0 * zp0);
+    const int seg = lane >> 3, gi = lane & 7;
+    const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
+    double accF = 0.0;
+    const int rounds = (K + 3) / 4;
+    for (int q = 0; q < rounds; ++q) {
+      const int k = 4 * q + wave;
+      const bool on = k < K;
+      double alpha = 1.0, alphaq = 1.0, beta = 0.0, nu0 = 0.0;
+      SphNode nd{};
+      float R2 = 0.f, Z2 = 0.f;
+      if (on) {
+        alpha = tab[k];
+        alphaq = tab[K + k];
+        nu0 = tab[2 * K + k];
+        beta = 1.0 - 1.0 / tab[3 * K + k];
+        nd = sph_node(r, sth, alpha, alphaq, beta, seg, glx, glw);
+        R2 = (float)(nd.Rp * nd.Rp);
+        Z2 = (float)(nd.zp * nd.zp);
+      }
+      double aG = 0.0, aT = 0.0, aGR = 0.0, aGZ = 0.0, aTR = 0.0, aTZ = 0.0;
+      for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
+        const int cn = min(kSphChunk, Tp - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += 256) {
+          tc[t] = gtc[c0 + t];
+          tf[t] = gtf[c0 + t];
+        }
+        __syncthreads();
+        if (on) {
+          for (int t0 = 0; t0 < cn; t0 += 64) {
+            float sG = 0.f, sT = 0.f, sGR = 0.f, sGZ = 0.f, sTR = 0.f, sTZ = 0.f;
+#pragma unroll 16
+            for (int t = 0; t < 64; ++t) {
+              const float4 c = tc[t0 + t];
+              const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
+              const float pe = c.z * e, te = c.w * e;
+              sG += pe;
+              sT += te;
+              sGR = fmaf(c.x, pe, sGR);
+              sGZ = fmaf(c.y, pe, sGZ);
+              sTR = fmaf(c.x, te, sTR);
+              sTZ = fmaf(c.y, te, sTZ);
+            }
+            aG += (double)sG;
+            aT += (double)sT;
+            aGR += (double)sGR;
+            aGZ += (double)sGZ;
+            aTR += (double)sTR;
+            aTZ += (double)sTZ;
+          }
+        }
+        if (q == 0) {
+          for (int t = threadIdx.x; t < cn; t += 256) {
+            const float4 c = tc[t];
+            accF += (double)(tf[t] * fast_exp2(fmaf(c.x, R20, c.y * Z20)));
+          }
+        }
+      }
+      if (on) {
+        const double kap = 2.0 * (alphaq - alpha);
+        const double nu = nu0 * nd.en;
+        const double H = aT + kap * aG;
+        // d/dbeta of the node: s' = s (r/r')^(1-beta) -> ds'/dbeta = s' tau
+        const double ds = nd.clamped ? 0.0 : nd.st * nd.tau;
+        const double dc = nd.ct > 0.0 ? -nd.st * ds / nd.ct : 0.0;
+        const double dR = nd.rp * ds, dz = nd.rp * dc;
+        const double dR2 = 2.0 * nd.Rp * dR, dZ2 = 2.0 * nd.zp * dz;
+        const double dnu = -nu * (alpha * dR2 + alphaq * dZ2);
+        // the term coefficients carry log2 e: dE/d(R'^2) = ln 2 c.x E
+        const double dG = kLn2 * (aGR * dR2 + aGZ * dZ2);
+        const double dH = kLn2 * (aTR * dR2 + aTZ * dZ2) + kap * dG;
+        const double lrp = log(nd.rp);
+        const double pP = nd.wn * pow(nd.rp, 2.0 * beta + 1.0);
+        const double pD = nd.wn * pow(nd.rp, 3.0 * beta + 1.0);
+        double fP = pP * nu * aG;
+        double fD = pD * nd.Rp * nu * H;
+        double bP = pP * (2.0 * lrp * nu * aG + dnu * aG + nu * dG);
+        double bD = pD * (3.0 * lrp * nd.Rp * nu * H + dR * nu * H + nd.Rp * dnu * H +
+                          nd.Rp * nu * dH);
+        double qP = pP * aG * (-nd.zp * nd.zp * nu);
+        double qD = pD * nd.Rp * (-nd.zp * nd.zp * nu * H + nu * 2.0 * aG);
+        double eP = pP * nd.en * aG;
+        double eD = pD * nd.Rp * nd.en * H;
+        fP = wave_sum(fP);
+        fD = wave_sum(fD);
+        bP = wave_sum(bP);
+        bD = wave_sum(bD);
+        qP = wave_sum(qP);
+        qD = wave_sum(qD);
+        eP = wave_sum(eP);
+        eD = wave_sum(eD);
+        if (lane == 0) {
+          const double lnr = log(r);
+          const double rb = pow(r, -2.0 * beta), rd = pow(r, 1.0 - 3.0 * beta);
+          const double P = rb * fP;
+          const double muP = lr + (1.0 - beta) * (lt + lp);
+          const double muD = lp * (1.0 - beta) * sth * rd;
+          const double dbeta = muP * rb * bP + muD * bD - (lt + lp) * P - 2.0 * lnr * muP * P -
+                               fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - beta) * lnr);
+          double *row = adj.rows + ((int64_t)cell * K + k) * 3;
+          row[0] = dbeta;
+          row[1] = muP * rb * qP + muD * qD;
+          row[2] = muP * rb * eP + muD * eD;
+        }
+      }
+    }
+    const double Gphi = block_sum256(accF, sh);   // synchronises the block (rows written)
+    // A_phi -= nu(cell) R0^2 G_phi, nu(cell) = sum_k nu0_k exp(-(alpha R0^2 + alphaq z0^2))
+    for (int k = threadIdx.x; k < K; k += 256) {
+      const double e0 = exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
+      double *row = adj.rows + ((int64_t)cell * K + k) * 3;
+      row[1] += lp * Rp0 * Rp0 * Gphi * tab[2 * K + k] * e0 * zp0 * zp0;
+      row[2] += -lp * Rp0 * Rp0 * Gphi * e0;
+    }
+    __syncthreads();
+  }
+}
+
+// Term-major sensitivities.  Item (m, 256-term tile, point range); thread =
+// term.  Each 256-point chunk of the range is regenerated (thread = point):
+// node position and the cotangents phi = dL/dG, psi = dL/dG_theta at the
+// node; then every term sums phi E, psi E and their R'^2, z'^2 moments over
+// the chunk in FP32, folded into FP64.
+__global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ geoms,
+                                                  const ModelDev *__restrict__ models,
+                                                  const Item *__restrict__ items, int n_it,
+                                                  const double *__restrict__ gauss,
+                                                  const float4 *__restrict__ terms,
+                                                  const int *__restrict__ st_ws,
+                                                  double *__restrict__ sens) {
+  __shared__ float4 pa[256];   // (R'^2, z'^2, phi, psi)
+  __shared__ float4 pb[256];   // (phi R'^2, psi R'^2, phi z'^2, psi z'^2)
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
+    const double *tab = gauss + md.gauss_off;
+    const int t = it.a * 256 + threadIdx.x;
+    const bool tv = t < Tp;
+    const float4 c = tv ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t len = sph_range_len(K, md.n_sens_parts), P = sph_points(K);
+    const int64_t p0 = (int64_t)it.b * len, p1 = min(P, p0 + len);
+    double SP = 0.0, ST = 0.0, SxP = 0.0, SxT = 0.0, SyP = 0.0, SyT = 0.0;
+    for (int64_t c0 = p0; c0 < p1; c0 += 256) {
+      // regenerate this chunk's points
+      const int64_t p = c0 + threadIdx.x;
+      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+      if (p < p1) {
+        const int cell = (int)(p / ((int64_t)K * kSphNodes));
+        const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
+        double r, sth, cth;
+        sph_cell(g, cell, r, sth, cth);
+        const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1];
+        const double lp = adj.dtab[3 * cell + 2];
+        const double alpha = tab[k], alphaq = tab[K + k], nu0 = tab[2 * K + k];
+        const double beta = 1.0 - 1.0 / tab[3 * K + k];
+        const int gi = node & 7;
+        const SphNode nd = sph_node(r, sth, alpha, alphaq, beta, node >> 3,
+                                    geoms[md.geom].gl8_x[gi], geoms[md.geom].gl8_w[gi]);
+        const double nu = nu0 * nd.en;
+        const double muP = lr + (1.0 - beta) * (lt + lp);
+        const double muD = lp * (1.0 - beta) * sth * pow(r, 1.0 - 3.0 * beta);
+        const double dD = muD * nd.wn * pow(nd.rp, 3.0 * beta + 1.0) * nd.Rp * nu;
+        const double phi = muP * pow(r, -2.0 * beta) * nd.wn * pow(nd.rp, 2.0 * beta + 1.0) * nu +
+                           dD * 2.0 * (alphaq - alpha);
+        const double psi = dD;
+        const float R2 = (float)(nd.Rp * nd.Rp), Z2 = (float)(nd.zp * nd.zp);
+        const float fphi = (float)phi, fpsi = (float)psi;
+        va = make_float4(R2, Z2, fphi, fpsi);
+        vb = make_float4(fphi * R2, fpsi * R2, fphi * Z2, fpsi * Z2);
+      }
+      __syncthreads();
+      pa[threadIdx.x] = va;
+      pb[threadIdx.x] = vb;
+      __syncthreads();
+      const int cnt = (int)min((int64_t)256, p1 - c0);
+      float sP = 0.f, sT = 0.f, sxP = 0.f, sxT = 0.f, syP = 0.f, syT = 0.f;
+      if (tv) {
+        for (int j = 0; j < cnt; ++j) {
+          const float4 A = pa[j], B = pb[j];
+          const float e = fast_exp2(fmaf(c.x, A.x, c.y * A.y));
+          sP = fmaf(A.z, e, sP);
+          sT = fmaf(A.w, e, sT);
+          sxP = fmaf(B.x, e, sxP);
+          sxT = fmaf(B.y, e, sxT);
+          syP = fmaf(B.z, e, syP);
+          syT = fmaf(B.w, e, syT);
+        }
+      }
+      SP += (double)sP;
+      ST += (double)sT;
+      SxP += (double)sxP;
+      SxT += (double)sxT;
+      SyP += (double)syP;
+      SyT += (double)syT;
+    }
+    if (tv) {
+      double *o = adj.sparts + ((int64_t)it.b * Tp + t) * 6;
+      o[0] = SP;
+      o[1] = ST;
+      o[2] = SxP;
+      o[3] = SxT;
+      o[4] = SyP;
+      o[5] = SyT;
+    }
+    __syncthreads();
+  }
+}
+
+// Term sensitivities of the table points' G_phi term (chi = -lambda_phi nu
+// R0^2 per cell).  Item (m, 256-term tile); thread = term, 256 cells a chunk.
+__global__ void __launch_bounds__(256) k_sph_sens_cells(const GeomDev *__restrict__ geoms,
+                                                        const ModelDev *__restrict__ models,
+                                                        const Item *__restrict__ items, int n_it,
+                                                        const double *__restrict__ gauss,
+                                                        const float4 *__restrict__ terms,
+                                                        const int *__restrict__ st_ws,
+                                                        double *__restrict__ sens) {
+  __shared__ float4 pc[256];   // (R0^2, z0^2, chi, 0)
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
+    const double *tab = gauss + md.gauss_off;
+    const int t = it.a * 256 + threadIdx.x;
+    const bool tv = t < Tp;
+    const float4 c = tv ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    double SF = 0.0, SxF = 0.0, SyF = 0.0;
+    for (int c0 = 0; c0 < kSphCells; c0 += 256) {
+      const int cell = c0 + threadIdx.x;
+      double r, sth, cth;
+      sph_cell(g, cell, r, sth, cth);
+      const double R0 = r * sth, z0 = r * cth;
+      double nus = 0.0;
+      for (int k = 0; k < K; ++k) nus += tab[2 * K + k] * exp(-(tab[k] * R0 * R0 + tab[K + k] * z0 * z0));
+      const double chi = -adj.dtab[3 * cell + 2] * nus * R0 * R0;
+      __syncthreads();
+      pc[threadIdx.x] = make_float4((float)(R0 * R0), (float)(z0 * z0), (float)chi, 0.f);
+      __syncthreads();
+      float sF = 0.f, sx = 0.f, sy = 0.f;
+      if (tv) {
+        for (int j = 0; j < 256; ++j) {
+          const float4 A = pc[j];
+          const float e = A.z * fast_exp2(fmaf(c.x, A.x, c.y * A.y));
+          sF += e;
+          sx = fmaf(A.x, e, sx);
+          sy = fmaf(A.y, e, sy);
+        }
+      }
+      SF += (double)sF;
+      SxF += (double)sx;
+      SyF += (double)sy;
+    }
+    if (tv) {
+      double *o = adj.cparts + (int64_t)t * 3;
+      o[0] = SF;
+      o[1] = SxF;
+      o[2] = SyF;
+    }
+    __syncthreads();
+  }
+}
+
+// Per-term chain (FP64): the sensitivities summed over the point ranges in a
+// fixed order, then through the coefficients' dependence on e_j^2 and K_j.
+// Item (m, 256-term tile); thread = term.
+__global__ void __launch_bounds__(256) k_sph_chain(const GeomDev *__restrict__ geoms,
+                                                   const ModelDev *__restrict__ models,
+                                                   const Item *__restrict__ items, int n_it,
+                                                   const double *__restrict__ gauss,
+                                                   const int *__restrict__ st_ws,
+                                                   double *__restrict__ sens) {
+  constexpr double kLn2 = 0.6931471805599453, kLog2e = 1.4426950408889634;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const int Tp = sph_terms_padded(g.J1, g.n_u), T = g.J1 * g.n_u;
+    const int t = it.a * 256 + threadIdx.x;
+    if (t >= T) continue;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int rg = 0; rg < md.n_sens_parts; ++rg) {
+      const double *o = adj.sparts + ((int64_t)rg * Tp + t) * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) S[c] += o[c];
+    }
+    const double *cp = adj.cparts + (int64_t)t * 3;
+    const double *mt = gauss + md.gauss_off + 4 * g.K;
+    const int j = t / g.n_u, n = t % g.n_u;
+    const double rj = mt[j], e2 = mt[g.J1 + j], Kp = mt[2 * g.J1 + j];
+    const double u = g.u[n], u2 = u * u, w = g.w[n];
+    const double h = 1.0 - e2 * u2, h15 = h * sqrt(h);
+    // coefficients per unit K_j
+    const double P1 = w * 2.0 * rj * u2 / h15;
+    const double T1 = w * e2 * 4.0 * rj * rj * u2 * u2 * u2 / (h15 * h);
+    const double F1 = w * e2 * 2.0 * rj * u2 * u2 / h15;
+    const double cy = -rj * u2 / h * kLog2e;
+    const double dcy = kLn2 * Kp * (P1 * S[4] + T1 * S[5] + F1 * cp[2]);   // dL/dc_y
+    const double dP1 = P1 * 1.5 * u2 / h;
+    const double dT1 = w * 4.0 * rj * rj * u2 * u2 * u2 * (1.0 / (h15 * h) + e2 * 2.5 * u2 / (h15 * h * h));
+    const double dF1 = w * 2.0 * rj * u2 * u2 * (1.0 / h15 + e2 * 1.5 * u2 / (h15 * h));
+    double *o = adj.tchain + (int64_t)t * 2;
+    o[0] = Kp * (S[0] * dP1 + S[1] * dT1 + cp[0] * dF1) + dcy * cy * u2 / h;   // d/de2
+    o[1] = S[0] * P1 + S[1] * T1 + cp[0] * F1;                                // d/dKp
+  }
+}
+
+// Surface-brightness rows: dL/dI0_k through I, sum_p lambda_I[p] exp(-x^2 /
+// 2 sigma'^2 - y^2 / 2 sigma'^2 q'^2).  Item (m, k); fixed-order sums.
+__global__ void __launch_bounds__(256) k_sph_sb_adj(const GeomDev *__restrict__ geoms,
+                                                    const ModelDev *__restrict__ models,
+                                                    const Item *__restrict__ items, int n_it,
+                                                    const int *__restrict__ st_ws,
+                                                    const double *__restrict__ pix,
+                                                    double *__restrict__ sens) {
+  __shared__ double sh[256];
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;
+    const int k = it.a;
+    const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
+    const double sk = g.lum_sigma[k], qo = g.lum_q[k];
+    const double ax = 0.5 / (sk * sk), ay = ax / (qo * qo);
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < g.n_pix; q += 256) {
+      const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
+      acc += lamI[q] * exp(-ax * x * x - ay * y * y);
+    }
+    const double s = block_sum256(acc, sh);
+    if (threadIdx.x == 0) sph_adj_of(sens, md, g).sbrow[k] = s;
+  }
+}
+
+// Per-model gradients.  Block per model: sums over cells (rows), u-nodes
+// (per-term chain) and pixel blocks (line-of-sight partials) in a fixed
+// order, then the set-up's derivatives (App. A) to the parameters.
+__global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ geoms,
+                                                   const ModelDev *__restrict__ models, int n,
+                                                   ParamsDev p, const double *__restrict__ gauss,
+                                                   const int *__restrict__ st_ws,
+                                                   double *__restrict__ sens, GradsDev out) {
+  __shared__ double sh[256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    const ModelDev md = models[m];
+    const GeomDev g = geoms[md.geom];
+    const bool ok = st_ws[m] == 0;
+    const double nan = __builtin_nan("");
+    const int K = g.K, J1 = g.J1, J = J1 - 1;
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const double *tab = gauss + md.gauss_off;
+    const double *mt = tab + 4 * K;
+    const double inc = p.inc[m];
+    const double si = sin(inc), ci = cos(inc);
+    // dq/di of a deprojected Gaussian of observed axis ratio qo
+    auto dqdi = [&](double qo, double q) { return ci * (1.0 - qo * qo) / (q * si * si * si); };
+    double di = 0.0;
+    // tracers: rows summed over cells (lanes split the cells, wave sum)
+    for (int k = wave; k < K; k += 4) {
+      double b = 0.0, aq = 0.0, nv = 0.0;
+      if (ok)
+        for (int cell = lane; cell < kSphCells; cell += 64) {
+          const double *row = adj.rows + ((int64_t)cell * K + k) * 3;
+          b += row[0];
+          aq += row[1];
+          nv += row[2];
+        }
+      b = wave_sum(b);
+      aq = wave_sum(aq);
+      nv = wave_sum(nv);
+      if (lane == 0) {
+        const double qo = g.lum_q[k], sk = g.lum_sigma[k];
+        const double alpha = tab[k], q = sqrt(alpha / tab[K + k]);
+        const double dq = dqdi(qo, q);
+        // alphaq = alpha / q^2, nu0 = qo I0 / (sqrt(2 pi) sigma q)
+        di += aq * (-2.0 * alpha / (q * q * q)) * dq + nv * (-tab[2 * K + k] / q) * dq;
+        if (out.beta) out.beta[md.lum_off + k] = ok ? b : nan;
+        if (out.lum_I0)
+          out.lum_I0[md.lum_off + k] =
+              ok ? nv * qo / (sqrt(2.0 * kPi) * sk * q) + adj.sbrow[k] : nan;
+      }
+    }
+    // mass Gaussians and the BH: per-term chain summed over u-nodes
+    const double sp = g.s_pc, Gc = grav_const();
+    const double ml = p.mass_scale[m];
+    double dml = 0.0;
+    for (int j = threadIdx.x; j < J1; j += 256) {
+      double de2 = 0.0, dK = 0.0;
+      if (ok)
+        for (int nn = 0; nn < g.n_u; ++nn) {
+          const double *o = adj.tchain + ((int64_t)j * g.n_u + nn) * 2;
+          de2 += o[0];
+          dK += o[1];
+        }
+      if (j < J) {
+        const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+        const double q = sqrt(fmax(1.0 - mt[J1 + j], 0.0));
+        di += de2 * (-2.0 * q) * dqdi(qo, q);
+        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+        // K_j = sqrt(2/pi) G M_j / (s sigma_j), M_j = ml 2 pi S0_j (s sigma'_j)^2 q'_j
+        const double unit = sqrt(2.0 / kPi) * Gc * 2.0 * kPi * (sp * sj) * (sp * sj) * qo / (sp * sj);
+        if (out.mass_S0) out.mass_S0[md.mass_off + j] = ok ? dK * ml * unit : nan;
+        dml += dK * S0 * unit;
+      } else if (out.m_bh) {
+        out.m_bh[m] = ok ? dK * sqrt(2.0 / kPi) * Gc / (sp * g.bh_sigma) : nan;
+      }
+    }
+    // line-of-sight partials: i at fixed node scale, and the node scale
+    // a = min_k sigma_k q_k / 4 through its minimising tracer's q_k(i)
+    double li = 0.0, la = 0.0;
+    const int npb = (g.n_pix + 63) / 64;
+    if (ok)
+      for (int b = threadIdx.x; b < npb; b += 256) {
+        li += adj.losp[2 * b];
+        la += adj.losp[2 * b + 1];
+      }
+    const double dis = block_sum256(di, sh);
+    const double dmls = block_sum256(dml, sh);
+    const double lis = block_sum256(li, sh);
+    const double las = block_sum256(la, sh);
+    if (threadIdx.x == 0) {
+      double smin = 1e300, dadi = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double sk = sqrt(0.5 / tab[k]), q = sqrt(tab[k] / tab[K + k]);
+        if (sk * q < smin) {
+          smin = sk * q;
+          dadi = 0.25 * sk * dqdi(g.lum_q[k], q);
+        }
+      }
+      if (out.inc) out.inc[m] = ok ? dis + lis + las * dadi : nan;
+      if (out.mass_scale) out.mass_scale[m] = ok ? dmls : nan;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Radial anisotropy profile sampled per tracer Gaussian (Sect. 6):
 // beta_k = beta_0 + (beta_inf - beta_0) / (1 + (r_a / sigma_k)^alpha).
 // Block per model, thread per Gaussian; an invalid profile (r_a or alpha not
@@ -1708,6 +2372,28 @@ void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_i
                     hipStream_t st) {
   hipLaunchKernelGGL(k_sph_num, dim3(grid_of((n_it + 3) / 4)), dim3(256), 0, st, g, m, it, n_it,
                      gauss, st_ws, table, pix);
+}
+void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
+                        int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
+                        int n_sens, const Item *it_tile, int n_tile, const Item *it_k, int n_k,
+                        ParamsDev p, const double *gauss, const float4 *terms,
+                        const int *st_ws, const double *table, const double *pix, double *sens,
+                        GradsDev out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, sens);
+  hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of((n_los + 3) / 4)), dim3(256), 0, st, g, m,
+                     it_los, n_los, gauss, st_ws, table, pix, sens);
+  hipLaunchKernelGGL(k_sph_moments_adj, dim3(grid_of(n_cell)), dim3(256), 0, st, g, m, it_cell,
+                     n_cell, gauss, terms, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
+                     gauss, terms, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_sens_cells, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile,
+                     n_tile, gauss, terms, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_chain, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile, n_tile,
+                     gauss, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_sb_adj, dim3(grid_of(n_k)), dim3(256), 0, st, g, m, it_k, n_k, st_ws,
+                     pix, sens);
+  hipLaunchKernelGGL(k_sph_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, gauss, st_ws,
+                     sens, out);
 }
 void launch_beta_logistic(const GeomDev *g, const ModelDev *m, int n, const double *prof,
                           double *beta, hipStream_t st) {

@@ -4,7 +4,7 @@ Every value here comes from the FP64 oracle (``oracle/``) evaluated on the
 seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
 from the GPU library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5] [sph1]
+    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5] [sph1] [sph_grad]
 """
 import json
 import os
@@ -115,8 +115,63 @@ def sph1(n_models=3):
         config3_models=[2, 5], vrms2=V, seconds=time.time() - t))
 
 
+def _sph_grad_case(seed, beta, inc_deg):
+    g = inputs.small_geometry(seed=seed, n_lum=2, n_mass=2, nx=6, ny=5, ss=1, psf_n=3,
+                              n_bins=3, n_u=16)
+    p = inputs.with_overrides(inputs.small_params(g, seed=seed), beta=np.array(beta),
+                              inc=np.deg2rad(inc_deg))
+    return g, p
+
+
+def sph_grad():
+    """Gradient of sum_b cot_b v_rms^2_b of the spherically aligned oracle by
+    central differences (FP64; the inclination step is kept at 1e-7 rad so
+    that line-of-sight nodes almost never cross a table cell edge, where the
+    bilinear interpolation has a kink; the other steps are 1e-6 relative)."""
+    t = time.time()
+    out = []
+    for seed, beta, inc_deg in ((5, (0.25, -0.15), 62.0), (6, (-0.1, 0.3), 75.0)):
+        g, p = _sph_grad_case(seed, beta, inc_deg)
+        cot = inputs.cotangent(g.n_bins, 1, seed=seed)[0]
+        I0 = np.array(g.lum_I0, np.float64)
+        S0 = np.array(g.mass_S0, np.float64)
+        base = dict(inc=float(p.inc), beta=np.array(beta, np.float64),
+                    mass_scale=float(p.mass_scale), m_bh=float(p.m_bh), lum_I0=I0, mass_S0=S0)
+
+        def L(par):
+            q = inputs.with_overrides(p, inc=par["inc"], beta=par["beta"],
+                                      mass_scale=par["mass_scale"], m_bh=par["m_bh"],
+                                      lum_I0=par["lum_I0"], mass_S0=par["mass_S0"])
+            return float(np.dot(cot, osph.vrms2(g, q)))
+
+        grad = {}
+        for key in ("inc", "beta", "mass_scale", "m_bh", "lum_I0", "mass_S0"):
+            v = np.atleast_1d(np.asarray(base[key], np.float64))
+            gk = np.zeros_like(v)
+            for i in range(v.size):
+                h = 1e-7 if key == "inc" else 1e-6 * max(abs(v[i]), 1e-3)
+                hi = {k: (np.array(x, np.float64) if np.ndim(x) else x) for k, x in base.items()}
+                lo = {k: (np.array(x, np.float64) if np.ndim(x) else x) for k, x in base.items()}
+                if np.ndim(base[key]):
+                    hi[key][i] += h
+                    lo[key][i] -= h
+                else:
+                    hi[key] = base[key] + h
+                    lo[key] = base[key] - h
+                gk[i] = (L(hi) - L(lo)) / (2 * h)
+            grad[key] = gk.tolist()
+        V = osph.vrms2(g, p)
+        out.append(dict(seed=seed, beta=list(beta), inc_deg=inc_deg, cot=cot.tolist(),
+                        vrms2=V.tolist(), grad=grad))
+    _dump("sph_grad.json", dict(
+        source="central differences of oracle/jam_sph.py vrms2 on two tiny seeded geometries "
+               "(inputs.small_geometry(seed, n_lum=2, n_mass=2, nx=6, ny=5, ss=1, psf_n=3, "
+               "n_bins=3, n_u=16)), cot = inputs.cotangent(n_bins, 1, seed)",
+        cases=out, seconds=time.time() - t))
+
+
 if __name__ == "__main__":
     torch.set_num_threads(max(1, os.cpu_count() or 1))
-    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5", "sph1"]
+    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5", "sph1", "sph_grad"]
     for name in todo:
         globals()[name]()

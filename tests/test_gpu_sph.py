@@ -84,7 +84,7 @@ def test_isotropic_spherical_close_to_cylindrical():
     sph.close()
 
 
-def test_batch_status_graph_and_unsupported_adjoint():
+def test_batch_status_graph_and_adjoint_status():
     dev = _dev()
     w3 = inputs.config3(n_models=6)
     bad = inputs.with_overrides(w3.params[1], inc=0.05)
@@ -101,10 +101,104 @@ def test_batch_status_graph_and_unsupported_adjoint():
         assert np.array_equal(Vg, V, equal_nan=True), rep
         _eval(eager, w, dev)
     p = binding.pack_params(w, dev, amplitudes=True)
-    Vd = torch.as_tensor(np.nan_to_num(V), device=dev)
-    with pytest.raises(binding.JamError) as e:
-        eager.vjp(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"], p["lum_I0"],
+    Vd = torch.as_tensor(V, device=dev)
+    g = eager.vjp(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"], p["lum_I0"],
                   p["mass_S0"], Vd, torch.ones_like(Vd))
-    assert e.value.status == 6
+    gi = g["inc"].cpu().numpy()
+    assert np.isnan(gi[1]) and np.all(np.isfinite(np.delete(gi, 1)))
+    K = w.geometries[0].n_lum
+    gb = g["beta"].cpu().numpy()
+    assert np.all(np.isnan(gb[K:2 * K])) and np.all(np.isfinite(np.delete(gb, np.s_[K:2 * K])))
     eager.close()
     graph.close()
+
+
+KEYS = ("inc", "beta", "mass_scale", "m_bh", "lum_I0", "mass_S0")
+
+
+def _case(c):
+    g = inputs.small_geometry(seed=c["seed"], n_lum=2, n_mass=2, nx=6, ny=5, ss=1, psf_n=3,
+                              n_bins=3, n_u=16)
+    p = inputs.with_overrides(inputs.small_params(g, seed=c["seed"]), beta=np.array(c["beta"]),
+                              inc=np.deg2rad(c["inc_deg"]))
+    return g, p
+
+
+def test_adjoint_vs_oracle_differences():
+    """Gradient of sum_b cot_b v_rms^2_b against central differences of the
+    FP64 oracle (stored), at the adjoint tests' bar: 1e-4 of the gradient's
+    norm and every component within 1e-3 relative or 1e-6 of the largest."""
+    dev = _dev()
+    gold = json.load(open(os.path.join(HERE, "golden", "sph_grad.json")))
+    for c in gold["cases"]:
+        g, p = _case(c)
+        w = inputs.Workload("g", [g], np.zeros(1, np.int32), [p])
+        ctx = binding.Context([g], alignment=1)
+        pk = binding.pack_params(w, dev, amplitudes=True)
+        V, st = ctx.eval_batch(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
+                               pk["lum_I0"], pk["mass_S0"])
+        assert int(st[0]) == 0
+        assert np.max(np.abs(V.cpu().numpy() / np.array(c["vrms2"]) - 1)) <= RTOL
+        cot = torch.as_tensor(np.array(c["cot"]), device=dev)
+        gr = ctx.vjp(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
+                     pk["lum_I0"], pk["mass_S0"], V, cot)
+        a = np.concatenate([np.atleast_1d(gr[k].cpu().numpy()) for k in KEYS])
+        b = np.concatenate([np.atleast_1d(np.array(c["grad"][k])) for k in KEYS])
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        comp = np.abs(a - b) <= np.maximum(1e-3 * np.abs(b), 1e-6 * np.max(np.abs(b)))
+        print(f"seed {c['seed']}: grad rel norm err {err:.3e}; components ok {comp.sum()}/{comp.size}")
+        for k in KEYS:
+            print("  ", k, np.atleast_1d(gr[k].cpu().numpy()), np.array(c["grad"][k]))
+        assert err <= 1e-4 and comp.all()
+        # recomputed forward inside the adjoint gives the same gradient
+        gr2 = ctx.vjp(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
+                      pk["lum_I0"], pk["mass_S0"], None, cot)
+        a2 = np.concatenate([np.atleast_1d(gr2[k].cpu().numpy()) for k in KEYS])
+        assert np.allclose(a2, a, rtol=1e-12, atol=1e-12 * np.max(np.abs(a)))
+        ctx.close()
+
+
+def test_adjoint_batch_matches_single_models():
+    """A batch of proposals on the config-1 geometry: each model's gradient
+    equals the one computed alone (per-model work is independent)."""
+    dev = _dev()
+    w3 = inputs.config3(n_models=4)
+    ctx = binding.Context(w3.geometries, alignment=1)
+    pk = binding.pack_params(w3, dev, amplitudes=True)
+    nb = w3.geometries[0].n_bins
+    cot = torch.as_tensor(inputs.cotangent(nb, 4, seed=1).ravel(), device=dev)
+    gb = ctx.vjp(w3.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"], pk["lum_I0"],
+                 pk["mass_S0"], None, cot)
+    K, J = w3.geometries[0].n_lum, w3.geometries[0].n_mass
+    for m in (0, 3):
+        w1 = inputs.Workload("one", w3.geometries, np.zeros(1, np.int32), [w3.params[m]])
+        p1 = binding.pack_params(w1, dev, amplitudes=True)
+        g1 = ctx.vjp(w1.geom_idx, p1["inc"], p1["mass_scale"], p1["m_bh"], p1["beta"],
+                     p1["lum_I0"], p1["mass_S0"], None, cot[m * nb:(m + 1) * nb].contiguous())
+        for k, sl in (("inc", slice(m, m + 1)), ("beta", slice(m * K, (m + 1) * K)),
+                      ("lum_I0", slice(m * K, (m + 1) * K)), ("mass_S0", slice(m * J, (m + 1) * J))):
+            a, b = gb[k][sl].cpu().numpy(), g1[k].cpu().numpy()
+            assert np.allclose(a, b, rtol=1e-9, atol=1e-9 * np.max(np.abs(b))), (m, k)
+    ctx.close()
+
+
+def test_chi2_adjoint_spherical():
+    """jam_vjp_chi2 on the spherical model equals jam_vjp fed d chi^2 / d V."""
+    dev = _dev()
+    w3 = inputs.config3(n_models=3)
+    g = w3.geometries[0]
+    ctx = binding.Context(w3.geometries, alignment=1)
+    vo, cov = inputs.kinematic_data(g.n_bins, seed=2)
+    ctx.set_kinematics(0, vo, cov)
+    pk = binding.pack_params(w3, dev, amplitudes=True)
+    args = (w3.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"], pk["lum_I0"],
+            pk["mass_S0"])
+    c2, V, st = ctx.eval_chi2(*args, keep_vrms2=True)
+    cot = torch.ones(3, dtype=torch.float64, device=dev)
+    ga = ctx.vjp_chi2(*args, cot, vrms2=V)
+    _, d = ctx.chi2(w3.geom_idx, V, want_grad=True)
+    gb = ctx.vjp(*args, V, d)
+    for k in KEYS:
+        a, b = ga[k].cpu().numpy(), gb[k].cpu().numpy()
+        assert np.allclose(a, b, rtol=1e-10, atol=1e-10 * np.max(np.abs(b))), k
+    ctx.close()
