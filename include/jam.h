@@ -108,9 +108,12 @@ typedef struct {
  *       integral); 1 = spherically aligned (eqs. J1, J2 of Sect. 2.4; beta_k
  *       = 1 - v_theta^2 / v_r^2), solved along the characteristics of the
  *       Jeans equations into a 128 x 24 polar table of the intrinsic moments
- *       per model and integrated along the line of sight (64 nodes); forward
- *       only (jam_vjp and jam_vjp_chi2 return JAM_E_UNSUPPORTED), form and
- *       autotune do not apply.                                              */
+ *       per model and integrated along the line of sight (64 nodes); form,
+ *       autotune and launch do not apply.  jam_vjp / jam_vjp_chi2 run the
+ *       model's own adjoint (always recomputing the moment table; the table
+ *       cotangent is accumulated with FP64 atomic adds, so gradients can
+ *       differ between calls in the last bits) and need a larger workspace
+ *       (jam_workspace_size).                                               */
 typedef struct {
   int32_t form;
   int32_t autotune;

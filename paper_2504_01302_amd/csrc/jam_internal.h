@@ -184,7 +184,7 @@ void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_i
                     hipStream_t st);
 // Adjoint of the spherically aligned model, after the bin adjoint has filled
 // lambda_N and lambda_I: zero the table cotangents (block per model), the
-// line-of-sight adjoint (items as launch_sph_num), the characteristic
+// line-of-sight adjoint (items (m, 256-pixel block)), the characteristic
 // integrals' adjoint (items as launch_sph_moments), the term-major
 // sensitivities over point ranges (items (m, 256-term tile, range)) and over
 // the table points (items (m, 256-term tile)), the per-term chain (items (m,

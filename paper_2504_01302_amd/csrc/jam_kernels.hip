@@ -1541,11 +1541,13 @@ __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ ge
   }
 }
 
-// Line-of-sight adjoint.  Item (m, 64-pixel block), thread = pixel, as the
-// forward.  The table cotangent receives lambda_N w_z (n.e_f)^2 times the
-// bilinear weights (atomic FP64 adds); the derivatives of the node's
-// integrand at fixed table with respect to i (line of sight and node
-// position) and to the node scale a are summed per item (wave sums).
+// Line-of-sight adjoint.  Item (m, 256-pixel block), thread = pixel.  The
+// table cotangent receives lambda_N w_z (n.e_f)^2 times the bilinear weights,
+// accumulated in a block-private LDS copy of the table (FP64 LDS atomics) and
+// added to the model's table once per block (FP64 global atomics, non-zero
+// entries only); the derivatives of the node's integrand at fixed table with
+// respect to i (line of sight and node position) and to the node scale a are
+// summed per 64-pixel wave.
 __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
                                                      const Item *__restrict__ items, int n_it,
@@ -1554,113 +1556,124 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
                                                      const double *__restrict__ table,
                                                      const double *__restrict__ pix,
                                                      double *__restrict__ sens) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t iw = gid >> 6;                 // item of this wave
-  if (iw >= n_it) return;                      // whole waves only
-  const Item it = items[iw];
-  const ModelDev md = models[it.m];
-  const GeomDev g = geoms[md.geom];
-  if (st_ws[it.m] != 0) return;                // uniform per wave
-  const SphAdj adj = sph_adj_of(sens, md, g);
-  const int q = it.a * 64 + (int)(gid & 63);
-  const bool on = q < g.n_pix;
-  const int K = g.K;
-  const double *tab = gauss + md.gauss_off;
-  const double *mt = tab + 4 * K;
-  const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
-  double smin = 1e300, smax = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
-    smin = fmin(smin, sk * qk);
-    smax = fmax(smax, sk);
-  }
-  const double a = 0.25 * smin, cW = 12.0 * smax, W = asinh(cW / a);
-  const double Wa = -(cW / (a * a)) / sqrt(1.0 + (cW / a) * (cW / a));   // dW/da
-  const double x = on ? g.xs[q % g.n_ux] : 0.0, y = on ? g.ys[q / g.n_ux] : 0.0;
-  const double lamN = on ? pix[md.pix_off + 2 * (int64_t)g.n_pix + q] : 0.0;
-  const double *T = table + md.sph_off;
-  const double dth = 0.5 * kPi / (kSphNT - 1);
-  const double hw = 2.0 * W / kSphSeg;
-  const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
-  double acc_i = 0.0, acc_a = 0.0;
-  for (int nd = 0; on && nd < kSphNodes; ++nd) {
-    const int seg = nd >> 3, gi = nd & 7;
-    const double om = -1.0 + (seg + 0.5 + 0.5 * glx[gi]) / 4.0;   // w = W om
-    const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
-    const double shw = sinh(w), chw = cosh(w);
-    const double zp = a * shw, wz = 0.5 * glw[gi] * hw * a * chw;
-    const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
-    const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
-    const double ct = Z / r, st = R / r;
-    const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
-    const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
-    if (xf > kSphNR - 1) continue;
-    const double yf = acos(fmin(1.0, fabs(ct))) / dth;
-    const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
-    const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
-    const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-    const int64_t i00 = ((int64_t)xi * kSphNT + yi) * 3;
-    const double *c00 = T + i00;
-    const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
-    const double ner = si * st * sp + ci * ct;
-    const double net = si * ct * sp - ci * st;
-    const double nep = si * cp;
-    const double nf[3] = {ner, net, nep};
-    // table cotangent
-    const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
-    double *d00 = adj.dtab + i00;
-    double *d10 = d00 + kSphNT * 3, *d01 = d00 + 3, *d11 = d10 + 3;
-    double A[3], AL[3], AT[3];
-    const bool xin = xf >= 0.0;          // below the first radius the table is constant
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const double cf = lamN * wz * nf[f] * nf[f];
-      atomicAdd(d00 + f, cf * w00);
-      atomicAdd(d10 + f, cf * w10);
-      atomicAdd(d01 + f, cf * w01);
-      atomicAdd(d11 + f, cf * w11);
-      A[f] = w00 * c00[f] + w10 * c10[f] + w01 * c01[f] + w11 * c11[f];
-      AL[f] = xin ? ((1 - fy) * (c10[f] - c00[f]) + fy * (c11[f] - c01[f])) / g.sph_dlnr : 0.0;
-      AT[f] = ((1 - fx) * (c01[f] - c00[f]) + fx * (c11[f] - c10[f])) / dth;
+  __shared__ double ldt[3 * kSphCells];
+  for (int ii = blockIdx.x; ii < n_it; ii += gridDim.x) {
+    const Item it = items[ii];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;              // uniform per block
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) ldt[i] = 0.0;
+    __syncthreads();
+    const int q = it.a * 256 + threadIdx.x;
+    const bool on = q < g.n_pix;
+    const int K = g.K;
+    const double *tab = gauss + md.gauss_off;
+    const double *mt = tab + 4 * K;
+    const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
+    double smin = 1e300, smax = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
+      smin = fmin(smin, sk * qk);
+      smax = fmax(smax, sk);
     }
-    // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
-    const double r2 = r * r, sz = Z < 0.0 ? -1.0 : 1.0;
-    const double lY = Y / r2, lZ = Z / r2;
-    const double tY = R > 0.0 ? fabs(Z) * (Y / R) / r2 : 0.0, tZ = -R * sz / r2;
-    // line-of-sight components and their derivatives (Y, Z; explicit i)
-    double nY[3] = {0.0, 0.0, 0.0}, nZ[3] = {0.0, 0.0, 0.0}, ni[3] = {0.0, 0.0, 0.0};
-    nY[0] = (si - ner * Y / r) / r;
-    nZ[0] = (ci - ner * Z / r) / r;
-    ni[0] = (ci * Y - si * Z) / r;
-    if (R > 0.0) {
-      const double rR = r * R;
-      nY[1] = ((si * Z - 2.0 * ci * Y) - net * (Y / r * R + r * Y / R)) / rR;
-      nZ[1] = (si * Y - net * (Z / r) * R) / rR;
-      ni[1] = (ci * Z * Y + si * R * R) / rR;
-      nY[2] = -si * X * Y / (R * R * R);
-      ni[2] = ci * X / R;
+    const double a = 0.25 * smin, cW = 12.0 * smax, W = asinh(cW / a);
+    const double Wa = -(cW / (a * a)) / sqrt(1.0 + (cW / a) * (cW / a));   // dW/da
+    const double x = on ? g.xs[q % g.n_ux] : 0.0, y = on ? g.ys[q / g.n_ux] : 0.0;
+    const double lamN = on ? pix[md.pix_off + 2 * (int64_t)g.n_pix + q] : 0.0;
+    const double *T = table + md.sph_off;
+    const double dth = 0.5 * kPi / (kSphNT - 1);
+    const double hw = 2.0 * W / kSphSeg;
+    const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
+    double acc_i = 0.0, acc_a = 0.0;
+    for (int nd = 0; on && nd < kSphNodes; ++nd) {
+      const int seg = nd >> 3, gi = nd & 7;
+      const double om = -1.0 + (seg + 0.5 + 0.5 * glx[gi]) / 4.0;   // w = W om
+      const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
+      const double shw = sinh(w), chw = cosh(w);
+      const double zp = a * shw, wz = 0.5 * glw[gi] * hw * a * chw;
+      const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
+      const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
+      const double ct = Z / r, st = R / r;
+      const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
+      const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
+      if (xf > kSphNR - 1) continue;
+      const double yf = acos(fmin(1.0, fabs(ct))) / dth;
+      const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
+      const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
+      const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
+      const int64_t i00 = ((int64_t)xi * kSphNT + yi) * 3;
+      const double *c00 = T + i00;
+      const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
+      const double ner = si * st * sp + ci * ct;
+      const double net = si * ct * sp - ci * st;
+      const double nep = si * cp;
+      const double nf[3] = {ner, net, nep};
+      // table cotangent
+      const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+      double *d00 = ldt + i00;
+      double *d10 = d00 + kSphNT * 3, *d01 = d00 + 3, *d11 = d10 + 3;
+      double A[3], AL[3], AT[3];
+      const bool xin = xf >= 0.0;          // below the first radius the table is constant
+  #pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const double cf = lamN * wz * nf[f] * nf[f];
+        atomicAdd(d00 + f, cf * w00);
+        atomicAdd(d10 + f, cf * w10);
+        atomicAdd(d01 + f, cf * w01);
+        atomicAdd(d11 + f, cf * w11);
+        A[f] = w00 * c00[f] + w10 * c10[f] + w01 * c01[f] + w11 * c11[f];
+        AL[f] = xin ? ((1 - fy) * (c10[f] - c00[f]) + fy * (c11[f] - c01[f])) / g.sph_dlnr : 0.0;
+        AT[f] = ((1 - fx) * (c01[f] - c00[f]) + fx * (c11[f] - c10[f])) / dth;
+      }
+      // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
+      const double r2 = r * r, sz = Z < 0.0 ? -1.0 : 1.0;
+      const double lY = Y / r2, lZ = Z / r2;
+      const double tY = R > 0.0 ? fabs(Z) * (Y / R) / r2 : 0.0, tZ = -R * sz / r2;
+      // line-of-sight components and their derivatives (Y, Z; explicit i)
+      double nY[3] = {0.0, 0.0, 0.0}, nZ[3] = {0.0, 0.0, 0.0}, ni[3] = {0.0, 0.0, 0.0};
+      nY[0] = (si - ner * Y / r) / r;
+      nZ[0] = (ci - ner * Z / r) / r;
+      ni[0] = (ci * Y - si * Z) / r;
+      if (R > 0.0) {
+        const double rR = r * R;
+        nY[1] = ((si * Z - 2.0 * ci * Y) - net * (Y / r * R + r * Y / R)) / rR;
+        nZ[1] = (si * Y - net * (Z / r) * R) / rR;
+        ni[1] = (ci * Z * Y + si * R * R) / rR;
+        nY[2] = -si * X * Y / (R * R * R);
+        ni[2] = ci * X / R;
+      }
+      double F = 0.0, FY = 0.0, FZ = 0.0, Fi = 0.0;
+  #pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const double dAY = AL[f] * lY + AT[f] * tY, dAZ = AL[f] * lZ + AT[f] * tZ;
+        F += nf[f] * nf[f] * A[f];
+        FY += 2.0 * nf[f] * nY[f] * A[f] + nf[f] * nf[f] * dAY;
+        FZ += 2.0 * nf[f] * nZ[f] * A[f] + nf[f] * nf[f] * dAZ;
+        Fi += 2.0 * nf[f] * ni[f] * A[f];
+      }
+      const double Yi = zp * ci + y * si, Zi = y * ci - zp * si;
+      acc_i += lamN * wz * (Fi + FY * Yi + FZ * Zi);
+      const double dzp = shw + a * chw * om * Wa;
+      const double dwz = 0.5 * glw[gi] * (2.0 / kSphSeg) *
+                         (Wa * a * chw + W * chw + W * a * shw * om * Wa);
+      acc_a += lamN * (dwz * F + wz * (FY * si + FZ * ci) * dzp);
     }
-    double F = 0.0, FY = 0.0, FZ = 0.0, Fi = 0.0;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const double dAY = AL[f] * lY + AT[f] * tY, dAZ = AL[f] * lZ + AT[f] * tZ;
-      F += nf[f] * nf[f] * A[f];
-      FY += 2.0 * nf[f] * nY[f] * A[f] + nf[f] * nf[f] * dAY;
-      FZ += 2.0 * nf[f] * nZ[f] * A[f] + nf[f] * nf[f] * dAZ;
-      Fi += 2.0 * nf[f] * ni[f] * A[f];
+    acc_i = wave_sum(acc_i);
+    acc_a = wave_sum(acc_a);
+    if ((threadIdx.x & 63) == 0) {
+      const int wb = it.a * 4 + (threadIdx.x >> 6);   // 64-pixel block of this wave
+      if (wb < (g.n_pix + 63) / 64) {
+        adj.losp[2 * wb] = acc_i;
+        adj.losp[2 * wb + 1] = acc_a;
+      }
     }
-    const double Yi = zp * ci + y * si, Zi = y * ci - zp * si;
-    acc_i += lamN * wz * (Fi + FY * Yi + FZ * Zi);
-    const double dzp = shw + a * chw * om * Wa;
-    const double dwz = 0.5 * glw[gi] * (2.0 / kSphSeg) *
-                       (Wa * a * chw + W * chw + W * a * shw * om * Wa);
-    acc_a += lamN * (dwz * F + wz * (FY * si + FZ * ci) * dzp);
-  }
-  acc_i = wave_sum(acc_i);
-  acc_a = wave_sum(acc_a);
-  if ((gid & 63) == 0) {
-    adj.losp[2 * it.a] = acc_i;
-    adj.losp[2 * it.a + 1] = acc_a;
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) {
+      const double v = ldt[i];
+      if (v != 0.0) atomicAdd(adj.dtab + i, v);
+    }
+    __syncthreads();
   }
 }
 
@@ -1678,6 +1691,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
                                                          const int *__restrict__ st_ws,
                                                          double *__restrict__ sens) {
   __shared__ float4 tc[kSphChunk];
+  __shared__ float4 tx[kSphChunk];   // (gP c_x, gP c_y, gT c_x, gT c_y)
   __shared__ float tf[kSphChunk];
   __shared__ double sh[256];
   constexpr double kLn2 = 0.6931471805599453;
@@ -1723,7 +1737,9 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
         const int cn = min(kSphChunk, Tp - c0);
         __syncthreads();
         for (int t = threadIdx.x; t < cn; t += 256) {
-          tc[t] = gtc[c0 + t];
+          const float4 c = gtc[c0 + t];
+          tc[t] = c;
+          tx[t] = make_float4(c.z * c.x, c.z * c.y, c.w * c.x, c.w * c.y);
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
@@ -1732,15 +1748,14 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
             float sG = 0.f, sT = 0.f, sGR = 0.f, sGZ = 0.f, sTR = 0.f, sTZ = 0.f;
 #pragma unroll 16
             for (int t = 0; t < 64; ++t) {
-              const float4 c = tc[t0 + t];
+              const float4 c = tc[t0 + t], d = tx[t0 + t];
               const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
-              const float pe = c.z * e, te = c.w * e;
-              sG += pe;
-              sT += te;
-              sGR = fmaf(c.x, pe, sGR);
-              sGZ = fmaf(c.y, pe, sGZ);
-              sTR = fmaf(c.x, te, sTR);
-              sTZ = fmaf(c.y, te, sTZ);
+              sG = fmaf(c.z, e, sG);
+              sT = fmaf(c.w, e, sT);
+              sGR = fmaf(d.x, e, sGR);
+              sGZ = fmaf(d.y, e, sGZ);
+              sTR = fmaf(d.z, e, sTR);
+              sTZ = fmaf(d.w, e, sTZ);
             }
             aG += (double)sG;
             aT += (double)sT;
@@ -1877,10 +1892,10 @@ __global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ ge
       pa[threadIdx.x] = va;
       pb[threadIdx.x] = vb;
       __syncthreads();
-      const int cnt = (int)min((int64_t)256, p1 - c0);
       float sP = 0.f, sT = 0.f, sxP = 0.f, sxT = 0.f, syP = 0.f, syT = 0.f;
       if (tv) {
-        for (int j = 0; j < cnt; ++j) {
+#pragma unroll 16
+        for (int j = 0; j < 256; ++j) {   // points past the range are zero
           const float4 A = pa[j], B = pb[j];
           const float e = fast_exp2(fmaf(c.x, A.x, c.y * A.y));
           sP = fmaf(A.z, e, sP);
@@ -2380,8 +2395,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                         const int *st_ws, const double *table, const double *pix, double *sens,
                         GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, sens);
-  hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of((n_los + 3) / 4)), dim3(256), 0, st, g, m,
-                     it_los, n_los, gauss, st_ws, table, pix, sens);
+  hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
+                     gauss, st_ws, table, pix, sens);
   hipLaunchKernelGGL(k_sph_moments_adj, dim3(grid_of(n_cell)), dim3(256), 0, st, g, m, it_cell,
                      n_cell, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
