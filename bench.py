@@ -493,6 +493,9 @@ def main():
         extras = {
             "batched_4096_small": lambda: time_batch(torch, binding, inputs.config3(4096), dev,
                                                      k, a.form, a.launch, a.graph),
+            "ifu_scale_batch_8": lambda: time_batch(
+                torch, binding, inputs.Workload("cfg2x8", [g], np.zeros(8, np.int32), [p] * 8),
+                dev, k, a.form, a.launch, a.graph),
             "uneven_1024": lambda: time_batch(torch, binding, inputs.config4(1024), dev, 2,
                                               a.form, a.launch, a.graph),
             "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,

@@ -311,6 +311,7 @@ struct Plan {
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
          off_bins = 0, off_vfwd = 0, off_sph = 0, off_sens = 0, off_vtmp = 0, off_cot = 0,
+         off_sbp = 0,
          ws_fwd = 0, ws_vjp = 0;
   // captured evaluations (forward, adjoint, forward + chi^2, adjoint of chi^2)
   hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -549,7 +550,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
       it_red, it_sph;
   std::vector<double> c_num, c_sens;
-  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0;
+  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
   for (int m = 0; m < n; ++m) {
     const int gi = geom_idx[m];
@@ -574,6 +575,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     d.sens_off = sens;
     d.bin_off = bins;
     d.sph_off = sph;
+    d.sbp_off = sbp;
+    sbp += (int64_t)g.K * jam::sb_tiles(g.n_ux, g.n_uy);
     if (spherical) {
       sph += (int64_t)jam::kSphNR * jam::kSphNT * 3;
       for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
@@ -588,7 +591,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       d.n_sens_parts = jam::sph_ranges(g.K);
       sens += jam::sph_adj_size(g.K, g.n_pix, tsph, d.n_sens_parts);
     } else {
-      sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * (3 * g.J1 + 1);
+      sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * 3 * g.J1;
     }
     p->total_lum += g.K;
     p->total_mass += g.J;
@@ -630,11 +633,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       }
     for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
-    for (int k = 0; k < g.K; ++k)
-      if (spherical)
-        it_chain.push_back({m, k, 0, 0});
-      else
-        for (int jb = 0; jb <= (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
+    if (!spherical)
+      for (int k = 0; k < g.K; ++k)
+        for (int jb = 0; jb < (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
   }
   if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
     return fail(JAM_E_UNSUPPORTED, "batch too large");
@@ -696,6 +697,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_sens = w;   w = align256(w + sizeof(double) * sens);
   p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->off_cot = w;    w = align256(w + sizeof(double) * p->total_bins);
+  p->off_sbp = w;    w = align256(w + sizeof(double) * sbp);
   p->ws_vjp = w;
   out = std::move(p);
   return JAM_OK;
@@ -779,15 +781,17 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     cot = c;
   }
   jam::launch_bins_adjoint(ctx->d_geoms, p->d_models, p->d_pix, p->n_pix, V, cot, binws, st_ws, pix, st);
+  double *sbp = (double *)(w + p->off_sbp);
+  jam::launch_sb_adjoint(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, st_ws, pix, sbp, st);
   const jam::GradsDev gd{grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
                          grads->mass_S0};
   if (p->spherical) {
     const bool ts = ctx->t_sens.begin(st, capturing);
     jam::launch_sph_adjoint(ctx->d_geoms, p->d_models, p->n, p->d_pix, p->n_pix, p->d_sph,
-                            p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, p->d_chain,
-                            p->n_chain, pd, (const double *)(w + p->off_gauss),
+                            p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, pd,
+                            (const double *)(w + p->off_gauss),
                             (const float4 *)(w + p->off_terms), st_ws,
-                            (const double *)(w + p->off_sph), pix, sens, gd, st);
+                            (const double *)(w + p->off_sph), pix, sbp, sens, gd, st);
     if (ts) ctx->t_sens.end(st);
     return;
   }
@@ -797,7 +801,7 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
                    p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
   if (timed) ctx->t_sens.end(st);
   jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
-  jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, st_ws, gd, st);
+  jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, sbp, st_ws, gd, st);
 }
 
 // ---------------------------------------------------------------------------

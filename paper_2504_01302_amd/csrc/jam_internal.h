@@ -72,7 +72,13 @@ struct ModelDev {
   int64_t sens_off;  // doubles, per-term adjoint sensitivities + chain rows
   int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
   int64_t sph_off;   // doubles, spherical moment table [kSphNR][kSphNT][3]
+  int64_t sbp_off;   // doubles, surface-brightness adjoint partials [K][sb items]
 };
+// Surface-brightness tiles: kSbRows rows x 64 columns of the unique-pixel map.
+constexpr int kSbRows = 8;
+__host__ __device__ inline int sb_tiles(int n_ux, int n_uy) {
+  return ((n_uy + kSbRows - 1) / kSbRows) * ((n_ux + 63) / 64);
+}
 
 // Observed kinematics of one geometry for the chi^2 of eq. (chi2_dyn):
 // v_rms per bin and the inverse covariance of their errors (row-major,
@@ -159,15 +165,14 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const float4 *terms, const double *pix, const int *st_ws, double *sens,
                  int *queue, int grid, hipStream_t st);
 // sens region per model: n_sens_parts blocks of [S0 | S1 | Sg] (T doubles
-// each), then the chain rows: [K][J1][3] doubles and [K] doubles.  Chain
-// items (m, k, jb) for jb <= ceil(J1 / 4) (the last one per k is the
-// surface-brightness path).  The per-pixel kernel
+// each), then the chain rows [K][J1][3].  Chain items (m, k, jb) for
+// jb < ceil(J1 / 4), one mass Gaussian per wave.  The per-pixel kernel
 // writes one block; the MFMA kernel one block per 32-row x tile (items
 // (m, x tile, 256-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   const double *pix, double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
-                  const int *st_ws, GradsDev out, hipStream_t st);
+                  const double *sbp, const int *st_ws, GradsDev out, hipStream_t st);
 // Spherically aligned model.  Terms: items (m, block of 256 terms), the
 // model's FP32 (j, u) coefficients into its term region.  Moments: items (m,
 // table point i_r * kSphNT + i_theta), one workgroup each, writing A_r,
@@ -182,34 +187,39 @@ void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);
+// Surface-brightness adjoint, after the bin adjoint has filled lambda_I:
+// items (m, row tile, column tile) as launch_sb; sbp[m][k][tile] = sum over
+// the tile of lambda_I exp(-x^2 / 2 sigma'^2 - y^2 / 2 sigma'^2 q'^2).
+void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                       const int *st_ws, const double *pix, double *sbp, hipStream_t st);
 // Adjoint of the spherically aligned model, after the bin adjoint has filled
 // lambda_N and lambda_I: zero the table cotangents (block per model), the
 // line-of-sight adjoint (items (m, 256-pixel block)), the characteristic
 // integrals' adjoint (items as launch_sph_moments), the term-major
 // sensitivities over point ranges (items (m, 256-term tile, range)) and over
 // the table points (items (m, 256-term tile)), the per-term chain (items (m,
-// 256-term tile)), the surface-brightness rows (items (m, k)), and the
-// per-model gradients (block per model).
+// 256-term tile)), and the per-model gradients (block per model; they read
+// the surface-brightness partials sbp).
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
-                        int n_sens, const Item *it_tile, int n_tile, const Item *it_k, int n_k,
-                        ParamsDev p, const double *gauss, const float4 *terms,
-                        const int *st_ws, const double *table, const double *pix, double *sens,
+                        int n_sens, const Item *it_tile, int n_tile, ParamsDev p,
+                        const double *gauss, const float4 *terms, const int *st_ws,
+                        const double *table, const double *pix, const double *sbp, double *sens,
                         GradsDev out, hipStream_t st);
 // Adjoint of the spherically aligned model.  Per model, in the sensitivity
 // region (doubles): the table cotangent [kSphNR*kSphNT][3], per (cell,
 // tracer) rows (d/dbeta, d/dalphaq, d/dnu0) [cells][K][3], line-of-sight
 // partials (d/di at fixed node scale, d/d node scale) per 64-pixel block,
 // per-term sensitivities per point range [n_rng][Tp][6] and of the cell
-// points [Tp][3], per-term chain values (d/de2, d/dKp) [Tp][2], and the
-// surface-brightness rows [K].  n_rng is ModelDev::n_sens_parts.
+// points [Tp][3] and per-term chain values (d/de2, d/dKp) [Tp][2].  n_rng is
+// ModelDev::n_sens_parts.
 constexpr int kSphCells = kSphNR * kSphNT;
 struct SphAdj {
-  double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *sbrow;
+  double *dtab, *rows, *losp, *sparts, *cparts, *tchain;
 };
 __host__ __device__ inline int64_t sph_adj_size(int K, int n_pix, int Tp, int n_rng) {
   return 3LL * kSphCells + 3LL * kSphCells * K + 2LL * ((n_pix + 63) / 64) +
-         6LL * n_rng * Tp + 5LL * Tp + K;
+         6LL * n_rng * Tp + 5LL * Tp;
 }
 __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix, int Tp,
                                                  int n_rng) {
@@ -220,7 +230,6 @@ __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix,
   a.sparts = a.losp + 2LL * ((n_pix + 63) / 64);
   a.cparts = a.sparts + 6LL * n_rng * Tp;
   a.tchain = a.cparts + 3LL * Tp;
-  a.sbrow = a.tchain + 2LL * Tp;
   return a;
 }
 // Points of one model's characteristic integrals: (cell, tracer, node).

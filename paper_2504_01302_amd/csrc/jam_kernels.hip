@@ -161,6 +161,50 @@ __global__ void __launch_bounds__(64) k_setup(const GeomDev *__restrict__ geoms,
   }
 }
 
+// Surface-brightness adjoint: the derivative of sum_p lambda_I[p] I[p] with
+// respect to I0_k, per tile of kSbRows rows x 64 columns (the forward's
+// items): lane = column, waves split the Gaussians; FP64, wave sums; the
+// per-tile partials are summed by the gradient kernels in tile order.
+__global__ void __launch_bounds__(256) k_sb_adj(const GeomDev *__restrict__ geoms,
+                                                const ModelDev *__restrict__ models,
+                                                const Item *__restrict__ items, int n_it,
+                                                const int *__restrict__ st_ws,
+                                                const double *__restrict__ pix,
+                                                double *__restrict__ sbp) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;
+    const int y0 = it.a * kSbRows;
+    const int ix = it.b * 64 + lane;
+    const bool vx = ix < g.n_ux;
+    const double x = vx ? g.xs[ix] : 0.0;
+    const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
+    double lam[kSbRows], yy[kSbRows];
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r) {
+      const bool v = vx && y0 + r < g.n_uy;
+      const double y = y0 + r < g.n_uy ? g.ys[y0 + r] : 0.0;
+      yy[r] = y * y;
+      lam[r] = v ? lamI[(int64_t)(y0 + r) * g.n_ux + ix] : 0.0;
+    }
+    const int tile = it.a * ((g.n_ux + 63) / 64) + it.b;
+    const int n_tiles = sb_tiles(g.n_ux, g.n_uy);
+    for (int k = wave; k < g.K; k += 4) {
+      const double sig = g.lum_sigma[k], qo = g.lum_q[k];
+      const double a = 1.0 / (2.0 * sig * sig), ay = a / (qo * qo);
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kSbRows; ++r) acc += lam[r] * exp(-ay * yy[r]);
+      acc = wave_sum(acc * exp(-a * x * x));
+      if (lane == 0) sbp[md.sbp_off + (int64_t)k * n_tiles + tile] = acc;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Term table: FP64 coefficients of every (k, j, n) term, stored as FP32
 // (-c1 log2e, -gamma log2e, C0, C1).  Term t = (k * J1 + j) * n_u + n.
@@ -220,7 +264,6 @@ __global__ void __launch_bounds__(256) k_terms(const GeomDev *__restrict__ geoms
 // computed once per workgroup, the column factor once per thread and k.
 // pix region per model: [N | I | lambda_N | lambda_I], n_pix doubles each.
 // ---------------------------------------------------------------------------
-constexpr int kSbRows = 8;
 
 // Item (m, block of 8 rows, block of 64 columns); lane = column, wave w takes
 // luminous Gaussians k = w, w + 4, ...; the four partial sums are combined in
@@ -642,10 +685,24 @@ __global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms
       if (want_n) an[u] += wv * Nm[q];
       ai[u] += wv * Im[q];
     }
-    const double an_t = (an[0] + an[1]) + (an[2] + an[3]);
-    const double ai_t = (ai[0] + ai[1]) + (ai[2] + ai[3]);
-    const double sn = want_n ? block_sum1024(an_t, sh) : 0.0;
-    const double si = block_sum1024(ai_t, sh);
+    // deterministic two-level sums: wave butterflies, then the 16 wave
+    // partials in a fixed order
+    const double an_w = wave_sum((an[0] + an[1]) + (an[2] + an[3]));
+    const double ai_w = wave_sum((ai[0] + ai[1]) + (ai[2] + ai[3]));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+      sh[wv] = an_w;
+      sh[16 + wv] = ai_w;
+    }
+    __syncthreads();
+    double sn = 0.0, si = 0.0;
+    if (threadIdx.x == 0)
+      for (int w = 0; w < 16; ++w) {
+        sn += sh[w];
+        si += sh[16 + w];
+      }
+    if (!want_n) sn = 0.0;
+    __syncthreads();
     if (threadIdx.x == 0) {
       const bool ok = st_ws[it.m] == 0;
       if (binws) {
@@ -965,7 +1022,6 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
                                                ParamsDev p, const double *__restrict__ pix,
                                                double *__restrict__ sens,
                                                const int *__restrict__ st_ws) {
-  __shared__ double sh[256];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
@@ -977,34 +1033,6 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
     const int J1 = g.J1, J = J1 - 1;
     double *rows = chain_rows(sens, md, g);
     const double qok = g.lum_q[k], sk = g.lum_sigma[k];
-    if (it.b * 4 >= J1) {
-      // surface-brightness path of I0_k, separable in x and y: the row
-      // factors of up to 256 rows go through LDS, the column factor is
-      // computed once per column and row chunk.
-      const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
-      const double ax = 0.5 / (sk * sk), ay = ax / (qok * qok);
-      double acc = 0.0;
-      for (int y0 = 0; y0 < g.n_uy; y0 += 256) {
-        const int ny = min(256, g.n_uy - y0);
-        __syncthreads();
-        if (threadIdx.x < ny) {
-          const double yv = g.ys[y0 + threadIdx.x];
-          sh[threadIdx.x] = exp(-ay * yv * yv);
-        }
-        __syncthreads();
-        for (int ix = threadIdx.x; ix < g.n_ux; ix += 256) {
-          const double xv = g.xs[ix];
-          const double *col = lamI + (int64_t)y0 * g.n_ux + ix;
-          double cs = 0.0;
-          for (int r = 0; r < ny; ++r) cs += col[(int64_t)r * g.n_ux] * sh[r];
-          acc += exp(-ax * xv * xv) * cs;
-        }
-      }
-      __syncthreads();   // row factors in sh are still being read
-      const double t = block_sum256(acc, sh);
-      if (threadIdx.x == 0) rows[(int64_t)g.K * J1 * 3 + k] = t;
-      continue;
-    }
     const int j = it.b * 4 + wave;
     if (j >= J1) continue;            // uniform per wave; no block barrier follows
     const double inc = p.inc[it.m];
@@ -1041,12 +1069,27 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
     double acc_i = 0.0, acc_b = 0.0, hj = 0.0;
     for (int n = lane; n < g.n_u; n += 64) {
       const int64_t t = ((int64_t)k * J1 + j) * g.n_u + n;
+      // partial sensitivities of the x-row blocks, summed in block order;
+      // eight blocks' loads are issued before their adds
       double S0 = 0.0, S1 = 0.0, Sg = 0.0;
-      for (int q = 0; q < np_; ++q) {
-        const double *blk = S0a + (int64_t)q * 3 * g.T;
-        S0 += blk[t];
-        S1 += blk[g.T + t];
-        Sg += blk[2 * (int64_t)g.T + t];
+      for (int q0 = 0; q0 < np_; q0 += 8) {
+        double v0[8], v1[8], v2[8];
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          v0[qq] = v1[qq] = v2[qq] = 0.0;
+          if (q0 + qq < np_) {
+            const double *blk = S0a + (int64_t)(q0 + qq) * 3 * g.T;
+            v0[qq] = blk[t];
+            v1[qq] = blk[g.T + t];
+            v2[qq] = blk[2 * (int64_t)g.T + t];
+          }
+        }
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          S0 += v0[qq];
+          S1 += v1[qq];
+          Sg += v2[qq];
+        }
       }
       const double u = g.u[n], wq = g.w[n];
       const double u2 = u * u;
@@ -1087,6 +1130,7 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
 __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms,
                                                const ModelDev *__restrict__ models, int n,
                                                ParamsDev p, double *__restrict__ sens,
+                                               const double *__restrict__ sbp,
                                                const int *__restrict__ st_ws, GradsDev out) {
   __shared__ double part[4][2];
   __shared__ double mpart[4][64];
@@ -1116,15 +1160,20 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
         db += o[1];
         dI += mass(j) * o[2];
       }
+      // surface-brightness path of I0_k: the tile partials, in tile order
+      double sb = 0.0;
+      const int n_tiles = sb_tiles(g.n_ux, g.n_uy);
+      if (ok)
+        for (int tl = lane; tl < n_tiles; tl += 64) sb += sbp[md.sbp_off + (int64_t)k * n_tiles + tl];
       a = wave_sum(a);
       db = wave_sum(db);
       dI = wave_sum(dI);
+      sb = wave_sum(sb);
       di += a;
       if (lane == 0) {
         const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
         if (out.beta) out.beta[md.lum_off + k] = ok ? db * b * b : nan;   // db/dbeta = b^2
-        if (out.lum_I0)
-          out.lum_I0[md.lum_off + k] = ok ? dI + rows[(int64_t)K * J1 * 3 + k] : nan;
+        if (out.lum_I0) out.lum_I0[md.lum_off + k] = ok ? dI + sb : nan;
       }
     }
     // d/dM_j = sum_k I0_k H_kj; then the mass scale, Sigma0_j and the BH
@@ -1132,11 +1181,24 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
     for (int j0 = 0; j0 < J1; j0 += 64) {
       const int j = j0 + lane;
       double dM = 0.0;
-      if (j < J1)
-        for (int k = wave; k < K; k += 4) {
-          const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-          dM += I0 * rows[((int64_t)k * J1 + j) * 3 + 2];
+      if (j < J1) {
+        // loads of eight tracers are issued before their (ordered) adds
+        for (int k0 = wave; k0 < K; k0 += 32) {
+          double iv[8], hv[8];
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            const int k = k0 + 4 * kk;
+            iv[kk] = 0.0;
+            hv[kk] = 0.0;
+            if (k < K) {
+              iv[kk] = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+              hv[kk] = rows[((int64_t)k * J1 + j) * 3 + 2];
+            }
+          }
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) dM += iv[kk] * hv[kk];
         }
+      }
       __syncthreads();
       mpart[wave][lane] = dM;
       __syncthreads();
@@ -2029,34 +2091,6 @@ __global__ void __launch_bounds__(256) k_sph_chain(const GeomDev *__restrict__ g
   }
 }
 
-// Surface-brightness rows: dL/dI0_k through I, sum_p lambda_I[p] exp(-x^2 /
-// 2 sigma'^2 - y^2 / 2 sigma'^2 q'^2).  Item (m, k); fixed-order sums.
-__global__ void __launch_bounds__(256) k_sph_sb_adj(const GeomDev *__restrict__ geoms,
-                                                    const ModelDev *__restrict__ models,
-                                                    const Item *__restrict__ items, int n_it,
-                                                    const int *__restrict__ st_ws,
-                                                    const double *__restrict__ pix,
-                                                    double *__restrict__ sens) {
-  __shared__ double sh[256];
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
-    const Item it = items[i];
-    const ModelDev md = models[it.m];
-    const GeomDev g = geoms[md.geom];
-    if (st_ws[it.m] != 0) continue;
-    const int k = it.a;
-    const double *lamI = pix + md.pix_off + 3 * (int64_t)g.n_pix;
-    const double sk = g.lum_sigma[k], qo = g.lum_q[k];
-    const double ax = 0.5 / (sk * sk), ay = ax / (qo * qo);
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < g.n_pix; q += 256) {
-      const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-      acc += lamI[q] * exp(-ax * x * x - ay * y * y);
-    }
-    const double s = block_sum256(acc, sh);
-    if (threadIdx.x == 0) sph_adj_of(sens, md, g).sbrow[k] = s;
-  }
-}
-
 // Per-model gradients.  Block per model: sums over cells (rows), u-nodes
 // (per-term chain) and pixel blocks (line-of-sight partials) in a fixed
 // order, then the set-up's derivatives (App. A) to the parameters.
@@ -2064,7 +2098,8 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
                                                    const ModelDev *__restrict__ models, int n,
                                                    ParamsDev p, const double *__restrict__ gauss,
                                                    const int *__restrict__ st_ws,
-                                                   double *__restrict__ sens, GradsDev out) {
+                                                   double *__restrict__ sens,
+                                                   const double *__restrict__ sbp, GradsDev out) {
   __shared__ double sh[256];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -2092,9 +2127,14 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
           aq += row[1];
           nv += row[2];
         }
+      double sb = 0.0;
+      const int n_tiles = sb_tiles(g.n_ux, g.n_uy);
+      if (ok)
+        for (int tl = lane; tl < n_tiles; tl += 64) sb += sbp[md.sbp_off + (int64_t)k * n_tiles + tl];
       b = wave_sum(b);
       aq = wave_sum(aq);
       nv = wave_sum(nv);
+      sb = wave_sum(sb);
       if (lane == 0) {
         const double qo = g.lum_q[k], sk = g.lum_sigma[k];
         const double alpha = tab[k], q = sqrt(alpha / tab[K + k]);
@@ -2104,7 +2144,7 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
         if (out.beta) out.beta[md.lum_off + k] = ok ? b : nan;
         if (out.lum_I0)
           out.lum_I0[md.lum_off + k] =
-              ok ? nv * qo / (sqrt(2.0 * kPi) * sk * q) + adj.sbrow[k] : nan;
+              ok ? nv * qo / (sqrt(2.0 * kPi) * sk * q) + sb : nan;
       }
     }
     // mass Gaussians and the BH: per-term chain summed over u-nodes
@@ -2368,8 +2408,14 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                      st_ws);
 }
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
-                  const int *st_ws, GradsDev out, hipStream_t st) {
-  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, st_ws, out);
+                  const double *sbp, const int *st_ws, GradsDev out, hipStream_t st) {
+  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, sbp, st_ws,
+                     out);
+}
+void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                       const int *st_ws, const double *pix, double *sbp, hipStream_t st) {
+  hipLaunchKernelGGL(k_sb_adj, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, st_ws, pix,
+                     sbp);
 }
 void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                       const double *gauss, const int *st_ws, float4 *terms, hipStream_t st) {
@@ -2390,9 +2436,9 @@ void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_i
 }
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
-                        int n_sens, const Item *it_tile, int n_tile, const Item *it_k, int n_k,
-                        ParamsDev p, const double *gauss, const float4 *terms,
-                        const int *st_ws, const double *table, const double *pix, double *sens,
+                        int n_sens, const Item *it_tile, int n_tile, ParamsDev p,
+                        const double *gauss, const float4 *terms, const int *st_ws,
+                        const double *table, const double *pix, const double *sbp, double *sens,
                         GradsDev out, hipStream_t st) {
   hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, sens);
   hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
@@ -2405,10 +2451,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                      n_tile, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_chain, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile, n_tile,
                      gauss, st_ws, sens);
-  hipLaunchKernelGGL(k_sph_sb_adj, dim3(grid_of(n_k)), dim3(256), 0, st, g, m, it_k, n_k, st_ws,
-                     pix, sens);
   hipLaunchKernelGGL(k_sph_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, gauss, st_ws,
-                     sens, out);
+                     sens, sbp, out);
 }
 void launch_beta_logistic(const GeomDev *g, const ModelDev *m, int n, const double *prof,
                           double *beta, hipStream_t st) {
