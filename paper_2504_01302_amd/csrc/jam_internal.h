@@ -207,8 +207,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                         const double *table, const double *pix, const double *sbp, double *sens,
                         GradsDev out, hipStream_t st);
 // Adjoint of the spherically aligned model.  Per model, in the sensitivity
-// region (doubles): the table cotangent [kSphNR*kSphNT][3], per (cell,
-// tracer) rows (d/dbeta, d/dalphaq, d/dnu0) [cells][K][3], line-of-sight
+// region (doubles): the table cotangent [kSphNR*kSphNT][3], per (tracer,
+// cell) rows (d/dbeta, d/dalphaq, d/dnu0) [K][cells][3], line-of-sight
 // partials (d/di at fixed node scale, d/d node scale) per 64-pixel block,
 // per-term sensitivities per point range [n_rng][Tp][6] and of the cell
 // points [Tp][3] and per-term chain values (d/de2, d/dKp) [Tp][2].  n_rng is

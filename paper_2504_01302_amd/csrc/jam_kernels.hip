@@ -1123,17 +1123,18 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
   }
 }
 
-// Final per-model gradients from the chain rows.  One 256-thread block per
+// Final per-model gradients from the chain rows.  One 1024-thread block per
 // model: each wave reduces one luminous Gaussian's row at a time over the
 // mass Gaussians (lanes), then the waves reduce the mass derivatives over
 // the luminous Gaussians; partial sums are combined in a fixed order.
-__global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms,
+__global__ void __launch_bounds__(1024) k_grads(const GeomDev *__restrict__ geoms,
                                                const ModelDev *__restrict__ models, int n,
                                                ParamsDev p, double *__restrict__ sens,
                                                const double *__restrict__ sbp,
                                                const int *__restrict__ st_ws, GradsDev out) {
-  __shared__ double part[4][2];
-  __shared__ double mpart[4][64];
+  constexpr int kW = 16;   // waves per block
+  __shared__ double part[kW];
+  __shared__ double mpart[kW][64];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
@@ -1152,7 +1153,7 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
     };
     // d/di, d/dbeta_k, d/dI0_k
     double di = 0.0;
-    for (int k = wave; k < K; k += 4) {
+    for (int k = wave; k < K; k += kW) {
       double a = 0.0, db = 0.0, dI = 0.0;
       for (int j = lane; j < J1; j += 64) {
         const double *o = rows + ((int64_t)k * J1 + j) * 3;
@@ -1183,11 +1184,11 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
       double dM = 0.0;
       if (j < J1) {
         // loads of eight tracers are issued before their (ordered) adds
-        for (int k0 = wave; k0 < K; k0 += 32) {
+        for (int k0 = wave; k0 < K; k0 += 8 * kW) {
           double iv[8], hv[8];
 #pragma unroll
           for (int kk = 0; kk < 8; ++kk) {
-            const int k = k0 + 4 * kk;
+            const int k = k0 + kW * kk;
             iv[kk] = 0.0;
             hv[kk] = 0.0;
             if (k < K) {
@@ -1203,7 +1204,8 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
       mpart[wave][lane] = dM;
       __syncthreads();
       if (wave == 0 && j < J1) {
-        dM = ((mpart[0][lane] + mpart[1][lane]) + mpart[2][lane]) + mpart[3][lane];
+        dM = 0.0;
+        for (int w = 0; w < kW; ++w) dM += mpart[w][lane];
         if (j < J) {
           const double qo = g.mass_q[j], sj = g.mass_sigma[j];
           const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
@@ -1216,10 +1218,11 @@ __global__ void __launch_bounds__(256) k_grads(const GeomDev *__restrict__ geoms
       }
     }
     if (wave == 0) dml = wave_sum(dml);
-    if (lane == 0) part[wave][0] = di;
+    if (lane == 0) part[wave] = di;
     __syncthreads();
     if (threadIdx.x == 0) {
-      const double dsum = ((part[0][0] + part[1][0]) + part[2][0]) + part[3][0];
+      double dsum = 0.0;
+      for (int w = 0; w < kW; ++w) dsum += part[w];
       if (out.inc) out.inc[m] = ok ? dsum : nan;
       if (out.mass_scale) out.mass_scale[m] = ok ? dml : nan;
     }
@@ -1875,7 +1878,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
           const double muD = lp * (1.0 - beta) * sth * rd;
           const double dbeta = muP * rb * bP + muD * bD - (lt + lp) * P - 2.0 * lnr * muP * P -
                                fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - beta) * lnr);
-          double *row = adj.rows + ((int64_t)cell * K + k) * 3;
+          double *row = adj.rows + ((int64_t)k * kSphCells + cell) * 3;
           row[0] = dbeta;
           row[1] = muP * rb * qP + muD * qD;
           row[2] = muP * rb * eP + muD * eD;
@@ -1886,7 +1889,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
     // A_phi -= nu(cell) R0^2 G_phi, nu(cell) = sum_k nu0_k exp(-(alpha R0^2 + alphaq z0^2))
     for (int k = threadIdx.x; k < K; k += 256) {
       const double e0 = exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
-      double *row = adj.rows + ((int64_t)cell * K + k) * 3;
+      double *row = adj.rows + ((int64_t)k * kSphCells + cell) * 3;
       row[1] += lp * Rp0 * Rp0 * Gphi * tab[2 * K + k] * e0 * zp0 * zp0;
       row[2] += -lp * Rp0 * Rp0 * Gphi * e0;
     }
@@ -2094,13 +2097,14 @@ __global__ void __launch_bounds__(256) k_sph_chain(const GeomDev *__restrict__ g
 // Per-model gradients.  Block per model: sums over cells (rows), u-nodes
 // (per-term chain) and pixel blocks (line-of-sight partials) in a fixed
 // order, then the set-up's derivatives (App. A) to the parameters.
-__global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ geoms,
+__global__ void __launch_bounds__(512) k_sph_grads(const GeomDev *__restrict__ geoms,
                                                    const ModelDev *__restrict__ models, int n,
                                                    ParamsDev p, const double *__restrict__ gauss,
                                                    const int *__restrict__ st_ws,
                                                    double *__restrict__ sens,
                                                    const double *__restrict__ sbp, GradsDev out) {
-  __shared__ double sh[256];
+  constexpr int kW = 8;    // waves per block
+  __shared__ double sh[4][kW];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
@@ -2117,15 +2121,29 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
     // dq/di of a deprojected Gaussian of observed axis ratio qo
     auto dqdi = [&](double qo, double q) { return ci * (1.0 - qo * qo) / (q * si * si * si); };
     double di = 0.0;
-    // tracers: rows summed over cells (lanes split the cells, wave sum)
-    for (int k = wave; k < K; k += 4) {
+    // tracers: rows summed over cells (lanes split the cells, four cells'
+    // loads in flight, wave sum)
+    for (int k = wave; k < K; k += kW) {
       double b = 0.0, aq = 0.0, nv = 0.0;
       if (ok)
-        for (int cell = lane; cell < kSphCells; cell += 64) {
-          const double *row = adj.rows + ((int64_t)cell * K + k) * 3;
-          b += row[0];
-          aq += row[1];
-          nv += row[2];
+        for (int c0 = lane; c0 < kSphCells; c0 += 4 * 64) {
+          double vb[4], vq[4], vn[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            vb[u] = vq[u] = vn[u] = 0.0;
+            if (c0 + 64 * u < kSphCells) {
+              const double *row = adj.rows + ((int64_t)k * kSphCells + c0 + 64 * u) * 3;
+              vb[u] = row[0];
+              vq[u] = row[1];
+              vn[u] = row[2];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            b += vb[u];
+            aq += vq[u];
+            nv += vn[u];
+          }
         }
       double sb = 0.0;
       const int n_tiles = sb_tiles(g.n_ux, g.n_uy);
@@ -2151,14 +2169,17 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
     const double sp = g.s_pc, Gc = grav_const();
     const double ml = p.mass_scale[m];
     double dml = 0.0;
-    for (int j = threadIdx.x; j < J1; j += 256) {
+    for (int j = wave; j < J1; j += kW) {
       double de2 = 0.0, dK = 0.0;
       if (ok)
-        for (int nn = 0; nn < g.n_u; ++nn) {
+        for (int nn = lane; nn < g.n_u; nn += 64) {
           const double *o = adj.tchain + ((int64_t)j * g.n_u + nn) * 2;
           de2 += o[0];
           dK += o[1];
         }
+      de2 = wave_sum(de2);
+      dK = wave_sum(dK);
+      if (lane != 0) continue;
       if (j < J) {
         const double qo = g.mass_q[j], sj = g.mass_sigma[j];
         const double q = sqrt(fmax(1.0 - mt[J1 + j], 0.0));
@@ -2177,15 +2198,30 @@ __global__ void __launch_bounds__(256) k_sph_grads(const GeomDev *__restrict__ g
     double li = 0.0, la = 0.0;
     const int npb = (g.n_pix + 63) / 64;
     if (ok)
-      for (int b = threadIdx.x; b < npb; b += 256) {
+      for (int b = threadIdx.x; b < npb; b += 512) {
         li += adj.losp[2 * b];
         la += adj.losp[2 * b + 1];
       }
-    const double dis = block_sum256(di, sh);
-    const double dmls = block_sum256(dml, sh);
-    const double lis = block_sum256(li, sh);
-    const double las = block_sum256(la, sh);
+    // fixed-order block sums: wave butterflies, then the 16 wave partials
+    di = wave_sum(di);
+    dml = wave_sum(dml);
+    li = wave_sum(li);
+    la = wave_sum(la);
+    if (lane == 0) {
+      sh[0][wave] = di;
+      sh[1][wave] = dml;
+      sh[2][wave] = li;
+      sh[3][wave] = la;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+      double dis = 0.0, dmls = 0.0, lis = 0.0, las = 0.0;
+      for (int w = 0; w < kW; ++w) {
+        dis += sh[0][w];
+        dmls += sh[1][w];
+        lis += sh[2][w];
+        las += sh[3][w];
+      }
       double smin = 1e300, dadi = 0.0;
       for (int k = 0; k < K; ++k) {
         const double sk = sqrt(0.5 / tab[k]), q = sqrt(tab[k] / tab[K + k]);
@@ -2409,7 +2445,7 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 }
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const double *sbp, const int *st_ws, GradsDev out, hipStream_t st) {
-  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, sens, sbp, st_ws,
+  hipLaunchKernelGGL(k_grads, dim3(grid_of(n)), dim3(1024), 0, st, g, m, n, p, sens, sbp, st_ws,
                      out);
 }
 void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
@@ -2451,7 +2487,7 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                      n_tile, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_chain, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile, n_tile,
                      gauss, st_ws, sens);
-  hipLaunchKernelGGL(k_sph_grads, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, p, gauss, st_ws,
+  hipLaunchKernelGGL(k_sph_grads, dim3(grid_of(n)), dim3(512), 0, st, g, m, n, p, gauss, st_ws,
                      sens, sbp, out);
 }
 void launch_beta_logistic(const GeomDev *g, const ModelDev *m, int n, const double *prof,
