@@ -1911,6 +1911,13 @@ __global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ ge
                                                   double *__restrict__ sens) {
   __shared__ float4 pa[256];   // (R'^2, z'^2, phi, psi)
   __shared__ float4 pb[256];   // (phi R'^2, psi R'^2, phi z'^2, psi z'^2)
+  __shared__ double sc[2][kSphNT];   // sin, cos of the table's polar angles
+  if (threadIdx.x < kSphNT) {
+    const double th = threadIdx.x * (0.5 * kPi / (kSphNT - 1));
+    sc[0][threadIdx.x] = sin(th);
+    sc[1][threadIdx.x] = cos(th);
+  }
+  __syncthreads();
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
@@ -1930,23 +1937,33 @@ __global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ ge
       const int64_t p = c0 + threadIdx.x;
       float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
       if (p < p1) {
+        // the node as in the forward, with the powers of r and r' written
+        // as exponentials of ln r and tau (r' = r e^tau)
         const int cell = (int)(p / ((int64_t)K * kSphNodes));
         const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
-        double r, sth, cth;
-        sph_cell(g, cell, r, sth, cth);
+        const int ir = cell / kSphNT, ith = cell % kSphNT;
+        const double lnr = g.sph_lnr0 + ir * g.sph_dlnr, r = exp(lnr);
+        const double sth = sc[0][ith];
         const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1];
         const double lp = adj.dtab[3 * cell + 2];
         const double alpha = tab[k], alphaq = tab[K + k], nu0 = tab[2 * K + k];
         const double beta = 1.0 - 1.0 / tab[3 * K + k];
         const int gi = node & 7;
-        const SphNode nd = sph_node(r, sth, alpha, alphaq, beta, node >> 3,
-                                    geoms[md.geom].gl8_x[gi], geoms[md.geom].gl8_w[gi]);
-        const double nu = nu0 * nd.en;
+        const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
+        const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
+        const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
+        const double lrp = lnr + tau, rp = exp(lrp);
+        const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
+        const double ct = sqrt(fmax(0.0, 1.0 - st * st));
+        const double Rp = rp * st, zp = rp * ct;
+        const double wn = 0.5 * glw * hs * rp;
+        const double nu = nu0 * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
         const double muP = lr + (1.0 - beta) * (lt + lp);
-        const double muD = lp * (1.0 - beta) * sth * pow(r, 1.0 - 3.0 * beta);
-        const double dD = muD * nd.wn * pow(nd.rp, 3.0 * beta + 1.0) * nd.Rp * nu;
-        const double phi = muP * pow(r, -2.0 * beta) * nd.wn * pow(nd.rp, 2.0 * beta + 1.0) * nu +
+        const double muD = lp * (1.0 - beta) * sth * exp((1.0 - 3.0 * beta) * lnr);
+        const double dD = muD * wn * exp((3.0 * beta + 1.0) * lrp) * Rp * nu;
+        const double phi = muP * wn * exp((2.0 * beta + 1.0) * lrp - 2.0 * beta * lnr) * nu +
                            dD * 2.0 * (alphaq - alpha);
+        const SphNode nd{rp, st, ct, Rp, zp, wn, 0.0, tau, false};
         const double psi = dD;
         const float R2 = (float)(nd.Rp * nd.Rp), Z2 = (float)(nd.zp * nd.zp);
         const float fphi = (float)phi, fpsi = (float)psi;
