@@ -53,7 +53,7 @@ def _args():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, the reference "
                          "kernel for scaling the HBM byte counters of a profile")
-    ap.add_argument("--cpu-sample", type=int, default=4096,
+    ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="padded sub-pixels the oracle evaluates for the CPU baseline")
     return ap.parse_args()
 
@@ -504,8 +504,8 @@ def main():
             "beta_profile_chi2_4096_small": lambda: time_beta_profile(
                 torch, binding, inputs.config3(4096), dev, k),
             "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
-            "spherical_4096_small": lambda: time_spherical(torch, binding, inputs.config3(4096),
-                                                           dev, k),
+            "spherical_1024_small": lambda: time_spherical(torch, binding, inputs.config3(1024),
+                                                           dev, max(2, k // 2)),
         }
         names = [x for x in a.extra.split(",") if x] or list(extras)
         unknown = [x for x in names if x not in extras]
