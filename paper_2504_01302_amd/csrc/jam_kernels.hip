@@ -467,8 +467,8 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
     for (int bx = 0; bx < BX; ++bx)
 #pragma unroll
       for (int by = 0; by < BY; ++by) d[bx][by] = zero;
-    if (tc + KC2 <= t1) {          // whole chunk (wave-uniform)
-#pragma unroll 2
+    if (tc + KC2 <= t1) {          // whole chunk (wave-uniform), fully unrolled
+#pragma unroll
       for (int s2 = 0; s2 < KC2 / 2; ++s2) {
         const float4 c = cs[2 * s2 + kh];
         float a[BX], b[BY];
