@@ -302,10 +302,11 @@ struct Plan {
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
-            *d_red = nullptr, *d_sph = nullptr;
+            *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0, n_sph = 0;
+      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0;
   bool spherical = false;
+  bool fused_prologue = true;
   int grid_num = 1, grid_sens = 1;
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
@@ -377,6 +378,10 @@ struct jam_ctx {
 namespace {
 
 constexpr size_t kMaxPlans = 8;
+// Batches of at most this many models run the cylindrical prologue as one
+// launch (each term block recomputes its (k, j) pairs' set-up, which costs
+// latency per block but saves two launches).
+constexpr int kFusedPrologueModels = 32;
 
 // Numerator variant and term-range split of one model under a schedule.
 // `gran` is the slice length in units: (k, j) pairs for the per-pixel
@@ -548,7 +553,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph;
+      it_red, it_sph, it_pro;
   std::vector<double> c_num, c_sens;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
@@ -639,11 +644,20 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   }
   if (p->total_bins > INT32_MAX || p->total_lum > INT32_MAX || p->total_mass > INT32_MAX)
     return fail(JAM_E_UNSUPPORTED, "batch too large");
+  // prologue of the cylindrical model: a few models run set-up, terms and
+  // surface brightness in one launch (terms from the parameters); many run
+  // the set-up first and then terms from its table beside the tiles
+  p->fused_prologue = n <= kFusedPrologueModels;
+  if (p->fused_prologue)
+    for (int m = 0; m < n; ++m) it_pro.push_back({m, 0, 0, 0});
+  for (const jam::Item &t : it_terms) it_pro.push_back({t.m, t.a, 0, p->fused_prologue ? 1 : 3});
+  for (const jam::Item &t : it_sb) it_pro.push_back({t.m, t.a, t.b, 2});
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 10;
-  std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix,  &it_num, &it_bins, &it_maps,
-                                           &it_chain, &it_sens, &it_sb,  &it_red,  &it_sph};
+  constexpr int kLists = 11;
+  std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
+                                           &it_maps,  &it_chain, &it_sens, &it_sb,
+                                           &it_red,   &it_sph, &it_pro};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -664,10 +678,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   HIP_TRY(hipMemcpy(p->arena, stage.data(), off, hipMemcpyHostToDevice));
   char *base = (char *)p->arena;
   p->d_models = (jam::ModelDev *)(base + o_models);
-  jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins, &p->d_maps,
-                            &p->d_chain, &p->d_sens, &p->d_sb,  &p->d_red,  &p->d_sph};
-  int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins, &p->n_maps,
-                      &p->n_chain, &p->n_sens, &p->n_sb,  &p->n_red,  &p->n_sph};
+  jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
+                            &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
+                            &p->d_red,   &p->d_sph,   &p->d_pro};
+  int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
+                      &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
+                      &p->n_red,   &p->n_sph,   &p->n_pro};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -717,13 +733,17 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   float4 *terms = (float4 *)(ws + p->off_terms);
   double *pix = (double *)(ws + p->off_pix);
   double *part = (double *)(ws + p->off_part);
-  jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
-  if (p->spherical)
+  if (p->spherical) {
+    jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
     jam::launch_sph_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms,
                           st);
-  else
-    jam::launch_terms(ctx->d_geoms, p->d_models, p->d_terms, p->n_terms, gauss, st_ws, terms, st);
-  jam::launch_sb(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, pd, pix, st);
+    jam::launch_sb(ctx->d_geoms, p->d_models, p->d_sb, p->n_sb, pd, pix, st);
+  } else {
+    if (!p->fused_prologue)
+      jam::launch_setup(ctx->d_geoms, p->d_models, p->n, pd, gauss, st_ws, status, queue, st);
+    jam::launch_prologue(ctx->d_geoms, p->d_models, p->d_pro, p->n_pro, pd, gauss, st_ws, status,
+                         queue, terms, pix, p->fused_prologue, st);
+  }
   if (p->spherical) {
     if (!need_numerator) return;
     double *tabs = (double *)(ws + p->off_sph);

@@ -128,11 +128,18 @@ struct GradsDev {
 __host__ __device__ inline int64_t gauss_size(int K, int J1) { return 4 * K + 3 * J1 + 2; }
 
 // Kernel launchers (jam_kernels.hip).  All asynchronous on `st`.
+// Set-up + term table + surface brightness of the cylindrical model in one
+// launch: items (m, 0, 0, 0) set-up, (m, term block, 0, 1) terms from the
+// parameters, (m, row tile, column tile, 2) surface brightness, (m, term
+// block, 0, 3) terms from the Gaussian table of an earlier launch_setup
+// (fused: kinds 0, 1, 2; otherwise kinds 2, 3); also zeroes queues[0..1]
+// (may be NULL).
+void launch_prologue(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+                     double *gauss, int *st_ws, int32_t *st_out, int *queues, float4 *terms,
+                     double *pix, bool fused, hipStream_t st);
 // Also zeroes the two work-queue counters queues[0..1] (may be NULL).
 void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *gauss,
                   int *st_ws, int32_t *st_out, int *queues, hipStream_t st);
-void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                  const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
 // Items (m, block of 8 unique-pixel rows, block of 64 columns).
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);

@@ -91,6 +91,71 @@ __device__ inline double wave_sum(double v) {
 // Set-up: App. A deprojection and per-Gaussian derived quantities (FP64),
 // per-model validity.
 // ---------------------------------------------------------------------------
+// One model's set-up; every thread of the block calls it (block-wide ORs).
+__device__ void setup_item(const GeomDev *__restrict__ geoms, const ModelDev *__restrict__ models,
+                           int m, const ParamsDev &p, double *__restrict__ gauss,
+                           int *__restrict__ st_ws, int32_t *__restrict__ st_out) {
+  const ModelDev md = models[m];
+  const GeomDev g = geoms[md.geom];
+  double *tab = gauss + md.gauss_off;
+  const double inc = p.inc[m];
+  const double si = sin(inc), ci = cos(inc);
+  const double si2 = si * si, ci2 = ci * ci;
+  const double ml = p.mass_scale[m];
+  const double mbh = p.m_bh[m];
+  const double G = grav_const();
+  const double s = g.s_pc;
+  int bad_dep = !(si > 0.0) || !isfinite(inc);
+  int bad_phys = !(ml >= 0.0) || !(mbh >= 0.0) || !isfinite(ml) || !isfinite(mbh);
+  const int K = g.K, J = g.J1 - 1;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double qo = g.lum_q[k], sig = g.lum_sigma[k];
+    const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+    const double beta = p.beta[md.lum_off + k];
+    if (!(qo * qo > ci2)) bad_dep = 1;
+    if (!(beta < 1.0) || !(I0 >= 0.0) || !isfinite(I0)) bad_phys = 1;
+    const double q = sqrt(fmax(qo * qo - ci2, 0.0)) / si;
+    const double alpha = 0.5 / (sig * sig);
+    tab[k] = alpha;
+    tab[K + k] = alpha / (q * q);
+    tab[2 * K + k] = qo * I0 / (sqrt(2.0 * kPi) * sig * q);
+    tab[3 * K + k] = 1.0 / (1.0 - beta);
+  }
+  double *mt = tab + 4 * K;
+  for (int j = threadIdx.x; j < J + 1; j += blockDim.x) {
+    double r, e2, Kp;
+    if (j < J) {
+      const double qo = g.mass_q[j], sig = g.mass_sigma[j];
+      const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+      if (!(qo * qo > ci2)) bad_dep = 1;
+      if (!(S0 >= 0.0) || !isfinite(S0)) bad_phys = 1;
+      const double q = sqrt(fmax(qo * qo - ci2, 0.0)) / si;
+      const double M = ml * 2.0 * kPi * S0 * (s * sig) * (s * sig) * qo;
+      r = 0.5 / (sig * sig);
+      e2 = 1.0 - q * q;
+      Kp = sqrt(2.0 / kPi) * G * M / (s * sig);
+    } else {
+      r = 0.5 / (g.bh_sigma * g.bh_sigma);
+      e2 = 0.0;
+      Kp = sqrt(2.0 / kPi) * G * mbh / (s * g.bh_sigma);
+    }
+    mt[j] = r;
+    mt[g.J1 + j] = e2;
+    mt[2 * g.J1 + j] = Kp;
+  }
+  if (threadIdx.x == 0) {
+    mt[3 * g.J1] = si2;
+    mt[3 * g.J1 + 1] = ci2;
+  }
+  const int any_dep = __syncthreads_or(bad_dep);
+  const int any_phys = __syncthreads_or(bad_phys);
+  if (threadIdx.x == 0) {
+    const int code = any_dep ? 2 : (any_phys ? 3 : 0);
+    st_ws[m] = code;
+    if (st_out) st_out[m] = code;
+  }
+}
+
 __global__ void __launch_bounds__(64) k_setup(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models, int n,
                                               ParamsDev p, double *__restrict__ gauss,
@@ -98,67 +163,8 @@ __global__ void __launch_bounds__(64) k_setup(const GeomDev *__restrict__ geoms,
                                               int *__restrict__ queues) {
   // Work-queue counters of the kernels that follow on the stream.
   if (queues && blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;
-  for (int m = blockIdx.x; m < n; m += gridDim.x) {
-    const ModelDev md = models[m];
-    const GeomDev g = geoms[md.geom];
-    double *tab = gauss + md.gauss_off;
-    const double inc = p.inc[m];
-    const double si = sin(inc), ci = cos(inc);
-    const double si2 = si * si, ci2 = ci * ci;
-    const double ml = p.mass_scale[m];
-    const double mbh = p.m_bh[m];
-    const double G = grav_const();
-    const double s = g.s_pc;
-    int bad_dep = !(si > 0.0) || !isfinite(inc);
-    int bad_phys = !(ml >= 0.0) || !(mbh >= 0.0) || !isfinite(ml) || !isfinite(mbh);
-    const int K = g.K, J = g.J1 - 1;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-      const double qo = g.lum_q[k], sig = g.lum_sigma[k];
-      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-      const double beta = p.beta[md.lum_off + k];
-      if (!(qo * qo > ci2)) bad_dep = 1;
-      if (!(beta < 1.0) || !(I0 >= 0.0) || !isfinite(I0)) bad_phys = 1;
-      const double q = sqrt(fmax(qo * qo - ci2, 0.0)) / si;
-      const double alpha = 0.5 / (sig * sig);
-      tab[k] = alpha;
-      tab[K + k] = alpha / (q * q);
-      tab[2 * K + k] = qo * I0 / (sqrt(2.0 * kPi) * sig * q);
-      tab[3 * K + k] = 1.0 / (1.0 - beta);
-    }
-    double *mt = tab + 4 * K;
-    for (int j = threadIdx.x; j < J + 1; j += blockDim.x) {
-      double r, e2, Kp;
-      if (j < J) {
-        const double qo = g.mass_q[j], sig = g.mass_sigma[j];
-        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
-        if (!(qo * qo > ci2)) bad_dep = 1;
-        if (!(S0 >= 0.0) || !isfinite(S0)) bad_phys = 1;
-        const double q = sqrt(fmax(qo * qo - ci2, 0.0)) / si;
-        const double M = ml * 2.0 * kPi * S0 * (s * sig) * (s * sig) * qo;
-        r = 0.5 / (sig * sig);
-        e2 = 1.0 - q * q;
-        Kp = sqrt(2.0 / kPi) * G * M / (s * sig);
-      } else {
-        r = 0.5 / (g.bh_sigma * g.bh_sigma);
-        e2 = 0.0;
-        Kp = sqrt(2.0 / kPi) * G * mbh / (s * g.bh_sigma);
-      }
-      mt[j] = r;
-      mt[g.J1 + j] = e2;
-      mt[2 * g.J1 + j] = Kp;
-    }
-    if (threadIdx.x == 0) {
-      mt[3 * g.J1] = si2;
-      mt[3 * g.J1 + 1] = ci2;
-    }
-    const int any_dep = __syncthreads_or(bad_dep);
-    const int any_phys = __syncthreads_or(bad_phys);
-    if (threadIdx.x == 0) {
-      const int code = any_dep ? 2 : (any_phys ? 3 : 0);
-      st_ws[m] = code;
-      if (st_out) st_out[m] = code;
-    }
-  }
+  for (int m = blockIdx.x; m < n; m += gridDim.x)
+    setup_item(geoms, models, m, p, gauss, st_ws, st_out);
 }
 
 // Surface-brightness adjoint: the derivative of sum_p lambda_I[p] I[p] with
@@ -209,12 +215,9 @@ __global__ void __launch_bounds__(256) k_sb_adj(const GeomDev *__restrict__ geom
 // Term table: FP64 coefficients of every (k, j, n) term, stored as FP32
 // (-c1 log2e, -gamma log2e, C0, C1).  Term t = (k * J1 + j) * n_u + n.
 // ---------------------------------------------------------------------------
-__device__ inline void term_fp64(const double *tab, int K, int J1, int k, int j, double u,
-                                 double wq, double &c1, double &gam, double &C0, double &C1) {
-  const double alpha = tab[k], alphaq = tab[K + k], nu0 = tab[2 * K + k], b = tab[3 * K + k];
-  const double *mt = tab + 4 * K;
-  const double r = mt[j], e2 = mt[J1 + j], Kp = mt[2 * J1 + j];
-  const double si2 = mt[3 * J1], ci2 = mt[3 * J1 + 1];
+__device__ inline void term_coeffs(double alpha, double alphaq, double nu0, double b, double r,
+                                   double e2, double Kp, double si2, double ci2, double u,
+                                   double wq, double &c1, double &gam, double &C0, double &C1) {
   const double u2 = u * u;
   const double h = 1.0 - e2 * u2;
   c1 = alpha + r * u2;
@@ -232,29 +235,39 @@ __device__ inline void term_fp64(const double *tab, int K, int J1, int k, int j,
   C1 = f * Q;
 }
 
-__global__ void __launch_bounds__(256) k_terms(const GeomDev *__restrict__ geoms,
-                                               const ModelDev *__restrict__ models,
-                                               const Item *__restrict__ items, int n_it,
-                                               const double *__restrict__ gauss,
-                                               const int *__restrict__ st_ws,
-                                               float4 *__restrict__ terms) {
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
-    const Item it = items[i];
-    const ModelDev md = models[it.m];
-    const GeomDev g = geoms[md.geom];
-    const int t = it.a * 256 + threadIdx.x;
-    if (t >= g.T) continue;
-    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (st_ws[it.m] == 0) {
-      const int n = t % g.n_u;
-      const int kj = t / g.n_u;
-      const int j = kj % g.J1, k = kj / g.J1;
-      double c1, gam, C0, C1;
-      term_fp64(gauss + md.gauss_off, g.K, g.J1, k, j, g.u[n], g.w[n], c1, gam, C0, C1);
-      out = make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
-    }
-    terms[md.term_off + t] = out;
+
+// The per-(k, j) quantities of the set-up straight from the parameters (its
+// formulas and operation order), for kernels that run beside the set-up:
+// v = (alpha, alphaq, nu0, b, r, e2, Kp, si2, ci2).
+__device__ inline void pair_from_params(const GeomDev &g, const ModelDev &md, int m,
+                                        const ParamsDev &p, int k, int j, double *v) {
+  const double inc = p.inc[m];
+  const double si = sin(inc), ci = cos(inc);
+  const double si2 = si * si, ci2 = ci * ci;
+  const double qo = g.lum_q[k], sig = g.lum_sigma[k];
+  const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+  const double q = sqrt(fmax(qo * qo - ci2, 0.0)) / si;
+  const double alpha = 0.5 / (sig * sig);
+  v[0] = alpha;
+  v[1] = alpha / (q * q);
+  v[2] = qo * I0 / (sqrt(2.0 * kPi) * sig * q);
+  v[3] = 1.0 / (1.0 - p.beta[md.lum_off + k]);
+  const double G = grav_const(), sp = g.s_pc;
+  if (j < g.J1 - 1) {
+    const double qoj = g.mass_q[j], sj = g.mass_sigma[j];
+    const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+    const double qj = sqrt(fmax(qoj * qoj - ci2, 0.0)) / si;
+    const double M = p.mass_scale[m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qoj;
+    v[4] = 0.5 / (sj * sj);
+    v[5] = 1.0 - qj * qj;
+    v[6] = sqrt(2.0 / kPi) * G * M / (sp * sj);
+  } else {
+    v[4] = 0.5 / (g.bh_sigma * g.bh_sigma);
+    v[5] = 0.0;
+    v[6] = sqrt(2.0 / kPi) * G * p.m_bh[m] / (sp * g.bh_sigma);
   }
+  v[7] = si2;
+  v[8] = ci2;
 }
 
 // ---------------------------------------------------------------------------
@@ -268,49 +281,130 @@ __global__ void __launch_bounds__(256) k_terms(const GeomDev *__restrict__ geoms
 // Item (m, block of 8 rows, block of 64 columns); lane = column, wave w takes
 // luminous Gaussians k = w, w + 4, ...; the four partial sums are combined in
 // a fixed order.
+// One surface-brightness tile; every thread of the block calls it.
+__device__ void sb_item(const Item &it, const ModelDev &md, const GeomDev &g, const ParamsDev &p,
+                        double *__restrict__ pix, double (*red)[kSbRows][64]) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int y0 = it.a * kSbRows;
+  const int ix = it.b * 64 + lane;
+  const bool vx = ix < g.n_ux;
+  const double x = vx ? g.xs[ix] : 0.0;
+  double yy[kSbRows];
+#pragma unroll
+  for (int r = 0; r < kSbRows; ++r) {
+    const double y = y0 + r < g.n_uy ? g.ys[y0 + r] : 0.0;
+    yy[r] = y * y;
+  }
+  double acc[kSbRows];
+#pragma unroll
+  for (int r = 0; r < kSbRows; ++r) acc[r] = 0.0;
+  for (int k = wave; k < g.K; k += 4) {
+    const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+    const double sig = g.lum_sigma[k], qo = g.lum_q[k];
+    const double a = 1.0 / (2.0 * sig * sig);
+    const double fx = I0 * exp(-a * x * x);
+    const double ay = a / (qo * qo);
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r) acc[r] += fx * exp(-ay * yy[r]);
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r) red[wave - 1][r][lane] = acc[r];
+  __syncthreads();
+  if (wave == 0 && vx) {
+#pragma unroll
+    for (int r = 0; r < kSbRows; ++r)
+      if (y0 + r < g.n_uy)
+        pix[md.pix_off + g.n_pix + (int64_t)(y0 + r) * g.n_ux + ix] =
+            ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(256) k_sb(const GeomDev *__restrict__ geoms,
                                             const ModelDev *__restrict__ models,
                                             const Item *__restrict__ items, int n_it, ParamsDev p,
                                             double *__restrict__ pix) {
   __shared__ double red[3][kSbRows][64];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const int y0 = it.a * kSbRows;
-    const int ix = it.b * 64 + lane;
-    const bool vx = ix < g.n_ux;
-    const double x = vx ? g.xs[ix] : 0.0;
-    double yy[kSbRows];
-#pragma unroll
-    for (int r = 0; r < kSbRows; ++r) {
-      const double y = y0 + r < g.n_uy ? g.ys[y0 + r] : 0.0;
-      yy[r] = y * y;
+    sb_item(it, md, g, p, pix, red);
+  }
+}
+
+// Prologue of the cylindrical model: items of four kinds (Item::c): 0 set-up
+// of model m (status, Gaussian table); 1 a block of 256 FP32 terms computed
+// straight from the parameters, so it needs nothing from set-up items running
+// in the same launch (a model with a bad status gets meaningless terms, which
+// every later kernel skips); 2 a surface-brightness tile; 3 a block of terms
+// from the Gaussian table of a set-up that ran in an earlier launch (zero
+// terms for a bad status).  One launch of kinds 0, 1, 2 suits a few large
+// models; many small ones run the set-up first and then kinds 2 and 3, which
+// avoids recomputing each (k, j) pair's set-up in every term block.
+template <bool kFused>
+__global__ void __launch_bounds__(256) k_prologue(const GeomDev *__restrict__ geoms,
+                                                  const ModelDev *__restrict__ models,
+                                                  const Item *__restrict__ items, int n_it,
+                                                  ParamsDev p, double *__restrict__ gauss,
+                                                  int *__restrict__ st_ws,
+                                                  int32_t *__restrict__ st_out,
+                                                  int *__restrict__ queues,
+                                                  float4 *__restrict__ terms,
+                                                  double *__restrict__ pix) {
+  __shared__ double red[3][kSbRows][64];
+  // per-(k, j) quantities of a term block (kind 1 only)
+  __shared__ double pv[kFused ? 258 : 1][9];
+  if (queues && blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (kFused && it.c == 0) {       // uniform per block
+      setup_item(geoms, models, it.m, p, gauss, st_ws, st_out);
+      continue;
     }
-    double acc[kSbRows];
-#pragma unroll
-    for (int r = 0; r < kSbRows; ++r) acc[r] = 0.0;
-    for (int k = wave; k < g.K; k += 4) {
-      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-      const double sig = g.lum_sigma[k], qo = g.lum_q[k];
-      const double a = 1.0 / (2.0 * sig * sig);
-      const double fx = I0 * exp(-a * x * x);
-      const double ay = a / (qo * qo);
-#pragma unroll
-      for (int r = 0; r < kSbRows; ++r) acc[r] += fx * exp(-ay * yy[r]);
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (it.c == 2) {
+      sb_item(it, md, g, p, pix, red);
+      continue;
     }
-    if (wave > 0)
-#pragma unroll
-      for (int r = 0; r < kSbRows; ++r) red[wave - 1][r][lane] = acc[r];
+    if (!kFused) {                   // kind 3
+      const int t = it.a * 256 + threadIdx.x;
+      if (t < g.T) {
+        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (st_ws[it.m] == 0) {
+          const int n = t % g.n_u;
+          const int kj = t / g.n_u;
+          const int j = kj % g.J1, k = kj / g.J1;
+          const double *tab = gauss + md.gauss_off, *mt = tab + 4 * g.K;
+          double c1, gam, C0, C1;
+          term_coeffs(tab[k], tab[g.K + k], tab[2 * g.K + k], tab[3 * g.K + k], mt[j],
+                      mt[g.J1 + j], mt[2 * g.J1 + j], mt[3 * g.J1], mt[3 * g.J1 + 1], g.u[n],
+                      g.w[n], c1, gam, C0, C1);
+          out = make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
+        }
+        terms[md.term_off + t] = out;
+      }
+      continue;
+    }
+    // kind 1: the (k, j) pairs of this block's 256 terms, once each, then
+    // the terms
+    const int t0 = it.a * 256;
+    const int kj0 = t0 / g.n_u, kj1 = (min(t0 + 256, g.T) - 1) / g.n_u;
+    for (int q = threadIdx.x; q <= kj1 - kj0; q += 256)
+      pair_from_params(g, md, it.m, p, (kj0 + q) / g.J1, (kj0 + q) % g.J1, pv[q]);
     __syncthreads();
-    if (wave == 0 && vx) {
-#pragma unroll
-      for (int r = 0; r < kSbRows; ++r)
-        if (y0 + r < g.n_uy)
-          pix[md.pix_off + g.n_pix + (int64_t)(y0 + r) * g.n_ux + ix] =
-              ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+    const int t = t0 + threadIdx.x;
+    if (t < g.T) {
+      const int n = t % g.n_u;
+      const double *v = pv[t / g.n_u - kj0];
+      double c1, gam, C0, C1;
+      term_coeffs(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], g.u[n], g.w[n], c1, gam,
+                  C0, C1);
+      terms[md.term_off + t] =
+          make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
     }
     __syncthreads();
   }
@@ -2396,10 +2490,15 @@ void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
   hipLaunchKernelGGL(k_setup, dim3(grid_of(n)), dim3(64), 0, st, g, m, n, p, gauss, st_ws, st_out,
                      queues);
 }
-void launch_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                  const double *gauss, const int *st_ws, float4 *terms, hipStream_t st) {
-  hipLaunchKernelGGL(k_terms, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss, st_ws,
-                     terms);
+void launch_prologue(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+                     double *gauss, int *st_ws, int32_t *st_out, int *queues, float4 *terms,
+                     double *pix, bool fused, hipStream_t st) {
+  if (fused)
+    hipLaunchKernelGGL(k_prologue<true>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p,
+                       gauss, st_ws, st_out, queues, terms, pix);
+  else
+    hipLaunchKernelGGL(k_prologue<false>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p,
+                       gauss, st_ws, st_out, queues, terms, pix);
 }
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st) {
