@@ -98,9 +98,10 @@ def profiled_traffic():
     return float(b.group(1))
 
 
-def time_batch(torch, binding, w, dev, steps, form, launch, graph):
-    """Forward and forward+adjoint throughput of one whole batch per launch."""
-    ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph)
+def time_batch(torch, binding, w, dev, steps, form, launch, graph, autotune=0):
+    """Forward and forward+adjoint throughput of one whole batch per launch
+    (with autotune, the schedule search runs at the first call, untimed)."""
+    ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph, autotune=autotune)
     par = binding.pack_params(w, dev, amplitudes=True)
     nb, _, _ = ctx.sizes(w.geom_idx)
     V = torch.empty(nb, dtype=torch.float64, device=dev)
@@ -135,9 +136,11 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph):
     ms_fb = e0.elapsed_time(e1) / steps
     n = len(w.geom_idx)
     ok = bool((st == 0).all().item())
+    sched = ctx.plan_info(w.geom_idx)
     ctx.close()
     return {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
-            "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok}
+            "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok,
+            "schedule": sched}
 
 
 def time_spherical(torch, binding, w, dev, steps, backward=True):
@@ -498,6 +501,8 @@ def main():
                 dev, k, a.form, a.launch, a.graph),
             "uneven_1024": lambda: time_batch(torch, binding, inputs.config4(1024), dev, 2,
                                               a.form, a.launch, a.graph),
+            "uneven_1024_autotuned_graph": lambda: time_batch(
+                torch, binding, inputs.config4(1024), dev, 2, 0, 0, 1, autotune=1),
             "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,
                                                  a.form, a.launch, a.graph),
             "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
