@@ -349,7 +349,7 @@ def time_mge_pipeline(torch, binding, dev, steps, n=4096):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                           "(the path shards by model or by pixel rows across GPUs, "
                           "which is documented but not built)"}))
         sys.exit(2)

@@ -50,7 +50,7 @@ typedef enum {
   JAM_E_NONPHYSICAL = 3,   /* per model: beta_k >= 1, negative mass or amplitude  */
   JAM_E_WORKSPACE = 4,     /* workspace missing or smaller than required          */
   JAM_E_DEVICE = 5,        /* a HIP runtime call or kernel launch failed          */
-  JAM_E_UNSUPPORTED = 6    /* option or size outside what this build supports     */
+  JAM_E_UNSUPPORTED = 6    /* option or size outside what this library supports   */
 } jam_status;
 
 /* One galaxy model's fixed description (what a sampler does not vary).

@@ -79,7 +79,7 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"JAM HIP library not built: {path} is missing "
-                           "(run __graft_entry__.build())")
+                           "(build it with python paper_2504_01302_amd/build.py)")
     lib = ctypes.CDLL(path)
     lib.jam_create.argtypes = [c_int32, ctypes.POINTER(JamGeometry), ctypes.POINTER(JamOptions),
                                ctypes.POINTER(c_void_p)]

@@ -1,7 +1,7 @@
 """GPU adjoint against the FP64 oracle gradient (autograd of the oracle) and
 against central differences of the GPU forward.
 
-Tolerance (the brief states none for gradients): per model the gradient
+Tolerance (no gradient bar is fixed by the problem): per model the gradient
 vector error ||g_gpu - g_ref|| <= 1e-4 ||g_ref||, and every component within
 1e-3 relative or 1e-6 of the largest component.  The forward parity bar is
 1e-5 per bin; one gradient component sums many signed forward terms, so it
