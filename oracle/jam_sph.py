@@ -47,8 +47,10 @@ moments but not its layout; these are the readings both sides use):
 * intrinsic moments summed over the tracer Gaussians, A_r = sum P_k,
   A_theta = sum (1 - beta_k) P_k, A_phi = sum nu v_phi^2_k, tabulated on a
   polar grid of N_R radii log-spaced on [r_lo, r_hi] and N_TH angles evenly
-  spaced on [0, pi/2], and interpolated bilinearly in (ln r, theta); below
-  r_lo the first radius is used, beyond r_hi the moments are zero;
+  spaced on [0, pi/2], and interpolated cubically (Catmull-Rom) in ln r and
+  linearly in theta (at the ends of the radial range the missing radius is
+  extrapolated linearly); below r_lo the first radius is used, beyond r_hi
+  the moments are zero;
 * line of sight: z' = a sinh(w), w on [-W, W] with sinh(W) a = Z, SEG_LOS
   segments of NODE_LOS Gauss-Legendre nodes, a = min_k sigma_k q_k / 4,
   Z = 12 max_k sigma_k.
@@ -171,20 +173,37 @@ def moment_table(geom, params):
     return m, r, th, intrinsic_moments(m, RR, TT)
 
 
+def radial_weights(fx):
+    """Catmull-Rom weights of the four radii i-1, i, i+1, i+2 around a point
+    at fraction fx of cell [i, i+1] (cubic convolution, a = -1/2)."""
+    f2, f3 = fx * fx, fx * fx * fx
+    return ((-f3 + 2.0 * f2 - fx) / 2.0, (3.0 * f3 - 5.0 * f2 + 2.0) / 2.0,
+            (-3.0 * f3 + 4.0 * f2 + fx) / 2.0, (f3 - f2) / 2.0)
+
+
 def _interp(table, r, th, rq, tq):
-    """Bilinear in (ln r, theta); first radius below the table, zero beyond."""
+    """Cubic (Catmull-Rom) in ln r, linear in theta; at the table's ends the
+    missing radius is extrapolated linearly from the two nearest; the first
+    radius stands for smaller ones, zero beyond the last."""
     lr = np.log(r)
+    n = len(r)
     x = (np.log(rq) - lr[0]) / (lr[1] - lr[0])
     y = tq / (th[1] - th[0])
-    out = []
-    xi = np.clip(np.floor(x), 0, len(r) - 2).astype(int)
+    xi = np.clip(np.floor(x), 0, n - 2).astype(int)
     yi = np.clip(np.floor(y), 0, len(th) - 2).astype(int)
     fx = np.clip(x - xi, 0.0, 1.0)
     fy = np.clip(y - yi, 0.0, 1.0)
+    w = radial_weights(fx)
+    out = []
     for T in table:
-        v = ((1 - fx) * (1 - fy) * T[xi, yi] + fx * (1 - fy) * T[xi + 1, yi] +
-             (1 - fx) * fy * T[xi, yi + 1] + fx * fy * T[xi + 1, yi + 1])
-        out.append(np.where(x > len(r) - 1, 0.0, v))
+        def col(i):          # linear in theta at radius index i (with end extrapolation)
+            lo = (1 - fy) * T[np.clip(i, 0, n - 1), yi] + fy * T[np.clip(i, 0, n - 1), yi + 1]
+            return lo
+        p0, p1 = col(xi), col(xi + 1)
+        pm = np.where(xi >= 1, col(xi - 1), 2.0 * p0 - p1)
+        p2 = np.where(xi + 2 <= n - 1, col(xi + 2), 2.0 * p1 - p0)
+        v = w[0] * pm + w[1] * p0 + w[2] * p1 + w[3] * p2
+        out.append(np.where(x > n - 1, 0.0, v))
     return out
 
 

@@ -1652,6 +1652,39 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
 // exponentials and their sums over 64 or 256 points, as in the forward.
 // ---------------------------------------------------------------------------
 
+// Radial interpolation of the moment table: Catmull-Rom (cubic convolution,
+// a = -1/2) in ln r over the radii xi - 1 .. xi + 2 around the cell [xi,
+// xi + 1] holding fraction fx; at the ends of the range the missing radius is
+// the linear extrapolation of the two nearest, folded into the weights.
+// ew: weights of radii xi - 1 + a (0 where out of range); dew: d ew / d fx.
+__device__ inline void sph_radial_weights(int xi, double fx, double *ew, double *dew) {
+  const double f2 = fx * fx, f3 = f2 * fx;
+  ew[0] = 0.5 * (-f3 + 2.0 * f2 - fx);
+  ew[1] = 0.5 * (3.0 * f3 - 5.0 * f2 + 2.0);
+  ew[2] = 0.5 * (-3.0 * f3 + 4.0 * f2 + fx);
+  ew[3] = 0.5 * (f3 - f2);
+  dew[0] = 0.5 * (-3.0 * f2 + 4.0 * fx - 1.0);
+  dew[1] = 0.5 * (9.0 * f2 - 10.0 * fx);
+  dew[2] = 0.5 * (-9.0 * f2 + 8.0 * fx + 1.0);
+  dew[3] = 0.5 * (3.0 * f2 - 2.0 * fx);
+  if (xi == 0) {                  // radius -1 = 2 r_0 - r_1
+    ew[1] += 2.0 * ew[0];
+    ew[2] -= ew[0];
+    ew[0] = 0.0;
+    dew[1] += 2.0 * dew[0];
+    dew[2] -= dew[0];
+    dew[0] = 0.0;
+  }
+  if (xi + 2 > kSphNR - 1) {      // radius NR = 2 r_(NR-1) - r_(NR-2)
+    ew[2] += 2.0 * ew[3];
+    ew[1] -= ew[3];
+    ew[3] = 0.0;
+    dew[2] += 2.0 * dew[3];
+    dew[1] -= dew[3];
+    dew[3] = 0.0;
+  }
+}
+
 // Node of tracer k's characteristic through table point (r, theta): the same
 // FP64 operations as the forward moment kernel.
 struct SphNode {
@@ -1701,7 +1734,7 @@ __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ ge
 }
 
 // Line-of-sight adjoint.  Item (m, 256-pixel block), thread = pixel.  The
-// table cotangent receives lambda_N w_z (n.e_f)^2 times the bilinear weights,
+// table cotangent receives lambda_N w_z (n.e_f)^2 times the interpolation weights,
 // accumulated in a block-private LDS copy of the table (FP64 LDS atomics) and
 // added to the model's table once per block (FP64 global atomics, non-zero
 // entries only); the derivatives of the node's integrand at fixed table with
@@ -1761,29 +1794,32 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
       const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
       const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
       const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-      const int64_t i00 = ((int64_t)xi * kSphNT + yi) * 3;
-      const double *c00 = T + i00;
-      const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
+      double ew[4], dew[4];
+      sph_radial_weights(xi, fx, ew, dew);
       const double ner = si * st * sp + ci * ct;
       const double net = si * ct * sp - ci * st;
       const double nep = si * cp;
       const double nf[3] = {ner, net, nep};
       // table cotangent
-      const double w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
-      double *d00 = ldt + i00;
-      double *d10 = d00 + kSphNT * 3, *d01 = d00 + 3, *d11 = d10 + 3;
-      double A[3], AL[3], AT[3];
+      double A[3] = {0.0, 0.0, 0.0}, AL[3] = {0.0, 0.0, 0.0}, AT[3] = {0.0, 0.0, 0.0};
       const bool xin = xf >= 0.0;          // below the first radius the table is constant
-  #pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const double cf = lamN * wz * nf[f] * nf[f];
-        atomicAdd(d00 + f, cf * w00);
-        atomicAdd(d10 + f, cf * w10);
-        atomicAdd(d01 + f, cf * w01);
-        atomicAdd(d11 + f, cf * w11);
-        A[f] = w00 * c00[f] + w10 * c10[f] + w01 * c01[f] + w11 * c11[f];
-        AL[f] = xin ? ((1 - fy) * (c10[f] - c00[f]) + fy * (c11[f] - c01[f])) / g.sph_dlnr : 0.0;
-        AT[f] = ((1 - fx) * (c01[f] - c00[f]) + fx * (c11[f] - c10[f])) / dth;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (ew[a] == 0.0 && dew[a] == 0.0) continue;   // out of range (folded)
+        const int64_t i0 = ((int64_t)(xi - 1 + a) * kSphNT + yi) * 3;
+        const double *c0 = T + i0, *c1 = c0 + 3;
+        double *d0 = ldt + i0, *d1 = d0 + 3;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const double cf = lamN * wz * nf[f] * nf[f] * ew[a];
+          if (cf != 0.0) {
+            atomicAdd(d0 + f, cf * (1 - fy));
+            atomicAdd(d1 + f, cf * fy);
+          }
+          A[f] += ew[a] * ((1 - fy) * c0[f] + fy * c1[f]);
+          if (xin) AL[f] += dew[a] * ((1 - fy) * c0[f] + fy * c1[f]) / g.sph_dlnr;
+          AT[f] += ew[a] * (c1[f] - c0[f]) / dth;
+        }
       }
       // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
       const double r2 = r * r, sz = Z < 0.0 ? -1.0 : 1.0;
@@ -2411,9 +2447,9 @@ __global__ void __launch_bounds__(256) k_beta_logistic_vjp(const GeomDev *__rest
 // Line-of-sight integral of the projected moment table into the unique-pixel
 // N map.  Item (m, 64-pixel block); thread = pixel.  Nodes z' = a sinh(w), w
 // on [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
-// a sinh(W) = 12 max_k sigma_k; the table is interpolated bilinearly in
-// (ln r, theta), the first radius standing for smaller ones and zero beyond
-// the last.  FP64.
+// a sinh(W) = 12 max_k sigma_k; the table is interpolated cubically in ln r
+// (sph_radial_weights) and linearly in theta, the first radius standing for
+// smaller ones and zero beyond the last.  FP64.
 __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geoms,
                                                  const ModelDev *__restrict__ models,
                                                  const Item *__restrict__ items, int n_it,
@@ -2464,12 +2500,16 @@ __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geo
     const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
     const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
     const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-    const double *c00 = T + ((int64_t)xi * kSphNT + yi) * 3;
-    const double *c10 = c00 + kSphNT * 3, *c01 = c00 + 3, *c11 = c10 + 3;
-    double A[3];
-    for (int f = 0; f < 3; ++f)
-      A[f] = (1 - fx) * (1 - fy) * c00[f] + fx * (1 - fy) * c10[f] + (1 - fx) * fy * c01[f] +
-             fx * fy * c11[f];
+    double ew[4], dew[4];
+    sph_radial_weights(xi, fx, ew, dew);
+    double A[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (ew[a] == 0.0) continue;           // out of range (folded) or a zero weight
+      const double *c0 = T + ((int64_t)(xi - 1 + a) * kSphNT + yi) * 3, *c1 = c0 + 3;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) A[f] += ew[a] * ((1 - fy) * c0[f] + fy * c1[f]);
+    }
     const double ner = si * st * sp + ci * ct;
     const double net = si * ct * sp - ci * st;
     const double nep = si * cp;

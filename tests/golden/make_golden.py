@@ -127,7 +127,8 @@ def sph_grad():
     """Gradient of sum_b cot_b v_rms^2_b of the spherically aligned oracle by
     central differences (FP64; the inclination step is kept at 1e-7 rad so
     that line-of-sight nodes almost never cross a table cell edge, where the
-    bilinear interpolation has a kink; the other steps are 1e-6 relative)."""
+    interpolation, linear in theta, has a kink; the other steps are 1e-6
+    relative)."""
     t = time.time()
     out = []
     for seed, beta, inc_deg in ((5, (0.25, -0.15), 62.0), (6, (-0.1, 0.3), 75.0)):

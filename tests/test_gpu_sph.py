@@ -79,7 +79,7 @@ def test_isotropic_spherical_close_to_cylindrical():
     Vs, _ = _eval(sph, w, dev)
     err = np.max(np.abs(Vs / Vc - 1))
     print(f"isotropic spherical vs cylindrical: {err:.2e}")
-    assert err <= 2e-3
+    assert err <= 2e-4
     cyl.close()
     sph.close()
 
@@ -307,3 +307,43 @@ def test_graph_replay_adjoint_and_autograd():
         assert np.allclose(a, b, rtol=1e-10, atol=1e-10 * np.max(np.abs(b))), k
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("seed,kw,over", [
+    (40, dict(n_lum=1, n_mass=0, nx=1, ny=1, ss=3, psf_n=1, n_bins=1, n_u=8), {}),
+    (41, dict(n_lum=2, n_mass=1, nx=5, ny=4, ss=1, psf_n=5, n_bins=2, n_u=5, xc=0.02), dict(inc=np.pi / 2)),
+    (42, dict(n_lum=4, n_mass=3, nx=6, ny=6, ss=2, psf_n=3, n_bins=3, n_u=12), dict(beta=np.array([0.9, -0.8, 0.5, 0.0]))),
+])
+def test_edge_cases_vs_oracle(seed, kw, over):
+    """Single Gaussian with only the BH as mass, a single super-sampled pixel
+    without PSF; edge-on; strong radial and tangential anisotropy."""
+    dev = _dev()
+    g = inputs.small_geometry(seed=seed, **kw)
+    p = inputs.with_overrides(inputs.small_params(g, seed=seed), **over)
+    w = inputs.Workload("e", [g], np.zeros(1, np.int32), [p])
+    ctx = binding.Context([g], alignment=1)
+    V, st = _eval(ctx, w, dev)
+    ref = osph.vrms2(g, p)
+    err = np.max(np.abs(V / ref - 1))
+    print(f"edge case {seed}: max rel err {err:.2e}")
+    assert st[0] == 0 and err <= RTOL
+    ctx.close()
+
+
+def test_isotropic_spherical_close_to_cylindrical_ifu_scale():
+    """At the IFU scale (40 x 40 Gaussians, 200^2 px, 2x supersampling) with
+    beta = 0 the spherical path agrees with the cylindrical closed form, whose
+    full-size parity is pinned separately, to the table's interpolation."""
+    dev = _dev()
+    w = inputs.config2()
+    p = inputs.with_overrides(w.params[0], beta=np.zeros(w.geometries[0].n_lum))
+    w = inputs.Workload("iso2", w.geometries, w.geom_idx, [p])
+    cyl = binding.Context(w.geometries)
+    sph = binding.Context(w.geometries, alignment=1)
+    Vc, _ = _eval(cyl, w, dev)
+    Vs, st = _eval(sph, w, dev)
+    err = np.max(np.abs(Vs / Vc - 1))
+    print(f"IFU-scale isotropic spherical vs cylindrical: {err:.2e}")
+    assert st[0] == 0 and err <= 1e-3
+    cyl.close()
+    sph.close()

@@ -127,8 +127,8 @@ def test_jeans_equations_hold(monkeypatch):
 
 
 def test_table_interpolation_error_is_small():
-    """The polar table (128 x 24, bilinear in ln r and theta) stays within
-    1e-3 of the moments evaluated at every line-of-sight node."""
+    """The polar table (128 x 24, cubic in ln r and linear in theta) stays
+    within 1e-3 of the moments evaluated at every line-of-sight node."""
     g = _geom(4, n_u=32)
     p = inputs.small_params(g, seed=4)
     x, y, _ = ojam.padded_subgrid(g)
@@ -137,3 +137,23 @@ def test_table_interpolation_error_is_small():
     Nd = S.numerator_direct(g, p, X.ravel()[idx], Y.ravel()[idx])
     Nt = S.numerator_table(g, p, X.ravel()[idx], Y.ravel()[idx])
     assert np.max(np.abs(Nt / Nd - 1)) <= 1e-3
+
+
+def test_table_interpolation_reproduces_quadratics():
+    """Catmull-Rom in ln r reproduces any quadratic in ln r (times a linear
+    function of theta) exactly inside the table, passes through the table's
+    values, and its weights sum to one."""
+    r = np.exp(np.linspace(np.log(0.01), np.log(50.0), 40))
+    th = np.linspace(0.0, 0.5 * np.pi, 7)
+    L, TH = np.meshgrid(np.log(r), th, indexing="ij")
+    T = (0.3 + 1.7 * L - 0.45 * L ** 2) * (2.0 + 0.8 * TH)
+    rng = np.random.default_rng(3)
+    rq = np.exp(rng.uniform(np.log(r[1]), np.log(r[-2]), 200))
+    tq = rng.uniform(0.0, 0.5 * np.pi, 200)
+    (v,) = S._interp([T], r, th, rq, tq)
+    exact = (0.3 + 1.7 * np.log(rq) - 0.45 * np.log(rq) ** 2) * (2.0 + 0.8 * tq)
+    assert np.max(np.abs(v - exact)) <= 1e-11 * np.max(np.abs(exact))
+    (vn,) = S._interp([T], r, th, r[[0, 5, 38]], th[[0, 3, 6]])
+    assert np.allclose(vn, T[[0, 5, 38], [0, 3, 6]], rtol=1e-12, atol=0)
+    for fx in np.linspace(0.0, 1.0, 11):
+        assert abs(sum(S.radial_weights(fx)) - 1.0) < 1e-15
