@@ -47,10 +47,11 @@ moments but not its layout; these are the readings both sides use):
 * intrinsic moments summed over the tracer Gaussians, A_r = sum P_k,
   A_theta = sum (1 - beta_k) P_k, A_phi = sum nu v_phi^2_k, tabulated on a
   polar grid of N_R radii log-spaced on [r_lo, r_hi] and N_TH angles evenly
-  spaced on [0, pi/2], and interpolated cubically (Catmull-Rom) in ln r and
-  linearly in theta (at the ends of the radial range the missing radius is
-  extrapolated linearly); below r_lo the first radius is used, beyond r_hi
-  the moments are zero;
+  spaced on [0, pi/2], and interpolated bicubically (Catmull-Rom in ln r and
+  in theta; at the ends of the radial range the missing radius is
+  extrapolated linearly, and the moments are even about theta = 0 and
+  theta = pi/2, so the missing angles are mirror images); below r_lo the
+  first radius is used, beyond r_hi the moments are zero;
 * line of sight: z' = a sinh(w), w on [-W, W] with sinh(W) a = Z, SEG_LOS
   segments of NODE_LOS Gauss-Legendre nodes, a = min_k sigma_k q_k / 4,
   Z = 12 max_k sigma_k.
@@ -182,27 +183,34 @@ def radial_weights(fx):
 
 
 def _interp(table, r, th, rq, tq):
-    """Cubic (Catmull-Rom) in ln r, linear in theta; at the table's ends the
-    missing radius is extrapolated linearly from the two nearest; the first
-    radius stands for smaller ones, zero beyond the last."""
+    """Bicubic (Catmull-Rom in ln r and in theta).  In r the missing radius at
+    either end is extrapolated linearly from the two nearest; in theta the
+    moments are even about the axis (theta = 0) and about the equatorial plane
+    (theta = pi/2), so the missing angles are mirror images.  The first radius
+    stands for smaller ones; zero beyond the last."""
     lr = np.log(r)
-    n = len(r)
+    n, nt = len(r), len(th)
     x = (np.log(rq) - lr[0]) / (lr[1] - lr[0])
     y = tq / (th[1] - th[0])
     xi = np.clip(np.floor(x), 0, n - 2).astype(int)
-    yi = np.clip(np.floor(y), 0, len(th) - 2).astype(int)
+    yi = np.clip(np.floor(y), 0, nt - 2).astype(int)
     fx = np.clip(x - xi, 0.0, 1.0)
     fy = np.clip(y - yi, 0.0, 1.0)
-    w = radial_weights(fx)
+    wx = radial_weights(fx)
+    wy = radial_weights(fy)
     out = []
     for T in table:
-        def col(i):          # linear in theta at radius index i (with end extrapolation)
-            lo = (1 - fy) * T[np.clip(i, 0, n - 1), yi] + fy * T[np.clip(i, 0, n - 1), yi + 1]
-            return lo
-        p0, p1 = col(xi), col(xi + 1)
-        pm = np.where(xi >= 1, col(xi - 1), 2.0 * p0 - p1)
-        p2 = np.where(xi + 2 <= n - 1, col(xi + 2), 2.0 * p1 - p0)
-        v = w[0] * pm + w[1] * p0 + w[2] * p1 + w[3] * p2
+        def row(i):          # cubic in theta at radius index i (mirrored angles)
+            v = 0.0
+            for b in range(4):
+                j = yi - 1 + b
+                j = np.where(j < 0, -j, np.where(j > nt - 1, 2 * (nt - 1) - j, j))
+                v = v + wy[b] * T[i, j]
+            return v
+        p0, p1 = row(xi), row(xi + 1)
+        pm = np.where(xi >= 1, row(np.maximum(xi - 1, 0)), 2.0 * p0 - p1)
+        p2 = np.where(xi + 2 <= n - 1, row(np.minimum(xi + 2, n - 1)), 2.0 * p1 - p0)
+        v = wx[0] * pm + wx[1] * p0 + wx[2] * p1 + wx[3] * p2
         out.append(np.where(x > n - 1, 0.0, v))
     return out
 

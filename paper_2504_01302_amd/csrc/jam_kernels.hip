@@ -1685,6 +1685,33 @@ __device__ inline void sph_radial_weights(int xi, double fx, double *ew, double 
   }
 }
 
+// Angular weights, Catmull-Rom in theta over the angles yi - 1 .. yi + 2;
+// the moments are even about theta = 0 and theta = pi/2, so a missing angle
+// is the mirror image of the one inside, folded into the weights.
+__device__ inline void sph_angular_weights(int yi, double fy, double *ew, double *dew) {
+  const double f2 = fy * fy, f3 = f2 * fy;
+  ew[0] = 0.5 * (-f3 + 2.0 * f2 - fy);
+  ew[1] = 0.5 * (3.0 * f3 - 5.0 * f2 + 2.0);
+  ew[2] = 0.5 * (-3.0 * f3 + 4.0 * f2 + fy);
+  ew[3] = 0.5 * (f3 - f2);
+  dew[0] = 0.5 * (-3.0 * f2 + 4.0 * fy - 1.0);
+  dew[1] = 0.5 * (9.0 * f2 - 10.0 * fy);
+  dew[2] = 0.5 * (-9.0 * f2 + 8.0 * fy + 1.0);
+  dew[3] = 0.5 * (3.0 * f2 - 2.0 * fy);
+  if (yi == 0) {                  // angle -1 mirrors angle 1 (= yi + 1)
+    ew[2] += ew[0];
+    ew[0] = 0.0;
+    dew[2] += dew[0];
+    dew[0] = 0.0;
+  }
+  if (yi + 2 > kSphNT - 1) {      // angle NT mirrors angle NT - 2 (= yi)
+    ew[1] += ew[3];
+    ew[3] = 0.0;
+    dew[1] += dew[3];
+    dew[3] = 0.0;
+  }
+}
+
 // Node of tracer k's characteristic through table point (r, theta): the same
 // FP64 operations as the forward moment kernel.
 struct SphNode {
@@ -1794,8 +1821,9 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
       const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
       const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
       const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-      double ew[4], dew[4];
+      double ew[4], dew[4], tw[4], dtw[4];
       sph_radial_weights(xi, fx, ew, dew);
+      sph_angular_weights(yi, fy, tw, dtw);
       const double ner = si * st * sp + ci * ct;
       const double net = si * ct * sp - ci * st;
       const double nep = si * cp;
@@ -1806,19 +1834,20 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (ew[a] == 0.0 && dew[a] == 0.0) continue;   // out of range (folded)
-        const int64_t i0 = ((int64_t)(xi - 1 + a) * kSphNT + yi) * 3;
-        const double *c0 = T + i0, *c1 = c0 + 3;
-        double *d0 = ldt + i0, *d1 = d0 + 3;
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-          const double cf = lamN * wz * nf[f] * nf[f] * ew[a];
-          if (cf != 0.0) {
-            atomicAdd(d0 + f, cf * (1 - fy));
-            atomicAdd(d1 + f, cf * fy);
+        for (int b = 0; b < 4; ++b) {
+          if (tw[b] == 0.0 && dtw[b] == 0.0) continue;
+          const int64_t i0 = ((int64_t)(xi - 1 + a) * kSphNT + (yi - 1 + b)) * 3;
+          const double *c = T + i0;
+          double *d = ldt + i0;
+#pragma unroll
+          for (int f = 0; f < 3; ++f) {
+            const double cf = lamN * wz * nf[f] * nf[f] * ew[a] * tw[b];
+            if (cf != 0.0) atomicAdd(d + f, cf);
+            A[f] += ew[a] * tw[b] * c[f];
+            if (xin) AL[f] += dew[a] * tw[b] * c[f] / g.sph_dlnr;
+            AT[f] += ew[a] * dtw[b] * c[f] / dth;
           }
-          A[f] += ew[a] * ((1 - fy) * c0[f] + fy * c1[f]);
-          if (xin) AL[f] += dew[a] * ((1 - fy) * c0[f] + fy * c1[f]) / g.sph_dlnr;
-          AT[f] += ew[a] * (c1[f] - c0[f]) / dth;
         }
       }
       // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
@@ -2447,8 +2476,8 @@ __global__ void __launch_bounds__(256) k_beta_logistic_vjp(const GeomDev *__rest
 // Line-of-sight integral of the projected moment table into the unique-pixel
 // N map.  Item (m, 64-pixel block); thread = pixel.  Nodes z' = a sinh(w), w
 // on [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
-// a sinh(W) = 12 max_k sigma_k; the table is interpolated cubically in ln r
-// (sph_radial_weights) and linearly in theta, the first radius standing for
+// a sinh(W) = 12 max_k sigma_k; the table is interpolated bicubically
+// (sph_radial_weights, sph_angular_weights), the first radius standing for
 // smaller ones and zero beyond the last.  FP64.
 __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geoms,
                                                  const ModelDev *__restrict__ models,
@@ -2500,15 +2529,21 @@ __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geo
     const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
     const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
     const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-    double ew[4], dew[4];
+    double ew[4], dew[4], tw[4], dtw[4];
     sph_radial_weights(xi, fx, ew, dew);
+    sph_angular_weights(yi, fy, tw, dtw);
     double A[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if (ew[a] == 0.0) continue;           // out of range (folded) or a zero weight
-      const double *c0 = T + ((int64_t)(xi - 1 + a) * kSphNT + yi) * 3, *c1 = c0 + 3;
 #pragma unroll
-      for (int f = 0; f < 3; ++f) A[f] += ew[a] * ((1 - fy) * c0[f] + fy * c1[f]);
+      for (int b = 0; b < 4; ++b) {
+        if (tw[b] == 0.0) continue;
+        const double *c = T + ((int64_t)(xi - 1 + a) * kSphNT + (yi - 1 + b)) * 3;
+        const double wab = ew[a] * tw[b];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) A[f] += wab * c[f];
+      }
     }
     const double ner = si * st * sp + ci * ct;
     const double net = si * ct * sp - ci * st;

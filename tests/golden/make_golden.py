@@ -127,7 +127,7 @@ def sph_grad():
     """Gradient of sum_b cot_b v_rms^2_b of the spherically aligned oracle by
     central differences (FP64; the inclination step is kept at 1e-7 rad so
     that line-of-sight nodes almost never cross a table cell edge, where the
-    interpolation, linear in theta, has a kink; the other steps are 1e-6
+    interpolant's second derivative jumps; the other steps are 1e-6
     relative)."""
     t = time.time()
     out = []

@@ -68,7 +68,8 @@ def test_cfg1_geometry_vs_golden():
 
 def test_isotropic_spherical_close_to_cylindrical():
     """With beta = 0 the two alignments coincide; the spherical path differs
-    from the cylindrical closed form only by its table interpolation."""
+    from the cylindrical closed form only by its discretisation (measured
+    1e-5 on this geometry)."""
     dev = _dev()
     w = inputs.config1()
     p = inputs.with_overrides(w.params[0], beta=np.zeros(w.geometries[0].n_lum))
@@ -79,7 +80,7 @@ def test_isotropic_spherical_close_to_cylindrical():
     Vs, _ = _eval(sph, w, dev)
     err = np.max(np.abs(Vs / Vc - 1))
     print(f"isotropic spherical vs cylindrical: {err:.2e}")
-    assert err <= 2e-4
+    assert err <= 5e-5
     cyl.close()
     sph.close()
 
@@ -344,6 +345,6 @@ def test_isotropic_spherical_close_to_cylindrical_ifu_scale():
     Vs, st = _eval(sph, w, dev)
     err = np.max(np.abs(Vs / Vc - 1))
     print(f"IFU-scale isotropic spherical vs cylindrical: {err:.2e}")
-    assert st[0] == 0 and err <= 1e-3
+    assert st[0] == 0 and err <= 1e-4
     cyl.close()
     sph.close()

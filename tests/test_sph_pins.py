@@ -127,7 +127,7 @@ def test_jeans_equations_hold(monkeypatch):
 
 
 def test_table_interpolation_error_is_small():
-    """The polar table (128 x 24, cubic in ln r and linear in theta) stays
+    """The polar table (128 x 24, bicubic in ln r and theta) stays
     within 1e-3 of the moments evaluated at every line-of-sight node."""
     g = _geom(4, n_u=32)
     p = inputs.small_params(g, seed=4)
@@ -140,20 +140,36 @@ def test_table_interpolation_error_is_small():
 
 
 def test_table_interpolation_reproduces_quadratics():
-    """Catmull-Rom in ln r reproduces any quadratic in ln r (times a linear
-    function of theta) exactly inside the table, passes through the table's
-    values, and its weights sum to one."""
+    """The bicubic (Catmull-Rom) interpolation reproduces any product of a
+    quadratic in ln r and an even quadratic-plus-cos(2 theta) profile in
+    theta exactly inside the table where the mirrored angles are exact, passes
+    through the table's values, and its weights sum to one."""
     r = np.exp(np.linspace(np.log(0.01), np.log(50.0), 40))
     th = np.linspace(0.0, 0.5 * np.pi, 7)
     L, TH = np.meshgrid(np.log(r), th, indexing="ij")
-    T = (0.3 + 1.7 * L - 0.45 * L ** 2) * (2.0 + 0.8 * TH)
+    T = (0.3 + 1.7 * L - 0.45 * L ** 2) * (2.0 + 0.8 * (TH - 0.6) ** 2)
     rng = np.random.default_rng(3)
     rq = np.exp(rng.uniform(np.log(r[1]), np.log(r[-2]), 200))
-    tq = rng.uniform(0.0, 0.5 * np.pi, 200)
+    tq = rng.uniform(th[1], th[-2], 200)
     (v,) = S._interp([T], r, th, rq, tq)
-    exact = (0.3 + 1.7 * np.log(rq) - 0.45 * np.log(rq) ** 2) * (2.0 + 0.8 * tq)
+    exact = (0.3 + 1.7 * np.log(rq) - 0.45 * np.log(rq) ** 2) * (2.0 + 0.8 * (tq - 0.6) ** 2)
     assert np.max(np.abs(v - exact)) <= 1e-11 * np.max(np.abs(exact))
     (vn,) = S._interp([T], r, th, r[[0, 5, 38]], th[[0, 3, 6]])
     assert np.allclose(vn, T[[0, 5, 38], [0, 3, 6]], rtol=1e-12, atol=0)
     for fx in np.linspace(0.0, 1.0, 11):
         assert abs(sum(S.radial_weights(fx)) - 1.0) < 1e-15
+
+
+def test_table_interpolation_even_in_theta_at_the_ends():
+    """With data even about theta = 0 and pi/2 (cos(2 theta) and cos(4
+    theta) profiles) the mirrored end angles keep the interpolant close to
+    the truth in the first and last angular cells."""
+    r = np.exp(np.linspace(np.log(0.01), np.log(50.0), 20))
+    th = np.linspace(0.0, 0.5 * np.pi, 24)
+    L, TH = np.meshgrid(np.log(r), th, indexing="ij")
+    T = 1.0 + 0.3 * np.cos(2 * TH) + 0.1 * np.cos(4 * TH)
+    tq = np.concatenate([np.linspace(0.0, th[1], 9), np.linspace(th[-2], th[-1], 9)])
+    rq = np.full_like(tq, r[7])
+    (v,) = S._interp([T], r, th, rq, tq)
+    exact = 1.0 + 0.3 * np.cos(2 * tq) + 0.1 * np.cos(4 * tq)
+    assert np.max(np.abs(v - exact)) <= 2e-5
