@@ -1513,8 +1513,9 @@ __global__ void __launch_bounds__(256) k_sph_terms(const GeomDev *__restrict__ g
   }
 }
 
-// Item (m, table point).  In round q wave w takes tracer k = 4 q + w; lane l
-// is node l of the composite Gauss-Legendre rule in tau = ln(r'/r) on
+// Item (m, table point).  In round q wave w takes tracers k = 8 q + w and
+// 8 q + 4 + w (each coefficient read from LDS feeds both); lane l is node l
+// of the composite Gauss-Legendre rule in tau = ln(r'/r) on
 // [0, ln(r_max / r)], r_max^2 = r^2 + 50 sigma_k^2.  The per-model term
 // coefficients go through LDS in chunks; each group of 64 terms is summed in
 // FP32 (fully unrolled, the coefficient reads are wave-wide broadcasts) and
@@ -1557,50 +1558,64 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
     double Ar = 0.0, At = 0.0, Ap = 0.0;   // this wave's tracers (lane 0)
     double accF = 0.0;                      // this thread's share of G_phi
-    const int rounds = (K + 3) / 4;
+    constexpr int kTr = 2;                  // tracers per wave and round
+    const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
     for (int q = 0; q < rounds; ++q) {
-      const int k = 4 * q + wave;
-      const bool on = k < K;                // uniform per wave
-      double alpha = 1.0, alphaq = 1.0, beta = 0.0, wn = 0.0, nuv = 0.0, rp = r, Rp = 0.0;
-      float R2 = 0.f, Z2 = 0.f;
-      if (on) {
-        alpha = tab[k];
-        alphaq = tab[K + k];
-        beta = 1.0 - 1.0 / tab[3 * K + k];
-        const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r));
-        const double hs = tmax / kSphSeg;
-        const double tau = (seg + 0.5 + 0.5 * glx) * hs;
-        rp = r * exp(tau);
-        const double st = fmin(1.0, sth * pow(r / rp, 1.0 - beta));
-        const double ct = sqrt(fmax(0.0, 1.0 - st * st));
-        Rp = rp * st;
-        const double zp = rp * ct;
-        R2 = (float)(Rp * Rp);
-        Z2 = (float)(zp * zp);
-        wn = 0.5 * glw * hs * rp;                  // dr' = r' dtau
-        nuv = tab[2 * K + k] * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
+      double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr];
+      float R2[kTr], Z2[kTr];
+      bool on[kTr];
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) {
+        const int k = 4 * (kTr * q + u) + wave;
+        on[u] = k < K;                      // uniform per wave
+        alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; wn[u] = 0.0; nuv[u] = 0.0;
+        rp[u] = r; Rp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
+        if (on[u]) {
+          alpha[u] = tab[k];
+          alphaq[u] = tab[K + k];
+          beta[u] = 1.0 - 1.0 / tab[3 * K + k];
+          const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha[u]) / (r * r));
+          const double hs = tmax / kSphSeg;
+          const double tau = (seg + 0.5 + 0.5 * glx) * hs;
+          rp[u] = r * exp(tau);
+          const double st = fmin(1.0, sth * pow(r / rp[u], 1.0 - beta[u]));
+          const double ct = sqrt(fmax(0.0, 1.0 - st * st));
+          Rp[u] = rp[u] * st;
+          const double zp = rp[u] * ct;
+          R2[u] = (float)(Rp[u] * Rp[u]);
+          Z2[u] = (float)(zp * zp);
+          wn[u] = 0.5 * glw * hs * rp[u];
+          nuv[u] = tab[2 * K + k] * exp(-(alpha[u] * Rp[u] * Rp[u] + alphaq[u] * zp * zp));
+        }
       }
-      double accG = 0.0, accT = 0.0;
+      double accG[kTr], accT[kTr];
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) { accG[u] = 0.0; accT[u] = 0.0; }
       for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
-        const int cn = min(kSphChunk, Tp - c0);   // a multiple of 64
+        const int cn = min(kSphChunk, Tp - c0);
         __syncthreads();
         for (int t = threadIdx.x; t < cn; t += 256) {
           tc[t] = gtc[c0 + t];
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
-        if (on) {
+        if (on[0]) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
-            float sg = 0.f, sd = 0.f;
+            float sg0 = 0.f, sd0 = 0.f, sg1 = 0.f, sd1 = 0.f;
 #pragma unroll
             for (int t = 0; t < 64; ++t) {
               const float4 c = tc[t0 + t];
-              const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
-              sg = fmaf(c.z, e, sg);
-              sd = fmaf(c.w, e, sd);
+              const float e0 = fast_exp2(fmaf(c.x, R2[0], c.y * Z2[0]));
+              const float e1 = fast_exp2(fmaf(c.x, R2[1], c.y * Z2[1]));
+              sg0 = fmaf(c.z, e0, sg0);
+              sd0 = fmaf(c.w, e0, sd0);
+              sg1 = fmaf(c.z, e1, sg1);
+              sd1 = fmaf(c.w, e1, sd1);
             }
-            accG += (double)sg;
-            accT += (double)sd;
+            accG[0] += (double)sg0;
+            accT[0] += (double)sd0;
+            accG[1] += (double)sg1;
+            accT[1] += (double)sd1;
           }
         }
         if (q == 0) {
@@ -1610,17 +1625,19 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           }
         }
       }
-      if (on) {
-        const double sk2 = 0.5 / alpha, qk2 = alpha / alphaq;
-        double fP = wn * pow(rp, 2.0 * beta + 1.0) * nuv * accG;
-        double fD = wn * pow(rp, 3.0 * beta + 1.0) * Rp * nuv *
-                    (accT + accG * (1.0 / qk2 - 1.0) / sk2);
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) {
+        if (!on[u]) continue;
+        const double sk2 = 0.5 / alpha[u], qk2 = alpha[u] / alphaq[u];
+        double fP = wn[u] * pow(rp[u], 2.0 * beta[u] + 1.0) * nuv[u] * accG[u];
+        double fD = wn[u] * pow(rp[u], 3.0 * beta[u] + 1.0) * Rp[u] * nuv[u] *
+                    (accT[u] + accG[u] * (1.0 / qk2 - 1.0) / sk2);
         fP = wave_sum(fP);
         fD = wave_sum(fD);
-        const double P = pow(r, -2.0 * beta) * fP;
+        const double P = pow(r, -2.0 * beta[u]) * fP;
         Ar += P;
-        At += (1.0 - beta) * P;
-        Ap += (1.0 - beta) * P + (1.0 - beta) * sth * pow(r, 1.0 - 3.0 * beta) * fD;
+        At += (1.0 - beta[u]) * P;
+        Ap += (1.0 - beta[u]) * P + (1.0 - beta[u]) * sth * pow(r, 1.0 - 3.0 * beta[u]) * fD;
       }
     }
     if (lane == 0) {
@@ -1902,11 +1919,11 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
 }
 
 // Characteristic integrals' adjoint.  Item (m, table cell), the forward's
-// layout: wave w takes tracer k = 4 q + w, lane = node.  Per node the term
-// sums G, G_theta and their derivatives in R'^2 and z'^2; per (cell,
-// tracer) the derivatives of the cell's L = lambda . (A_r, A_theta, A_phi)
-// with respect to beta_k, alphaq_k and nu0_k go to rows; the A_phi term
-// -nu R^2 G_phi adds its alphaq_k, nu0_k derivatives after.
+// layout: wave w takes tracers 8 q + w and 8 q + 4 + w, lane = node.  Per
+// node the term sums G, G_theta and their derivatives in R'^2 and z'^2; per
+// (cell, tracer) the derivatives of the cell's L = lambda . (A_r, A_theta,
+// A_phi) with respect to beta_k, alphaq_k and nu0_k go to rows; the A_phi
+// term -nu R^2 G_phi adds its alphaq_k, nu0_k derivatives after.
 __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restrict__ geoms,
                                                          const ModelDev *__restrict__ models,
                                                          const Item *__restrict__ items, int n_it,
@@ -1940,23 +1957,35 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
     const int seg = lane >> 3, gi = lane & 7;
     const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
     double accF = 0.0;
-    const int rounds = (K + 3) / 4;
+    constexpr int kTr = 2;                  // tracers per wave and round
+    const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
     for (int q = 0; q < rounds; ++q) {
-      const int k = 4 * q + wave;
-      const bool on = k < K;
-      double alpha = 1.0, alphaq = 1.0, beta = 0.0, nu0 = 0.0;
-      SphNode nd{};
-      float R2 = 0.f, Z2 = 0.f;
-      if (on) {
-        alpha = tab[k];
-        alphaq = tab[K + k];
-        nu0 = tab[2 * K + k];
-        beta = 1.0 - 1.0 / tab[3 * K + k];
-        nd = sph_node(r, sth, alpha, alphaq, beta, seg, glx, glw);
-        R2 = (float)(nd.Rp * nd.Rp);
-        Z2 = (float)(nd.zp * nd.zp);
+      int kk[kTr];
+      bool on[kTr];
+      double alpha[kTr], alphaq[kTr], beta[kTr], nu0[kTr];
+      SphNode nd[kTr];
+      float R2[kTr], Z2[kTr];
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) {
+        kk[u] = 4 * (kTr * q + u) + wave;
+        on[u] = kk[u] < K;                  // uniform per wave
+        alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; nu0[u] = 0.0;
+        nd[u] = SphNode{};
+        R2[u] = 0.f; Z2[u] = 0.f;
+        if (on[u]) {
+          const int k = kk[u];
+          alpha[u] = tab[k];
+          alphaq[u] = tab[K + k];
+          nu0[u] = tab[2 * K + k];
+          beta[u] = 1.0 - 1.0 / tab[3 * K + k];
+          nd[u] = sph_node(r, sth, alpha[u], alphaq[u], beta[u], seg, glx, glw);
+          R2[u] = (float)(nd[u].Rp * nd[u].Rp);
+          Z2[u] = (float)(nd[u].zp * nd[u].zp);
+        }
       }
-      double aG = 0.0, aT = 0.0, aGR = 0.0, aGZ = 0.0, aTR = 0.0, aTZ = 0.0;
+      double aG[kTr], aT[kTr], aGR[kTr], aGZ[kTr], aTR[kTr], aTZ[kTr];
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) aG[u] = aT[u] = aGR[u] = aGZ[u] = aTR[u] = aTZ[u] = 0.0;
       for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
         const int cn = min(kSphChunk, Tp - c0);
         __syncthreads();
@@ -1967,26 +1996,40 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
-        if (on) {
+        if (on[0]) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
-            float sG = 0.f, sT = 0.f, sGR = 0.f, sGZ = 0.f, sTR = 0.f, sTZ = 0.f;
+            float sG0 = 0.f, sT0 = 0.f, sGR0 = 0.f, sGZ0 = 0.f, sTR0 = 0.f, sTZ0 = 0.f;
+            float sG1 = 0.f, sT1 = 0.f, sGR1 = 0.f, sGZ1 = 0.f, sTR1 = 0.f, sTZ1 = 0.f;
 #pragma unroll 16
             for (int t = 0; t < 64; ++t) {
               const float4 c = tc[t0 + t], d = tx[t0 + t];
-              const float e = fast_exp2(fmaf(c.x, R2, c.y * Z2));
-              sG = fmaf(c.z, e, sG);
-              sT = fmaf(c.w, e, sT);
-              sGR = fmaf(d.x, e, sGR);
-              sGZ = fmaf(d.y, e, sGZ);
-              sTR = fmaf(d.z, e, sTR);
-              sTZ = fmaf(d.w, e, sTZ);
+              const float e0 = fast_exp2(fmaf(c.x, R2[0], c.y * Z2[0]));
+              const float e1 = fast_exp2(fmaf(c.x, R2[1], c.y * Z2[1]));
+              sG0 = fmaf(c.z, e0, sG0);
+              sT0 = fmaf(c.w, e0, sT0);
+              sGR0 = fmaf(d.x, e0, sGR0);
+              sGZ0 = fmaf(d.y, e0, sGZ0);
+              sTR0 = fmaf(d.z, e0, sTR0);
+              sTZ0 = fmaf(d.w, e0, sTZ0);
+              sG1 = fmaf(c.z, e1, sG1);
+              sT1 = fmaf(c.w, e1, sT1);
+              sGR1 = fmaf(d.x, e1, sGR1);
+              sGZ1 = fmaf(d.y, e1, sGZ1);
+              sTR1 = fmaf(d.z, e1, sTR1);
+              sTZ1 = fmaf(d.w, e1, sTZ1);
             }
-            aG += (double)sG;
-            aT += (double)sT;
-            aGR += (double)sGR;
-            aGZ += (double)sGZ;
-            aTR += (double)sTR;
-            aTZ += (double)sTZ;
+            aG[0] += (double)sG0;
+            aT[0] += (double)sT0;
+            aGR[0] += (double)sGR0;
+            aGZ[0] += (double)sGZ0;
+            aTR[0] += (double)sTR0;
+            aTZ[0] += (double)sTZ0;
+            aG[1] += (double)sG1;
+            aT[1] += (double)sT1;
+            aGR[1] += (double)sGR1;
+            aGZ[1] += (double)sGZ1;
+            aTR[1] += (double)sTR1;
+            aTZ[1] += (double)sTZ1;
           }
         }
         if (q == 0) {
@@ -1996,31 +2039,35 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
           }
         }
       }
-      if (on) {
-        const double kap = 2.0 * (alphaq - alpha);
-        const double nu = nu0 * nd.en;
-        const double H = aT + kap * aG;
+#pragma unroll
+      for (int u = 0; u < kTr; ++u) {
+        if (!on[u]) continue;               // uniform per wave
+        const SphNode &n = nd[u];
+        const double be = beta[u];
+        const double kap = 2.0 * (alphaq[u] - alpha[u]);
+        const double nu = nu0[u] * n.en;
+        const double H = aT[u] + kap * aG[u];
         // d/dbeta of the node: s' = s (r/r')^(1-beta) -> ds'/dbeta = s' tau
-        const double ds = nd.clamped ? 0.0 : nd.st * nd.tau;
-        const double dc = nd.ct > 0.0 ? -nd.st * ds / nd.ct : 0.0;
-        const double dR = nd.rp * ds, dz = nd.rp * dc;
-        const double dR2 = 2.0 * nd.Rp * dR, dZ2 = 2.0 * nd.zp * dz;
-        const double dnu = -nu * (alpha * dR2 + alphaq * dZ2);
+        const double ds = n.clamped ? 0.0 : n.st * n.tau;
+        const double dc = n.ct > 0.0 ? -n.st * ds / n.ct : 0.0;
+        const double dR = n.rp * ds, dz = n.rp * dc;
+        const double dR2 = 2.0 * n.Rp * dR, dZ2 = 2.0 * n.zp * dz;
+        const double dnu = -nu * (alpha[u] * dR2 + alphaq[u] * dZ2);
         // the term coefficients carry log2 e: dE/d(R'^2) = ln 2 c.x E
-        const double dG = kLn2 * (aGR * dR2 + aGZ * dZ2);
-        const double dH = kLn2 * (aTR * dR2 + aTZ * dZ2) + kap * dG;
-        const double lrp = log(nd.rp);
-        const double pP = nd.wn * pow(nd.rp, 2.0 * beta + 1.0);
-        const double pD = nd.wn * pow(nd.rp, 3.0 * beta + 1.0);
-        double fP = pP * nu * aG;
-        double fD = pD * nd.Rp * nu * H;
-        double bP = pP * (2.0 * lrp * nu * aG + dnu * aG + nu * dG);
-        double bD = pD * (3.0 * lrp * nd.Rp * nu * H + dR * nu * H + nd.Rp * dnu * H +
-                          nd.Rp * nu * dH);
-        double qP = pP * aG * (-nd.zp * nd.zp * nu);
-        double qD = pD * nd.Rp * (-nd.zp * nd.zp * nu * H + nu * 2.0 * aG);
-        double eP = pP * nd.en * aG;
-        double eD = pD * nd.Rp * nd.en * H;
+        const double dG = kLn2 * (aGR[u] * dR2 + aGZ[u] * dZ2);
+        const double dH = kLn2 * (aTR[u] * dR2 + aTZ[u] * dZ2) + kap * dG;
+        const double lrp = log(n.rp);
+        const double pP = n.wn * pow(n.rp, 2.0 * be + 1.0);
+        const double pD = n.wn * pow(n.rp, 3.0 * be + 1.0);
+        double fP = pP * nu * aG[u];
+        double fD = pD * n.Rp * nu * H;
+        double bP = pP * (2.0 * lrp * nu * aG[u] + dnu * aG[u] + nu * dG);
+        double bD = pD * (3.0 * lrp * n.Rp * nu * H + dR * nu * H + n.Rp * dnu * H +
+                          n.Rp * nu * dH);
+        double qP = pP * aG[u] * (-n.zp * n.zp * nu);
+        double qD = pD * n.Rp * (-n.zp * n.zp * nu * H + nu * 2.0 * aG[u]);
+        double eP = pP * n.en * aG[u];
+        double eD = pD * n.Rp * n.en * H;
         fP = wave_sum(fP);
         fD = wave_sum(fD);
         bP = wave_sum(bP);
@@ -2031,13 +2078,13 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
         eD = wave_sum(eD);
         if (lane == 0) {
           const double lnr = log(r);
-          const double rb = pow(r, -2.0 * beta), rd = pow(r, 1.0 - 3.0 * beta);
+          const double rb = pow(r, -2.0 * be), rd = pow(r, 1.0 - 3.0 * be);
           const double P = rb * fP;
-          const double muP = lr + (1.0 - beta) * (lt + lp);
-          const double muD = lp * (1.0 - beta) * sth * rd;
+          const double muP = lr + (1.0 - be) * (lt + lp);
+          const double muD = lp * (1.0 - be) * sth * rd;
           const double dbeta = muP * rb * bP + muD * bD - (lt + lp) * P - 2.0 * lnr * muP * P -
-                               fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - beta) * lnr);
-          double *row = adj.rows + ((int64_t)k * kSphCells + cell) * 3;
+                               fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - be) * lnr);
+          double *row = adj.rows + ((int64_t)kk[u] * kSphCells + cell) * 3;
           row[0] = dbeta;
           row[1] = muP * rb * qP + muD * qD;
           row[2] = muP * rb * eP + muD * eD;
