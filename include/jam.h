@@ -18,7 +18,9 @@
  * Units: lengths on the sky in arcsec, distance in Mpc, masses in Msun,
  * Sigma0 in Msun/pc^2, luminous amplitudes in any unit (they cancel),
  * inclination in radians (pi/2 = edge-on), output in (km/s)^2.
- * Anisotropy beta_k = 1 - v_z^2 / v_R^2 per luminous Gaussian.
+ * Anisotropy beta_k per luminous Gaussian: 1 - v_z^2 / v_R^2 for the
+ * cylindrically aligned model, 1 - v_theta^2 / v_r^2 for the spherically
+ * aligned one (jam_options.alignment).
  *
  * Memory: every pointer is a HOST pointer unless its comment says DEVICE.
  * Arrays are contiguous, float64 unless stated, row-major.  The library
@@ -200,7 +202,8 @@ jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map,
  * beta_k, mass scale, BH mass, lum_I0 and mass_S0.  vrms2 is the forward
  * output for the same batch (DEVICE), or NULL to have it recomputed; cot is
  * DEVICE, packed like vrms2.  Nothing from the forward is kept: intermediates
- * are recomputed.  Models with a non-OK status get NaN gradients.
+ * are recomputed.  Models with a non-OK status get NaN gradients.  The
+ * spherically aligned model runs its own adjoint (jam_options.alignment).
  * ws_bytes >= jam_workspace_size(..., 1).                                    */
 jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2,
                    const double *cot, jam_grads *grads, void *ws, size_t ws_bytes,
