@@ -1075,13 +1075,11 @@ __global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
 // FP64 chain from per-term sensitivities to the parameters.  Forward-mode
 // dual numbers carry d/d(inclination) through the deprojection and the term
 // coefficients.  Items (m, k, jb): wave w of the workgroup takes mass
-// Gaussian j = 4 jb + w (BH last) and its lanes the u-nodes; with
-// jb = ceil(J1 / 4) the item instead computes the surface-brightness path of
-// luminous Gaussian k.  Chain rows per model (doubles, after the
-// sensitivity blocks): [K][J1][3] = (d/di, d/db_k, H_kj) for the terms of
-// (k, j), with H_kj = sum_n (S0 c0 + S1 c1) the derivative with respect to
-// the amplitude product I0_k M_j; then [K] surface-brightness terms
-// sum_p lambda_I[p] exp(-(x^2 + y^2/q'^2)/(2 sigma'^2)).
+// Gaussian j = 4 jb + w (BH last) and its lanes the u-nodes.  Chain rows per
+// model (doubles, after the sensitivity blocks): [K][J1][3] = (d/di, d/db_k,
+// H_kj) for the terms of (k, j), with H_kj = sum_n (S0 c0 + S1 c1) the
+// derivative with respect to the amplitude product I0_k M_j.  The
+// surface-brightness path of I0_k is k_sb_adj's.
 // ---------------------------------------------------------------------------
 struct dual {
   double v, d;
