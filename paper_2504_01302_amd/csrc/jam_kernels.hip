@@ -730,7 +730,17 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
     if (u < g.n_pix) {
       const double *pp = part + md.part_off + (int64_t)x * (32 * md.n_yt) + y;
       const int64_t stride = part_slice_size(md);
-      for (int s = wave; s < md.n_slices; s += 4) acc += pp[s * stride];
+      // eight slices' loads in flight, added in slice order
+      for (int s0 = wave; s0 < md.n_slices; s0 += 32) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int s = s0 + 4 * k;
+          v[k] = s < md.n_slices ? pp[s * stride] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+      }
     }
     if (wave > 0) red[wave - 1][lane] = acc;
     __syncthreads();
