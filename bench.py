@@ -509,6 +509,10 @@ def main():
             "beta_profile_chi2_4096_small": lambda: time_beta_profile(
                 torch, binding, inputs.config3(4096), dev, k),
             "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
+            "cylindrical_composite_42x95": lambda: time_batch(
+                torch, binding, inputs.config_composite(), dev, k, a.form, a.launch, a.graph),
+            "spherical_composite_42x95": lambda: time_spherical(
+                torch, binding, inputs.config_composite(), dev, max(2, k // 2)),
             "spherical_1024_small": lambda: time_spherical(torch, binding, inputs.config3(1024),
                                                            dev, max(2, k // 2)),
         }

@@ -263,6 +263,18 @@ def config5(n_models: int = 256, seed: int = 0) -> Workload:
     return w
 
 
+def config_composite(seed: int = 0) -> Workload:
+    """The IFU-scale grid of config 2 with the Gaussian counts of the paper's
+    composite lens model (42 light and 95 mass Gaussians + BH), for timing
+    the spherically aligned path at the size the paper quotes."""
+    rng = _rng(6, seed)
+    g = _geometry(rng, 42, 95, 200, 0.025, 2, 0.14, 31, 60, 128)
+    inc = draw_inclination(rng, _q_min(g))
+    beta = rng.uniform(-0.2, 0.4, 42)
+    p = Params(inc, beta, 1.0, 10.0 ** 8.5)
+    return Workload("composite", [g], np.zeros(1, np.int32), [p])
+
+
 def cotangent(n_bins: int, n_models: int, seed: int = 0) -> np.ndarray:
     """Seeded N(0,1) cotangent per bin and model, ``[n_models, n_bins]``."""
     return _rng(5, seed).standard_normal((n_models, n_bins))
