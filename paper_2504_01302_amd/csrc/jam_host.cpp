@@ -820,7 +820,7 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
                    (const float4 *)(w + p->off_terms), pix, st_ws, sens,
                    p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
   if (timed) ctx->t_sens.end(st);
-  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, pix, sens, st_ws, st);
+  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, sens, st_ws, st);
   jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, sbp, st_ws, gd, st);
 }
 

@@ -177,7 +177,7 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // writes one block; the MFMA kernel one block per 32-row x tile (items
 // (m, x tile, 256-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
-                  const double *pix, double *sens, const int *st_ws, hipStream_t st);
+                  double *sens, const int *st_ws, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const double *sbp, const int *st_ws, GradsDev out, hipStream_t st);
 // Spherically aligned model.  Terms: items (m, block of 256 terms), the

@@ -68,20 +68,6 @@ __device__ double block_sum256(double v, double *sh) {
   return r;
 }
 
-// Deterministic block sum of one double over a 1024-thread block.
-__device__ double block_sum1024(double v, double *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -1102,7 +1088,6 @@ __device__ inline dual operator/(dual a, dual b) {
   return {r, (a.d - r * b.d) / b.v};
 }
 __device__ inline dual operator*(double s, dual a) { return {s * a.v, s * a.d}; }
-__device__ inline dual operator+(double s, dual a) { return {s + a.v, a.d}; }
 __device__ inline dual operator-(double s, dual a) { return {s - a.v, -a.d}; }
 __device__ inline dual operator/(double s, dual a) {
   const double r = s / a.v;
@@ -1121,8 +1106,7 @@ __device__ inline double *chain_rows(double *sens, const ModelDev &md, const Geo
 __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms,
                                                const ModelDev *__restrict__ models,
                                                const Item *__restrict__ items, int n_it,
-                                               ParamsDev p, const double *__restrict__ pix,
-                                               double *__restrict__ sens,
+                                               ParamsDev p, double *__restrict__ sens,
                                                const int *__restrict__ st_ws) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2685,9 +2669,8 @@ int occupancy_sens() {
   return nb < 1 ? 1 : nb;
 }
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
-                  const double *pix, double *sens, const int *st_ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_chain, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, pix, sens,
-                     st_ws);
+                  double *sens, const int *st_ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_chain, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, sens, st_ws);
 }
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const double *sbp, const int *st_ws, GradsDev out, hipStream_t st) {
