@@ -98,10 +98,9 @@ typedef struct {
  *       on it with fixed valid parameters and keep the fastest; results are
  *       cached per composition, and in the text file tune_cache if not NULL
  *       (read at jam_create, rewritten after each tuning).
- * launch: 0 = one worker per work item (a workgroup, or a wave for the
- *       matrix-core numerator), dispatched by the hardware; 1 = persistent
- *       grid whose workers pull work items from a device queue (largest
- *       first).
+ * launch: 0 = one workgroup per work item, dispatched by the hardware;
+ *       1 = persistent grid whose workgroups pull work items from a device
+ *       queue (largest first).
  * graph: 1 = record each prepared composition's evaluation (and adjoint) as
  *       a HIP graph on first use and replay it while the call's pointers are
  *       unchanged (re-recorded when they change).

@@ -278,8 +278,8 @@ struct Tune {
                     // into 64-wide tiles
   int gran = 0;     // slice length: units of 64 terms per MFMA item, or (k, j) pairs per
                     // per-pixel item; 0 = derived from the batch
-  int launch = 0;   // 0 one worker per item (a workgroup, or a wave for the matrix-core
-                    // numerator); 1 persistent grid pulling items from a device queue
+  int launch = 0;   // 0 one workgroup per item; 1 persistent grid pulling items from a
+                    // device queue
 };
 
 // Pointers a captured graph was recorded with; replay only on an exact match.
