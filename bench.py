@@ -77,8 +77,16 @@ def cpu_baseline(g, p, n_sample):
     ojam.point_values(g, p, x[ix], y[iy])
     dt = time.perf_counter() - t0
     per_model = dt * (len(x) * len(y)) / n_sample
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f
+                              if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return dict(value=1.0 / per_model, unit="models/s", cores=torch.get_num_threads(),
-                kind="oracle",
+                kind="oracle", cpu_model=cpu_model, nproc=os.cpu_count(),
+                affinity=len(os.sched_getaffinity(0)),
                 sample=f"N and I at {n_sample} of {len(x) * len(y)} padded sub-pixels of the "
                        f"IFU-scale model ({dt:.1f} s), scaled to one model")
 
@@ -499,6 +507,7 @@ def main():
                    "schedule": ctx.plan_info(w.geom_idx)},
         "fwd_bwd_per_s": n * 1000.0 / ms_fb,
         "ms_per_fwd_bwd": ms_fb,
+        "integrand_evals_per_s": float(n_pix) * T * n * 1000.0 / ms_f,
         "max_rel_err_vs_oracle": max_rel,
         "wall_s_forward_loop": wall_f,
         "roofline": roof,
