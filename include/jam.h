@@ -112,9 +112,9 @@ typedef struct {
  *       per model and integrated along the line of sight (64 nodes); form,
  *       autotune and launch do not apply.  jam_vjp / jam_vjp_chi2 run the
  *       model's own adjoint (always recomputing the moment table; the table
- *       cotangent is accumulated with FP64 atomic adds, so gradients can
- *       differ between calls in the last bits) and need a larger workspace
- *       (jam_workspace_size).                                               */
+ *       cotangent is summed as 64-bit fixed-point integers at a per-model
+ *       power-of-two scale, so gradients are bitwise reproducible) and need
+ *       a larger workspace (jam_workspace_size).                            */
 typedef struct {
   int32_t form;
   int32_t autotune;

@@ -222,11 +222,11 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
 // ModelDev::n_sens_parts.
 constexpr int kSphCells = kSphNR * kSphNT;
 struct SphAdj {
-  double *dtab, *rows, *losp, *sparts, *cparts, *tchain;
+  double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *dscale;
 };
 __host__ __device__ inline int64_t sph_adj_size(int K, int n_pix, int Tp, int n_rng) {
   return 3LL * kSphCells + 3LL * kSphCells * K + 2LL * ((n_pix + 63) / 64) +
-         6LL * n_rng * Tp + 5LL * Tp;
+         6LL * n_rng * Tp + 5LL * Tp + 1;
 }
 __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix, int Tp,
                                                  int n_rng) {
@@ -237,6 +237,7 @@ __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix,
   a.sparts = a.losp + 2LL * ((n_pix + 63) / 64);
   a.cparts = a.sparts + 6LL * n_rng * Tp;
   a.tchain = a.cparts + 3LL * Tp;
+  a.dscale = a.tchain + 2LL * Tp;
   return a;
 }
 // Points of one model's characteristic integrals: (cell, tracer, node).

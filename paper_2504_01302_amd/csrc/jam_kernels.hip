@@ -1758,24 +1758,77 @@ __device__ inline SphAdj sph_adj_of(double *sens, const ModelDev &md, const Geom
                         md.n_sens_parts);
 }
 
+// Start of the line-of-sight adjoint, block per model: clears the table
+// cotangent and fixes its fixed-point scale.  Every contribution to the
+// cotangent is lambda_N w_z (n.e_f)^2 times interpolation weights, so the
+// sum of their magnitudes over all pixels, nodes and cells is at most
+// sum_p |lambda_N| x sum_nodes w_z (the node rule integrates a cosh(w) over
+// [-W, W]: 2 a sinh W = 24 max sigma_k, taken as 25) x sum |radial weights|
+// x sum |angular weights| (each below 2; sum_f (n.e_f)^2 = 1).  The scale is
+// the power of two that maps that bound below 2^61, so the 64-bit integer
+// sums cannot overflow and do not depend on the order of the additions.
+// A non-finite bound stores NaN, which k_sph_dtab_fix turns into a NaN
+// cotangent.
 __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ geoms,
                                                   const ModelDev *__restrict__ models, int n,
+                                                  const double *__restrict__ gauss,
+                                                  const int *__restrict__ st_ws,
+                                                  const double *__restrict__ pix,
                                                   double *__restrict__ sens) {
+  __shared__ double sh[256];
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
-    double *d = sph_adj_of(sens, md, g).dtab;
-    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) d[i] = 0.0;
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    unsigned long long *d = reinterpret_cast<unsigned long long *>(adj.dtab);
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) d[i] = 0ull;
+    if (st_ws[m] != 0) continue;   // uniform per block
+    const double *lam = pix + md.pix_off + 2 * (int64_t)g.n_pix;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < g.n_pix; q += 256) s += fabs(lam[q]);
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) {
+      const double *tab = gauss + md.gauss_off;
+      double smax = 0.0;
+      for (int k = 0; k < g.K; ++k) smax = fmax(smax, sqrt(0.5 / tab[k]));
+      const double bound = s * 25.0 * smax * 4.0;
+      double scale = __builtin_nan("");
+      if (bound == 0.0) scale = 1.0;
+      else if (bound < __builtin_inf()) scale = ldexp(1.0, 60 - ilogb(bound));
+      adj.dscale[0] = scale;
+    }
+  }
+}
+
+// End of the line-of-sight adjoint, block per model: the fixed-point table
+// cotangent back to FP64 in place.
+__global__ void __launch_bounds__(256) k_sph_dtab_fix(const GeomDev *__restrict__ geoms,
+                                                      const ModelDev *__restrict__ models, int n,
+                                                      const int *__restrict__ st_ws,
+                                                      double *__restrict__ sens) {
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    if (st_ws[m] != 0) continue;   // uniform per block
+    const ModelDev md = models[m];
+    const GeomDev g = geoms[md.geom];
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const double scale = adj.dscale[0];
+    long long *d = reinterpret_cast<long long *>(adj.dtab);
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) {
+      const long long v = d[i];
+      adj.dtab[i] = scale == scale ? (double)v / scale : scale;
+    }
   }
 }
 
 // Line-of-sight adjoint.  Item (m, 256-pixel block), thread = pixel.  The
-// table cotangent receives lambda_N w_z (n.e_f)^2 times the interpolation weights,
-// accumulated in a block-private LDS copy of the table (FP64 LDS atomics) and
-// added to the model's table once per block (FP64 global atomics, non-zero
-// entries only); the derivatives of the node's integrand at fixed table with
-// respect to i (line of sight and node position) and to the node scale a are
-// summed per 64-pixel wave.
+// table cotangent receives lambda_N w_z (n.e_f)^2 times the interpolation
+// weights, each rounded to a 64-bit fixed-point integer at the model's scale
+// (k_sph_zero), accumulated in a block-private LDS copy of the table
+// (integer LDS atomics) and added to the model's table once per block
+// (integer global atomics, non-zero entries only): integer sums, so the
+// result does not depend on the order of the additions.  The derivatives of
+// the node's integrand at fixed table with respect to i (line of sight and
+// node position) and to the node scale a are summed per 64-pixel wave.
 __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
                                                      const Item *__restrict__ items, int n_it,
@@ -1784,14 +1837,16 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
                                                      const double *__restrict__ table,
                                                      const double *__restrict__ pix,
                                                      double *__restrict__ sens) {
-  __shared__ double ldt[3 * kSphCells];
+  __shared__ unsigned long long ldt[3 * kSphCells];
   for (int ii = blockIdx.x; ii < n_it; ii += gridDim.x) {
     const Item it = items[ii];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
     if (st_ws[it.m] != 0) continue;              // uniform per block
     const SphAdj adj = sph_adj_of(sens, md, g);
-    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) ldt[i] = 0.0;
+    const double scale = adj.dscale[0];
+    const bool fixed = scale == scale;           // NaN: non-finite cotangent
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) ldt[i] = 0ull;
     __syncthreads();
     const int q = it.a * 256 + threadIdx.x;
     const bool on = q < g.n_pix;
@@ -1848,11 +1903,12 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
           if (tw[b] == 0.0 && dtw[b] == 0.0) continue;
           const int64_t i0 = ((int64_t)(xi - 1 + a) * kSphNT + (yi - 1 + b)) * 3;
           const double *c = T + i0;
-          double *d = ldt + i0;
+          unsigned long long *d = ldt + i0;
 #pragma unroll
           for (int f = 0; f < 3; ++f) {
             const double cf = lamN * wz * nf[f] * nf[f] * ew[a] * tw[b];
-            if (cf != 0.0) atomicAdd(d + f, cf);
+            if (cf != 0.0 && fixed)
+              atomicAdd(d + f, (unsigned long long)__double2ll_rn(cf * scale));
             A[f] += ew[a] * tw[b] * c[f];
             if (xin) AL[f] += dew[a] * tw[b] * c[f] / g.sph_dlnr;
             AT[f] += ew[a] * dtw[b] * c[f] / dth;
@@ -1902,9 +1958,10 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
       }
     }
     __syncthreads();
+    unsigned long long *dt = reinterpret_cast<unsigned long long *>(adj.dtab);
     for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) {
-      const double v = ldt[i];
-      if (v != 0.0) atomicAdd(adj.dtab + i, v);
+      const unsigned long long v = ldt[i];
+      if (v != 0ull) atomicAdd(dt + i, v);
     }
     __syncthreads();
   }
@@ -2705,9 +2762,11 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                         const double *gauss, const float4 *terms, const int *st_ws,
                         const double *table, const double *pix, const double *sbp, double *sens,
                         GradsDev out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, sens);
+  hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, gauss, st_ws, pix,
+                     sens);
   hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
                      gauss, st_ws, table, pix, sens);
+  hipLaunchKernelGGL(k_sph_dtab_fix, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws, sens);
   hipLaunchKernelGGL(k_sph_moments_adj, dim3(grid_of(n_cell)), dim3(256), 0, st, g, m, it_cell,
                      n_cell, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
