@@ -1765,8 +1765,9 @@ __device__ inline SphAdj sph_adj_of(double *sens, const ModelDev &md, const Geom
 // sum_p |lambda_N| x sum_nodes w_z (the node rule integrates a cosh(w) over
 // [-W, W]: 2 a sinh W = 24 max sigma_k, taken as 25) x sum |radial weights|
 // x sum |angular weights| (each below 2; sum_f (n.e_f)^2 = 1).  The scale is
-// the power of two that maps that bound below 2^61, so the 64-bit integer
-// sums cannot overflow and do not depend on the order of the additions.
+// the power of two that maps that bound below 2^61 (at most 2^1000, for
+// tiny bounds), so the 64-bit integer sums cannot overflow and do not depend
+// on the order of the additions.
 // A non-finite bound stores NaN, which k_sph_dtab_fix turns into a NaN
 // cotangent.
 __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ geoms,
@@ -1794,7 +1795,7 @@ __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ ge
       const double bound = s * 25.0 * smax * 4.0;
       double scale = __builtin_nan("");
       if (bound == 0.0) scale = 1.0;
-      else if (bound < __builtin_inf()) scale = ldexp(1.0, 60 - ilogb(bound));
+      else if (bound < __builtin_inf()) scale = ldexp(1.0, min(1000, 60 - ilogb(bound)));
       adj.dscale[0] = scale;
     }
   }
