@@ -111,10 +111,11 @@ typedef struct {
  *       Jeans equations into a 128 x 24 polar table of the intrinsic moments
  *       per model and integrated along the line of sight (64 nodes); form,
  *       autotune and launch do not apply.  jam_vjp / jam_vjp_chi2 run the
- *       model's own adjoint (always recomputing the moment table; the table
- *       cotangent is summed as 64-bit fixed-point integers at a per-model
- *       power-of-two scale, so gradients are bitwise reproducible) and need
- *       a larger workspace (jam_workspace_size).                            */
+ *       model's own adjoint (recomputing the moment table in one pass with
+ *       the cotangent-free sums of its adjoint; the table cotangent is
+ *       summed as 64-bit fixed-point integers at a per-model power-of-two
+ *       scale, so gradients are bitwise reproducible) and need a larger
+ *       workspace (jam_workspace_size).                                     */
 typedef struct {
   int32_t form;
   int32_t autotune;

@@ -783,8 +783,22 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   double *sens = (double *)(w + p->off_sens);
   const jam::ParamsDev pd = params_of(b);
   const bool recompute = (vrms2 == nullptr);
-  // the spherical adjoint needs the moment table, so it always recomputes it
-  launch_forward_maps(ctx, p, pd, nullptr, w, st, recompute || p->spherical, capturing);
+  if (p->spherical) {
+    // the spherical adjoint needs the moment table: one pass computes it with
+    // the node sums of the characteristic integrals' adjoint; the numerator
+    // map follows only when V is recomputed
+    launch_forward_maps(ctx, p, pd, nullptr, w, st, false, capturing);
+    const double *gauss = (const double *)(w + p->off_gauss);
+    double *tabs = (double *)(w + p->off_sph);
+    jam::launch_sph_moments_jac(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss,
+                                (const float4 *)(w + p->off_terms), st_ws, tabs,
+                                (double *)(w + p->off_sens), st);
+    if (recompute)
+      jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix,
+                          st);
+  } else {
+    launch_forward_maps(ctx, p, pd, nullptr, w, st, recompute, capturing);
+  }
   // V per bin: the caller's forward output, or recomputed into workspace.
   const double *V = vrms2;
   if (recompute) {

@@ -207,6 +207,11 @@ void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int 
 // the table points (items (m, 256-term tile)), the per-term chain (items (m,
 // 256-term tile)), and the per-model gradients (block per model; they read
 // the surface-brightness partials sbp).
+// The moment table together with the cotangent-free node sums of its
+// adjoint (SphAdj::jac, gphi), for the adjoint's forward pass.
+void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                            const double *gauss, const float4 *terms, const int *st_ws,
+                            double *table, double *sens, hipStream_t st);
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
                         int n_sens, const Item *it_tile, int n_tile, ParamsDev p,
@@ -218,15 +223,17 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
 // cell) rows (d/dbeta, d/dalphaq, d/dnu0) [K][cells][3], line-of-sight
 // partials (d/di at fixed node scale, d/d node scale) per 64-pixel block,
 // per-term sensitivities per point range [n_rng][Tp][6] and of the cell
-// points [Tp][3] and per-term chain values (d/de2, d/dKp) [Tp][2].  n_rng is
-// ModelDev::n_sens_parts.
+// points [Tp][3], per-term chain values (d/de2, d/dKp) [Tp][2], the table
+// cotangent's fixed-point scale [1], the cotangent-free node sums of the
+// characteristic integrals' adjoint per (tracer, cell) [K][cells][8] and
+// G_phi per cell [cells].  n_rng is ModelDev::n_sens_parts.
 constexpr int kSphCells = kSphNR * kSphNT;
 struct SphAdj {
-  double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *dscale;
+  double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *dscale, *jac, *gphi;
 };
 __host__ __device__ inline int64_t sph_adj_size(int K, int n_pix, int Tp, int n_rng) {
   return 3LL * kSphCells + 3LL * kSphCells * K + 2LL * ((n_pix + 63) / 64) +
-         6LL * n_rng * Tp + 5LL * Tp + 1;
+         6LL * n_rng * Tp + 5LL * Tp + 1 + 8LL * kSphCells * K + kSphCells;
 }
 __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix, int Tp,
                                                  int n_rng) {
@@ -238,6 +245,8 @@ __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix,
   a.cparts = a.sparts + 6LL * n_rng * Tp;
   a.tchain = a.cparts + 3LL * Tp;
   a.dscale = a.tchain + 2LL * Tp;
+  a.jac = a.dscale + 1;
+  a.gphi = a.jac + 8LL * kSphCells * K;
   return a;
 }
 // Points of one model's characteristic integrals: (cell, tracer, node).

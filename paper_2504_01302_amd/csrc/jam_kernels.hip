@@ -1968,23 +1968,28 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
   }
 }
 
-// Characteristic integrals' adjoint.  Item (m, table cell), the forward's
-// layout: wave w takes tracers 8 q + w and 8 q + 4 + w, lane = node.  Per
-// node the term sums G, G_theta and their derivatives in R'^2 and z'^2; per
-// (cell, tracer) the derivatives of the cell's L = lambda . (A_r, A_theta,
-// A_phi) with respect to beta_k, alphaq_k and nu0_k go to rows; the A_phi
-// term -nu R^2 G_phi adds its alphaq_k, nu0_k derivatives after.
-__global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restrict__ geoms,
+// Forward pass of the adjoint: the moment table (as k_sph_moments) with the
+// node sums its adjoint needs.  Item (m, table cell), the forward's layout:
+// wave w takes tracers 8 q + w and 8 q + 4 + w, lane = node.  Per node the
+// term sums G, G_theta and their derivatives in R'^2 and z'^2; per (cell,
+// tracer) the node sums of the characteristic integrals (fP, fD) and of
+// their derivatives with respect to beta_k (bP, bD), alphaq_k (qP, qD) and
+// nu0_k (eP, eD) go to SphAdj::jac, none of which depends on the table
+// cotangent, and the cell's G_phi to SphAdj::gphi; k_sph_rows combines
+// them with the cotangent once the line-of-sight adjoint has produced it.
+__global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restrict__ geoms,
                                                          const ModelDev *__restrict__ models,
                                                          const Item *__restrict__ items, int n_it,
                                                          const double *__restrict__ gauss,
                                                          const float4 *__restrict__ terms,
                                                          const int *__restrict__ st_ws,
+                                                         double *__restrict__ table,
                                                          double *__restrict__ sens) {
   __shared__ float4 tc[kSphChunk];
   __shared__ float4 tx[kSphChunk];   // (gP c_x, gP c_y, gT c_x, gT c_y)
   __shared__ float tf[kSphChunk];
   __shared__ double sh[256];
+  __shared__ double wred[3][4];
   constexpr double kLn2 = 0.6931471805599453;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1992,7 +1997,11 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    if (st_ws[it.m] != 0) continue;          // uniform per block
+    double *out = table + md.sph_off + (int64_t)it.a * 3;
+    if (st_ws[it.m] != 0) {                  // uniform per block
+      if (threadIdx.x < 3) out[threadIdx.x] = 0.0;
+      continue;
+    }
     const SphAdj adj = sph_adj_of(sens, md, g);
     const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
     const float4 *gtc = terms + md.term_off;
@@ -2001,12 +2010,12 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
     const int cell = it.a;
     double r, sth, cth;
     sph_cell(g, cell, r, sth, cth);
-    const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1], lp = adj.dtab[3 * cell + 2];
     const double Rp0 = r * sth, zp0 = r * cth;
     const float R20 = (float)(Rp0 * Rp0), Z20 = (float)(zp0 * zp0);
     const int seg = lane >> 3, gi = lane & 7;
     const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
     double accF = 0.0;
+    double Ar = 0.0, At = 0.0, Ap = 0.0;    // this wave's tracers (lane 0)
     constexpr int kTr = 2;                  // tracers per wave and round
     const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
     for (int q = 0; q < rounds; ++q) {
@@ -2127,29 +2136,77 @@ __global__ void __launch_bounds__(256) k_sph_moments_adj(const GeomDev *__restri
         eP = wave_sum(eP);
         eD = wave_sum(eD);
         if (lane == 0) {
-          const double lnr = log(r);
-          const double rb = pow(r, -2.0 * be), rd = pow(r, 1.0 - 3.0 * be);
-          const double P = rb * fP;
-          const double muP = lr + (1.0 - be) * (lt + lp);
-          const double muD = lp * (1.0 - be) * sth * rd;
-          const double dbeta = muP * rb * bP + muD * bD - (lt + lp) * P - 2.0 * lnr * muP * P -
-                               fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - be) * lnr);
-          double *row = adj.rows + ((int64_t)kk[u] * kSphCells + cell) * 3;
-          row[0] = dbeta;
-          row[1] = muP * rb * qP + muD * qD;
-          row[2] = muP * rb * eP + muD * eD;
+          double *jr = adj.jac + ((int64_t)kk[u] * kSphCells + cell) * 8;
+          jr[0] = fP; jr[1] = fD; jr[2] = bP; jr[3] = bD;
+          jr[4] = qP; jr[5] = qD; jr[6] = eP; jr[7] = eD;
+          const double P = pow(r, -2.0 * be) * fP;
+          Ar += P;
+          At += (1.0 - be) * P;
+          Ap += (1.0 - be) * P + (1.0 - be) * sth * pow(r, 1.0 - 3.0 * be) * fD;
         }
       }
     }
-    const double Gphi = block_sum256(accF, sh);   // synchronises the block (rows written)
-    // A_phi -= nu(cell) R0^2 G_phi, nu(cell) = sum_k nu0_k exp(-(alpha R0^2 + alphaq z0^2))
-    for (int k = threadIdx.x; k < K; k += 256) {
-      const double e0 = exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
-      double *row = adj.rows + ((int64_t)k * kSphCells + cell) * 3;
-      row[1] += lp * Rp0 * Rp0 * Gphi * tab[2 * K + k] * e0 * zp0 * zp0;
-      row[2] += -lp * Rp0 * Rp0 * Gphi * e0;
+    if (lane == 0) {
+      wred[0][wave] = Ar;
+      wred[1][wave] = At;
+      wred[2][wave] = Ap;
+    }
+    const double Gphi = block_sum256(accF, sh);   // synchronises the block
+    if (threadIdx.x == 0) {
+      double nus = 0.0;
+      for (int k = 0; k < K; ++k)
+        nus += tab[2 * K + k] * exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
+      out[0] = ((wred[0][0] + wred[0][1]) + wred[0][2]) + wred[0][3];
+      out[1] = ((wred[1][0] + wred[1][1]) + wred[1][2]) + wred[1][3];
+      out[2] = (((wred[2][0] + wred[2][1]) + wred[2][2]) + wred[2][3]) - nus * Rp0 * Rp0 * Gphi;
+      adj.gphi[cell] = Gphi;
     }
     __syncthreads();
+  }
+}
+
+// Rows of the characteristic integrals' adjoint: per (cell, tracer) the
+// derivatives of the cell's L = lambda . (A_r, A_theta, A_phi) with respect
+// to beta_k, alphaq_k and nu0_k from the node sums of k_sph_moments_jac and
+// the table cotangent lambda; the A_phi term -nu R^2 G_phi adds its
+// alphaq_k, nu0_k derivatives.  Item (m, table cell), thread = tracer.
+__global__ void __launch_bounds__(64) k_sph_rows(const GeomDev *__restrict__ geoms,
+                                                 const ModelDev *__restrict__ models,
+                                                 const Item *__restrict__ items, int n_it,
+                                                 const double *__restrict__ gauss,
+                                                 const int *__restrict__ st_ws,
+                                                 double *__restrict__ sens) {
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const int K = g.K, cell = it.a;
+    const double *tab = gauss + md.gauss_off;
+    double r, sth, cth;
+    sph_cell(g, cell, r, sth, cth);
+    const double Rp0 = r * sth, zp0 = r * cth;
+    const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1], lp = adj.dtab[3 * cell + 2];
+    const double Gphi = adj.gphi[cell];
+    const double lnr = log(r);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const double *jr = adj.jac + ((int64_t)k * kSphCells + cell) * 8;
+      const double fP = jr[0], fD = jr[1], bP = jr[2], bD = jr[3];
+      const double qP = jr[4], qD = jr[5], eP = jr[6], eD = jr[7];
+      const double be = 1.0 - 1.0 / tab[3 * K + k];
+      const double rb = pow(r, -2.0 * be), rd = pow(r, 1.0 - 3.0 * be);
+      const double P = rb * fP;
+      const double muP = lr + (1.0 - be) * (lt + lp);
+      const double muD = lp * (1.0 - be) * sth * rd;
+      const double dbeta = muP * rb * bP + muD * bD - (lt + lp) * P - 2.0 * lnr * muP * P -
+                           fD * lp * sth * rd * (1.0 + 3.0 * (1.0 - be) * lnr);
+      const double e0 = exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
+      double *row = adj.rows + ((int64_t)k * kSphCells + cell) * 3;
+      row[0] = dbeta;
+      row[1] = (muP * rb * qP + muD * qD) + lp * Rp0 * Rp0 * Gphi * tab[2 * K + k] * e0 * zp0 * zp0;
+      row[2] = (muP * rb * eP + muD * eD) + -lp * Rp0 * Rp0 * Gphi * e0;
+    }
   }
 }
 
@@ -2751,6 +2808,12 @@ void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int
   hipLaunchKernelGGL(k_sph_moments, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
                      terms, st_ws, table);
 }
+void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                            const double *gauss, const float4 *terms, const int *st_ws,
+                            double *table, double *sens, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_moments_jac, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it,
+                     gauss, terms, st_ws, table, sens);
+}
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st) {
@@ -2768,8 +2831,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
   hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
                      gauss, st_ws, table, pix, sens);
   hipLaunchKernelGGL(k_sph_dtab_fix, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws, sens);
-  hipLaunchKernelGGL(k_sph_moments_adj, dim3(grid_of(n_cell)), dim3(256), 0, st, g, m, it_cell,
-                     n_cell, gauss, terms, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_rows, dim3(grid_of(n_cell)), dim3(64), 0, st, g, m, it_cell, n_cell,
+                     gauss, st_ws, sens);
   hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
                      gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_sens_cells, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile,
