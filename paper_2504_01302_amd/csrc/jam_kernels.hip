@@ -452,15 +452,13 @@ __device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__res
 //   A[x, t] = 2^(cx_t x^2) (C0_t + C1_t x^2),   B[y, t] = 2^(cy_t y^2),
 // an exact factorisation of the same sum, evaluated as a dense FP32
 // contraction over terms with v_mfma_f32_32x32x2f32.  Each 32x32 output
-// block accumulates a chunk of 32 terms in FP32 and folds it into FP64.
+// block accumulates a chunk of 64 terms in FP32 and folds it into FP64.
 //
 // Operand layout of v_mfma_f32_32x32x2f32 (lane l): A[l % 32][l / 32],
 // B[l / 32][l % 32]; accumulator r of lane l is D[i][j] with
 // i = (r % 4) + 4 (l / 32) + 8 (r / 4), j = l % 32.
 // ---------------------------------------------------------------------------
 typedef float v16f __attribute__((ext_vector_type(16)));
-
-constexpr int KC = 32;   // terms per chunk
 
 __device__ inline int mfma_row(int r, int lane) { return (r & 3) + 4 * (lane >> 5) + 8 * (r >> 2); }
 
@@ -469,7 +467,7 @@ constexpr int KC2 = 64;  // terms per chunk of the matrix-core numerator
 
 // Term range of one slice, in whole chunks of `unit` terms.
 __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int &t1,
-                                   int unit = KC) {
+                                   int unit) {
   const int chunks = (T + unit - 1) / unit;
   const int per = (chunks + n_slices - 1) / n_slices;
   t0 = min(T, slice * per * unit);
