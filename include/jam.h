@@ -29,6 +29,11 @@
  * one context must not overlap in time (one stream at a time); separate
  * contexts are independent.
  *
+ * Reproducibility: every sum runs in a fixed order (or in integers), so
+ * outputs and gradients are bitwise identical across calls with the same
+ * inputs, launch mode and batch composition; there is no non-deterministic
+ * fast path to switch off.
+ *
  * Errors: every call returns a jam_status; on anything but JAM_OK nothing
  * was launched unless stated, and jam_last_error() returns a message
  * (thread-local, valid until the next call on the same thread).
