@@ -31,8 +31,10 @@
  *
  * Reproducibility: every sum runs in a fixed order (or in integers), so
  * outputs and gradients are bitwise identical across calls with the same
- * inputs, launch mode and batch composition; there is no non-deterministic
- * fast path to switch off.
+ * inputs, batch composition and numerator schedule (the schedule is fixed
+ * by the options, except that the autotuner may time its way to another
+ * one in a new context unless it reads the same tune_cache file); there is
+ * no non-deterministic fast path to switch off.
  *
  * Errors: every call returns a jam_status; on anything but JAM_OK nothing
  * was launched unless stated, and jam_last_error() returns a message
