@@ -34,7 +34,7 @@ def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--form", type=int, default=2,
                     help="1 per-pixel VALU kernel, 2 matrix-core kernel (0 = library default)")
     ap.add_argument("--launch", type=int, default=0,
