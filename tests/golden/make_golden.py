@@ -4,7 +4,7 @@ Every value here comes from the FP64 oracle (``oracle/``) evaluated on the
 seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
 from the GPU library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [cfg2] [cfg3] [cfg4] [cfg5] [sph1] [sph_grad]
+    python tests/golden/make_golden.py [cfg2] [composite] [cfg3] [cfg4] [cfg5] [sph1] [sph_grad]
 """
 import json
 import os
@@ -46,6 +46,24 @@ def cfg2():
     _dump("cfg2_seed0.json", dict(
         source="oracle/jam.py vrms2 and point_values on inputs.config2(seed=0)",
         vrms2=V.tolist(), pix_iy=iy.tolist(), pix_ix=ix.tolist(),
+        N=N.numpy().tolist(), I=I.numpy().tolist(), seconds=time.time() - t))
+
+
+def composite():
+    """The composite-model size (42 light, 95 mass Gaussians + BH) on the
+    IFU-scale grid: N and I at 64 seeded padded sub-pixels (the full map would
+    take the oracle hours)."""
+    t = time.time()
+    w = inputs.config_composite(seed=0)
+    g, p = w.geometries[0], w.params[0]
+    x, y, _ = ojam.padded_subgrid(g)
+    rng = np.random.default_rng(321)
+    iy = rng.integers(0, len(y), 64)
+    ix = rng.integers(0, len(x), 64)
+    N, I = ojam.point_values(g, p, x[ix], y[iy])
+    _dump("composite_seed0.json", dict(
+        source="oracle/jam.py point_values on inputs.config_composite(seed=0)",
+        pix_iy=iy.tolist(), pix_ix=ix.tolist(),
         N=N.numpy().tolist(), I=I.numpy().tolist(), seconds=time.time() - t))
 
 
@@ -173,6 +191,6 @@ def sph_grad():
 
 if __name__ == "__main__":
     torch.set_num_threads(max(1, os.cpu_count() or 1))
-    todo = sys.argv[1:] or ["cfg2", "cfg3", "cfg4", "cfg5", "sph1", "sph_grad"]
+    todo = sys.argv[1:] or ["cfg2", "composite", "cfg3", "cfg4", "cfg5", "sph1", "sph_grad"]
     for name in todo:
         globals()[name]()

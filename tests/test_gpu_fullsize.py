@@ -77,6 +77,31 @@ def test_cfg2_sampled_map_values():
     ctx.close()
 
 
+@pytest.mark.parametrize("form", [2, 1])
+def test_composite_sampled_map_values(form):
+    """The composite-model size (42 light, 95 mass Gaussians + BH, 516,096
+    terms per pixel) on the IFU-scale grid, as the benchmark runs it."""
+    dev = _dev()
+    gd = _golden("composite_seed0.json")
+    w = inputs.config_composite(seed=0)
+    g = w.geometries[0]
+    ctx = binding.Context(w.geometries, form=form)
+    p = binding.pack_params(w, dev)
+    N, I, st = ctx.eval_maps(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"])
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == 0
+    nxp = g.nx * g.supersample + g.psf_n - 1
+    nyp = g.ny * g.supersample + g.psf_n - 1
+    N = N.cpu().numpy().reshape(nyp, nxp)
+    I = I.cpu().numpy().reshape(nyp, nxp)
+    iy, ix = np.array(gd["pix_iy"]), np.array(gd["pix_ix"])
+    rN = np.abs(N[iy, ix] / np.array(gd["N"]) - 1).max()
+    rI = np.abs(I[iy, ix] / np.array(gd["I"]) - 1).max()
+    print(f"composite sampled maps form={form}: N {rN:.3e}, I {rI:.3e}")
+    assert rN <= RTOL and rI <= 1e-12
+    ctx.close()
+
+
 def test_cfg3_full_batch():
     dev = _dev()
     gd = _golden("cfg3_subset.json")
