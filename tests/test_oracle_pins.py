@@ -63,22 +63,45 @@ def test_gauss_legendre_exact_on_polynomials():
 # P1: App. A deprojection projects back onto the observed Gaussian.
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("inc_deg,qobs", [(60.0, 0.7), (85.0, 0.6), (48.0, 0.8)])
-def test_deprojection_projects_back(inc_deg, qobs):
+@pytest.mark.parametrize("inc_deg", [60.0, 85.0, 90.0, 57.0])
+def test_deprojection_projects_back(inc_deg):
+    # Three observed Gaussians of different flattening and amplitude: the
+    # numerical line-of-sight integral of the sum of their deprojected
+    # densities (App. A) must equal the oracle's eq. (sb_mge_2D) map.
+    g = _geom(lum_sigma=np.array([0.9, 0.3, 2.0]), lum_q=np.array([0.7, 0.85, 0.6]),
+              lum_I0=np.array([2.5, 0.4, 7.0]))
     inc = torch.tensor(np.deg2rad(inc_deg), dtype=DT)
-    sig, I0 = 0.9, 2.5
-    q = jam.intrinsic_axis_ratio(torch.tensor([qobs], dtype=DT), inc)[0].item()
-    nu0 = jam.peak_density(torch.tensor(I0, dtype=DT), sig, qobs, q).item()
+    q_obs = torch.tensor(g.lum_q, dtype=DT)
+    q = jam.intrinsic_axis_ratio(q_obs, inc).numpy()
+    nu0 = jam.peak_density(torch.tensor(g.lum_I0, dtype=DT), torch.tensor(g.lum_sigma, dtype=DT),
+                           q_obs, torch.tensor(q, dtype=DT)).numpy()
     si, ci = math.sin(np.deg2rad(inc_deg)), math.cos(np.deg2rad(inc_deg))
-    for xp, yp in [(0.0, 0.0), (0.4, -0.3), (1.1, 0.7)]:
+    pts = [(0.0, 0.0), (0.4, -0.3), (1.1, 0.7), (0.05, 2.3), (-1.7, -0.9)]
+    sb = jam.surface_brightness(g, g.lum_I0, [p[0] for p in pts], [p[1] for p in pts]).numpy()
+    for (xp, yp), expect in zip(pts, sb):
         def nu(zp):
             # line of sight (0, sin i, cos i); sky y' along (0, -cos i, sin i)
             y = -yp * ci + zp * si
             z = yp * si + zp * ci
-            return nu0 * math.exp(-(xp ** 2 + y ** 2 + z ** 2 / q ** 2) / (2 * sig ** 2))
-        val, _ = integrate.quad(nu, -np.inf, np.inf, epsabs=0, epsrel=1e-13)
-        expect = I0 * math.exp(-(xp ** 2 + yp ** 2 / qobs ** 2) / (2 * sig ** 2))
+            return float(np.sum(nu0 * np.exp(-(xp ** 2 + y ** 2 + z ** 2 / q ** 2)
+                                              / (2 * g.lum_sigma ** 2))))
+        val, _ = integrate.quad(nu, -np.inf, np.inf, epsabs=0, epsrel=1e-13, limit=200)
         assert abs(val / expect - 1.0) < 1e-11
+
+
+@pytest.mark.parametrize("qobs", [0.6, 0.85, 1.0])
+def test_gaussian_total_mass_sky_integral(qobs):
+    # eq. (smd_mge): one term Sigma0 exp(-(x'^2 + y'^2/q'^2)/(2 sigma'^2)) in
+    # Msun/pc^2, integrated numerically over the sky plane in pc, is the
+    # oracle's total mass of that Gaussian.
+    S0, sig, D = 1234.5, 0.37, 850.0
+    s = jam.pc_per_arcsec(D)
+    sp = s * sig
+    f = lambda Y, X: S0 * math.exp(-(X * X + Y * Y / (qobs * qobs)) / (2 * sp * sp))
+    L = 14.0 * sp
+    val, _ = integrate.dblquad(f, -L, L, -L * qobs, L * qobs, epsabs=0, epsrel=1e-13)
+    M = jam.gaussian_total_mass(S0, sig, qobs, s)
+    assert abs(val / M - 1.0) < 1e-12
 
 
 def test_deprojection_limit_raises():
