@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <list>
 #include <queue>
 #include <memory>
@@ -282,14 +283,23 @@ struct Tune {
                     // device queue
 };
 
-// Pointers a captured graph was recorded with; replay only on an exact match.
+// Every pointer a captured graph was recorded with (parameters, outputs,
+// cotangents, gradients, workspace) in a fixed order, and the workspace
+// size; a graph is replayed only when all of them match exactly.
 struct GraphKey {
-  const void *p[10] = {};
+  static constexpr int kMax = 16;
+  const void *p[kMax] = {};
+  int n = 0;
   size_t ws_bytes = 0;
+  GraphKey() = default;
+  GraphKey(std::initializer_list<const void *> ptrs, size_t ws) : ws_bytes(ws) {
+    for (const void *q : ptrs) p[n++] = q;
+  }
   bool operator==(const GraphKey &o) const {
-    for (int i = 0; i < 10; ++i)
+    if (n != o.n || ws_bytes != o.ws_bytes) return false;
+    for (int i = 0; i < n; ++i)
       if (p[i] != o.p[i]) return false;
-    return ws_bytes == o.ws_bytes;
+    return true;
   }
 };
 
@@ -1386,11 +1396,8 @@ jam_status jam_eval_batch(jam_ctx *ctx, const jam_batch *batch, double *vrms2, i
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   if (ctx->opt.graph) {
-    GraphKey k;
-    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
-                            batch->mass_S0, vrms2, status, ws, nullptr};
-    std::copy(ptrs, ptrs + 10, k.p);
-    k.ws_bytes = ws_bytes;
+    const GraphKey k({batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                      batch->mass_S0, vrms2, status, ws}, ws_bytes);
     const jam_batch b = *batch;
     s = run_graph(ctx, p, 0, k, st, [&](hipStream_t cs) {
       launch_eval(ctx, p, &b, vrms2, status, w, cs, true);
@@ -1443,17 +1450,11 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, co
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   if (ctx->opt.graph) {
-    GraphKey k;
-    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta,
-                            batch->lum_I0, batch->mass_S0, vrms2, cot, ws, nullptr};
-    std::copy(ptrs, ptrs + 10, k.p);
-    k.ws_bytes = ws_bytes;
     // gradient outputs are part of the recorded launches
-    const void *gp[6] = {grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
-                         grads->mass_S0};
-    uintptr_t hsh = 0;
-    for (const void *q : gp) hsh = hsh * 1000003u ^ (uintptr_t)q;
-    k.p[9] = (const void *)hsh;
+    const GraphKey k({batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                      batch->mass_S0, vrms2, cot, ws, grads->inc, grads->mass_scale, grads->m_bh,
+                      grads->beta, grads->lum_I0, grads->mass_S0},
+                     ws_bytes);
     const jam_batch b = *batch;
     const jam_grads g = *grads;
     s = run_graph(ctx, p, 1, k, st, [&](hipStream_t cs) {
@@ -1552,11 +1553,9 @@ jam_status jam_eval_chi2(jam_ctx *ctx, const jam_batch *batch, double *chi2, dou
                      (const int *)(w + p->off_status), chi2, nullptr, nullptr, cs);
   };
   if (ctx->opt.graph) {
-    GraphKey k;
-    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
-                            batch->mass_S0, V, status, ws, chi2};
-    std::copy(ptrs, ptrs + 10, k.p);
-    k.ws_bytes = ws_bytes;
+    const GraphKey k({batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                      batch->mass_S0, V, status, ws, chi2, ctx->d_kin},
+                     ws_bytes);
     const jam_batch b = *batch;
     s = run_graph(ctx, p, 2, k, st, [&](hipStream_t cs) { record(&b, cs, true); });
     if (s != JAM_OK) return s;
@@ -1583,16 +1582,10 @@ jam_status jam_vjp_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms
   hipStream_t st = (hipStream_t)stream;
   char *w = (char *)ws;
   if (ctx->opt.graph) {
-    GraphKey k;
-    const void *ptrs[10] = {batch->inc, batch->mass_scale, batch->m_bh, batch->beta,
-                            batch->lum_I0, batch->mass_S0, vrms2, cot, ws, nullptr};
-    std::copy(ptrs, ptrs + 10, k.p);
-    k.ws_bytes = ws_bytes;
-    const void *gp[6] = {grads->inc, grads->mass_scale, grads->m_bh, grads->beta, grads->lum_I0,
-                         grads->mass_S0};
-    uintptr_t hsh = 0;
-    for (const void *q : gp) hsh = hsh * 1000003u ^ (uintptr_t)q;
-    k.p[9] = (const void *)hsh;
+    const GraphKey k({batch->inc, batch->mass_scale, batch->m_bh, batch->beta, batch->lum_I0,
+                      batch->mass_S0, vrms2, cot, ws, grads->inc, grads->mass_scale, grads->m_bh,
+                      grads->beta, grads->lum_I0, grads->mass_S0, ctx->d_kin},
+                     ws_bytes);
     const jam_batch b = *batch;
     const jam_grads g = *grads;
     s = run_graph(ctx, p, 3, k, st, [&](hipStream_t cs) {

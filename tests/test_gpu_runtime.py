@@ -119,6 +119,51 @@ def test_graph_replay_vjp_matches_eager():
     g.close()
 
 
+def test_graph_replay_vjp_alternating_gradient_buffers():
+    # The recorded adjoint writes into the gradient buffers it was recorded
+    # with; calls that alternate between buffer sets, including a set with
+    # two buffers swapped, must each fill exactly the buffers they pass.
+    dev = _dev()
+    n = 8
+    w = inputs.config5(n_models=n)
+    p = binding.pack_params(w, dev, amplitudes=True)
+    cot = torch.as_tensor(inputs.cotangent(w.geometries[0].n_bins, n).reshape(-1), device=dev)
+    eager = binding.Context(w.geometries, form=2)
+    V, _ = eager.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"],
+                            p["lum_I0"], p["mass_S0"])
+    ge = eager.vjp(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"], p["lum_I0"],
+                   p["mass_S0"], V, cot)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy() for k, v in ge.items()}
+    keys = ("inc", "mass_scale", "m_bh", "beta", "lum_I0", "mass_S0")
+    g = binding.Context(w.geometries, form=2, graph=1)
+    ws = g.workspace(w.geom_idx, True, dev)
+    s = torch.cuda.current_stream(dev).cuda_stream
+
+    def bufs():
+        return {k: torch.empty_like(ge[k]) for k in keys}
+
+    A, B = bufs(), bufs()
+    # set C: A's buffers with inc <-> mass_scale and beta <-> lum_I0 swapped
+    C = dict(A, inc=A["mass_scale"], mass_scale=A["inc"], beta=A["lum_I0"], lum_I0=A["beta"])
+    for rep in range(2):
+        for name, S in (("A", A), ("B", B), ("C", C), ("A", A)):
+            for t in list(A.values()) + list(B.values()):
+                t.fill_(float("nan"))
+            binding.jam_vjp(g.handle, w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"],
+                            p["beta"], p["lum_I0"], p["mass_S0"], V, cot, S["inc"],
+                            S["mass_scale"], S["m_bh"], S["beta"], S["lum_I0"], S["mass_S0"],
+                            ws, s)
+            torch.cuda.synchronize()
+            for k in keys:
+                assert np.array_equal(S[k].cpu().numpy(), ref[k]), (rep, name, k)
+            other = B if S is not B else A
+            for k in keys:
+                assert np.all(np.isnan(other[k].cpu().numpy())), (rep, name, k)
+    eager.close()
+    g.close()
+
+
 def test_autotuner_and_cache_file(tmp_path):
     dev = _dev()
     w = _uneven(n=16, seed=3)
