@@ -196,6 +196,22 @@ jam_status jam_eval_batch(jam_ctx *ctx, const jam_batch *batch, double *vrms2,
 jam_status jam_eval(jam_ctx *ctx, const jam_batch *one, double *vrms2,
                     int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and outputs as jam_eval_batch (vrms2, status
+ * as there), with the workspace taken from a fixed device array inside the
+ * library (64 MiB; each GPU the library runs on holds one copy until the
+ * process ends) instead of a caller's buffer.  It calls no allocating
+ * routine and records no graph: the composition must have been prepared on
+ * this context (jam_prepare or an earlier call that built it), else
+ * JAM_E_INVALID_ARG; a composition whose forward workspace
+ * (jam_workspace_size(..., 0)) exceeds 64 MiB gets JAM_E_WORKSPACE.  All
+ * calls on one GPU share the array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other contexts, other
+ * threads) race and must be serialised by the caller.                       */
+jam_status jam_eval_batch_noalloc(jam_ctx *ctx, const jam_batch *batch, double *vrms2,
+                                  int32_t *status, void *stream);
+
 /* Unconvolved sky maps on the padded sub-pixel grid of every model:
  * N = int rho_* v_los^2 dz' (numerator of eq. (VLos)) and I (eq.
  * (sb_mge_2D)), each DEVICE, nyp x nxp doubles per model, model after model,

@@ -34,7 +34,8 @@ EXPORTED = ("jam_create", "jam_destroy", "jam_batch_sizes", "jam_workspace_size"
             "jam_prepare", "jam_eval_batch", "jam_eval", "jam_eval_maps", "jam_vjp",
             "jam_gauss_legendre", "jam_timing", "jam_plan_info", "jam_last_error",
             "jam_set_kinematics", "jam_chi2", "jam_eval_chi2", "jam_vjp_chi2", "jam_mge1d",
-            "jam_mge1d_vjp", "jam_beta_logistic", "jam_beta_logistic_vjp")
+            "jam_mge1d_vjp", "jam_beta_logistic", "jam_beta_logistic_vjp",
+            "jam_eval_batch_noalloc")
 
 
 class JamGeometry(ctypes.Structure):
@@ -93,6 +94,8 @@ def load(path: str = LIB_PATH):
     for fn in (lib.jam_eval_batch, lib.jam_eval):
         fn.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p, c_void_p,
                        c_size_t, c_void_p]
+    lib.jam_eval_batch_noalloc.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p,
+                                           c_void_p, c_void_p]
     lib.jam_eval_maps.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]
     lib.jam_vjp.argtypes = [c_void_p, ctypes.POINTER(JamBatch), c_void_p, c_void_p,
@@ -237,6 +240,14 @@ def jam_eval(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
     b = _batch(gi, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
     _check(load().jam_eval(c_void_p(ctx), ctypes.byref(b), _ptr(vrms2), _ptr(status),
                            _ptr(ws), ws.numel() * ws.element_size(), c_void_p(stream)))
+
+
+def jam_eval_batch_noalloc(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,
+                           vrms2, status, stream: int):
+    gi = _idx(geom_idx)
+    b = _batch(gi, inc, mass_scale, m_bh, beta, lum_I0, mass_S0)
+    _check(load().jam_eval_batch_noalloc(c_void_p(ctx), ctypes.byref(b), _ptr(vrms2),
+                                         _ptr(status), c_void_p(stream)))
 
 
 def jam_eval_maps(ctx, geom_idx, inc, mass_scale, m_bh, beta, lum_I0, mass_S0,

@@ -20,6 +20,7 @@
 #include <list>
 #include <queue>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -355,6 +356,35 @@ struct KernelTimer {
   void end(hipStream_t st) { (void)hipEventRecord(stop[used++], st); }
 };
 
+// ---------------------------------------------------------------------------
+// Fixed scratch memory of jam_eval_batch_noalloc.  Each GPU the library runs
+// on holds its own copy of this array until the process ends.  In host code
+// its name is only a host-side stand-in: the device address is taken once
+// per device with hipGetSymbolAddress (at jam_create, with that device
+// current) and that address, never the name, is what host code passes on.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+jam_status scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(JAM_E_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return JAM_OK;
+}
+}  // namespace
+
 struct jam_ctx {
   int device = 0;
   int n_cu = 256;
@@ -368,6 +398,7 @@ struct jam_ctx {
   std::list<std::unique_ptr<Plan>> plans;   // most recent first
   KernelTimer t_num, t_sens;
   hipStream_t cap_stream = nullptr;         // graph capture only
+  void *scratch = nullptr;                  // device address of the fixed scratch array
   // observed kinematics per geometry (chi^2): one device buffer each holding
   // [vrms_obs | inverse covariance], and the device table of pointers
   std::vector<void *> kin_buf;
@@ -1023,6 +1054,13 @@ jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out
   return JAM_OK;
 }
 
+// A prepared plan of this composition, or NULL; builds nothing.
+Plan *find_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx) {
+  for (auto &pl : ctx->plans)
+    if (pl->n == n && std::equal(pl->key.begin(), pl->key.end(), geom_idx)) return pl.get();
+  return nullptr;
+}
+
 // Switch to the context's device for the duration of a call.
 struct DeviceGuard {
   int prev = -1;
@@ -1257,6 +1295,10 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
   ctx->occ_num_pix = jam::occupancy_num(false);
   ctx->occ_num_mfma = jam::occupancy_num(true);
   ctx->occ_sens = jam::occupancy_sens();
+  {
+    const jam_status s = scratch_address(ctx->device, &ctx->scratch);
+    if (s != JAM_OK) return s;
+  }
   load_tune_file(ctx.get());
   ctx->gh.resize(n_geom);
   {
@@ -1414,6 +1456,29 @@ jam_status jam_eval(jam_ctx *ctx, const jam_batch *one, double *vrms2, int32_t *
                     size_t ws_bytes, void *stream) {
   if (one && one->n != 1) return fail(JAM_E_INVALID_ARG, "jam_eval takes exactly one model");
   return jam_eval_batch(ctx, one, vrms2, status, ws, ws_bytes, stream);
+}
+
+jam_status jam_eval_batch_noalloc(jam_ctx *ctx, const jam_batch *batch, double *vrms2,
+                                  int32_t *status, void *stream) {
+  if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
+  jam_status s = check_batch(batch);
+  if (s != JAM_OK) return s;
+  if (!vrms2) return fail(JAM_E_INVALID_ARG, "vrms2 is NULL");
+  if (batch->n < 1 || !batch->geom_idx) return fail(JAM_E_INVALID_ARG, "invalid batch");
+  if (!ctx->scratch) return fail(JAM_E_DEVICE, "fixed scratch memory is not available");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(JAM_E_DEVICE, "cannot select the context's device");
+  Plan *p = find_plan(ctx, batch->n, batch->geom_idx);
+  if (!p)
+    return fail(JAM_E_INVALID_ARG,
+                "batch composition not prepared: call jam_prepare (which allocates) first");
+  if (p->ws_fwd > kScratchBytes)
+    return fail(JAM_E_WORKSPACE, "composition needs %zu bytes of workspace, above the %zu bytes "
+                "of fixed scratch", p->ws_fwd, kScratchBytes);
+  // eager launches only (instantiating a graph allocates); no timing events
+  launch_eval(ctx, p, batch, vrms2, status, (char *)ctx->scratch, (hipStream_t)stream, true);
+  HIP_TRY(hipGetLastError());
+  return JAM_OK;
 }
 
 jam_status jam_eval_maps(jam_ctx *ctx, const jam_batch *batch, double *N_map, double *I_map,

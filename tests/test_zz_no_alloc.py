@@ -1,0 +1,93 @@
+"""The allocation-free forward entry point, jam_eval_batch_noalloc, called
+through the C ABI: its v_rms^2 and status must equal those of
+jam_eval_batch (same kernels and plan, caller-owned workspace) bitwise, on
+two calls in a row, the second with a smaller batch; unprepared and
+oversized compositions are refused on the host before any launch."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_01302_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+JAM_E_INVALID_ARG = 1
+JAM_E_WORKSPACE = 4
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _mixed(n, seed):
+    """Models on the small proposal geometry and two hand-sized geometries."""
+    base = inputs.config3(n_models=n, seed=seed)
+    gs = [base.geometries[0],
+          inputs.small_geometry(seed=71, n_lum=4, n_mass=3, nx=23, ny=17, ss=2, psf_n=3,
+                                n_bins=5, n_u=24, pixsize=0.04),
+          inputs.small_geometry(seed=72, n_lum=2, n_mass=5, nx=40, ny=40, ss=1, psf_n=5,
+                                n_bins=9, n_u=40, pixsize=0.05)]
+    gi = np.array([m % 3 for m in range(n)], dtype=np.int32)
+    ps = [base.params[m] if gi[m] == 0 else inputs.small_params(gs[gi[m]], seed=500 + seed + m)
+          for m in range(n)]
+    return inputs.Workload("mixed", gs, gi, ps)
+
+
+def _compare(ctx, w, dev, stream):
+    p = binding.pack_params(w, dev, amplitudes=True)
+    nb, _, _ = ctx.sizes(w.geom_idx)
+    n = len(w.geom_idx)
+    binding.jam_prepare(ctx.handle, w.geom_idx)
+    ref, st_ref = ctx.eval_batch(w.geom_idx, p["inc"], p["mass_scale"], p["m_bh"], p["beta"],
+                                 p["lum_I0"], p["mass_S0"])
+    V = torch.full((nb,), float("nan"), dtype=torch.float64, device=dev)
+    st = torch.full((n,), -7, dtype=torch.int32, device=dev)
+    binding.jam_eval_batch_noalloc(ctx.handle, w.geom_idx, p["inc"], p["mass_scale"],
+                                   p["m_bh"], p["beta"], p["lum_I0"], p["mass_S0"], V, st,
+                                   stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), st_ref.cpu().numpy())
+    assert np.all(st.cpu().numpy() == 0)
+    a, b = V.cpu().numpy(), ref.cpu().numpy()
+    assert np.all(np.isfinite(a)) and np.array_equal(a, b)
+    return a
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_noalloc_matches_eval_batch_twice_second_smaller(form):
+    dev = _dev()
+    big, small = _mixed(12, seed=1), _mixed(5, seed=2)
+    ctx = binding.Context(big.geometries, form=form)
+    s = torch.cuda.current_stream(dev).cuda_stream
+    _compare(ctx, big, dev, s)
+    _compare(ctx, small, dev, s)
+    # the first composition again, after the smaller call left its contents
+    _compare(ctx, big, dev, s)
+    ctx.close()
+
+
+def test_noalloc_refuses_unprepared_and_oversized():
+    dev = _dev()
+    w = inputs.config3(n_models=6)
+    ctx = binding.Context(w.geometries)
+    p = binding.pack_params(w, dev)
+    V = torch.empty(6 * w.geometries[0].n_bins, dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream(dev).cuda_stream
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_eval_batch_noalloc(ctx.handle, w.geom_idx, p["inc"], p["mass_scale"],
+                                       p["m_bh"], p["beta"], None, None, V, None, s)
+    assert e.value.status == JAM_E_INVALID_ARG
+    # 512 proposals need more than the fixed scratch (their term tables alone
+    # are 512 x 13,000 x 16 bytes)
+    big = inputs.config3(n_models=512)
+    binding.jam_prepare(ctx.handle, big.geom_idx)
+    assert binding.jam_workspace_size(ctx.handle, big.geom_idx, False) > 64 << 20
+    pb = binding.pack_params(big, dev)
+    Vb = torch.empty(512 * big.geometries[0].n_bins, dtype=torch.float64, device=dev)
+    with pytest.raises(binding.JamError) as e:
+        binding.jam_eval_batch_noalloc(ctx.handle, big.geom_idx, pb["inc"], pb["mass_scale"],
+                                       pb["m_bh"], pb["beta"], None, None, Vb, None, s)
+    assert e.value.status == JAM_E_WORKSPACE
+    ctx.close()
