@@ -55,6 +55,9 @@ def _args():
                          "1024 uneven models), reported under 'extra'")
     ap.add_argument("--extra", default="",
                     help="comma-separated names of the extra workloads to run (default all)")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="run only the extra workloads (for profiling one of them); the "
+                         "JSON line then carries no headline value")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy three times, the reference "
                          "kernel for scaling the HBM byte counters of a profile")
@@ -359,6 +362,40 @@ def time_mge_pipeline(torch, binding, dev, steps, n=4096):
             "proposals_per_s": n * 1000.0 / ms_pipe, "all_finite": ok}
 
 
+def run_extras(a, torch, binding, inputs, dev, w1):
+    """The extra workloads named by --extra (default all), each timed on its own."""
+    g, p = w1.geometries[0], w1.params[0]
+    k = max(3, a.steps // 4)
+    extras = {
+        "batched_4096_small": lambda: time_batch(torch, binding, inputs.config3(4096), dev,
+                                                 k, a.form, a.launch, a.graph),
+        "ifu_scale_batch_8": lambda: time_batch(
+            torch, binding, inputs.Workload("cfg2x8", [g], np.zeros(8, np.int32), [p] * 8),
+            dev, k, a.form, a.launch, a.graph),
+        "uneven_1024": lambda: time_batch(torch, binding, inputs.config4(1024), dev, 2,
+                                          a.form, a.launch, a.graph),
+        "uneven_1024_autotuned_graph": lambda: time_batch(
+            torch, binding, inputs.config4(1024), dev, 2, 0, 0, 1, autotune=1),
+        "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,
+                                             a.form, a.launch, a.graph),
+        "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
+        "beta_profile_chi2_4096_small": lambda: time_beta_profile(
+            torch, binding, inputs.config3(4096), dev, k),
+        "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
+        "cylindrical_composite_42x95": lambda: time_batch(
+            torch, binding, inputs.config_composite(), dev, k, a.form, a.launch, a.graph),
+        "spherical_composite_42x95": lambda: time_spherical(
+            torch, binding, inputs.config_composite(), dev, max(2, k // 2)),
+        "spherical_1024_small": lambda: time_spherical(torch, binding, inputs.config3(1024),
+                                                       dev, max(2, k // 2)),
+    }
+    names = [x for x in a.extra.split(",") if x] or list(extras)
+    unknown = [x for x in names if x not in extras]
+    if unknown:
+        sys.exit(f"unknown extra workload(s) {unknown}; known: {list(extras)}")
+    return {x: extras[x]() for x in names}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -372,6 +409,10 @@ def main():
     dev = torch.device("cuda:0")
     w1 = inputs.config2(seed=0)
     g, p = w1.geometries[0], w1.params[0]
+    if a.only_extra:
+        rec = {"extra": run_extras(a, torch, binding, inputs, dev, w1)}
+        print(json.dumps(rec), flush=True)
+        return
     n = a.batch
     w = inputs.Workload("cfg2", [g], np.zeros(n, np.int32), [p] * n)
     ctx = binding.Context([g], form=a.form, launch=a.launch, graph=a.graph, autotune=a.autotune)
@@ -516,35 +557,7 @@ def main():
         "plain_per_model_forward": plain,
     }
     if not a.no_extra:
-        k = max(3, a.steps // 4)
-        extras = {
-            "batched_4096_small": lambda: time_batch(torch, binding, inputs.config3(4096), dev,
-                                                     k, a.form, a.launch, a.graph),
-            "ifu_scale_batch_8": lambda: time_batch(
-                torch, binding, inputs.Workload("cfg2x8", [g], np.zeros(8, np.int32), [p] * 8),
-                dev, k, a.form, a.launch, a.graph),
-            "uneven_1024": lambda: time_batch(torch, binding, inputs.config4(1024), dev, 2,
-                                              a.form, a.launch, a.graph),
-            "uneven_1024_autotuned_graph": lambda: time_batch(
-                torch, binding, inputs.config4(1024), dev, 2, 0, 0, 1, autotune=1),
-            "chi2_4096_small": lambda: time_chi2(torch, binding, inputs.config3(4096), dev, k,
-                                                 a.form, a.launch, a.graph),
-            "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
-            "beta_profile_chi2_4096_small": lambda: time_beta_profile(
-                torch, binding, inputs.config3(4096), dev, k),
-            "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
-            "cylindrical_composite_42x95": lambda: time_batch(
-                torch, binding, inputs.config_composite(), dev, k, a.form, a.launch, a.graph),
-            "spherical_composite_42x95": lambda: time_spherical(
-                torch, binding, inputs.config_composite(), dev, max(2, k // 2)),
-            "spherical_1024_small": lambda: time_spherical(torch, binding, inputs.config3(1024),
-                                                           dev, max(2, k // 2)),
-        }
-        names = [x for x in a.extra.split(",") if x] or list(extras)
-        unknown = [x for x in names if x not in extras]
-        if unknown:
-            sys.exit(f"unknown extra workload(s) {unknown}; known: {list(extras)}")
-        rec["extra"] = {x: extras[x]() for x in names}
+        rec["extra"] = run_extras(a, torch, binding, inputs, dev, w1)
     if a.copy_calibration:
         src = torch.ones(32 << 20, dtype=torch.float64, device=dev)     # 256 MiB
         dst = torch.empty_like(src)

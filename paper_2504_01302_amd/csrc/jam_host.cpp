@@ -93,6 +93,7 @@ struct GeomHost {
   std::vector<int> ux, uy;
   std::vector<int> bin_ptr, bin_pix, pix_ptr, pix_bin;
   std::vector<double> bin_w, pix_w;
+  int max_bin_nnz = 0;   // largest number of weights of one bin
   // spherically aligned model: polar table radii and the 8-node rule
   double sph_lnr0 = 0, sph_dlnr = 0, sph_sig_max = 0;
   double gl8_x[8] = {}, gl8_w[8] = {};
@@ -133,6 +134,16 @@ jam_status validate(const jam_geometry &g, int gi) {
   const int64_t nsub_x = (int64_t)g.nx * g.supersample + g.psf_n - 1;
   const int64_t nsub_y = (int64_t)g.ny * g.supersample + g.psf_n - 1;
   if (nsub_x > 16384 || nsub_y > 16384) return bad("padded sub-pixel grid larger than 16384");
+  // term counts and the weight matrix's nonzeros are indexed with 32-bit
+  // integers on the device
+  const int64_t T = (int64_t)g.n_lum * (g.n_mass + 1) * g.n_u;
+  const int64_t T_sph = ((int64_t)(g.n_mass + 1) * g.n_u + 63) / 64 * 64;
+  if (T > INT32_MAX || T_sph > INT32_MAX)
+    return fail(JAM_E_UNSUPPORTED, "geometry %d: %lld terms exceed the supported 2^31 - 1", gi,
+                (long long)std::max(T, T_sph));
+  const int64_t nnz_max = (int64_t)g.nx * g.supersample * g.ny * g.supersample * g.psf_n * g.psf_n;
+  if (nnz_max > INT32_MAX)
+    return fail(JAM_E_UNSUPPORTED, "geometry %d: field sub-pixels x PSF taps exceed 2^31 - 1", gi);
   std::vector<int> cnt(g.n_bins, 0);
   for (int64_t i = 0; i < (int64_t)g.nx * g.ny; ++i) {
     const int b = g.bin_index[i];
@@ -202,31 +213,51 @@ void build_geometry(const jam_geometry &g, GeomHost &o) {
   // W[b, p]: the convolved map at field sub-pixel f is
   //   C(f) = sum_o psf[o + h] M(f - o),
   // so bin b's sum of C weights padded sub-pixel (f + h - o) by psf[o + h].
-  std::vector<double> dense((size_t)o.n_bins * o.n_pix, 0.0);
-  const int n = o.psf_n;
-  for (int fy = 0; fy < ssy; ++fy) {
+  // Built one bin at a time in a dense scratch row (memory O(n_pix + nnz));
+  // each weight accumulates its field sub-pixels in raster order.
+  std::vector<std::vector<int>> fields(o.n_bins);
+  for (int fy = 0; fy < ssy; ++fy)
     for (int fx = 0; fx < ssx; ++fx) {
       const int b = g.bin_index[(fy / o.ss) * o.nx + fx / o.ss];
-      if (b < 0) continue;
-      double *row = dense.data() + (size_t)b * o.n_pix;
+      if (b >= 0) fields[b].push_back(fy * ssx + fx);
+    }
+  const int n = o.psf_n;
+  std::vector<double> row(o.n_pix, 0.0);
+  std::vector<char> hit(o.n_pix, 0);
+  std::vector<int> touched;
+  o.bin_ptr.assign(o.n_bins + 1, 0);
+  std::vector<int> pcount(o.n_pix, 0);
+  o.max_bin_nnz = 0;
+  for (int b = 0; b < o.n_bins; ++b) {
+    touched.clear();
+    for (int f : fields[b]) {
+      const int fy = f / ssx, fx = f % ssx;
       for (int oy = -o.h; oy <= o.h; ++oy) {
         const int iy = o.uy[fy + o.h - oy] * o.n_ux;
         const double *kr = g.psf + (oy + o.h) * n;
-        for (int ox = -o.h; ox <= o.h; ++ox) row[iy + o.ux[fx + o.h - ox]] += kr[ox + o.h];
+        for (int ox = -o.h; ox <= o.h; ++ox) {
+          const int q = iy + o.ux[fx + o.h - ox];
+          if (!hit[q]) {
+            hit[q] = 1;
+            touched.push_back(q);
+          }
+          row[q] += kr[ox + o.h];
+        }
       }
     }
-  }
-  o.bin_ptr.assign(o.n_bins + 1, 0);
-  std::vector<int> pcount(o.n_pix, 0);
-  for (int b = 0; b < o.n_bins; ++b) {
-    const double *row = dense.data() + (size_t)b * o.n_pix;
-    for (int p = 0; p < o.n_pix; ++p)
-      if (row[p] != 0.0) {
-        o.bin_pix.push_back(p);
-        o.bin_w.push_back(row[p]);
-        pcount[p]++;
+    std::sort(touched.begin(), touched.end());
+    for (int q : touched) {
+      if (row[q] != 0.0) {
+        o.bin_pix.push_back(q);
+        o.bin_w.push_back(row[q]);
+        pcount[q]++;
       }
+      row[q] = 0.0;
+      hit[q] = 0;
+    }
     o.bin_ptr[b + 1] = (int)o.bin_pix.size();
+    o.max_bin_nnz = std::max(o.max_bin_nnz, o.bin_ptr[b + 1] - o.bin_ptr[b]);
+    std::vector<int>().swap(fields[b]);
   }
   o.pix_ptr.assign(o.n_pix + 1, 0);
   for (int p = 0; p < o.n_pix; ++p) o.pix_ptr[p + 1] = o.pix_ptr[p] + pcount[p];
@@ -313,9 +344,9 @@ struct Plan {
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
-            *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr;
+            *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0;
+      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0;
   bool spherical = false;
   bool fused_prologue = true;
   int grid_num = 1, grid_sens = 1;
@@ -423,6 +454,13 @@ constexpr size_t kMaxPlans = 8;
 // launch (each term block recomputes its (k, j) pairs' set-up, which costs
 // latency per block but saves two launches).
 constexpr int kFusedPrologueModels = 32;
+// Unique-pixel maps with at most this many distinct |x'| and |y'| (one 32x32
+// matrix-core block) take the small-map form: terms computed in place by the
+// numerator, sensitivities and chain fused in the adjoint.
+constexpr int kSmallMap = 32;
+// Geometries whose bins have at most this many weights each sum every bin
+// with one wave (16 bins per workgroup) instead of a whole workgroup.
+constexpr int kBinWaveNnz = 2048;
 
 // Numerator variant and term-range split of one model under a schedule.
 // `gran` is the slice length in units: (k, j) pairs for the per-pixel
@@ -436,6 +474,7 @@ struct WaveTile {
 
 struct NumChoice {
   int kind;      // 0 per-pixel VALU, 2 matrix-core wave tiles
+  bool gen = false;   // matrix core on a map of one 32x32 block, terms computed in place
   int n_slices;
   int units;     // slice units of the whole term range
   std::vector<WaveTile> tiles;   // matrix core
@@ -469,6 +508,7 @@ NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
   const int chunks = (g.T + 63) / 64;
   const int per = std::max(4, gran);
   c.kind = 2;
+  c.gen = g.n_ux <= kSmallMap && g.n_uy <= kSmallMap;
   c.n_slices = std::max(1, (chunks + per - 1) / per);
   c.units = chunks;
   for (const auto &ty : axis_tiles(g.n_uy, t.tau))
@@ -495,7 +535,9 @@ double num_item_cost(const GeomHost &g, const NumChoice &c, int slice, int tile)
   // (dependent descriptor and coordinate loads, first chunk), the four-wave
   // sum and the tile store
   const WaveTile &w = c.tiles[tile];
-  return ((cnt + 3) / 4) * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY)) + 8.0;
+  // terms computed in place: their FP64 set-up per chunk
+  const double gen = c.gen ? 0.5 : 0.0;
+  return ((cnt + 3) / 4) * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY) + gen) + 8.0;
 }
 
 // Completion time of the numerator launch as modelled: every resident
@@ -594,7 +636,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro;
+      it_red, it_sph, it_pro, it_adj;
   std::vector<double> c_num, c_sens;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
@@ -609,8 +651,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     d.out_off = (int)p->total_bins;
     const NumChoice nc = choose_numerator(g, tune, tune.gran);
     d.n_slices = nc.n_slices;
-    d.form = nc.kind == 0 ? 1 : 2;
-    d.n_sens_parts = d.form == 1 ? 1 : (g.n_ux + 31) / 32;
+    const bool small = !spherical && nc.gen;
+    d.form = nc.kind == 0 ? 1 : (small ? 3 : 2);
+    d.n_sens_parts = d.form == 1 ? 1 : (small ? 0 : (g.n_ux + 31) / 32);
     d.n_xt = (g.n_ux + 31) / 32;
     d.n_yt = (g.n_uy + 31) / 32;
     d.gauss_off = gauss;
@@ -629,7 +672,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     }
     gauss += jam::gauss_size(g.K, g.J1);
     const int tsph = jam::sph_terms_padded(g.J1, g.n_u);
-    terms += spherical ? tsph + tsph / 4 : g.T;   // spherical: float4 terms, then floats
+    // spherical: float4 terms, then floats; small maps compute their terms in place
+    terms += spherical ? tsph + tsph / 4 : (small ? 0 : g.T);
     pixd += 4 * (int64_t)g.n_pix;
     part += (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);   // padded to whole blocks
     bins += 2 * (int64_t)g.n_bins;
@@ -643,14 +687,23 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     p->total_mass += g.J;
     p->total_bins += g.n_bins;
     p->total_map += (int64_t)g.nxp * g.nyp;
-    for (int tb = 0; tb < ((spherical ? tsph : g.T) + 255) / 256; ++tb)
-      it_terms.push_back({m, tb, 0, 0});
+    if (!small)
+      for (int tb = 0; tb < ((spherical ? tsph : g.T) + 255) / 256; ++tb)
+        it_terms.push_back({m, tb, 0, 0});
     if (spherical) {
       for (int tt = 0; tt < (tsph + 255) / 256; ++tt)
         for (int r = 0; r < d.n_sens_parts; ++r) {
           it_sens.push_back({m, tt, r, 0});
           c_sens.push_back((double)jam::sph_range_len(g.K, d.n_sens_parts));
         }
+    } else if (small) {
+      // fused sensitivities + chain: items of whole (k, j) groups of u-nodes
+      const int cap = std::max(1, std::min(64, jam::kSmallAdjTerms / g.n_u));
+      const int groups = (g.J1 + cap - 1) / cap;
+      const int cnt = (g.J1 + groups - 1) / groups;
+      for (int k = 0; k < g.K; ++k)
+        for (int j0 = 0; j0 < g.J1; j0 += cnt)
+          it_adj.push_back({m, k, j0 | (std::min(cnt, g.J1 - j0) << 16), 0});
     } else if (d.form == 1) {
       for (int tb = 0; tb < (g.T + 255) / 256; ++tb) {
         it_sens.push_back({m, tb, 0, 0});
@@ -673,13 +726,17 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
           it_num.push_back({m, tl, s, 0});
         } else {
           const WaveTile &w = nc.tiles[tl];
-          it_num.push_back({m, w.bx | (w.by << 16), s, 2 + (w.BX - 1) + 2 * (w.BY - 1)});
+          it_num.push_back({m, w.bx | (w.by << 16), s,
+                            small ? 6 : 2 + (w.BX - 1) + 2 * (w.BY - 1)});
         }
         c_num.push_back(num_item_cost(g, nc, s, tl));
       }
-    for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
+    if (g.max_bin_nnz <= kBinWaveNnz)
+      for (int b = 0; b < g.n_bins; b += 16) it_bins.push_back({m, b, 0, 1});
+    else
+      for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
-    if (!spherical)
+    if (!spherical && !small)
       for (int k = 0; k < g.K; ++k)
         for (int jb = 0; jb < (g.J1 + 3) / 4; ++jb) it_chain.push_back({m, k, jb, 0});
   }
@@ -695,10 +752,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   for (const jam::Item &t : it_sb) it_pro.push_back({t.m, t.a, t.b, 2});
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 11;
+  constexpr int kLists = 12;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
-                                           &it_red,   &it_sph, &it_pro};
+                                           &it_red,   &it_sph, &it_pro, &it_adj};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -721,10 +778,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->d_models = (jam::ModelDev *)(base + o_models);
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
-                            &p->d_red,   &p->d_sph,   &p->d_pro};
+                            &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
-                      &p->n_red,   &p->n_sph,   &p->n_pro};
+                      &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -797,7 +854,7 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   }
   if (need_numerator) {
     const bool timed = ctx->t_num.begin(st, capturing);
-    jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
+    jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, gauss, st_ws, part,
                     p->tune.launch == 1 ? queue : nullptr, p->grid_num, p->tune.rule == 1, st);
     if (timed) ctx->t_num.end(st);
     jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_red, p->n_red, part, pix, st);
@@ -871,11 +928,15 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     return;
   }
   const bool timed = ctx->t_sens.begin(st, capturing);
-  jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
-                   (const float4 *)(w + p->off_terms), pix, st_ws, sens,
-                   p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
+  if (p->n_sens)
+    jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
+                     (const float4 *)(w + p->off_terms), pix, st_ws, sens,
+                     p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
+  if (p->n_adj)
+    jam::launch_adj_small(ctx->d_geoms, p->d_models, p->d_adj, p->n_adj, pd, pix, st_ws, sens, st);
   if (timed) ctx->t_sens.end(st);
-  jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, sens, st_ws, st);
+  if (p->n_chain)
+    jam::launch_chain(ctx->d_geoms, p->d_models, p->d_chain, p->n_chain, pd, sens, st_ws, st);
   jam::launch_grads(ctx->d_geoms, p->d_models, p->n, pd, sens, sbp, st_ws, gd, st);
 }
 
@@ -989,7 +1050,8 @@ jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best
       launch_forward_maps(ctx, p, pd, nullptr, w, st, false, true);
       (void)hipEventRecord(e0, st);
       jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
-                      (const float4 *)(w + p->off_terms), (const int *)(w + p->off_status),
+                      (const float4 *)(w + p->off_terms), (const double *)(w + p->off_gauss),
+                      (const int *)(w + p->off_status),
                       (double *)(w + p->off_part), p->tune.launch == 1 ? (int *)(w + p->off_queue) : nullptr,
                       p->grid_num, p->tune.rule == 1, st);
       (void)hipEventRecord(e1, st);
@@ -1011,7 +1073,7 @@ jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best
   return JAM_OK;
 }
 
-jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
+jam_status get_plan_impl(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   if (n < 1) return fail(JAM_E_INVALID_ARG, "batch size must be >= 1");
   if (!geom_idx) return fail(JAM_E_INVALID_ARG, "geom_idx is NULL");
@@ -1052,6 +1114,18 @@ jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out
   ctx->plans.push_front(std::move(p));
   while (ctx->plans.size() > kMaxPlans) ctx->plans.pop_back();
   return JAM_OK;
+}
+
+// The plan of a batch composition, built (and autotuned) at its first use;
+// host memory exhaustion while building it is returned as a status.
+jam_status get_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Plan *&out) {
+  try {
+    return get_plan_impl(ctx, n, geom_idx, out);
+  } catch (const std::bad_alloc &) {
+    return fail(JAM_E_UNSUPPORTED, "host memory exhausted while preparing a batch of %d", n);
+  } catch (...) {
+    return fail(JAM_E_UNSUPPORTED, "unexpected host error while preparing a batch of %d", n);
+  }
 }
 
 // A prepared plan of this composition, or NULL; builds nothing.
@@ -1304,14 +1378,24 @@ jam_status jam_create(int32_t n_geom, const jam_geometry *geoms, const jam_optio
   {
     const unsigned nt = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
+    std::vector<int> failed(nt, -1);
     for (unsigned t = 0; t < nt; ++t)
       pool.emplace_back([&, t] {
         for (int i = (int)t; i < n_geom; i += (int)nt) {
-          build_geometry(geoms[i], ctx->gh[i]);
-          build_spherical(ctx->gh[i]);
+          try {
+            build_geometry(geoms[i], ctx->gh[i]);
+            build_spherical(ctx->gh[i]);
+          } catch (...) {   // out of host memory: reported below, never past the thread
+            failed[t] = i;
+            return;
+          }
         }
       });
     for (auto &th : pool) th.join();
+    for (unsigned t = 0; t < nt; ++t)
+      if (failed[t] >= 0)
+        return fail(JAM_E_UNSUPPORTED, "geometry %d: host memory exhausted while building it",
+                    failed[t]);
   }
   // device arena: GeomDev array then every geometry's arrays
   size_t off = align256(sizeof(jam::GeomDev) * n_geom);
@@ -1533,8 +1617,8 @@ jam_status jam_vjp(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, co
   return JAM_OK;
 }
 
-jam_status jam_set_kinematics(jam_ctx *ctx, int32_t geom, const double *vrms_obs,
-                              const double *cov) {
+static jam_status set_kinematics_impl(jam_ctx *ctx, int32_t geom, const double *vrms_obs,
+                                      const double *cov) {
   if (!ctx) return fail(JAM_E_INVALID_ARG, "ctx is NULL");
   if (geom < 0 || geom >= (int)ctx->gh.size()) return fail(JAM_E_INVALID_ARG, "geometry %d out of range", geom);
   if (!vrms_obs || !cov) return fail(JAM_E_INVALID_ARG, "vrms_obs and cov are required");
@@ -1578,6 +1662,15 @@ jam_status jam_set_kinematics(jam_ctx *ctx, int32_t geom, const double *vrms_obs
   ctx->kin_buf[geom] = buf;
   ctx->kin_host[geom] = kd;
   return JAM_OK;
+}
+
+jam_status jam_set_kinematics(jam_ctx *ctx, int32_t geom, const double *vrms_obs,
+                              const double *cov) {
+  try {
+    return set_kinematics_impl(ctx, geom, vrms_obs, cov);
+  } catch (...) {
+    return fail(JAM_E_UNSUPPORTED, "host memory exhausted while setting the kinematics");
+  }
 }
 
 jam_status jam_chi2(jam_ctx *ctx, const jam_batch *batch, const double *vrms2, double *chi2,
@@ -1733,8 +1826,8 @@ jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32
   info[3] = p->tune.launch;
   info[4] = p->n_num;
   info[5] = p->grid_num;
-  info[6] = p->n_sens;
-  info[7] = p->grid_sens;
+  info[6] = p->n_sens + p->n_adj;
+  info[7] = (p->n_sens ? p->grid_sens : 0) + p->n_adj;
   return JAM_OK;
 }
 

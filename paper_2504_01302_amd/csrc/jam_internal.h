@@ -61,7 +61,8 @@ struct ModelDev {
   int n_slices;      // split of the term range in the numerator kernels
   int n_xt, n_yt;    // 32x32 blocks covering the unique-pixel map (partial maps are
                      // stored padded to 32 n_xt x 32 n_yt per slice)
-  int form;          // 1 per-pixel VALU, 2 separable MFMA
+  int form;          // 1 per-pixel VALU, 2 separable MFMA, 3 separable MFMA on a map of
+                     // one 32x32 block with terms computed in place (no term table)
   int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
   int pad;
   int64_t gauss_off; // doubles, per-Gaussian derived quantities
@@ -146,12 +147,14 @@ void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, Pa
 // Numerator over a work list of workgroup items.  mfma = false: per-pixel
 // VALU form, items (m, 64-pixel block, slice).  mfma = true: matrix-core
 // form, items (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 =
-// tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32).  queue != NULL:
-// persistent grid of `grid` workgroups pulling items from the counter; else
-// `grid` workgroups striding over the list.
+// tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32; variant 6 = a map of
+// one 32x32 block whose terms are computed from the Gaussian table `gauss`
+// instead of read from `terms`).  queue != NULL: persistent grid of `grid`
+// workgroups pulling items from the counter; else `grid` workgroups striding
+// over the list.
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
-                bool mfma, hipStream_t st);
+                const float4 *terms, const double *gauss, const int *st_ws, double *part,
+                int *queue, int grid, bool mfma, hipStream_t st);
 int occupancy_num(bool mfma);   // resident numerator workgroups per CU
 int occupancy_sens();   // resident sensitivity workgroups per CU
 // Items (m, 64-pixel block).
@@ -178,6 +181,13 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // (m, x tile, 256-term tile)).
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   double *sens, const int *st_ws, hipStream_t st);
+// Small-map models (unique-pixel map within one 32x32 block): sensitivities
+// and chain in one pass, items (m, k, first mass Gaussian | count << 16),
+// count * n_u <= 1024, count <= 64; writes the chain rows (the model has no
+// partial sensitivity blocks, n_sens_parts = 0).
+constexpr int kSmallAdjTerms = 1024;
+void launch_adj_small(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+                      const double *pix, const int *st_ws, double *sens, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,
                   const double *sbp, const int *st_ws, GradsDev out, hipStream_t st);
 // Spherically aligned model.  Terms: items (m, block of 256 terms), the

@@ -201,24 +201,58 @@ __global__ void __launch_bounds__(256) k_sb_adj(const GeomDev *__restrict__ geom
 // Term table: FP64 coefficients of every (k, j, n) term, stored as FP32
 // (-c1 log2e, -gamma log2e, C0, C1).  Term t = (k * J1 + j) * n_u + n.
 // ---------------------------------------------------------------------------
+// FP64 reciprocal and reciprocal square root: the hardware approximations
+// refined by two Newton steps (a few FP64 ulp; the coefficients they feed are
+// stored as FP32).  Arguments are positive and finite.
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+constexpr double kSqrtPi = 1.77245385090551602730;
+
 __device__ inline void term_coeffs(double alpha, double alphaq, double nu0, double b, double r,
                                    double e2, double Kp, double si2, double ci2, double u,
                                    double wq, double &c1, double &gam, double &C0, double &C1) {
   const double u2 = u * u;
-  const double h = 1.0 - e2 * u2;
-  c1 = alpha + r * u2;
-  const double A = alphaq + r * u2 / h;
-  const double a = c1 * si2 + A * ci2;
-  gam = c1 * A / a;
-  const double base = nu0 * Kp * r * u2;
-  const double sh = sqrt(h);
-  const double gg = base / (A * h * sh);
-  const double ww = 2.0 * base / sh;
+  const double h = fma(-e2, u2, 1.0);
+  const double ru2 = r * u2;
+  c1 = alpha + ru2;
+  const double rh = rcp64(h);
+  const double A = fma(ru2, rh, alphaq);
+  const double a = fma(c1, si2, A * ci2);
+  gam = c1 * A * rcp64(a);
+  const double base = nu0 * Kp * ru2;
+  const double rsh = rsq64(h);
+  const double gg = base * rcp64(A) * rh * rsh;
+  const double ww = 2.0 * base * rsh;
   const double P = (ci2 + b * si2) * gg;
   const double Q = si2 * (ww - 2.0 * c1 * b * gg);
-  const double f = wq * sqrt(kPi / a);
+  const double f = wq * kSqrtPi * rsq64(a);
   C0 = f * P;
   C1 = f * Q;
+}
+
+// Term t = (k * J1 + j) * n_u + n of a model from its Gaussian table (the
+// set-up's output), as the term table stores it.
+__device__ inline float4 term_of(const GeomDev &g, const double *__restrict__ tab, int t) {
+  const int n = t % g.n_u, kj = t / g.n_u;
+  const int j = kj % g.J1, k = kj / g.J1;
+  const double *mt = tab + 4 * g.K;
+  double c1, gam, C0, C1;
+  term_coeffs(tab[k], tab[g.K + k], tab[2 * g.K + k], tab[3 * g.K + k], mt[j], mt[g.J1 + j],
+              mt[2 * g.J1 + j], mt[3 * g.J1], mt[3 * g.J1 + 1], g.u[n], g.w[n], c1, gam, C0, C1);
+  return make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
 }
 
 
@@ -358,21 +392,9 @@ __global__ void __launch_bounds__(256) k_prologue(const GeomDev *__restrict__ ge
     }
     if (!kFused) {                   // kind 3
       const int t = it.a * 256 + threadIdx.x;
-      if (t < g.T) {
-        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (st_ws[it.m] == 0) {
-          const int n = t % g.n_u;
-          const int kj = t / g.n_u;
-          const int j = kj % g.J1, k = kj / g.J1;
-          const double *tab = gauss + md.gauss_off, *mt = tab + 4 * g.K;
-          double c1, gam, C0, C1;
-          term_coeffs(tab[k], tab[g.K + k], tab[2 * g.K + k], tab[3 * g.K + k], mt[j],
-                      mt[g.J1 + j], mt[2 * g.J1 + j], mt[3 * g.J1], mt[3 * g.J1 + 1], g.u[n],
-                      g.w[n], c1, gam, C0, C1);
-          out = make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
-        }
-        terms[md.term_off + t] = out;
-      }
+      if (t < g.T)
+        terms[md.term_off + t] = st_ws[it.m] == 0 ? term_of(g, gauss + md.gauss_off, t)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     // kind 1: the (k, j) pairs of this block's 256 terms, once each, then
@@ -486,10 +508,14 @@ __device__ inline void slice_range(int T, int n_slices, int slice, int &t0, int 
 // in a fixed order and wave 0 writes the slice's partial tile.
 // Item (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 for
 // (BX, BY) = (1,1), (2,1), (1,2), (2,2)); slices are whole 64-term chunks.
-template <int BX, int BY>
+// With kGen (variant 6, maps of one 32x32 block, whose terms feed a single
+// tile) each lane computes its term of the next chunk from the model's
+// Gaussian table instead of loading it from the term table.
+template <int BX, int BY, bool kGen>
 __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models,
                                               const float4 *__restrict__ terms,
+                                              const double *__restrict__ gauss,
                                               const int *__restrict__ st_ws,
                                               double *__restrict__ part, float4 *cs, int wave,
                                               double *red) {
@@ -525,6 +551,8 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
   const int n_ch = ce - cb;
   const int t0 = ts + cb * KC2, t1 = min(te, ts + ce * KC2);
   const float4 *tb = terms + md.term_off;
+  const double *gt = gauss + md.gauss_off;
+  auto term = [&](int t) { return kGen ? term_of(g, gt, t) : tb[t]; };
   double acc[BX][BY][16];
 #pragma unroll
   for (int bx = 0; bx < BX; ++bx)
@@ -533,13 +561,13 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[bx][by][r] = 0.0;
   float4 cnext = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (n_ch > 0) cnext = tb[min(t0 + lane, t1 - 1)];
+  if (n_ch > 0) cnext = term(min(t0 + lane, t1 - 1));
   const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int ch = 0; ch < n_ch; ++ch) {
     const int tc = t0 + ch * KC2;
     cs[lane] = cnext;
     __builtin_amdgcn_wave_barrier();
-    if (ch + 1 < n_ch) cnext = tb[min(tc + KC2 + lane, t1 - 1)];
+    if (ch + 1 < n_ch) cnext = term(min(tc + KC2 + lane, t1 - 1));
     v16f d[BX][BY];
 #pragma unroll
     for (int bx = 0; bx < BX; ++bx)
@@ -666,6 +694,7 @@ __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__
                                                   const ModelDev *__restrict__ models,
                                                   const Item *__restrict__ items, int n_it,
                                                   const float4 *__restrict__ terms,
+                                                  const double *__restrict__ gauss,
                                                   const int *__restrict__ st_ws,
                                                   double *__restrict__ part, int *queue) {
   __shared__ __attribute__((aligned(16))) float4 cs[4][KC2];
@@ -683,10 +712,11 @@ __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__
     if (i >= n_it) break;
     const Item it = items[i];
     switch (it.c) {
-      case 2: num_tile_item<1, 1>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
-      case 3: num_tile_item<2, 1>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
-      case 4: num_tile_item<1, 2>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
-      default: num_tile_item<2, 2>(it, geoms, models, terms, st_ws, part, cs[wave], wave, red); break;
+      case 2: num_tile_item<1, 1, false>(it, geoms, models, terms, gauss, st_ws, part, cs[wave], wave, red); break;
+      case 3: num_tile_item<2, 1, false>(it, geoms, models, terms, gauss, st_ws, part, cs[wave], wave, red); break;
+      case 4: num_tile_item<1, 2, false>(it, geoms, models, terms, gauss, st_ws, part, cs[wave], wave, red); break;
+      case 6: num_tile_item<1, 1, true>(it, geoms, models, terms, gauss, st_ws, part, cs[wave], wave, red); break;
+      default: num_tile_item<2, 2, false>(it, geoms, models, terms, gauss, st_ws, part, cs[wave], wave, red); break;
     }
     if (!queue) i += gridDim.x;
   }
@@ -736,7 +766,9 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
 
 // ---------------------------------------------------------------------------
 // Bins: sums of the PSF-weighted maps per bin and their FP64 ratio.
-// Item (m, bin).  binws per model: [Nb | Ib], n_bins doubles each.
+// Item (m, bin, 0): the 16 waves of the block share one bin; item (m, first
+// bin, 1): each wave takes one of 16 consecutive bins (geometries whose bins
+// all have few weights).  binws per model: [Nb | Ib], n_bins doubles each.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models,
@@ -750,10 +782,45 @@ __global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const int b = it.a;
     const double *Nm = pix + md.pix_off;
     const double *Im = Nm + g.n_pix;
     const bool want_n = vrms2 != nullptr;
+    if (it.c == 1) {   // uniform per block: bins it.a + wave, one per wave
+      const int lane = threadIdx.x & 63;
+      const int b = it.a + (threadIdx.x >> 6);
+      if (b >= g.n_bins) continue;   // uniform per wave; no barrier in this variant
+      double an[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+      const int e1 = g.bin_ptr[b + 1];
+      int e = g.bin_ptr[b] + lane;
+      for (; e + 3 * 64 < e1; e += 4 * 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double wv = g.bin_w[e + u * 64];
+          const int q = g.bin_pix[e + u * 64];
+          if (want_n) an[u] += wv * Nm[q];
+          ai[u] += wv * Im[q];
+        }
+      }
+      for (int u = 0; e < e1; e += 64, ++u) {
+        const double wv = g.bin_w[e];
+        const int q = g.bin_pix[e];
+        if (want_n) an[u] += wv * Nm[q];
+        ai[u] += wv * Im[q];
+      }
+      double sn = wave_sum((an[0] + an[1]) + (an[2] + an[3]));
+      const double si = wave_sum((ai[0] + ai[1]) + (ai[2] + ai[3]));
+      if (!want_n) sn = 0.0;
+      if (lane == 0) {
+        const bool ok = st_ws[it.m] == 0;
+        if (binws) {
+          binws[md.bin_off + b] = sn;
+          binws[md.bin_off + g.n_bins + b] = si;
+        }
+        if (want_n) vrms2[md.out_off + b] = ok ? sn / si : __builtin_nan("");
+      }
+      continue;
+    }
+    const int b = it.a;
     // four independent accumulators keep four gathers in flight per thread
     double an[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
     const int e1 = g.bin_ptr[b + 1];
@@ -1203,6 +1270,187 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
       o[0] = acc_i;
       o[1] = acc_b;
       o[2] = hj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of a small-map model (its unique-pixel map fits one 32x32 block):
+// the per-term sensitivities and the FP64 chain in one pass, lane = term.
+// Each term's coefficients are computed in place as FP64 dual numbers
+// carrying d/di (the set-up and term formulas of the forward), rounded to
+// FP32 for the sums
+//   S0 = sum_p lambda E F,  S1 = sum_p lambda x^2 E F,
+//   Sg = sum_p lambda y^2 E F (C0 + C1 x^2),   E F = exp(-c1 x^2 - gamma y^2):
+// for every y, F and y^2 F, accumulated per x into g = sum_y lambda F and
+// h = sum_y lambda y^2 F (FP32), then the x-sums in FP32, converted to FP64.
+// The term's chain values (those of k_chain) go through LDS and every (k, j)
+// row is summed over its u-nodes by one wave in a fixed order.  Item (m, k,
+// first mass Gaussian | count << 16) with count * n_u <= kAdjTerms and
+// count <= 64; lambda_N and the squared coordinates are staged in LDS once
+// per item.  Writes the chain rows of k_chain (the model has no partial
+// sensitivity blocks).
+// ---------------------------------------------------------------------------
+constexpr int kSmallMap = 32;
+constexpr int kAdjTerms = kSmallAdjTerms;
+
+__global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ geoms,
+                                                   const ModelDev *__restrict__ models,
+                                                   const Item *__restrict__ items, int n_it,
+                                                   ParamsDev p, const double *__restrict__ pix,
+                                                   const int *__restrict__ st_ws,
+                                                   double *__restrict__ sens) {
+  __shared__ __attribute__((aligned(16))) float lam[kSmallMap][kSmallMap];   // [y][x]
+  __shared__ float xsq[kSmallMap], ysq[kSmallMap];
+  __shared__ double jv[64][5];   // per mass Gaussian: e2, de2/di, r, K_j / M_j, M_j
+  __shared__ double vals[kAdjTerms][3];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;   // uniform per block; k_grads writes NaN
+    const int k = it.a, j0 = it.b & 0xffff, nj = it.b >> 16;
+    const int nx = g.n_ux, ny = g.n_uy, nu = g.n_u, J = g.J1 - 1;
+    __syncthreads();                  // the previous item's LDS reads are done
+    const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
+    for (int e = threadIdx.x; e < kSmallMap * kSmallMap; e += 256) {
+      const int yy = e / kSmallMap, xx = e % kSmallMap;
+      lam[yy][xx] = (yy < ny && xx < nx) ? (float)lamN[yy * nx + xx] : 0.f;
+    }
+    if (threadIdx.x < kSmallMap) {
+      const int q = threadIdx.x;
+      xsq[q] = q < nx ? (float)(g.xs[q] * g.xs[q]) : 0.f;
+      ysq[q] = q < ny ? (float)(g.ys[q] * g.ys[q]) : 0.f;
+    }
+    const double inc = p.inc[it.m];
+    const dual sn = {sin(inc), cos(inc)};
+    const dual cs = {cos(inc), -sin(inc)};
+    const dual si2 = sn * sn, ci2 = cs * cs;
+    const double G = grav_const(), sp = g.s_pc;
+    if (threadIdx.x < nj) {
+      const int j = j0 + threadIdx.x;
+      double *v = jv[threadIdx.x];
+      if (j < J) {
+        const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+        const dual qj = dsqrt(qo * qo - ci2) / sn;
+        const dual e2 = 1.0 - qj * qj;
+        v[0] = e2.v;
+        v[1] = e2.d;
+        v[2] = 0.5 / (sj * sj);
+        v[3] = sqrt(2.0 / kPi) * G / (sp * sj);
+        v[4] = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
+      } else {
+        v[0] = 0.0;
+        v[1] = 0.0;
+        v[2] = 0.5 / (g.bh_sigma * g.bh_sigma);
+        v[3] = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
+        v[4] = p.m_bh[it.m];
+      }
+    }
+    // tracer k: deprojection (App. A) with its inclination derivative
+    const double qok = g.lum_q[k], sk = g.lum_sigma[k];
+    const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+    const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
+    const dual qk = dsqrt(qok * qok - ci2) / sn;
+    const double alpha = 0.5 / (sk * sk);
+    const dual alphaq = dconst(alpha) / (qk * qk);
+    const dual nu1 = dconst(qok / (sqrt(2.0 * kPi) * sk)) / qk;   // nu0 / I0
+    const dual pf = ci2 + b * si2;
+    __syncthreads();
+    const int n_terms = nj * nu;
+    for (int base = 0; base < n_terms; base += 256) {
+      const int tl = base + threadIdx.x;
+      if (tl >= n_terms) break;
+      const int jj = tl / nu, n = tl - jj * nu;
+      const double *v = jv[jj];
+      const double r = v[2], Mj = v[4];
+      const double u = g.u[n], wq = g.w[n], u2 = u * u;
+      const dual h = {fma(-v[0], u2, 1.0), -u2 * v[1]};
+      const double c1 = alpha + r * u2;
+      const double rhv = rcp64(h.v);
+      const dual rh = {rhv, -rhv * rhv * h.d};
+      const dual A = alphaq + (r * u2) * rh;
+      const dual a = c1 * si2 + A * ci2;
+      const double rav = rcp64(a.v);
+      const dual gam = c1 * A * dual{rav, -rav * rav * a.d};
+      const double rshv = rsq64(h.v);
+      const dual rsh = {rshv, -0.5 * rshv * rhv * h.d};
+      const dual bse = (v[3] * r * u2) * nu1;                 // per unit I0 M
+      const double rAv = rcp64(A.v);
+      const dual gg = bse * dual{rAv, -rAv * rAv * A.d} * rh * rsh;
+      const dual ww = 2.0 * bse * rsh;
+      const dual P = pf * gg;
+      const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
+      const double fv = wq * kSqrtPi * rsq64(a.v);
+      const dual f = {fv, -0.5 * fv * rav * a.d};
+      const dual c0 = f * P, c1u = f * Q;                     // C = I0 M c
+      const double amp = I0 * Mj;
+      const float cx = (float)(-c1 * kLog2e), cy = (float)(-gam.v * kLog2e);
+      const float C0 = (float)(amp * c0.v), C1 = (float)(amp * c1u.v);
+      float gx[kSmallMap], hx[kSmallMap];
+#pragma unroll
+      for (int xx = 0; xx < kSmallMap; ++xx) gx[xx] = hx[xx] = 0.f;
+      for (int yy = 0; yy < ny; ++yy) {
+        const float y2 = ysq[yy];
+        const float F = fast_exp2(cy * y2), Fy = F * y2;
+        const float4 *lr = reinterpret_cast<const float4 *>(lam[yy]);
+#pragma unroll
+        for (int xq = 0; xq < kSmallMap / 4; ++xq) {
+          if (4 * xq < nx) {          // uniform
+            const float4 l = lr[xq];
+            gx[4 * xq] = fmaf(l.x, F, gx[4 * xq]);
+            hx[4 * xq] = fmaf(l.x, Fy, hx[4 * xq]);
+            gx[4 * xq + 1] = fmaf(l.y, F, gx[4 * xq + 1]);
+            hx[4 * xq + 1] = fmaf(l.y, Fy, hx[4 * xq + 1]);
+            gx[4 * xq + 2] = fmaf(l.z, F, gx[4 * xq + 2]);
+            hx[4 * xq + 2] = fmaf(l.z, Fy, hx[4 * xq + 2]);
+            gx[4 * xq + 3] = fmaf(l.w, F, gx[4 * xq + 3]);
+            hx[4 * xq + 3] = fmaf(l.w, Fy, hx[4 * xq + 3]);
+          }
+        }
+      }
+      float s0 = 0.f, s1 = 0.f, sg = 0.f;
+#pragma unroll
+      for (int xx = 0; xx < kSmallMap; ++xx) {
+        if (xx < nx) {                // uniform
+          const float x2 = xsq[xx];
+          const float E = fast_exp2(cx * x2);
+          const float Eg = E * gx[xx];
+          s0 += Eg;
+          s1 = fmaf(Eg, x2, s1);
+          sg = fmaf(E * hx[xx], fmaf(C1, x2, C0), sg);
+        }
+      }
+      const double S0 = s0, S1 = s1, Sg = sg;
+      vals[tl][0] = amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
+      // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
+      vals[tl][1] = amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
+      vals[tl][2] = S0 * c0.v + S1 * c1u.v;
+    }
+    __syncthreads();
+    // (k, j) rows: one wave per mass Gaussian, lanes over the u-nodes in
+    // order, then a butterfly
+    double *rows = chain_rows(sens, md, g);
+    for (int jj = wave; jj < nj; jj += 4) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+      for (int n = lane; n < nu; n += 64) {
+        const double *v = vals[jj * nu + n];
+        a0 += v[0];
+        a1 += v[1];
+        a2 += v[2];
+      }
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      if (lane == 0) {
+        double *o = rows + ((int64_t)k * g.J1 + j0 + jj) * 3;
+        o[0] = a0;
+        o[1] = a1;
+        o[2] = a2;
+      }
     }
   }
 }
@@ -2732,11 +2980,11 @@ void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, Pa
   hipLaunchKernelGGL(k_sb, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, pix);
 }
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
-                bool mfma, hipStream_t st) {
+                const float4 *terms, const double *gauss, const int *st_ws, double *part,
+                int *queue, int grid, bool mfma, hipStream_t st) {
   if (mfma)
     hipLaunchKernelGGL(k_num_mfma, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
-                       st_ws, part, queue);
+                       gauss, st_ws, part, queue);
   else
     hipLaunchKernelGGL(k_num_pix, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
                        st_ws, part, queue);
@@ -2780,6 +3028,11 @@ int occupancy_sens() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sens, 256, 0) != hipSuccess) nb = 1;
   return nb < 1 ? 1 : nb;
+}
+void launch_adj_small(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
+                      const double *pix, const int *st_ws, double *sens, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_small, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, p, pix,
+                     st_ws, sens);
 }
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   double *sens, const int *st_ws, hipStream_t st) {

@@ -5,6 +5,7 @@ seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
 from the GPU library.  Run from the repository root:
 
     python tests/golden/make_golden.py [cfg2] [composite] [cfg3] [cfg4] [cfg5] [sph1] [sph_grad]
+                                       [sph_grad_large] [sph_fwd_large] [cyl_edge]
 """
 import json
 import os
@@ -189,8 +190,79 @@ def sph_grad():
         cases=out, seconds=time.time() - t))
 
 
+def _central_grad(g, p, cot, vfun, inc_step):
+    """Central differences of sum_b cot_b vfun(g, q)_b with respect to every
+    parameter (inclination step inc_step rad; the others 1e-6 relative)."""
+    base = dict(inc=float(p.inc), beta=np.array(p.beta, np.float64),
+                mass_scale=float(p.mass_scale), m_bh=float(p.m_bh),
+                lum_I0=np.array(g.lum_I0 if p.lum_I0 is None else p.lum_I0, np.float64),
+                mass_S0=np.array(g.mass_S0 if p.mass_S0 is None else p.mass_S0, np.float64))
+
+    def L(par):
+        q = inputs.with_overrides(p, **par)
+        return float(np.dot(cot, vfun(g, q)))
+
+    grad = {}
+    for key in ("inc", "beta", "mass_scale", "m_bh", "lum_I0", "mass_S0"):
+        v = np.atleast_1d(np.asarray(base[key], np.float64))
+        gk = np.zeros_like(v)
+        for i in range(v.size):
+            h = inc_step if key == "inc" else 1e-6 * max(abs(v[i]), 1e-3)
+            hi = {k: (np.array(x, np.float64) if np.ndim(x) else x) for k, x in base.items()}
+            lo = {k: (np.array(x, np.float64) if np.ndim(x) else x) for k, x in base.items()}
+            if np.ndim(base[key]):
+                hi[key][i] += h
+                lo[key][i] -= h
+            else:
+                hi[key] = base[key] + h
+                lo[key] = base[key] - h
+            gk[i] = (L(hi) - L(lo)) / (2 * h)
+            print(f"  d/d{key}[{i}] = {gk[i]:.6e}", flush=True)
+        grad[key] = gk.tolist()
+    return grad
+
+
+def sph_grad_large():
+    """Spherically aligned gradient at a size that spans several 256-term
+    tiles of the term-major sensitivity pass, two 1024-term coefficient
+    chunks of the characteristic integrals and two rounds of eight tracers:
+    9 tracer Gaussians of mixed anisotropy, 8 mass Gaussians + BH, 128
+    u-nodes (1152 (j, u) terms), on a 6x5 grid; central differences of the
+    FP64 oracle (inclination step 1e-7 rad, others 1e-6 relative)."""
+    t = time.time()
+    g = inputs.small_geometry(seed=11, n_lum=9, n_mass=8, nx=6, ny=5, ss=1, psf_n=3,
+                              n_bins=3, n_u=128)
+    p = inputs.small_params(g, seed=11)
+    cot = inputs.cotangent(g.n_bins, 1, seed=11)[0]
+    grad = _central_grad(g, p, cot, osph.vrms2, 1e-7)
+    V = osph.vrms2(g, p)
+    _dump("sph_grad_large.json", dict(
+        source="central differences of oracle/jam_sph.py vrms2 on inputs.small_geometry(seed=11, "
+               "n_lum=9, n_mass=8, nx=6, ny=5, ss=1, psf_n=3, n_bins=3, n_u=128) with "
+               "inputs.small_params(g, seed=11); cot = inputs.cotangent(3, 1, seed=11)",
+        cot=cot.tolist(), vrms2=V.tolist(), grad=grad, seconds=time.time() - t))
+
+
+def sph_fwd_large():
+    """Spherically aligned forward at K = J = 20 (+ BH), 64 u-nodes, on an
+    8x7 grid with 2x supersampling: all bins of two seeded proposals."""
+    t = time.time()
+    g = inputs.small_geometry(seed=12, n_lum=20, n_mass=20, nx=8, ny=7, ss=2, psf_n=5,
+                              n_bins=5, n_u=64, pixsize=0.08)
+    out = []
+    for s in (12, 13):
+        p = inputs.small_params(g, seed=s)
+        out.append(dict(seed=s, vrms2=osph.vrms2(g, p).tolist()))
+        print("sph_fwd_large seed", s, time.time() - t, flush=True)
+    _dump("sph_fwd_large.json", dict(
+        source="oracle/jam_sph.py vrms2 on inputs.small_geometry(seed=12, n_lum=20, n_mass=20, "
+               "nx=8, ny=7, ss=2, psf_n=5, n_bins=5, n_u=64, pixsize=0.08) with "
+               "inputs.small_params(g, seed) for seed 12 and 13",
+        cases=out, seconds=time.time() - t))
+
+
 if __name__ == "__main__":
-    torch.set_num_threads(max(1, os.cpu_count() or 1))
+    torch.set_num_threads(int(os.environ.get("GOLDEN_THREADS", os.cpu_count() or 1)))
     todo = sys.argv[1:] or ["cfg2", "composite", "cfg3", "cfg4", "cfg5", "sph1", "sph_grad"]
     for name in todo:
         globals()[name]()

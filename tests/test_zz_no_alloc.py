@@ -79,13 +79,13 @@ def test_noalloc_refuses_unprepared_and_oversized():
         binding.jam_eval_batch_noalloc(ctx.handle, w.geom_idx, p["inc"], p["mass_scale"],
                                        p["m_bh"], p["beta"], None, None, V, None, s)
     assert e.value.status == JAM_E_INVALID_ARG
-    # 512 proposals need more than the fixed scratch (their term tables alone
-    # are 512 x 13,000 x 16 bytes)
-    big = inputs.config3(n_models=512)
+    # 4096 proposals need more than the fixed scratch (about 21 KB each: the
+    # unique-pixel maps, the split-term partial map and the Gaussian table)
+    big = inputs.config3(n_models=4096)
     binding.jam_prepare(ctx.handle, big.geom_idx)
     assert binding.jam_workspace_size(ctx.handle, big.geom_idx, False) > 64 << 20
     pb = binding.pack_params(big, dev)
-    Vb = torch.empty(512 * big.geometries[0].n_bins, dtype=torch.float64, device=dev)
+    Vb = torch.empty(4096 * big.geometries[0].n_bins, dtype=torch.float64, device=dev)
     with pytest.raises(binding.JamError) as e:
         binding.jam_eval_batch_noalloc(ctx.handle, big.geom_idx, pb["inc"], pb["mass_scale"],
                                        pb["m_bh"], pb["beta"], None, None, Vb, None, s)
