@@ -313,6 +313,8 @@ struct Tune {
                     // per-pixel item; 0 = derived from the batch
   int launch = 0;   // 0 one workgroup per item; 1 persistent grid pulling items from a
                     // device queue
+  int map = 0;      // derived from the batch, not tuned: 1 when rule 1 runs every model
+                    // with the whole-map matrix-core kernel (all maps of 7 x 7 blocks)
 };
 
 // Every pointer a captured graph was recorded with (parameters, outputs,
@@ -344,9 +346,11 @@ struct Plan {
   jam::ModelDev *d_models = nullptr;
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
-            *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr;
+            *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
+            *d_redf = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0;
+      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0;
+  int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
   int grid_num = 1, grid_sens = 1;
@@ -458,8 +462,15 @@ constexpr int kFusedPrologueModels = 32;
 // matrix-core block) take the small-map form: terms computed in place by the
 // numerator, sensitivities and chain fused in the adjoint.
 constexpr int kSmallMap = 32;
+// Whole-map numerator: longest slice, in units of 64 terms, summed in FP32.
+constexpr int kMapMaxUnits = 32;
+// Does a geometry's map suit the whole-map matrix-core numerator?
+bool map_fits(int n_ux, int n_uy) {
+  const int bx = (n_ux + 31) / 32, by = (n_uy + 31) / 32;
+  return bx == jam::kMapBlocks && by == jam::kMapBlocks;
+}
 // Geometries whose bins have at most this many weights each sum every bin
-// with one wave (16 bins per workgroup) instead of a whole workgroup.
+// with one wave (4 bins per workgroup) instead of a whole workgroup.
 constexpr int kBinWaveNnz = 2048;
 
 // Numerator variant and term-range split of one model under a schedule.
@@ -475,6 +486,7 @@ struct WaveTile {
 struct NumChoice {
   int kind;      // 0 per-pixel VALU, 2 matrix-core wave tiles
   bool gen = false;   // matrix core on a map of one 32x32 block, terms computed in place
+  bool map = false;   // matrix core, one workgroup per whole map and slice
   int n_slices;
   int units;     // slice units of the whole term range
   std::vector<WaveTile> tiles;   // matrix core
@@ -506,8 +518,17 @@ NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
     return c;
   }
   const int chunks = (g.T + 63) / 64;
-  const int per = std::max(4, gran);
   c.kind = 2;
+  if (t.map) {
+    // FP32 accumulation over a slice: at most kMapMaxUnits x 64 terms
+    const int per = std::max(1, std::min(kMapMaxUnits, gran));
+    c.map = true;
+    c.n_slices = std::max(1, (chunks + per - 1) / per);
+    c.units = chunks;
+    c.tiles.push_back({0, 0, (g.n_ux + 31) / 32, (g.n_uy + 31) / 32});
+    return c;
+  }
+  const int per = std::max(4, gran);
   c.gen = g.n_ux <= kSmallMap && g.n_uy <= kSmallMap;
   c.n_slices = std::max(1, (chunks + per - 1) / per);
   c.units = chunks;
@@ -535,6 +556,12 @@ double num_item_cost(const GeomHost &g, const NumChoice &c, int slice, int tile)
   // (dependent descriptor and coordinate loads, first chunk), the four-wave
   // sum and the tile store
   const WaveTile &w = c.tiles[tile];
+  if (c.map) {
+    // every wave runs every chunk for its quarter of the blocks; the
+    // workgroup generates the operands of all rows and columns once
+    const int nblk = w.BX * w.BY;
+    return cnt * (1.5 * ((nblk + 3) / 4) + 0.75) + 8.0;
+  }
   // terms computed in place: their FP64 set-up per chunk
   const double gen = c.gen ? 0.5 : 0.0;
   return ((cnt + 3) / 4) * (1.5 * w.BX * w.BY + 0.75 * (w.BX + w.BY) + gen) + 8.0;
@@ -585,7 +612,7 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
     }
   }
   // jobs a worker holds at once
-  const double per_slot = t.rule == 0 ? ctx->occ_num_pix : ctx->occ_num_mfma;
+  const double per_slot = t.rule == 0 ? ctx->occ_num_pix : (t.map ? 1 : ctx->occ_num_mfma);
   const double g0 = std::max(1.0, std::ceil(work / (slots * per_slot)));
   std::vector<int> cands;
   for (int k = -8; k <= 16; ++k)
@@ -632,11 +659,18 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->key.assign(geom_idx, geom_idx + n);
   p->n = n;
   p->tune = tune_in;
+  p->tune.map = 0;
+  if (p->tune.rule == 1 && ctx->opt.alignment != 1) {
+    bool all = true;
+    for (int m = 0; m < n && all; ++m)
+      all = map_fits(ctx->gh[geom_idx[m]].n_ux, ctx->gh[geom_idx[m]].n_uy);
+    p->tune.map = all ? 1 : 0;
+  }
   if (p->tune.gran <= 0) p->tune.gran = default_gran(ctx, n, geom_idx, p->tune);
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro, it_adj;
+      it_red, it_sph, it_pro, it_adj, it_redf;
   std::vector<double> c_num, c_sens;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
@@ -652,7 +686,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     const NumChoice nc = choose_numerator(g, tune, tune.gran);
     d.n_slices = nc.n_slices;
     const bool small = !spherical && nc.gen;
-    d.form = nc.kind == 0 ? 1 : (small ? 3 : 2);
+    d.form = nc.kind == 0 ? 1 : (small ? 3 : (nc.map ? 4 : 2));
+    d.part_f32 = nc.map ? 1 : 0;
     d.n_sens_parts = d.form == 1 ? 1 : (small ? 0 : (g.n_ux + 31) / 32);
     d.n_xt = (g.n_ux + 31) / 32;
     d.n_yt = (g.n_uy + 31) / 32;
@@ -697,13 +732,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
           c_sens.push_back((double)jam::sph_range_len(g.K, d.n_sens_parts));
         }
     } else if (small) {
-      // fused sensitivities + chain: items of whole (k, j) groups of u-nodes
-      const int cap = std::max(1, std::min(64, jam::kSmallAdjTerms / g.n_u));
-      const int groups = (g.J1 + cap - 1) / cap;
-      const int cnt = (g.J1 + groups - 1) / groups;
-      for (int k = 0; k < g.K; ++k)
-        for (int j0 = 0; j0 < g.J1; j0 += cnt)
-          it_adj.push_back({m, k, j0 | (std::min(cnt, g.J1 - j0) << 16), 0});
+      // fused sensitivities + chain: items of whole tracers, about 8192
+      // terms each
+      const int per = std::max(1, 8192 / (g.J1 * g.n_u));
+      for (int k = 0; k < g.K; k += per)
+        it_adj.push_back({m, k | (std::min(g.K, k + per) << 16), 0, 0});
     } else if (d.form == 1) {
       for (int tb = 0; tb < (g.T + 255) / 256; ++tb) {
         it_sens.push_back({m, tb, 0, 0});
@@ -717,7 +750,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
         }
     }
     for (int pb = 0; pb < (g.n_pix + 255) / 256; ++pb) it_pix.push_back({m, pb, 0, 0});
-    for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_red.push_back({m, pb, 0, 0});
+    if (nc.map)   // FP32 partials, reduced over the padded layout
+      for (int pb = 0; pb < (g.n_ux * 32 * d.n_yt + 255) / 256; ++pb) it_redf.push_back({m, pb, 0, 0});
+    else
+      for (int pb = 0; pb < (g.n_pix + 63) / 64; ++pb) it_red.push_back({m, pb, 0, 0});
     for (int rb = 0; rb < (g.n_uy + 7) / 8; ++rb)
       for (int cb = 0; cb < (g.n_ux + 63) / 64; ++cb) it_sb.push_back({m, rb, cb, 0});
     for (int s = 0; s < d.n_slices; ++s)
@@ -727,12 +763,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
         } else {
           const WaveTile &w = nc.tiles[tl];
           it_num.push_back({m, w.bx | (w.by << 16), s,
-                            small ? 6 : 2 + (w.BX - 1) + 2 * (w.BY - 1)});
+                            nc.map ? 7 : (small ? 6 : 2 + (w.BX - 1) + 2 * (w.BY - 1))});
         }
         c_num.push_back(num_item_cost(g, nc, s, tl));
       }
     if (g.max_bin_nnz <= kBinWaveNnz)
-      for (int b = 0; b < g.n_bins; b += 16) it_bins.push_back({m, b, 0, 1});
+      for (int b = 0; b < g.n_bins; b += 4) it_bins.push_back({m, b, 0, 1});
     else
       for (int b = 0; b < g.n_bins; ++b) it_bins.push_back({m, b, 0, 0});
     for (int r = 0; r < g.nyp; ++r) it_maps.push_back({m, r, 0, 0});
@@ -750,12 +786,17 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     for (int m = 0; m < n; ++m) it_pro.push_back({m, 0, 0, 0});
   for (const jam::Item &t : it_terms) it_pro.push_back({t.m, t.a, 0, p->fused_prologue ? 1 : 3});
   for (const jam::Item &t : it_sb) it_pro.push_back({t.m, t.a, t.b, 2});
+  // bin items: the one-bin-per-wave ones first (a launch of 256-thread
+  // blocks), then the one-bin-per-block ones (1024-thread blocks)
+  std::stable_partition(it_bins.begin(), it_bins.end(), [](const jam::Item &t) { return t.c == 1; });
+  p->n_bins_wave = (int)std::count_if(it_bins.begin(), it_bins.end(),
+                                      [](const jam::Item &t) { return t.c == 1; });
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 12;
+  constexpr int kLists = 13;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
-                                           &it_red,   &it_sph, &it_pro, &it_adj};
+                                           &it_red,   &it_sph, &it_pro, &it_adj, &it_redf};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -778,17 +819,17 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->d_models = (jam::ModelDev *)(base + o_models);
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
-                            &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj};
+                            &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
-                      &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj};
+                      &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
   }
   const int num_wg = p->n_num;   // one workgroup per numerator item
   if (tune.launch == 1) {
-    const int occ = tune.rule == 0 ? ctx->occ_num_pix : ctx->occ_num_mfma;
+    const int occ = tune.rule == 0 ? ctx->occ_num_pix : (tune.map ? 1 : ctx->occ_num_mfma);
     p->grid_num = std::max(1, std::min(num_wg, ctx->n_cu * occ));
     p->grid_sens = std::max(1, std::min(p->n_sens, ctx->n_cu * ctx->occ_sens));
   } else {
@@ -854,17 +895,23 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   }
   if (need_numerator) {
     const bool timed = ctx->t_num.begin(st, capturing);
-    jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, gauss, st_ws, part,
-                    p->tune.launch == 1 ? queue : nullptr, p->grid_num, p->tune.rule == 1, st);
+    if (p->tune.map)
+      jam::launch_num_map(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, st_ws, part,
+                          p->tune.launch == 1 ? queue : nullptr, p->grid_num, st);
+    else
+      jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num, terms, gauss, st_ws, part,
+                      p->tune.launch == 1 ? queue : nullptr, p->grid_num, p->tune.rule == 1, st);
     if (timed) ctx->t_num.end(st);
-    jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_red, p->n_red, part, pix, st);
+    if (p->n_red) jam::launch_reduce(ctx->d_geoms, p->d_models, p->d_red, p->n_red, part, pix, st);
+    if (p->n_redf)
+      jam::launch_reduce_f32(ctx->d_geoms, p->d_models, p->d_redf, p->n_redf, part, pix, st);
   }
 }
 
 void launch_eval(jam_ctx *ctx, Plan *p, const jam_batch *b, double *vrms2, int32_t *status,
                  char *w, hipStream_t st, bool capturing) {
   launch_forward_maps(ctx, p, params_of(b), status, w, st, true, capturing);
-  jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, (const double *)(w + p->off_pix),
+  jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, p->n_bins_wave, (const double *)(w + p->off_pix),
                    (const int *)(w + p->off_status), vrms2, (double *)(w + p->off_bins), st);
 }
 
@@ -901,10 +948,10 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   const double *V = vrms2;
   if (recompute) {
     double *vtmp = (double *)(w + p->off_vtmp);
-    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, vtmp, binws, st);
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, p->n_bins_wave, pix, st_ws, vtmp, binws, st);
     V = vtmp;
   } else {
-    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, pix, st_ws, nullptr, binws, st);
+    jam::launch_bins(ctx->d_geoms, p->d_models, p->d_bins, p->n_bins, p->n_bins_wave, pix, st_ws, nullptr, binws, st);
   }
   if (chi2_cot) {
     double *c = (double *)(w + p->off_cot);
@@ -1049,11 +1096,18 @@ jam_status autotune(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, Tune &best
     for (int rep = 0; rep < 3; ++rep) {
       launch_forward_maps(ctx, p, pd, nullptr, w, st, false, true);
       (void)hipEventRecord(e0, st);
-      jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
-                      (const float4 *)(w + p->off_terms), (const double *)(w + p->off_gauss),
-                      (const int *)(w + p->off_status),
-                      (double *)(w + p->off_part), p->tune.launch == 1 ? (int *)(w + p->off_queue) : nullptr,
-                      p->grid_num, p->tune.rule == 1, st);
+      if (p->tune.map)
+        jam::launch_num_map(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
+                            (const float4 *)(w + p->off_terms), (const int *)(w + p->off_status),
+                            (double *)(w + p->off_part),
+                            p->tune.launch == 1 ? (int *)(w + p->off_queue) : nullptr,
+                            p->grid_num, st);
+      else
+        jam::launch_num(ctx->d_geoms, p->d_models, p->d_num, p->n_num,
+                        (const float4 *)(w + p->off_terms), (const double *)(w + p->off_gauss),
+                        (const int *)(w + p->off_status),
+                        (double *)(w + p->off_part), p->tune.launch == 1 ? (int *)(w + p->off_queue) : nullptr,
+                        p->grid_num, p->tune.rule == 1, st);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         cleanup();

@@ -61,10 +61,11 @@ struct ModelDev {
   int n_slices;      // split of the term range in the numerator kernels
   int n_xt, n_yt;    // 32x32 blocks covering the unique-pixel map (partial maps are
                      // stored padded to 32 n_xt x 32 n_yt per slice)
-  int form;          // 1 per-pixel VALU, 2 separable MFMA, 3 separable MFMA on a map of
-                     // one 32x32 block with terms computed in place (no term table)
+  int form;          // 1 per-pixel VALU, 2 separable MFMA (wave tiles), 3 separable MFMA
+                     // on a map of one 32x32 block with terms computed in place (no term
+                     // table), 4 separable MFMA with one workgroup per whole map
   int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
-  int pad;
+  int part_f32;      // 1: the split-term partial maps are FP32 (whole-map numerator)
   int64_t gauss_off; // doubles, per-Gaussian derived quantities
   int64_t term_off;  // float4 entries, term table
   int64_t pix_off;   // doubles, unique-pixel maps (N, I, lambda)
@@ -155,12 +156,25 @@ void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, Pa
 void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                 const float4 *terms, const double *gauss, const int *st_ws, double *part,
                 int *queue, int grid, bool mfma, hipStream_t st);
+// Whole-map matrix-core numerator (maps of exactly kMapBlocks x kMapBlocks
+// blocks of 32x32): items (m, 0, slice, 7), one workgroup per item (queue as
+// launch_num); FP32 partial maps.
+constexpr int kMapBlocks = 7;
+void launch_num_map(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                    const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
+                    hipStream_t st);
 int occupancy_num(bool mfma);   // resident numerator workgroups per CU
 int occupancy_sens();   // resident sensitivity workgroups per CU
 // Items (m, 64-pixel block).
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st);
-void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+// FP32 partial maps (whole-map numerator): items (m, block of 256 positions
+// of the padded partial layout).
+void launch_reduce_f32(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                       const double *part, double *pix, hipStream_t st);
+// Bin items: the first n_wave are (m, first bin, 1) items of up to 4 bins,
+// one per wave; the rest (m, bin, 0) items of one bin each.
+void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, int n_wave,
                  const double *pix, const int *st_ws, double *vrms2, double *binws,
                  hipStream_t st);
 void launch_maps(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
@@ -182,9 +196,9 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                   double *sens, const int *st_ws, hipStream_t st);
 // Small-map models (unique-pixel map within one 32x32 block): sensitivities
-// and chain in one pass, items (m, k, first mass Gaussian | count << 16),
-// count * n_u <= 1024, count <= 64; writes the chain rows (the model has no
-// partial sensitivity blocks, n_sens_parts = 0).
+// and chain in one pass, items (m, first tracer | end tracer << 16); writes
+// the chain rows (the model has no partial sensitivity blocks,
+// n_sens_parts = 0).
 constexpr int kSmallAdjTerms = 1024;
 void launch_adj_small(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                       const double *pix, const int *st_ws, double *sens, hipStream_t st);

@@ -722,6 +722,216 @@ __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Whole-map matrix-core numerator.  One workgroup computes one slice of the
+// terms for the model's entire unique-pixel map (n_xt x n_yt <= 7 x 7 blocks
+// of 32x32).  Per chunk of 32 terms the 256 threads generate the operands of
+// every block once (thread i: row i of A = 2^(cx x^2)(C0 + C1 x^2) and
+// column i of B = 2^(cy y^2) for the chunk's terms) into LDS, double
+// buffered, while the waves run the previous chunk's MFMAs.  Wave w owns a
+// fixed run of consecutive blocks (row-major block order, 13/12/12/12 for
+// 7 x 7, known at compile time, so per pair of terms a wave reads the
+// operands of its 2-3 block rows and of the 7 block columns once) and
+// accumulates them over the whole slice in FP32 matrix-core accumulators;
+// the slice's partial map is stored in FP32 and the slices are summed in
+// FP64 by k_reduce in a fixed order.  Rows and columns past the map get
+// exact zero operands (exponent offset -inf), terms past the slice zero
+// coefficients.
+// ---------------------------------------------------------------------------
+constexpr int kMapC = 32;                 // terms per chunk
+constexpr int kMapLd = 256;               // floats per operand row (one per thread)
+
+struct MapLds {
+  float a[2][kMapC][kMapLd];
+  float b[2][kMapC][kMapLd];
+  float4 cs[2][kMapC];
+};
+
+// Wave W of a map of NXB x NYB blocks owns the row-major blocks
+// [map_q0, map_q0 + map_nb): the first (NXB NYB) % 4 waves one more.
+__host__ __device__ constexpr int map_nb(int nblk, int w) { return nblk / 4 + (w < nblk % 4 ? 1 : 0); }
+__host__ __device__ constexpr int map_q0(int nblk, int w) {
+  return w * (nblk / 4) + (w < nblk % 4 ? w : nblk % 4);
+}
+
+template <int NXB, int NYB, int W>
+__device__ __forceinline__ void num_map_item(const Item it, const ModelDev &md, const GeomDev &g,
+                                             const float4 *__restrict__ terms,
+                                             const int *__restrict__ st_ws,
+                                             double *__restrict__ part, MapLds &L) {
+  constexpr int NBLK = NXB * NYB;
+  constexpr int NB = map_nb(NBLK, W), Q0 = map_q0(NBLK, W);
+  constexpr int BX0 = Q0 / NYB, NR = (Q0 + NB - 1) / NYB - BX0 + 1;   // rows of this wave
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, c32 = lane & 31, kh = lane >> 5;
+  int ts, te;
+  slice_range(g.T, md.n_slices, it.b, ts, te, kMapC);
+  const int n_ch = (st_ws[it.m] == 0) ? (te - ts + kMapC - 1) / kMapC : 0;   // uniform
+  const float4 *tb = terms + md.term_off;
+  // this thread's generated row / column
+  float x2 = 0.f, xoff = -__builtin_inff(), y2 = 0.f, yoff = -__builtin_inff();
+  if (tid < g.n_ux) { const double x = g.xs[tid]; x2 = (float)(x * x); xoff = 0.f; }
+  if (tid < g.n_uy) { const double y = g.ys[tid]; y2 = (float)(y * y); yoff = 0.f; }
+  auto stage = [&](int buf, int ch) {   // coefficients of chunk ch (zero past the slice)
+    if (tid < kMapC) {
+      const int t = ts + ch * kMapC + tid;
+      L.cs[buf][tid] = t < te ? tb[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  // operands of a term with coefficients c, into row k of buffer buf
+  auto generate = [&](int buf, int k, float4 c) {
+    L.a[buf][k][tid] = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
+    L.b[buf][k][tid] = fast_exp2(fmaf(c.y, y2, yoff));
+  };
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  v16f acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc[i] = zero;
+  if (n_ch > 0) stage(0, 0);
+  __syncthreads();
+  if (n_ch > 0)
+    for (int k = 0; k < kMapC; ++k) generate(0, k, L.cs[0][k]);
+  if (n_ch > 1) stage(1, 1);
+  __syncthreads();
+  for (int ch = 0; ch < n_ch; ++ch) {
+    const int cur = ch & 1;
+    // the next chunk's coefficients (staged one chunk earlier; after the
+    // last chunk they are stale, and what they generate is never read)
+    float4 cn[kMapC];
+#pragma unroll
+    for (int k = 0; k < kMapC; ++k) cn[k] = L.cs[cur ^ 1][k];
+    // per pair of terms: the operands of this wave's block rows and of every
+    // block column (read one pair ahead), then the MFMAs beside two terms of
+    // the next chunk's operands; the scheduling barriers keep each pair's
+    // reads ahead of the previous pair's MFMAs
+    float av[2][NR], bv[2][NYB];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) av[0][r] = L.a[cur][kh][32 * (BX0 + r) + c32];
+#pragma unroll
+    for (int c = 0; c < NYB; ++c) bv[0][c] = L.b[cur][kh][32 * c + c32];
+#pragma unroll
+    for (int s2 = 0; s2 < kMapC / 2; ++s2) {
+      const int u = s2 & 1;
+      if (s2 + 1 < kMapC / 2) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          av[u ^ 1][r] = L.a[cur][2 * s2 + 2 + kh][32 * (BX0 + r) + c32];
+#pragma unroll
+        for (int c = 0; c < NYB; ++c) bv[u ^ 1][c] = L.b[cur][2 * s2 + 2 + kh][32 * c + c32];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u][(Q0 + i) / NYB - BX0],
+                                                      bv[u][(Q0 + i) % NYB], acc[i], 0, 0, 0);
+      generate(cur ^ 1, 2 * s2, cn[2 * s2]);
+      generate(cur ^ 1, 2 * s2 + 1, cn[2 * s2 + 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (ch + 2 < n_ch) stage(cur, ch + 2);
+    __syncthreads();
+  }
+  // FP32 partial map of the slice, padded and transposed as k_reduce reads it
+  float *pf = reinterpret_cast<float *>(part + md.part_off) + it.b * part_slice_size(md);
+  const int ldh = 32 * NYB;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    float *o = pf + (int64_t)(32 * ((Q0 + i) / NYB) + 4 * kh) * ldh + 32 * ((Q0 + i) % NYB) + c32;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[(int64_t)((r & 3) + 8 * (r >> 2)) * ldh] = acc[i][r];
+  }
+}
+
+__global__ void __launch_bounds__(256, 1) k_num_map(const GeomDev *__restrict__ geoms,
+                                                   const ModelDev *__restrict__ models,
+                                                   const Item *__restrict__ items, int n_it,
+                                                   const float4 *__restrict__ terms,
+                                                   const int *__restrict__ st_ws,
+                                                   double *__restrict__ part, int *queue) {
+  __shared__ MapLds L;
+  __shared__ int next;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int i = blockIdx.x;
+  for (;;) {
+    if (queue) {
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+      __syncthreads();
+      i = next;
+      __syncthreads();
+    }
+    if (i >= n_it) break;
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    // the map shape is 7 x 7 blocks (checked on the host)
+    switch (wave) {
+      case 0: num_map_item<7, 7, 0>(it, md, g, terms, st_ws, part, L); break;
+      case 1: num_map_item<7, 7, 1>(it, md, g, terms, st_ws, part, L); break;
+      case 2: num_map_item<7, 7, 2>(it, md, g, terms, st_ws, part, L); break;
+      default: num_map_item<7, 7, 3>(it, md, g, terms, st_ws, part, L); break;
+    }
+    __syncthreads();
+    if (!queue) i += gridDim.x;
+  }
+}
+
+// Sum FP32 split-term partial maps (whole-map numerator) in FP64, in a fixed
+// order, into the N map.  Item (m, block of 256 consecutive positions of the
+// padded partial layout, x * 32 n_yt + y): lane l holds positions 4l..4l+3
+// (one float4 per slice), wave w of 8 takes slices w, w + 8, ... in order
+// with 16 loads in flight, and the eight waves' sums are added in wave order.
+__global__ void __launch_bounds__(512) k_reduce_f32(const GeomDev *__restrict__ geoms,
+                                                    const ModelDev *__restrict__ models,
+                                                    const Item *__restrict__ items, int n_it,
+                                                    const double *__restrict__ part,
+                                                    double *__restrict__ pix) {
+  __shared__ double red[8][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const int ldh = 32 * md.n_yt;
+    const int p0 = it.a * 256 + 4 * lane;
+    const bool valid = p0 < g.n_ux * ldh;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      const float *pp = reinterpret_cast<const float *>(part + md.part_off) + p0;
+      const int64_t stride = part_slice_size(md);
+      for (int s0 = wave; s0 < md.n_slices; s0 += 8 * 16) {
+        float4 v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int sl = s0 + 8 * k;
+          v[k] = sl < md.n_slices ? *reinterpret_cast<const float4 *>(pp + sl * stride)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          acc[0] += (double)v[k].x;
+          acc[1] += (double)v[k].y;
+          acc[2] += (double)v[k].z;
+          acc[3] += (double)v[k].w;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[wave][4 * lane + c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 256) {
+      const int q = it.a * 256 + threadIdx.x;
+      const int x = q / ldh, y = q % ldh;
+      if (x < g.n_ux && y < g.n_uy) {
+        double v = red[0][threadIdx.x];
+        for (int w = 1; w < 8; ++w) v += red[w][threadIdx.x];
+        pix[md.pix_off + (int64_t)y * g.n_ux + x] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Sum the split-term partials in a fixed order into the N map.  Item
 // (m, block of 64 pixels in the partial maps' order, y fastest); the four
 // waves take every fourth slice and their sums are combined in a fixed order.
@@ -742,18 +952,33 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
     const int x = u / g.n_uy, y = u % g.n_uy;
     double acc = 0.0;
     if (u < g.n_pix) {
-      const double *pp = part + md.part_off + (int64_t)x * (32 * md.n_yt) + y;
+      const int64_t off = (int64_t)x * (32 * md.n_yt) + y;
       const int64_t stride = part_slice_size(md);
       // eight slices' loads in flight, added in slice order
-      for (int s0 = wave; s0 < md.n_slices; s0 += 32) {
-        double v[8];
+      if (md.part_f32) {
+        const float *pp = reinterpret_cast<const float *>(part + md.part_off) + off;
+        for (int s0 = wave; s0 < md.n_slices; s0 += 32) {
+          double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int s = s0 + 4 * k;
-          v[k] = s < md.n_slices ? pp[s * stride] : 0.0;
+          for (int k = 0; k < 8; ++k) {
+            const int s = s0 + 4 * k;
+            v[k] = s < md.n_slices ? (double)pp[s * stride] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc += v[k];
         }
+      } else {
+        const double *pp = part + md.part_off + off;
+        for (int s0 = wave; s0 < md.n_slices; s0 += 32) {
+          double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc += v[k];
+          for (int k = 0; k < 8; ++k) {
+            const int s = s0 + 4 * k;
+            v[k] = s < md.n_slices ? pp[s * stride] : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc += v[k];
+        }
       }
     }
     if (wave > 0) red[wave - 1][lane] = acc;
@@ -766,18 +991,20 @@ __global__ void __launch_bounds__(256) k_reduce(const GeomDev *__restrict__ geom
 
 // ---------------------------------------------------------------------------
 // Bins: sums of the PSF-weighted maps per bin and their FP64 ratio.
-// Item (m, bin, 0): the 16 waves of the block share one bin; item (m, first
-// bin, 1): each wave takes one of 16 consecutive bins (geometries whose bins
-// all have few weights).  binws per model: [Nb | Ib], n_bins doubles each.
+// Item (m, bin, 0), launched with 1024 threads: the 16 waves of the block
+// share one bin; item (m, first bin, 1), launched with 256 threads: each wave
+// takes one of 4 consecutive bins (geometries whose bins all have few
+// weights).  binws per model: [Nb | Ib], n_bins doubles each.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms,
+template <int BS>
+__global__ void __launch_bounds__(BS) k_bins(const GeomDev *__restrict__ geoms,
                                               const ModelDev *__restrict__ models,
                                               const Item *__restrict__ items, int n_it,
                                               const double *__restrict__ pix,
                                               const int *__restrict__ st_ws,
                                               double *__restrict__ vrms2,
                                               double *__restrict__ binws) {
-  __shared__ double sh[1024];
+  __shared__ double sh[2 * (BS / 64)];
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
@@ -825,36 +1052,36 @@ __global__ void __launch_bounds__(1024) k_bins(const GeomDev *__restrict__ geoms
     double an[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
     const int e1 = g.bin_ptr[b + 1];
     int e = g.bin_ptr[b] + threadIdx.x;
-    for (; e + 3 * 1024 < e1; e += 4 * 1024) {
+    for (; e + 3 * BS < e1; e += 4 * BS) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double wv = g.bin_w[e + u * 1024];
-        const int q = g.bin_pix[e + u * 1024];
+        const double wv = g.bin_w[e + u * BS];
+        const int q = g.bin_pix[e + u * BS];
         if (want_n) an[u] += wv * Nm[q];
         ai[u] += wv * Im[q];
       }
     }
-    for (int u = 0; e < e1; e += 1024, ++u) {
+    for (int u = 0; e < e1; e += BS, ++u) {
       const double wv = g.bin_w[e];
       const int q = g.bin_pix[e];
       if (want_n) an[u] += wv * Nm[q];
       ai[u] += wv * Im[q];
     }
-    // deterministic two-level sums: wave butterflies, then the 16 wave
-    // partials in a fixed order
+    // deterministic two-level sums: wave butterflies, then the wave partials
+    // in a fixed order
     const double an_w = wave_sum((an[0] + an[1]) + (an[2] + an[3]));
     const double ai_w = wave_sum((ai[0] + ai[1]) + (ai[2] + ai[3]));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) {
       sh[wv] = an_w;
-      sh[16 + wv] = ai_w;
+      sh[BS / 64 + wv] = ai_w;
     }
     __syncthreads();
     double sn = 0.0, si = 0.0;
     if (threadIdx.x == 0)
-      for (int w = 0; w < 16; ++w) {
+      for (int w = 0; w < BS / 64; ++w) {
         sn += sh[w];
-        si += sh[16 + w];
+        si += sh[BS / 64 + w];
       }
     if (!want_n) sn = 0.0;
     __syncthreads();
@@ -1282,17 +1509,67 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
 // FP32 for the sums
 //   S0 = sum_p lambda E F,  S1 = sum_p lambda x^2 E F,
 //   Sg = sum_p lambda y^2 E F (C0 + C1 x^2),   E F = exp(-c1 x^2 - gamma y^2):
-// for every y, F and y^2 F, accumulated per x into g = sum_y lambda F and
-// h = sum_y lambda y^2 F (FP32), then the x-sums in FP32, converted to FP64.
+// F(y) and y^2 F(y) for every y in registers, then per x the FP32 sums
+// g = sum_y lambda F and h = sum_y lambda y^2 F (lambda broadcast from LDS,
+// four y at a time) and the x-sums in FP32, converted to FP64; the y loops
+// are unrolled for the map's number of y quads.
 // The term's chain values (those of k_chain) go through LDS and every (k, j)
-// row is summed over its u-nodes by one wave in a fixed order.  Item (m, k,
-// first mass Gaussian | count << 16) with count * n_u <= kAdjTerms and
-// count <= 64; lambda_N and the squared coordinates are staged in LDS once
-// per item.  Writes the chain rows of k_chain (the model has no partial
-// sensitivity blocks).
+// row is summed over its u-nodes by one wave in a fixed order.  Item (m,
+// first tracer k0 | k1 << 16): tracers k0 <= k < k1, each in groups of at
+// most 64 mass Gaussians with count * n_u <= kAdjTerms; lambda_N and the
+// squared coordinates are staged in LDS once per item.  Writes the chain
+// rows of k_chain (the model has no partial sensitivity blocks).
 // ---------------------------------------------------------------------------
 constexpr int kSmallMap = 32;
 constexpr int kAdjTerms = kSmallAdjTerms;
+
+// The three FP32 map sums of one term (lane) over NYQ quads of y (past the
+// map y^2 = 0 and lambda = 0, so the padding adds nothing) and nx values of
+// x: F(y) and y^2 F(y) in registers, per x g and h over y with lambda read
+// four at a time from LDS (the same address in every lane), then E(x).
+template <int NYQ>
+__device__ __forceinline__ void small_sums(float cx, float cy, float C0, float C1,
+                                           const float (*lam)[kSmallMap], const float *xsq,
+                                           const float *ysq, int nx, float &s0, float &s1,
+                                           float &sg) {
+  float F[4 * NYQ], Fy[4 * NYQ];
+#pragma unroll
+  for (int yy = 0; yy < 4 * NYQ; ++yy) {
+    const float y2 = ysq[yy];
+    F[yy] = fast_exp2(cy * y2);
+    Fy[yy] = F[yy] * y2;
+  }
+  // an offset the compiler cannot prove loop-invariant, so that the lambda
+  // reads are not hoisted out of the caller's term loop into registers
+  int zoff;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
+  s0 = 0.f;
+  s1 = 0.f;
+  sg = 0.f;
+#pragma unroll 2
+  for (int xx = 0; xx < nx; ++xx) {
+    const float4 *lr = reinterpret_cast<const float4 *>(lam[xx]) + zoff;
+    float gs = 0.f, hs = 0.f;
+#pragma unroll
+    for (int yq = 0; yq < NYQ; ++yq) {
+      const float4 l = lr[yq];
+      gs = fmaf(l.x, F[4 * yq], gs);
+      hs = fmaf(l.x, Fy[4 * yq], hs);
+      gs = fmaf(l.y, F[4 * yq + 1], gs);
+      hs = fmaf(l.y, Fy[4 * yq + 1], hs);
+      gs = fmaf(l.z, F[4 * yq + 2], gs);
+      hs = fmaf(l.z, Fy[4 * yq + 2], hs);
+      gs = fmaf(l.w, F[4 * yq + 3], gs);
+      hs = fmaf(l.w, Fy[4 * yq + 3], hs);
+    }
+    const float x2 = xsq[xx];
+    const float E = fast_exp2(cx * x2);
+    const float Eg = E * gs;
+    s0 += Eg;
+    s1 = fmaf(Eg, x2, s1);
+    sg = fmaf(E * hs, fmaf(C1, x2, C0), sg);
+  }
+}
 
 __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ geoms,
                                                    const ModelDev *__restrict__ models,
@@ -1300,7 +1577,7 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
                                                    ParamsDev p, const double *__restrict__ pix,
                                                    const int *__restrict__ st_ws,
                                                    double *__restrict__ sens) {
-  __shared__ __attribute__((aligned(16))) float lam[kSmallMap][kSmallMap];   // [y][x]
+  __shared__ __attribute__((aligned(16))) float lam[kSmallMap][kSmallMap];   // [x][y]
   __shared__ float xsq[kSmallMap], ysq[kSmallMap];
   __shared__ double jv[64][5];   // per mass Gaussian: e2, de2/di, r, K_j / M_j, M_j
   __shared__ double vals[kAdjTerms][3];
@@ -1311,13 +1588,21 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
     if (st_ws[it.m] != 0) continue;   // uniform per block; k_grads writes NaN
-    const int k = it.a, j0 = it.b & 0xffff, nj = it.b >> 16;
-    const int nx = g.n_ux, ny = g.n_uy, nu = g.n_u, J = g.J1 - 1;
+    // block-uniform bounds in scalar registers, so the unrolled loops'
+    // guards are scalar branches
+    const int k0 = __builtin_amdgcn_readfirstlane(it.a & 0xffff);
+    const int k1 = __builtin_amdgcn_readfirstlane(it.a >> 16);
+    const int nx = __builtin_amdgcn_readfirstlane(g.n_ux);
+    const int ny = __builtin_amdgcn_readfirstlane(g.n_uy);
+    const int nu = __builtin_amdgcn_readfirstlane(g.n_u);
+    const int J1 = __builtin_amdgcn_readfirstlane(g.J1), J = J1 - 1;
+    const int cap = max(1, min(64, kAdjTerms / nu));
+    const int cnt = (J1 + (J1 + cap - 1) / cap - 1) / ((J1 + cap - 1) / cap);   // balanced groups
     __syncthreads();                  // the previous item's LDS reads are done
     const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
     for (int e = threadIdx.x; e < kSmallMap * kSmallMap; e += 256) {
-      const int yy = e / kSmallMap, xx = e % kSmallMap;
-      lam[yy][xx] = (yy < ny && xx < nx) ? (float)lamN[yy * nx + xx] : 0.f;
+      const int xx = e / kSmallMap, yy = e % kSmallMap;
+      lam[xx][yy] = (yy < ny && xx < nx) ? (float)lamN[yy * nx + xx] : 0.f;
     }
     if (threadIdx.x < kSmallMap) {
       const int q = threadIdx.x;
@@ -1329,127 +1614,110 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
     const dual cs = {cos(inc), -sin(inc)};
     const dual si2 = sn * sn, ci2 = cs * cs;
     const double G = grav_const(), sp = g.s_pc;
-    if (threadIdx.x < nj) {
-      const int j = j0 + threadIdx.x;
-      double *v = jv[threadIdx.x];
-      if (j < J) {
-        const double qo = g.mass_q[j], sj = g.mass_sigma[j];
-        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
-        const dual qj = dsqrt(qo * qo - ci2) / sn;
-        const dual e2 = 1.0 - qj * qj;
-        v[0] = e2.v;
-        v[1] = e2.d;
-        v[2] = 0.5 / (sj * sj);
-        v[3] = sqrt(2.0 / kPi) * G / (sp * sj);
-        v[4] = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
-      } else {
-        v[0] = 0.0;
-        v[1] = 0.0;
-        v[2] = 0.5 / (g.bh_sigma * g.bh_sigma);
-        v[3] = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
-        v[4] = p.m_bh[it.m];
-      }
-    }
-    // tracer k: deprojection (App. A) with its inclination derivative
-    const double qok = g.lum_q[k], sk = g.lum_sigma[k];
-    const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
-    const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
-    const dual qk = dsqrt(qok * qok - ci2) / sn;
-    const double alpha = 0.5 / (sk * sk);
-    const dual alphaq = dconst(alpha) / (qk * qk);
-    const dual nu1 = dconst(qok / (sqrt(2.0 * kPi) * sk)) / qk;   // nu0 / I0
-    const dual pf = ci2 + b * si2;
-    __syncthreads();
-    const int n_terms = nj * nu;
-    for (int base = 0; base < n_terms; base += 256) {
-      const int tl = base + threadIdx.x;
-      if (tl >= n_terms) break;
-      const int jj = tl / nu, n = tl - jj * nu;
-      const double *v = jv[jj];
-      const double r = v[2], Mj = v[4];
-      const double u = g.u[n], wq = g.w[n], u2 = u * u;
-      const dual h = {fma(-v[0], u2, 1.0), -u2 * v[1]};
-      const double c1 = alpha + r * u2;
-      const double rhv = rcp64(h.v);
-      const dual rh = {rhv, -rhv * rhv * h.d};
-      const dual A = alphaq + (r * u2) * rh;
-      const dual a = c1 * si2 + A * ci2;
-      const double rav = rcp64(a.v);
-      const dual gam = c1 * A * dual{rav, -rav * rav * a.d};
-      const double rshv = rsq64(h.v);
-      const dual rsh = {rshv, -0.5 * rshv * rhv * h.d};
-      const dual bse = (v[3] * r * u2) * nu1;                 // per unit I0 M
-      const double rAv = rcp64(A.v);
-      const dual gg = bse * dual{rAv, -rAv * rAv * A.d} * rh * rsh;
-      const dual ww = 2.0 * bse * rsh;
-      const dual P = pf * gg;
-      const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
-      const double fv = wq * kSqrtPi * rsq64(a.v);
-      const dual f = {fv, -0.5 * fv * rav * a.d};
-      const dual c0 = f * P, c1u = f * Q;                     // C = I0 M c
-      const double amp = I0 * Mj;
-      const float cx = (float)(-c1 * kLog2e), cy = (float)(-gam.v * kLog2e);
-      const float C0 = (float)(amp * c0.v), C1 = (float)(amp * c1u.v);
-      float gx[kSmallMap], hx[kSmallMap];
-#pragma unroll
-      for (int xx = 0; xx < kSmallMap; ++xx) gx[xx] = hx[xx] = 0.f;
-      for (int yy = 0; yy < ny; ++yy) {
-        const float y2 = ysq[yy];
-        const float F = fast_exp2(cy * y2), Fy = F * y2;
-        const float4 *lr = reinterpret_cast<const float4 *>(lam[yy]);
-#pragma unroll
-        for (int xq = 0; xq < kSmallMap / 4; ++xq) {
-          if (4 * xq < nx) {          // uniform
-            const float4 l = lr[xq];
-            gx[4 * xq] = fmaf(l.x, F, gx[4 * xq]);
-            hx[4 * xq] = fmaf(l.x, Fy, hx[4 * xq]);
-            gx[4 * xq + 1] = fmaf(l.y, F, gx[4 * xq + 1]);
-            hx[4 * xq + 1] = fmaf(l.y, Fy, hx[4 * xq + 1]);
-            gx[4 * xq + 2] = fmaf(l.z, F, gx[4 * xq + 2]);
-            hx[4 * xq + 2] = fmaf(l.z, Fy, hx[4 * xq + 2]);
-            gx[4 * xq + 3] = fmaf(l.w, F, gx[4 * xq + 3]);
-            hx[4 * xq + 3] = fmaf(l.w, Fy, hx[4 * xq + 3]);
+    double *rows = chain_rows(sens, md, g);
+    for (int k = k0; k < k1; ++k) {
+      // tracer k: deprojection (App. A) with its inclination derivative
+      const double qok = g.lum_q[k], sk = g.lum_sigma[k];
+      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+      const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
+      const dual qk = dsqrt(qok * qok - ci2) / sn;
+      const double alpha = 0.5 / (sk * sk);
+      const dual alphaq = dconst(alpha) / (qk * qk);
+      const dual nu1 = dconst(qok / (sqrt(2.0 * kPi) * sk)) / qk;   // nu0 / I0
+      const dual pf = ci2 + b * si2;
+      for (int j0 = 0; j0 < J1; j0 += cnt) {
+        const int nj = min(cnt, J1 - j0);
+        __syncthreads();              // earlier readers of jv and vals are done
+        if (threadIdx.x < nj) {
+          const int j = j0 + threadIdx.x;
+          double *v = jv[threadIdx.x];
+          if (j < J) {
+            const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+            const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+            const dual qj = dsqrt(qo * qo - ci2) / sn;
+            const dual e2 = 1.0 - qj * qj;
+            v[0] = e2.v;
+            v[1] = e2.d;
+            v[2] = 0.5 / (sj * sj);
+            v[3] = sqrt(2.0 / kPi) * G / (sp * sj);
+            v[4] = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
+          } else {
+            v[0] = 0.0;
+            v[1] = 0.0;
+            v[2] = 0.5 / (g.bh_sigma * g.bh_sigma);
+            v[3] = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
+            v[4] = p.m_bh[it.m];
           }
         }
-      }
-      float s0 = 0.f, s1 = 0.f, sg = 0.f;
-#pragma unroll
-      for (int xx = 0; xx < kSmallMap; ++xx) {
-        if (xx < nx) {                // uniform
-          const float x2 = xsq[xx];
-          const float E = fast_exp2(cx * x2);
-          const float Eg = E * gx[xx];
-          s0 += Eg;
-          s1 = fmaf(Eg, x2, s1);
-          sg = fmaf(E * hx[xx], fmaf(C1, x2, C0), sg);
+        __syncthreads();
+        const int n_terms = nj * nu;
+        for (int base = 0; base < n_terms; base += 256) {
+          const int tl = base + threadIdx.x;
+          if (tl >= n_terms) break;
+          const int jj = tl / nu, n = tl - jj * nu;
+          const double *v = jv[jj];
+          const double r = v[2], Mj = v[4];
+          const double u = g.u[n], wq = g.w[n], u2 = u * u;
+          const dual h = {fma(-v[0], u2, 1.0), -u2 * v[1]};
+          const double c1 = alpha + r * u2;
+          const double rhv = rcp64(h.v);
+          const dual rh = {rhv, -rhv * rhv * h.d};
+          const dual A = alphaq + (r * u2) * rh;
+          const dual a = c1 * si2 + A * ci2;
+          const double rav = rcp64(a.v);
+          const dual gam = c1 * A * dual{rav, -rav * rav * a.d};
+          const double rshv = rsq64(h.v);
+          const dual rsh = {rshv, -0.5 * rshv * rhv * h.d};
+          const dual bse = (v[3] * r * u2) * nu1;               // per unit I0 M
+          const double rAv = rcp64(A.v);
+          const dual gg = bse * dual{rAv, -rAv * rAv * A.d} * rh * rsh;
+          const dual ww = 2.0 * bse * rsh;
+          const dual P = pf * gg;
+          const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
+          const double fv = wq * kSqrtPi * rsq64(a.v);
+          const dual f = {fv, -0.5 * fv * rav * a.d};
+          const dual c0 = f * P, c1u = f * Q;                   // C = I0 M c
+          const double amp = I0 * Mj;
+          const float cx = (float)(-c1 * kLog2e), cy = (float)(-gam.v * kLog2e);
+          const float C0 = (float)(amp * c0.v), C1 = (float)(amp * c1u.v);
+          float s0, s1, sg;
+          switch ((ny + 3) >> 2) {    // uniform
+            case 1: small_sums<1>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 2: small_sums<2>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 3: small_sums<3>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 4: small_sums<4>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 5: small_sums<5>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 6: small_sums<6>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            case 7: small_sums<7>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+            default: small_sums<8>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          }
+          const double S0 = s0, S1 = s1, Sg = sg;
+          vals[tl][0] = amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
+          // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
+          vals[tl][1] = amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
+          vals[tl][2] = S0 * c0.v + S1 * c1u.v;
         }
-      }
-      const double S0 = s0, S1 = s1, Sg = sg;
-      vals[tl][0] = amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
-      // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
-      vals[tl][1] = amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
-      vals[tl][2] = S0 * c0.v + S1 * c1u.v;
-    }
-    __syncthreads();
-    // (k, j) rows: one wave per mass Gaussian, lanes over the u-nodes in
-    // order, then a butterfly
-    double *rows = chain_rows(sens, md, g);
-    for (int jj = wave; jj < nj; jj += 4) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-      for (int n = lane; n < nu; n += 64) {
-        const double *v = vals[jj * nu + n];
-        a0 += v[0];
-        a1 += v[1];
-        a2 += v[2];
-      }
-      a0 = wave_sum(a0);
-      a1 = wave_sum(a1);
-      a2 = wave_sum(a2);
-      if (lane == 0) {
-        double *o = rows + ((int64_t)k * g.J1 + j0 + jj) * 3;
-        o[0] = a0;
-        o[1] = a1;
-        o[2] = a2;
+        __syncthreads();
+        // (k, j) rows: one wave per mass Gaussian, lanes over the u-nodes in
+        // order, then a butterfly
+        for (int jj = wave; jj < nj; jj += 4) {
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+          for (int n = lane; n < nu; n += 64) {
+            const double *v = vals[jj * nu + n];
+            a0 += v[0];
+            a1 += v[1];
+            a2 += v[2];
+          }
+          a0 = wave_sum(a0);
+          a1 = wave_sum(a1);
+          a2 = wave_sum(a2);
+          if (lane == 0) {
+            double *o = rows + ((int64_t)k * J1 + j0 + jj) * 3;
+            o[0] = a0;
+            o[1] = a1;
+            o[2] = a2;
+          }
+        }
       }
     }
   }
@@ -2989,15 +3257,30 @@ void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
     hipLaunchKernelGGL(k_num_pix, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
                        st_ws, part, queue);
 }
+void launch_num_map(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                    const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_num_map, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
+                     st_ws, part, queue);
+}
+void launch_reduce_f32(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                       const double *part, double *pix, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_f32, dim3(grid_of(n_it)), dim3(512), 0, st, g, m, it, n_it, part,
+                     pix);
+}
 void launch_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                    const double *part, double *pix, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, part, pix);
 }
-void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+void launch_bins(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, int n_wave,
                  const double *pix, const int *st_ws, double *vrms2, double *binws,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_bins, dim3(grid_of(n_it)), dim3(1024), 0, st, g, m, it, n_it, pix, st_ws,
-                     vrms2, binws);
+  if (n_wave > 0)
+    hipLaunchKernelGGL(k_bins<256>, dim3(n_wave), dim3(256), 0, st, g, m, it, n_wave, pix,
+                       st_ws, vrms2, binws);
+  if (n_it > n_wave)
+    hipLaunchKernelGGL(k_bins<1024>, dim3(n_it - n_wave), dim3(1024), 0, st, g, m, it + n_wave,
+                       n_it - n_wave, pix, st_ws, vrms2, binws);
 }
 void launch_maps(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const double *pix, const int *st_ws, double *N_map, double *I_map,

@@ -379,3 +379,55 @@ def test_isotropic_spherical_close_to_cylindrical_ifu_scale():
     assert st[0] == 0 and err <= 1e-4
     cyl.close()
     sph.close()
+
+
+def test_forward_k20_j20_vs_golden():
+    """K = J = 20 (+ BH), 64 u-nodes, 2x-supersampled 8 x 7 grid, 5x5 PSF:
+    three rounds of eight tracers per moment-table point and 1344 (j, u)
+    terms in two LDS coefficient chunks, against the stored FP64 oracle."""
+    dev = _dev()
+    gold = json.load(open(os.path.join(HERE, "golden", "sph_fwd_large.json")))
+    g = inputs.small_geometry(seed=12, n_lum=20, n_mass=20, nx=8, ny=7, ss=2, psf_n=5,
+                              n_bins=5, n_u=64, pixsize=0.08)
+    params = [inputs.small_params(g, seed=c["seed"]) for c in gold["cases"]]
+    w = inputs.Workload("sph20", [g], np.zeros(len(params), np.int32), params)
+    ctx = binding.Context([g], alignment=1)
+    V, st = _eval(ctx, w, dev)
+    ref = np.concatenate([np.array(c["vrms2"]) for c in gold["cases"]])
+    err = np.max(np.abs(V / ref - 1))
+    print(f"K = J = 20: max rel err {err:.2e} over {len(V)} bins")
+    assert (st == 0).all() and err <= RTOL
+    ctx.close()
+
+
+def test_adjoint_multi_tile_vs_oracle_differences():
+    """Gradient at 9 tracers of mixed anisotropy x (8 mass Gaussians + BH) x
+    128 u-nodes = 1152 (j, u) terms: five 256-term tiles of the term-major
+    sensitivity pass, two 1024-term coefficient chunks and two tracer rounds
+    of the characteristic integrals' adjoint, against stored central
+    differences of the FP64 oracle, at the adjoint bar."""
+    dev = _dev()
+    gold = json.load(open(os.path.join(HERE, "golden", "sph_grad_large.json")))
+    g = inputs.small_geometry(seed=11, n_lum=9, n_mass=8, nx=6, ny=5, ss=1, psf_n=3,
+                              n_bins=3, n_u=128)
+    p = inputs.small_params(g, seed=11)
+    assert (np.array(p.beta) > 0).any() and (np.array(p.beta) < 0).any()
+    w = inputs.Workload("g", [g], np.zeros(1, np.int32), [p])
+    ctx = binding.Context([g], alignment=1)
+    pk = binding.pack_params(w, dev, amplitudes=True)
+    V, st = ctx.eval_batch(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
+                           pk["lum_I0"], pk["mass_S0"])
+    assert int(st[0]) == 0
+    ferr = np.max(np.abs(V.cpu().numpy() / np.array(gold["vrms2"]) - 1))
+    assert ferr <= RTOL, ferr
+    cot = torch.as_tensor(np.array(gold["cot"]), device=dev)
+    gr = ctx.vjp(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
+                 pk["lum_I0"], pk["mass_S0"], V, cot)
+    a = np.concatenate([np.atleast_1d(gr[k].cpu().numpy()) for k in KEYS])
+    b = np.concatenate([np.atleast_1d(np.array(gold["grad"][k])) for k in KEYS])
+    err = np.linalg.norm(a - b) / np.linalg.norm(b)
+    comp = np.abs(a - b) <= np.maximum(1e-3 * np.abs(b), 1e-6 * np.max(np.abs(b)))
+    print(f"1152 terms, 9 tracers: forward {ferr:.2e}; grad rel norm err {err:.3e}; "
+          f"components ok {comp.sum()}/{comp.size}")
+    assert err <= 1e-4 and comp.all(), np.nonzero(~comp)
+    ctx.close()
