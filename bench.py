@@ -94,19 +94,19 @@ def cpu_baseline(g, p, n_sample):
                        f"IFU-scale model ({dt:.1f} s), scaled to one model")
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the matrix-core quadrature kernel (k_num_mfma)
+def profiled_traffic(kernel):
+    """HBM bytes per launch of the quadrature kernel on the IFU-scale model
     from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None
     when the kernel source has changed since."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_num_mfma_ifu_scale_hbm.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_ifu_scale_hbm.md")
     src = os.path.join(ROOT, "paper_2504_01302_amd", "csrc", "jam_kernels.hip")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     h = re.search(r"Kernel source sha256: ([0-9a-f]{64})", text)
-    b = re.search(r"k_num_mfma_traffic_bytes_per_launch: ([0-9.]+)", text)
+    b = re.search(kernel + r"_traffic_bytes_per_launch: ([0-9.]+)", text)
     if not h or not b:
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
@@ -114,9 +114,41 @@ def profiled_traffic():
     return float(b.group(1))
 
 
+KERNEL_NAMES = {0: "k_num_pix", 1: "k_num_mfma", 2: "k_num_map", 3: "k_sph_moments"}
+
+
+def unique_units(g):
+    """Unique pixels (distinct |x'| x distinct |y'| of the padded sub-pixel
+    grid, the map the kernels evaluate) times terms K (J + 1) n_u."""
+    def distinct(n, c):
+        v = (np.arange(n * g.supersample + g.psf_n - 1) - (n * g.supersample + g.psf_n - 2) / 2.0)
+        return len(set(np.abs(c + v * (g.pixsize / g.supersample)).round(12)))
+    n_pix = distinct(g.nx, g.xc) * distinct(g.ny, g.yc)
+    return n_pix * g.n_lum * (g.n_mass + 1) * g.n_u
+
+
+def roofline_fracs(w, ms_fwd, ms_fb, num_ms=None, sens_ms=None):
+    """Fractions of the FP32 matrix-core peak at the algorithmic flop counts
+    per (unique pixel, term): 2 for the forward quadrature (N = A B^T), 4 for
+    the adjoint's two contractions, 6 for a forward + adjoint step."""
+    units = float(sum(unique_units(w.geometries[i]) for i in w.geom_idx))
+    out = {"units": units,
+           "forward_frac": 2 * units / (ms_fwd * 1e-3) / FP32_MFMA_PEAK,
+           "fwd_bwd_frac": 6 * units / (ms_fb * 1e-3) / FP32_MFMA_PEAK}
+    if num_ms:
+        out["numerator_kernel_ms"] = num_ms
+        out["numerator_kernel_frac"] = 2 * units / (num_ms * 1e-3) / FP32_MFMA_PEAK
+    if sens_ms:
+        out["adjoint_kernel_ms"] = sens_ms
+        out["adjoint_kernel_frac"] = 4 * units / (sens_ms * 1e-3) / FP32_MFMA_PEAK
+    return out
+
+
 def time_batch(torch, binding, w, dev, steps, form, launch, graph, autotune=0):
     """Forward and forward+adjoint throughput of one whole batch per launch
-    (with autotune, the schedule search runs at the first call, untimed)."""
+    (with autotune, the schedule search runs at the first call, untimed),
+    and the quadrature and adjoint kernels' average durations from an eager
+    loop of the same batch."""
     ctx = binding.Context(w.geometries, form=form, launch=launch, graph=graph, autotune=autotune)
     par = binding.pack_params(w, dev, amplitudes=True)
     nb, _, _ = ctx.sizes(w.geom_idx)
@@ -154,9 +186,30 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph, autotune=0):
     ok = bool((st == 0).all().item())
     sched = ctx.plan_info(w.geom_idx)
     ctx.close()
-    return {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
-            "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok,
-            "schedule": sched}
+    # kernel durations from eager launches (graph replays are not bracketed)
+    ek = binding.Context(w.geometries, form=form, launch=launch, graph=0, autotune=autotune)
+
+    def efwd():
+        ek.eval_batch(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                      par["lum_I0"], par["mass_S0"], out=V, status=st)
+
+    efwd()
+    ek.vjp(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+           par["lum_I0"], par["mass_S0"], V, cot)
+    torch.cuda.synchronize()
+    binding.jam_timing(ek.handle, True)
+    for _ in range(max(2, steps // 2)):
+        efwd()
+        ek.vjp(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+               par["lum_I0"], par["mass_S0"], V, cot)
+    num_ms, num_n, sens_ms, sens_n = binding.jam_timing(ek.handle, False)
+    ek.close()
+    rec = {"models": n, "ms_forward": ms_f, "models_per_s": n * 1000.0 / ms_f,
+           "ms_fwd_bwd": ms_fb, "fwd_bwd_per_s": n * 1000.0 / ms_fb, "all_status_ok": ok,
+           "schedule": sched, "numerator_kernel": KERNEL_NAMES.get(sched.get("num_kernel"))}
+    rec["roofline"] = roofline_fracs(w, ms_f, ms_fb, num_ms / max(1, num_n),
+                                     sens_ms / max(1, sens_n))
+    return rec
 
 
 def time_spherical(torch, binding, w, dev, steps, backward=True):
@@ -520,11 +573,12 @@ def main():
         flops = PIX_FLOPS_PER_INTEGRAND * n_pix * T * n
         roof = dict(bound="alu", peak=FP32_VECTOR_PEAK / 1e12)
     achieved = flops / avg_num_s / 1e12 if avg_num_s else None
-    traffic = profiled_traffic() if (form_used == 2 and n == 1 and a.launch == 0
-                                     and not a.autotune) else None
+    kname = KERNEL_NAMES.get(ctx.plan_info(w.geom_idx).get("num_kernel"), "k_num_pix")
+    traffic = profiled_traffic(kname) if (form_used == 2 and n == 1 and a.launch == 0
+                                          and not a.autotune) else None
     roof.update(achieved=achieved, unit="TFLOP/s",
                 frac=achieved / roof["peak"] if achieved else None, traffic=traffic,
-                kernel="k_num_mfma" if form_used == 2 else "k_num_pix", avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
+                kernel=kname, avg_launch_ms=avg_num_s * 1e3 if avg_num_s else None,
                 launches=num_n, flops_per_launch=flops)
 
     rec = {

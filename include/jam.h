@@ -328,10 +328,12 @@ jam_status jam_timing(jam_ctx *ctx, int32_t enable, double *numerator_ms,
                       int64_t *numerator_launches, double *sens_ms, int64_t *sens_launches);
 
 /* Schedule chosen for a batch composition (prepares it if needed):
- * info[0..7] = numerator rule (0 per-pixel, 1 MFMA), 64x64-tile threshold,
+ * info[0..8] = numerator rule (0 per-pixel, 1 MFMA), 64x64-tile threshold,
  * slice length per item ((k, j) pairs, or units of 64 terms), launch mode,
  * numerator work items, numerator workgroups launched, adjoint work items,
- * adjoint workgroups launched.                                               */
+ * adjoint workgroups launched, numerator kernel (0 per-pixel k_num_pix,
+ * 1 matrix-core tiles k_num_mfma, 2 whole-map matrix core k_num_map,
+ * 3 spherical moments k_sph_moments).  info holds 9 int32 (host memory). */
 jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32_t *info);
 
 /* Host utility: the n-node Gauss-Legendre rule on [0, 1] that the library

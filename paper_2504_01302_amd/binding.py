@@ -196,10 +196,11 @@ def jam_workspace_size(ctx: int, geom_idx, with_vjp: bool) -> int:
 
 def jam_plan_info(ctx: int, geom_idx) -> dict:
     gi = _idx(geom_idx)
-    info = np.zeros(8, np.int32)
+    info = np.zeros(9, np.int32)
     _check(load().jam_plan_info(c_void_p(ctx), len(gi), gi.ctypes.data_as(P_int32),
                                 info.ctypes.data_as(P_int32)))
-    keys = ("rule", "tau", "gran", "launch", "num_items", "num_grid", "sens_items", "sens_grid")
+    keys = ("rule", "tau", "gran", "launch", "num_items", "num_grid", "sens_items", "sens_grid",
+            "num_kernel")
     return dict(zip(keys, (int(v) for v in info)))
 
 

@@ -621,6 +621,9 @@ int default_gran(const jam_ctx *ctx, int n, const int32_t *geom_idx, const Tune 
     const int s_max = std::min(4096, (int)(4 * per_slot) * slots / std::max(1, big_tiles) + 1);
     for (int sl = 1; sl <= s_max; ++sl) cands.push_back((big_units + sl - 1) / sl);
   }
+  // whole-map slices are capped (FP32 accumulation): every length up to the cap
+  if (t.map)
+    for (int gr = 1; gr <= kMapMaxUnits; ++gr) cands.push_back(gr);
   std::sort(cands.begin(), cands.end());
   cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
   double best = 1e300;
@@ -710,7 +713,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     // spherical: float4 terms, then floats; small maps compute their terms in place
     terms += spherical ? tsph + tsph / 4 : (small ? 0 : g.T);
     pixd += 4 * (int64_t)g.n_pix;
-    part += (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);   // padded to whole blocks
+    // padded to whole blocks; FP32 partials (whole-map numerator) take half
+    const int64_t part_elems = (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);
+    part += nc.map ? (part_elems + 1) / 2 : part_elems;
     bins += 2 * (int64_t)g.n_bins;
     if (spherical) {
       d.n_sens_parts = jam::sph_ranges(g.K);
@@ -1882,6 +1887,7 @@ jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32
   info[5] = p->grid_num;
   info[6] = p->n_sens + p->n_adj;
   info[7] = (p->n_sens ? p->grid_sens : 0) + p->n_adj;
+  info[8] = p->spherical ? 3 : (p->tune.rule == 0 ? 0 : (p->tune.map ? 2 : 1));
   return JAM_OK;
 }
 
