@@ -87,11 +87,24 @@ def cpu_baseline(g, p, n_sample):
                               if ln.startswith("model name")), None)
     except OSError:
         pass
+    # a whole model end to end (every padded sub-pixel, PSF, all bins) on
+    # the small geometry, beside the sampled IFU-scale figure
+    from paper_2504_01302_amd import inputs
+    w1 = inputs.config1()
+    t0 = time.perf_counter()
+    ojam.vrms2(w1.geometries[0], w1.params[0])
+    dt1 = time.perf_counter() - t0
     return dict(value=1.0 / per_model, unit="models/s", cores=torch.get_num_threads(),
                 kind="oracle", cpu_model=cpu_model, nproc=os.cpu_count(),
                 affinity=len(os.sched_getaffinity(0)),
                 sample=f"N and I at {n_sample} of {len(x) * len(y)} padded sub-pixels of the "
-                       f"IFU-scale model ({dt:.1f} s), scaled to one model")
+                       f"IFU-scale model ({dt:.1f} s), scaled to one model; the oracle evaluates "
+                       f"every padded sub-pixel, i.e. all four mirror copies that the GPU "
+                       f"evaluates once",
+                whole_model_small_geometry={
+                    "seconds": dt1, "models_per_s": 1.0 / dt1,
+                    "workload": "oracle vrms2 end to end (30x30 px, 9x9 PSF, 20 bins, 10 x 12 "
+                                "Gaussians + BH, 100 u-nodes), one model"})
 
 
 def profiled_traffic(kernel):

@@ -514,7 +514,7 @@ NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
     c.kind = 0;
     c.n_slices = std::max(1, (pairs + per - 1) / per);
     c.units = pairs;
-    c.pix_blocks = (g.n_pix + 63) / 64;
+    c.pix_blocks = (g.n_pix + 255) / 256;
     return c;
   }
   const int chunks = (g.T + 63) / 64;
@@ -546,7 +546,7 @@ double num_item_cost(const GeomHost &g, const NumChoice &c, int slice, int tile)
     const int pairs = g.K * g.J1;
     const int per = (pairs + c.n_slices - 1) / c.n_slices;
     const int cnt = std::max(0, std::min(pairs, (slice + 1) * per) - slice * per);
-    return cnt * (double)g.n_u * 64.0 * 5.0 / 32768.0 + 1.0;
+    return cnt * (double)g.n_u * 256.0 * 5.0 / 32768.0 + 1.0;
   }
   const int chunks = (g.T + 63) / 64;
   const int per = (chunks + c.n_slices - 1) / c.n_slices;

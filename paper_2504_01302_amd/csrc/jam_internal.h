@@ -146,7 +146,7 @@ void launch_setup(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
 void launch_sb(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                double *pix, hipStream_t st);
 // Numerator over a work list of workgroup items.  mfma = false: per-pixel
-// VALU form, items (m, 64-pixel block, slice).  mfma = true: matrix-core
+// VALU form, items (m, 256-pixel block, slice).  mfma = true: matrix-core
 // form, items (m, tile origin in 32-blocks x | y << 16, slice, variant 2..5 =
 // tile of (1,1), (2,1), (1,2), (2,2) blocks of 32x32; variant 6 = a map of
 // one 32x32 block whose terms are computed from the Gaussian table `gauss`

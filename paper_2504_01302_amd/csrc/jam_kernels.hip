@@ -419,19 +419,19 @@ __global__ void __launch_bounds__(256) k_prologue(const GeomDev *__restrict__ ge
 }
 
 // ---------------------------------------------------------------------------
-// Per-pixel VALU quadrature.  Item (m, 64-pixel block, slice); the slice is a
-// range of (k, j) pairs, split over the 4 waves; lanes are unique pixels and
-// the term coefficients are wave-uniform (scalar loads).
+// Per-pixel VALU quadrature.  Item (m, block of 256 unique pixels, slice of
+// (k, j) pairs); thread = pixel.  The slice's terms are staged through LDS
+// in runs of whole (k, j) pairs (at most kPixStage terms), read back as
+// broadcasts (the same address in every lane); per pair the integrand is
+// summed over the u-nodes in FP32 and folded into an FP64 accumulator.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__restrict__ geoms,
-    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, char *smem) {
-  double *red = reinterpret_cast<double *>(smem);
+constexpr int kPixStage = 1024;
 
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__restrict__ geoms,
+    const ModelDev *__restrict__ models, const float4 *__restrict__ terms, const int *__restrict__ st_ws, double *__restrict__ part, float4 *stage) {
   const ModelDev md = models[it.m];
   const GeomDev g = geoms[md.geom];
-  const int q = it.a * 64 + lane;
+  const int q = it.a * 256 + threadIdx.x;
   const bool valid = q < g.n_pix;
   float x2 = 0.f, y2 = 0.f;
   if (valid) {
@@ -443,28 +443,39 @@ __device__ __forceinline__ void num_pix_item(const Item it, const GeomDev *__res
   const int per = (n_pairs + md.n_slices - 1) / md.n_slices;
   const int p0 = it.b * per;
   const int p1 = min(n_pairs, p0 + per);
+  const int nu = __builtin_amdgcn_readfirstlane(g.n_u);
+  const int run = max(1, kPixStage / nu);   // pairs per LDS run
   double acc = 0.0;
   if (st_ws[it.m] == 0) {
     const float4 *tb = terms + md.term_off;
-    const int nu = g.n_u;
-    for (int pr = p0 + wave; pr < p1; pr += 4) {
-      const float4 *tp = tb + (int64_t)pr * nu;
-      float s = 0.f;
-      for (int n = 0; n < nu; ++n) {
-        const float4 c = tp[n];
-        const float e = fast_exp2(fmaf(c.x, x2, c.y * y2));
-        s = fmaf(e, fmaf(c.w, x2, c.z), s);
+    for (int r0 = p0; r0 < p1; r0 += run) {
+      const int r1 = min(p1, r0 + run);
+      const int nt = (r1 - r0) * nu;
+      __syncthreads();                 // the previous run's reads are done
+      for (int e = threadIdx.x; e < nt; e += 256) stage[e] = tb[(int64_t)r0 * nu + e];
+      __syncthreads();
+      for (int pr = 0; pr < r1 - r0; ++pr) {
+        const float4 *tp = stage + pr * nu;
+        float s = 0.f;
+        int n = 0;
+        for (; n + 4 <= nu; n += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float4 c = tp[n + u];
+            const float e = fast_exp2(fmaf(c.x, x2, c.y * y2));
+            s = fmaf(e, fmaf(c.w, x2, c.z), s);
+          }
+        }
+        for (; n < nu; ++n) {
+          const float4 c = tp[n];
+          const float e = fast_exp2(fmaf(c.x, x2, c.y * y2));
+          s = fmaf(e, fmaf(c.w, x2, c.z), s);
+        }
+        acc += (double)s;
       }
-      acc += (double)s;
     }
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 64 && valid) {
-    const double v = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
-    part[md.part_off + it.b * part_slice_size(md) + part_index(md, g, q)] = v;
-  }
-  __syncthreads();
+  if (valid) part[md.part_off + it.b * part_slice_size(md) + part_index(md, g, q)] = acc;
 }
 
 
@@ -658,7 +669,7 @@ __device__ __forceinline__ void num_tile_item(const Item it, const GeomDev *__re
     }
 }
 
-// Numerator, per-pixel VALU form, over a work list of items (m, 64-pixel
+// Numerator, per-pixel VALU form, over a work list of items (m, 256-pixel
 // block, slice).  With a queue, every workgroup pulls the next item from a
 // device counter (a persistent grid; items are ordered largest first);
 // without one, workgroups stride over the list.
@@ -668,7 +679,7 @@ __global__ void __launch_bounds__(256) k_num_pix(const GeomDev *__restrict__ geo
                                                  const float4 *__restrict__ terms,
                                                  const int *__restrict__ st_ws,
                                                  double *__restrict__ part, int *queue) {
-  __shared__ double smem[256];
+  __shared__ float4 stage[kPixStage];
   __shared__ int next;
   int i = blockIdx.x;
   for (;;) {
@@ -679,7 +690,7 @@ __global__ void __launch_bounds__(256) k_num_pix(const GeomDev *__restrict__ geo
       __syncthreads();
     }
     if (i >= n_it) break;
-    num_pix_item(items[i], geoms, models, terms, st_ws, part, reinterpret_cast<char *>(smem));
+    num_pix_item(items[i], geoms, models, terms, st_ws, part, stage);
     if (!queue) i += gridDim.x;
   }
 }

@@ -4,8 +4,8 @@ Every value here comes from the FP64 oracle (``oracle/``) evaluated on the
 seeded synthetic workloads of ``paper_2504_01302_amd.inputs``; nothing comes
 from the GPU library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [cfg2] [composite] [cfg3] [cfg4] [cfg5] [sph1] [sph_grad]
-                                       [sph_grad_large] [sph_fwd_large] [cyl_edge]
+    python tests/golden/make_golden.py [cfg2] [composite] [cfg3] [cfg4] [cfg5_all] [sph1] [sph_grad]
+                                       [sph_grad_large] [sph_fwd_large] [cfg5_all]
 """
 import json
 import os
@@ -104,20 +104,20 @@ def cfg4(n_models=1024, n_check=32, bins_per_model=2):
         checks=out))
 
 
-def cfg5(n_models=256, n_check=8):
-    """Gradients: oracle autograd gradients of sum cot * vrms2 for a seeded
-    subset of the 256 config-5 models, cotangent inputs.cotangent(seed 0)."""
+def cfg5_all(n_models=256):
+    """Gradients of all 256 config-5 models: oracle autograd gradients of
+    sum cot * vrms2, cotangent inputs.cotangent(seed 0)."""
+    t = time.time()
     w = inputs.config5(n_models=n_models)
     cot = inputs.cotangent(w.geometries[0].n_bins, n_models)
-    idx = np.sort(np.random.default_rng(5).choice(n_models, n_check, replace=False))
     out = []
-    for m in idx:
+    for m in range(n_models):
         V, gr = ojam.vrms2_and_grad(w.geometries[0], w.params[m], cot[m])
-        out.append(dict(model=int(m), vrms2=V.numpy().tolist(),
+        out.append(dict(vrms2=V.numpy().tolist(),
                         grads={k: np.atleast_1d(v.numpy()).tolist() for k, v in gr.items()}))
-    _dump("cfg5_grads.json", dict(
-        source="oracle/jam.py vrms2_and_grad on inputs.config5(256), seeded subset",
-        checks=out))
+    _dump("cfg5_grads_all.json", dict(
+        source="oracle/jam.py vrms2_and_grad on inputs.config5(256), every model",
+        models=out, seconds=time.time() - t))
 
 
 def sph1(n_models=3):
@@ -263,6 +263,7 @@ def sph_fwd_large():
 
 if __name__ == "__main__":
     torch.set_num_threads(int(os.environ.get("GOLDEN_THREADS", os.cpu_count() or 1)))
-    todo = sys.argv[1:] or ["cfg2", "composite", "cfg3", "cfg4", "cfg5", "sph1", "sph_grad"]
+    todo = sys.argv[1:] or ["cfg2", "composite", "cfg3", "cfg4", "cfg5_all", "sph1", "sph_grad",
+                            "sph_grad_large", "sph_fwd_large"]
     for name in todo:
         globals()[name]()
