@@ -347,9 +347,9 @@ struct Plan {
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
             *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
-            *d_redf = nullptr;
+            *d_redf = nullptr, *d_sensw = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0;
+      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0;
   int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
@@ -673,8 +673,23 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro, it_adj, it_redf;
-  std::vector<double> c_num, c_sens;
+      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw;
+  std::vector<double> c_num, c_sens, c_sensw;
+  // 32-term groups per wide-sensitivity item: one compute unit's share of
+  // the batch's groups (over all parts), a multiple of the 4 waves
+  std::vector<jam::Item> &wide_list = it_sensw;
+  int wide_per = 4;
+  if (ctx->opt.alignment != 1) {
+    // work in units of (32-term group x 4 tiles)
+    int64_t tot = 0;
+    for (int m = 0; m < n; ++m) {
+      const GeomHost &g = ctx->gh[geom_idx[m]];
+      const int nx = (g.n_ux + 31) / 32;
+      if (nx >= 2) tot += (int64_t)nx * ((g.T + 31) / 32);
+    }
+    const int64_t share = (tot / 4 + ctx->n_cu - 1) / std::max(1, ctx->n_cu);
+    wide_per = (int)std::max<int64_t>(4, (share + 3) / 4 * 4);
+  }
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
   for (int m = 0; m < n; ++m) {
@@ -691,7 +706,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     const bool small = !spherical && nc.gen;
     d.form = nc.kind == 0 ? 1 : (small ? 3 : (nc.map ? 4 : 2));
     d.part_f32 = nc.map ? 1 : 0;
-    d.n_sens_parts = d.form == 1 ? 1 : (small ? 0 : (g.n_ux + 31) / 32);
+    // adjoint sensitivity blocks: one (per-pixel), none (small map), one per
+    // x tile (one tile), one per part of up to four x tiles (wide)
+    const int n_xt = (g.n_ux + 31) / 32;
+    const bool wide = !spherical && !small && d.form != 1 && n_xt >= 2;
+    d.n_sens_parts = d.form == 1 ? 1 : (small ? 0 : (wide ? (n_xt + 3) / 4 : n_xt));
     d.n_xt = (g.n_ux + 31) / 32;
     d.n_yt = (g.n_uy + 31) / 32;
     d.gauss_off = gauss;
@@ -747,6 +766,17 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
         it_sens.push_back({m, tb, 0, 0});
         c_sens.push_back((double)g.n_pix);
       }
+    } else if (wide) {
+      // parts of up to four x tiles, each split into items of about one
+      // compute unit's share of the batch's 32-term groups
+      // (a part of fewer tiles takes proportionally more groups per item)
+      const int groups = (g.T + 31) / 32;
+      for (int pt = 0; pt < d.n_sens_parts; ++pt) {
+        const int xt = std::min(4, n_xt - 4 * pt);
+        const int per = std::max(4, (wide_per * 4 / xt + 3) / 4 * 4);
+        for (int g0 = 0; g0 < groups; g0 += per)
+          wide_list.push_back({m, pt | (xt << 16), g0, std::min(groups, g0 + per)});
+      }
     } else {
       for (int xt = 0; xt < d.n_sens_parts; ++xt)
         for (int tt = 0; tt < (g.T + jam::kSensTerms - 1) / jam::kSensTerms; ++tt) {
@@ -798,10 +828,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
                                       [](const jam::Item &t) { return t.c == 1; });
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
-  constexpr int kLists = 13;
+
+  constexpr int kLists = 14;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
-                                           &it_red,   &it_sph, &it_pro, &it_adj, &it_redf};
+                                           &it_red,   &it_sph, &it_pro, &it_adj, &it_redf,
+                                           &it_sensw};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -824,10 +856,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->d_models = (jam::ModelDev *)(base + o_models);
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
-                            &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf};
+                            &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf,
+                            &p->d_sensw};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
-                      &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf};
+                      &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf,
+                      &p->n_sensw};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -984,6 +1018,10 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     jam::launch_sens(ctx->d_geoms, p->d_models, p->d_sens, p->n_sens,
                      (const float4 *)(w + p->off_terms), pix, st_ws, sens,
                      p->tune.launch == 1 ? queue + 1 : nullptr, p->grid_sens, st);
+  if (p->n_sensw)
+    jam::launch_sens_wide(ctx->d_geoms, p->d_models, p->d_sensw, p->n_sensw,
+                          (const float4 *)(w + p->off_terms), pix, st_ws, sens, nullptr,
+                          p->n_sensw, st);
   if (p->n_adj)
     jam::launch_adj_small(ctx->d_geoms, p->d_models, p->d_adj, p->n_adj, pd, pix, st_ws, sens, st);
   if (timed) ctx->t_sens.end(st);
@@ -1885,8 +1923,8 @@ jam_status jam_plan_info(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, int32
   info[3] = p->tune.launch;
   info[4] = p->n_num;
   info[5] = p->grid_num;
-  info[6] = p->n_sens + p->n_adj;
-  info[7] = (p->n_sens ? p->grid_sens : 0) + p->n_adj;
+  info[6] = p->n_sens + p->n_sensw + p->n_adj;
+  info[7] = (p->n_sens ? p->grid_sens : 0) + p->n_sensw + p->n_adj;
   info[8] = p->spherical ? 3 : (p->tune.rule == 0 ? 0 : (p->tune.map ? 2 : 1));
   return JAM_OK;
 }

@@ -188,6 +188,12 @@ void launch_bins_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, in
 void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  const float4 *terms, const double *pix, const int *st_ws, double *sens,
                  int *queue, int grid, hipStream_t st);
+// Wide matrix-core sensitivities: items (m, part p | tiles << 16 for the 1-4
+// consecutive 32-row x tiles 4p.., first 32-term group, end group); one
+// workgroup per CU; queue as launch_sens (the second counter).
+void launch_sens_wide(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                      const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                      int *queue, int grid, hipStream_t st);
 // sens region per model: n_sens_parts blocks of [S0 | S1 | Sg] (T doubles
 // each), then the chain rows [K][J1][3].  Chain items (m, k, jb) for
 // jb < ceil(J1 / 4), one mass Gaussian per wave.  The per-pixel kernel

@@ -1371,6 +1371,180 @@ __global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
 }
 
 // ---------------------------------------------------------------------------
+// Per-term adjoint sensitivities, wide matrix-core form: the contractions of
+// sens_mfma_item for a part of XT <= 4 consecutive 32-row x tiles at once, so
+// that each generated F_t(y) and y^2 F_t(y) feeds 2 XT MFMAs.  lambda_N of
+// the part's rows is staged in LDS for up to 256 y at a time (once per item
+// when the map has at most 256 distinct |y|) in the layout the MFMA steps
+// read: row x holds, for each half kh of the wave, the values at y = 2s + kh
+// for consecutive steps s, so one 16-byte read gives a lane four steps'
+// operands (LDS reads cost ~25 cycles each beside the MFMAs whatever their
+// width; rows are padded by 4 floats against bank conflicts).  Per term group
+// the FP32 matrix-core sums run over all y (no FP64 fold: the 2 XT
+// accumulator blocks take 128 registers at XT = 4), the next four steps'
+// operands read ahead.  Item (m, part p | XT << 16 covering x tiles 4p ..
+// 4p + XT - 1, first 32-term group, end group); wave w takes the item's
+// groups w, w + 4, ...; output per part, [S0 | S1 | Sg] (T doubles each), as
+// sens_mfma_item's per x tile.
+// ---------------------------------------------------------------------------
+constexpr int kWideTiles = 4;
+constexpr int kWideLd = YC + 4;   // floats per staged x row: 2 halves x YC/2 steps + pad
+
+struct SensWideLds {
+  float lam[32 * kWideTiles][kWideLd];
+  float ysq[YC];                   // [kh][s] = y^2 at y = 2s + kh
+  float xsq[32 * kWideTiles];      // x^2 of the part's rows (0 past the map)
+};
+
+template <int XT>
+__device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md, const GeomDev &g,
+                                               const float4 *__restrict__ terms,
+                                               const double *__restrict__ pix,
+                                               double *__restrict__ sens, SensWideLds &L,
+                                               int wave) {
+  const int lane = threadIdx.x & 63, c32 = lane & 31, kh = lane >> 5;
+  const int part = it.a & 0xffff;
+  const int x0 = 32 * kWideTiles * part;
+  const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
+  const int n_uy = __builtin_amdgcn_readfirstlane(g.n_uy);
+  const int n_yb = (n_uy + YC - 1) / YC;
+  const int g0 = it.b, g1 = it.c;
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool staged = false;
+  if (threadIdx.x < 32 * XT) {
+    const int xr = x0 + threadIdx.x;
+    float v = 0.f;
+    if (xr < g.n_ux) { const double xv = g.xs[xr]; v = (float)(xv * xv); }
+    L.xsq[threadIdx.x] = v;          // read after the first staging barrier
+  }
+  // the group's term coefficients, loaded one group ahead
+  auto coef = [&](int gr) {
+    const int t = gr * 32 + c32;
+    return (gr < g1 && t < g.T) ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  float4 cnext = coef(g0 + wave);
+  for (int gr = g0 + wave; gr - wave < g1; gr += 4) {   // same trip count in every wave
+    const int t = gr * 32 + c32;
+    const bool vt = gr < g1 && t < g.T;
+    const float4 c = cnext;
+    cnext = coef(gr + 4);
+    v16f dg[XT], dh[XT];
+#pragma unroll
+    for (int bt = 0; bt < XT; ++bt) dg[bt] = dh[bt] = zero;
+    for (int ybi = 0; ybi < n_yb; ++ybi) {
+      const int yb = ybi * YC;
+      const int ny = min(YC, n_uy - yb);
+      if (!staged || n_yb > 1) {        // uniform per block
+        __syncthreads();
+        for (int e = threadIdx.x; e < YC * 32 * XT; e += 256) {
+          const int yy = e / (32 * XT), xx = e % (32 * XT);
+          float v = 0.f;
+          if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
+          L.lam[xx][(yy & 1) * (YC / 2) + (yy >> 1)] = v;
+        }
+        for (int e = threadIdx.x; e < YC; e += 256) {
+          float v = 0.f;
+          if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
+          L.ysq[(e & 1) * (YC / 2) + (e >> 1)] = v;
+        }
+        __syncthreads();
+        staged = true;
+      }
+      // four y pairs per block of steps (rows past ny hold zero lambda)
+      const int blocks = (((ny + 1) >> 1) + 3) >> 2;
+      const float *yrow = L.ysq + kh * (YC / 2);
+      float4 a4[XT], y4 = *reinterpret_cast<const float4 *>(yrow);
+#pragma unroll
+      for (int bt = 0; bt < XT; ++bt)
+        a4[bt] = *reinterpret_cast<const float4 *>(&L.lam[32 * bt + c32][kh * (YC / 2)]);
+      for (int q = 0; q < blocks; ++q) {
+        const int qn = min(q + 1, YC / 8 - 1);
+        float4 an[XT];
+#pragma unroll
+        for (int bt = 0; bt < XT; ++bt)
+          an[bt] = *reinterpret_cast<const float4 *>(&L.lam[32 * bt + c32][kh * (YC / 2) + 4 * qn]);
+        const float4 yn = *reinterpret_cast<const float4 *>(yrow + 4 * qn);
+        __builtin_amdgcn_sched_barrier(0);
+        const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float b = fast_exp2(c.y * ys[u]);
+          const float by = b * ys[u];
+#pragma unroll
+          for (int bt = 0; bt < XT; ++bt) {
+            const float av = u == 0 ? a4[bt].x : (u == 1 ? a4[bt].y : (u == 2 ? a4[bt].z : a4[bt].w));
+            dg[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b, dg[bt], 0, 0, 0);
+            dh[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, by, dh[bt], 0, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int bt = 0; bt < XT; ++bt) a4[bt] = an[bt];
+        y4 = yn;
+      }
+    }
+    // rows past the map have zero lambda, so zero g and h
+    double s0 = 0.0, s1 = 0.0, sg = 0.0;
+#pragma unroll
+    for (int bt = 0; bt < XT; ++bt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float x2 = L.xsq[32 * bt + mfma_row(r, lane)];
+        const double e = (double)fast_exp2(c.x * x2);
+        s0 += e * (double)dg[bt][r];
+        s1 += (double)x2 * e * (double)dg[bt][r];
+        sg += e * (double)fmaf(c.w, x2, c.z) * (double)dh[bt][r];
+      }
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    sg += __shfl_xor(sg, 32, 64);
+    if (kh == 0 && vt) {
+      double *S = sens + md.sens_off + (int64_t)part * 3 * g.T;
+      S[t] = s0;
+      S[g.T + t] = s1;
+      S[2 * (int64_t)g.T + t] = sg;
+    }
+  }
+}
+
+// Wide adjoint sensitivities over a work list (one workgroup per CU: the
+// staged lambda takes 135 KB of LDS); queue-driven or strided as k_sens.
+__global__ void __launch_bounds__(256, 1) k_sens_wide(const GeomDev *__restrict__ geoms,
+                                                      const ModelDev *__restrict__ models,
+                                                      const Item *__restrict__ items, int n_it,
+                                                      const float4 *__restrict__ terms,
+                                                      const double *__restrict__ pix,
+                                                      const int *__restrict__ st_ws,
+                                                      double *__restrict__ sens, int *queue) {
+  __shared__ __attribute__((aligned(16))) SensWideLds L;
+  __shared__ int next;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int i = blockIdx.x;
+  for (;;) {
+    if (queue) {
+      if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+      __syncthreads();
+      i = next;
+      __syncthreads();
+    }
+    if (i >= n_it) break;
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] == 0) {            // uniform per block
+      switch (it.a >> 16) {
+        case 1: sens_wide_item<1>(it, md, g, terms, pix, sens, L, wave); break;
+        case 2: sens_wide_item<2>(it, md, g, terms, pix, sens, L, wave); break;
+        case 3: sens_wide_item<3>(it, md, g, terms, pix, sens, L, wave); break;
+        default: sens_wide_item<4>(it, md, g, terms, pix, sens, L, wave); break;
+      }
+    }
+    __syncthreads();
+    if (!queue) i += gridDim.x;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 chain from per-term sensitivities to the parameters.  Forward-mode
 // dual numbers carry d/d(inclination) through the deprojection and the term
 // coefficients.  Items (m, k, jb): wave w of the workgroup takes mass
@@ -3310,6 +3484,12 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  int *queue, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_sens, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms, pix,
                      st_ws, sens, queue);
+}
+void launch_sens_wide(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                      const float4 *terms, const double *pix, const int *st_ws, double *sens,
+                      int *queue, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_sens_wide, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
+                     pix, st_ws, sens, queue);
 }
 int occupancy_num(bool mfma) {
   int nb = 0;
