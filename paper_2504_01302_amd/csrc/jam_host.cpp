@@ -729,8 +729,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     }
     gauss += jam::gauss_size(g.K, g.J1);
     const int tsph = jam::sph_terms_padded(g.J1, g.n_u);
-    // spherical: float4 terms, then floats; small maps compute their terms in place
-    terms += spherical ? tsph + tsph / 4 : (small ? 0 : g.T);
+    // spherical: float4 terms, then floats; small maps compute their terms in
+    // place; cylindrical tables are zero-padded to a multiple of 32 terms
+    terms += spherical ? tsph + tsph / 4 : (small ? 0 : jam::padded_terms(g.T));
     pixd += 4 * (int64_t)g.n_pix;
     // padded to whole blocks; FP32 partials (whole-map numerator) take half
     const int64_t part_elems = (int64_t)d.n_slices * (32 * d.n_xt) * (32 * d.n_yt);

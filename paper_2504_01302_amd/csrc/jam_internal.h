@@ -67,7 +67,8 @@ struct ModelDev {
   int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
   int part_f32;      // 1: the split-term partial maps are FP32 (whole-map numerator)
   int64_t gauss_off; // doubles, per-Gaussian derived quantities
-  int64_t term_off;  // float4 entries, term table
+  int64_t term_off;  // float4 entries, term table (cylindrical: padded_terms(T) entries,
+                     // zero past T)
   int64_t pix_off;   // doubles, unique-pixel maps (N, I, lambda)
   int64_t part_off;  // doubles, split-term partial numerators
   int64_t map_off;   // doubles, padded full maps (jam_eval_maps)
@@ -76,6 +77,9 @@ struct ModelDev {
   int64_t sph_off;   // doubles, spherical moment table [kSphNR][kSphNT][3]
   int64_t sbp_off;   // doubles, surface-brightness adjoint partials [K][sb items]
 };
+// Entries of a cylindrical model's term table: T rounded up to a multiple of
+// 32, so that kernels reading whole chunks of 32 terms stay inside it.
+__host__ __device__ inline int64_t padded_terms(int T) { return ((int64_t)T + 31) / 32 * 32; }
 // Surface-brightness tiles: kSbRows rows x 64 columns of the unique-pixel map.
 constexpr int kSbRows = 8;
 __host__ __device__ inline int sb_tiles(int n_ux, int n_uy) {

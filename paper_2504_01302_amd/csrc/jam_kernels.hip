@@ -395,6 +395,8 @@ __global__ void __launch_bounds__(256) k_prologue(const GeomDev *__restrict__ ge
       if (t < g.T)
         terms[md.term_off + t] = st_ws[it.m] == 0 ? term_of(g, gauss + md.gauss_off, t)
                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      else if (t < padded_terms(g.T))
+        terms[md.term_off + t] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     // kind 1: the (k, j) pairs of this block's 256 terms, once each, then
@@ -413,6 +415,8 @@ __global__ void __launch_bounds__(256) k_prologue(const GeomDev *__restrict__ ge
                   C0, C1);
       terms[md.term_off + t] =
           make_float4((float)(-c1 * kLog2e), (float)(-gam * kLog2e), (float)C0, (float)C1);
+    } else if (t < padded_terms(g.T)) {
+      terms[md.term_off + t] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
   }
@@ -734,46 +738,56 @@ __global__ void __launch_bounds__(256, 2) k_num_mfma(const GeomDev *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Whole-map matrix-core numerator.  One workgroup computes one slice of the
-// terms for the model's entire unique-pixel map (n_xt x n_yt <= 7 x 7 blocks
-// of 32x32).  Per chunk of 32 terms the 256 threads generate the operands of
-// every block once (thread i: row i of A = 2^(cx x^2)(C0 + C1 x^2) and
-// column i of B = 2^(cy y^2) for the chunk's terms) into LDS, double
-// buffered, while the waves run the previous chunk's MFMAs.  Wave w owns a
-// fixed run of consecutive blocks (row-major block order, 13/12/12/12 for
-// 7 x 7, known at compile time, so per pair of terms a wave reads the
-// operands of its 2-3 block rows and of the 7 block columns once) and
+// Whole-map matrix-core numerator.  One workgroup of eight waves (two per
+// SIMD) computes one slice of the terms for the model's entire unique-pixel
+// map (n_xt x n_yt = 7 x 7 blocks of 32x32).  Per chunk of 32 terms the 512
+// threads generate the operands of every block once (row i of A =
+// 2^(cx x^2)(C0 + C1 x^2) and column i of B = 2^(cy y^2), thread i % 256
+// for terms 4 (i / 256) .. + 3 of each group of eight) into LDS, double
+// buffered, while the waves run the previous chunk's MFMAs.  Operand rows
+// hold a chunk's 32 terms contiguously (plus 4 floats of padding), so one
+// 16-byte LDS read gives a lane its value for four MFMA steps: in a group of
+// eight terms, half-wave kh supplies term 4 kh + j at step j, in A and B
+// alike (the contraction index is a sum, so any consistent assignment is
+// exact).  Wave w owns the six consecutive row-major blocks 6w .. 6w + 5 and
 // accumulates them over the whole slice in FP32 matrix-core accumulators;
-// the slice's partial map is stored in FP32 and the slices are summed in
-// FP64 by k_reduce in a fixed order.  Rows and columns past the map get
-// exact zero operands (exponent offset -inf), terms past the slice zero
-// coefficients.
+// the 49th block (6, 6) is shared out by steps (wave w takes steps 2w, 2w + 1
+// of every chunk) and its eight partial sums are added in wave order.  Every
+// SIMD so carries 12.25 blocks, and while one of its waves waits on operand
+// generation the other keeps the matrix core busy.  The slice's partial map
+// is stored in FP32 and the slices are summed in FP64 by k_reduce_f32 in a
+// fixed order.  Term coefficients are read straight from the term table at
+// wave-uniform addresses (scalar loads), a group ahead.  Rows and columns
+// past the map get exact zero operands (exponent offset -inf); terms past T
+// are the table's zero padding.
 // ---------------------------------------------------------------------------
 constexpr int kMapC = 32;                 // terms per chunk
-constexpr int kMapLd = 256;               // floats per operand row (one per thread)
+constexpr int kMapLd = kMapC + 4;         // floats per operand row (a chunk + padding)
+constexpr int kMapWaves = 8;
+constexpr int kMapThreads = 64 * kMapWaves;
 
 struct MapLds {
-  float a[2][kMapC][kMapLd];
-  float b[2][kMapC][kMapLd];
-  float4 cs[2][kMapC];
+  float a[2][256][kMapLd];                // [buffer][x row][term]
+  float b[2][256][kMapLd];                // [buffer][y column][term]
 };
 
-// Wave W of a map of NXB x NYB blocks owns the row-major blocks
-// [map_q0, map_q0 + map_nb): the first (NXB NYB) % 4 waves one more.
-__host__ __device__ constexpr int map_nb(int nblk, int w) { return nblk / 4 + (w < nblk % 4 ? 1 : 0); }
-__host__ __device__ constexpr int map_q0(int nblk, int w) {
-  return w * (nblk / 4) + (w < nblk % 4 ? w : nblk % 4);
-}
-
-template <int NXB, int NYB, int W>
+template <int W>
 __device__ __forceinline__ void num_map_item(const Item it, const ModelDev &md, const GeomDev &g,
                                              const float4 *__restrict__ terms,
                                              const int *__restrict__ st_ws,
                                              double *__restrict__ part, MapLds &L) {
-  constexpr int NBLK = NXB * NYB;
-  constexpr int NB = map_nb(NBLK, W), Q0 = map_q0(NBLK, W);
+  constexpr int NXB = kMapBlocks, NYB = kMapBlocks, NBLK = NXB * NYB;
+  static_assert(32 * NXB <= 256 && 32 * NYB <= 256, "one operand row per thread");
+  constexpr int NB = (NBLK - 1) / kMapWaves, Q0 = W * NB;            // owned blocks
+  static_assert(NB * kMapWaves == NBLK - 1, "the last block is the shared one");
   constexpr int BX0 = Q0 / NYB, NR = (Q0 + NB - 1) / NYB - BX0 + 1;   // rows of this wave
-  const int tid = threadIdx.x;
+  constexpr bool OWN_LAST_ROW = BX0 + NR == NXB;
+  constexpr int NG = kMapC / 8;                                       // groups per chunk
+  constexpr int SPW = kMapC / 2 / kMapWaves;     // steps of the shared block per wave
+  static_assert(SPW == 2, "a wave's shared steps lie in one group");
+  constexpr int QS = W * SPW / 4;                // the group holding them
+  constexpr int H = W / 4;                       // generates terms 4H .. 4H + 3 of a group
+  const int tid = threadIdx.x, row = tid & 255;
   const int lane = tid & 63, c32 = lane & 31, kh = lane >> 5;
   int ts, te;
   slice_range(g.T, md.n_slices, it.b, ts, te, kMapC);
@@ -781,85 +795,133 @@ __device__ __forceinline__ void num_map_item(const Item it, const ModelDev &md, 
   const float4 *tb = terms + md.term_off;
   // this thread's generated row / column
   float x2 = 0.f, xoff = -__builtin_inff(), y2 = 0.f, yoff = -__builtin_inff();
-  if (tid < g.n_ux) { const double x = g.xs[tid]; x2 = (float)(x * x); xoff = 0.f; }
-  if (tid < g.n_uy) { const double y = g.ys[tid]; y2 = (float)(y * y); yoff = 0.f; }
-  auto stage = [&](int buf, int ch) {   // coefficients of chunk ch (zero past the slice)
-    if (tid < kMapC) {
-      const int t = ts + ch * kMapC + tid;
-      L.cs[buf][tid] = t < te ? tb[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+  if (row < g.n_ux) { const double x = g.xs[row]; x2 = (float)(x * x); xoff = 0.f; }
+  if (row < g.n_uy) { const double y = g.ys[row]; y2 = (float)(y * y); yoff = 0.f; }
+  // coefficients of term 8q + 4H + k of chunk ch (only called with n_ch > 0).
+  // Slices end on a multiple of 32 terms or at T, and the table is zero from
+  // T to the next multiple of 32, so a whole chunk is always in the table and
+  // its terms past the slice are zero; the chunk after the last one repeats it.
+  auto coef = [&](int ch, int q, int k) {
+    return tb[ts + min(ch, n_ch - 1) * kMapC + 8 * q + 4 * H + k];
   };
-  // operands of a term with coefficients c, into row k of buffer buf
-  auto generate = [&](int buf, int k, float4 c) {
-    L.a[buf][k][tid] = fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z);
-    L.b[buf][k][tid] = fast_exp2(fmaf(c.y, y2, yoff));
-  };
+  auto gen_a = [&](float4 c) { return fast_exp2(fmaf(c.x, x2, xoff)) * fmaf(c.w, x2, c.z); };
+  auto gen_b = [&](float4 c) { return fast_exp2(fmaf(c.y, y2, yoff)); };
   const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  v16f acc[NB];
+  v16f acc[NB], acc_s = zero;
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = zero;
-  if (n_ch > 0) stage(0, 0);
-  __syncthreads();
-  if (n_ch > 0)
-    for (int k = 0; k < kMapC; ++k) generate(0, k, L.cs[0][k]);
-  if (n_ch > 1) stage(1, 1);
+  if (n_ch > 0) {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      float4 c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = coef(0, q, k);
+      const int k4 = 8 * q + 4 * H;
+      *reinterpret_cast<float4 *>(&L.a[0][row][k4]) =
+          make_float4(gen_a(c[0]), gen_a(c[1]), gen_a(c[2]), gen_a(c[3]));
+      *reinterpret_cast<float4 *>(&L.b[0][row][k4]) =
+          make_float4(gen_b(c[0]), gen_b(c[1]), gen_b(c[2]), gen_b(c[3]));
+    }
+  }
   __syncthreads();
   for (int ch = 0; ch < n_ch; ++ch) {
-    const int cur = ch & 1;
-    // the next chunk's coefficients (staged one chunk earlier; after the
-    // last chunk they are stale, and what they generate is never read)
-    float4 cn[kMapC];
+    const int cur = ch & 1, nxt = cur ^ 1;
+    // operands of this wave's block rows (and, in group QS, of the last
+    // row) and of every block column for the eight terms of group q
+    float4 av[2][NR], bv[2][NYB], al[2];
+    auto rd = [&](int u, int q) {
 #pragma unroll
-    for (int k = 0; k < kMapC; ++k) cn[k] = L.cs[cur ^ 1][k];
-    // per pair of terms: the operands of this wave's block rows and of every
-    // block column (read one pair ahead), then the MFMAs beside two terms of
-    // the next chunk's operands; the scheduling barriers keep each pair's
-    // reads ahead of the previous pair's MFMAs
-    float av[2][NR], bv[2][NYB];
+      for (int r = 0; r < NR; ++r)
+        av[u][r] = *reinterpret_cast<const float4 *>(&L.a[cur][32 * (BX0 + r) + c32][8 * q + 4 * kh]);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) av[0][r] = L.a[cur][kh][32 * (BX0 + r) + c32];
+      for (int c = 0; c < NYB; ++c)
+        bv[u][c] = *reinterpret_cast<const float4 *>(&L.b[cur][32 * c + c32][8 * q + 4 * kh]);
+      if (!OWN_LAST_ROW && q == QS)
+        al[u] = *reinterpret_cast<const float4 *>(&L.a[cur][32 * (NXB - 1) + c32][8 * q + 4 * kh]);
+    };
+    // coefficients of the next chunk's group (after the last chunk, the last
+    // chunk's again: what they generate is never read)
+    float4 cq[4], cn[4];
 #pragma unroll
-    for (int c = 0; c < NYB; ++c) bv[0][c] = L.b[cur][kh][32 * c + c32];
+    for (int k = 0; k < 4; ++k) cq[k] = coef(ch + 1, 0, k);
+    rd(0, 0);
 #pragma unroll
-    for (int s2 = 0; s2 < kMapC / 2; ++s2) {
-      const int u = s2 & 1;
-      if (s2 + 1 < kMapC / 2) {
+    for (int q = 0; q < NG; ++q) {
+      const int u = q & 1;
+      // the next group's reads and coefficients go out before this group's
+      // MFMAs; the scheduling barriers keep them there
+      if (q + 1 < NG) {
+        rd(u ^ 1, q + 1);
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
-          av[u ^ 1][r] = L.a[cur][2 * s2 + 2 + kh][32 * (BX0 + r) + c32];
-#pragma unroll
-        for (int c = 0; c < NYB; ++c) bv[u ^ 1][c] = L.b[cur][2 * s2 + 2 + kh][32 * c + c32];
+        for (int k = 0; k < 4; ++k) cn[k] = coef(ch + 1, q + 1, k);
       }
       __builtin_amdgcn_sched_barrier(0);
+      float ga[4], gb[4];
 #pragma unroll
-      for (int i = 0; i < NB; ++i)
-        acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u][(Q0 + i) / NYB - BX0],
-                                                      bv[u][(Q0 + i) % NYB], acc[i], 0, 0, 0);
-      generate(cur ^ 1, 2 * s2, cn[2 * s2]);
-      generate(cur ^ 1, 2 * s2 + 1, cn[2 * s2 + 1]);
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const float4 &xa = av[u][(Q0 + i) / NYB - BX0];
+          const float4 &yb = bv[u][(Q0 + i) % NYB];
+          const float fa = j == 0 ? xa.x : j == 1 ? xa.y : j == 2 ? xa.z : xa.w;
+          const float fb = j == 0 ? yb.x : j == 1 ? yb.y : j == 2 ? yb.z : yb.w;
+          acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa, fb, acc[i], 0, 0, 0);
+        }
+        if ((4 * q + j) / SPW == W) {              // this wave's steps of the shared block
+          const float4 &xa = OWN_LAST_ROW ? av[u][NR - 1] : al[u];
+          const float4 &yb = bv[u][NYB - 1];
+          const float fa = j == 0 ? xa.x : j == 1 ? xa.y : j == 2 ? xa.z : xa.w;
+          const float fb = j == 0 ? yb.x : j == 1 ? yb.y : j == 2 ? yb.z : yb.w;
+          acc_s = __builtin_amdgcn_mfma_f32_32x32x2f32(fa, fb, acc_s, 0, 0, 0);
+        }
+        // one term of the next chunk's group q beside the MFMAs
+        ga[j] = gen_a(cq[j]);
+        gb[j] = gen_b(cq[j]);
+      }
+      const int k4 = 8 * q + 4 * H;
+      *reinterpret_cast<float4 *>(&L.a[nxt][row][k4]) = make_float4(ga[0], ga[1], ga[2], ga[3]);
+      *reinterpret_cast<float4 *>(&L.b[nxt][row][k4]) = make_float4(gb[0], gb[1], gb[2], gb[3]);
       __builtin_amdgcn_sched_barrier(0);
+      if (q + 1 < NG) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cq[k] = cn[k];
+      }
     }
-    if (ch + 2 < n_ch) stage(cur, ch + 2);
     __syncthreads();
   }
-  // FP32 partial map of the slice, padded and transposed as k_reduce reads it
+  // FP32 partial map of the slice, padded and transposed as k_reduce_f32 reads it
   float *pf = reinterpret_cast<float *>(part + md.part_off) + it.b * part_slice_size(md);
   const int ldh = 32 * NYB;
+  auto store = [&](int blk, const v16f &v) {
+    float *o = pf + (int64_t)(32 * (blk / NYB) + 4 * kh) * ldh + 32 * (blk % NYB) + c32;
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    float *o = pf + (int64_t)(32 * ((Q0 + i) / NYB) + 4 * kh) * ldh + 32 * ((Q0 + i) % NYB) + c32;
+    for (int r = 0; r < 16; ++r) o[(int64_t)((r & 3) + 8 * (r >> 2)) * ldh] = v[r];
+  };
 #pragma unroll
-    for (int r = 0; r < 16; ++r) o[(int64_t)((r & 3) + 8 * (r >> 2)) * ldh] = acc[i][r];
+  for (int i = 0; i < NB; ++i) store(Q0 + i, acc[i]);
+  // the shared block: the eight waves' partial sums in wave order (the
+  // operand buffers are free after the last chunk's barrier)
+  float *red = &L.a[0][0][0];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) red[(W * 16 + r) * 64 + lane] = acc_s[r];
+  __syncthreads();
+  if (W == kMapWaves - 1) {
+    v16f s = zero;
+#pragma unroll
+    for (int w = 0; w < kMapWaves; ++w)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s[r] += red[(w * 16 + r) * 64 + lane];
+    store(NBLK - 1, s);
   }
 }
 
-__global__ void __launch_bounds__(256, 1) k_num_map(const GeomDev *__restrict__ geoms,
-                                                   const ModelDev *__restrict__ models,
-                                                   const Item *__restrict__ items, int n_it,
-                                                   const float4 *__restrict__ terms,
-                                                   const int *__restrict__ st_ws,
-                                                   double *__restrict__ part, int *queue) {
-  __shared__ MapLds L;
+__global__ void __launch_bounds__(kMapThreads, 1) k_num_map(const GeomDev *__restrict__ geoms,
+                                                           const ModelDev *__restrict__ models,
+                                                           const Item *__restrict__ items, int n_it,
+                                                           const float4 *__restrict__ terms,
+                                                           const int *__restrict__ st_ws,
+                                                           double *__restrict__ part, int *queue) {
+  __shared__ __attribute__((aligned(16))) MapLds L;
   __shared__ int next;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int i = blockIdx.x;
@@ -867,7 +929,7 @@ __global__ void __launch_bounds__(256, 1) k_num_map(const GeomDev *__restrict__ 
     if (queue) {
       if (threadIdx.x == 0) next = atomicAdd(queue, 1);
       __syncthreads();
-      i = next;
+      i = __builtin_amdgcn_readfirstlane(next);
       __syncthreads();
     }
     if (i >= n_it) break;
@@ -876,10 +938,14 @@ __global__ void __launch_bounds__(256, 1) k_num_map(const GeomDev *__restrict__ 
     const GeomDev g = geoms[md.geom];
     // the map shape is 7 x 7 blocks (checked on the host)
     switch (wave) {
-      case 0: num_map_item<7, 7, 0>(it, md, g, terms, st_ws, part, L); break;
-      case 1: num_map_item<7, 7, 1>(it, md, g, terms, st_ws, part, L); break;
-      case 2: num_map_item<7, 7, 2>(it, md, g, terms, st_ws, part, L); break;
-      default: num_map_item<7, 7, 3>(it, md, g, terms, st_ws, part, L); break;
+      case 0: num_map_item<0>(it, md, g, terms, st_ws, part, L); break;
+      case 1: num_map_item<1>(it, md, g, terms, st_ws, part, L); break;
+      case 2: num_map_item<2>(it, md, g, terms, st_ws, part, L); break;
+      case 3: num_map_item<3>(it, md, g, terms, st_ws, part, L); break;
+      case 4: num_map_item<4>(it, md, g, terms, st_ws, part, L); break;
+      case 5: num_map_item<5>(it, md, g, terms, st_ws, part, L); break;
+      case 6: num_map_item<6>(it, md, g, terms, st_ws, part, L); break;
+      default: num_map_item<7>(it, md, g, terms, st_ws, part, L); break;
     }
     __syncthreads();
     if (!queue) i += gridDim.x;
@@ -3445,8 +3511,8 @@ void launch_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_num_map(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const float4 *terms, const int *st_ws, double *part, int *queue, int grid,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_num_map, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
-                     st_ws, part, queue);
+  hipLaunchKernelGGL(k_num_map, dim3(grid_of(grid)), dim3(kMapThreads), 0, st, g, m, it, n_it,
+                     terms, st_ws, part, queue);
 }
 void launch_reduce_f32(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                        const double *part, double *pix, hipStream_t st) {
