@@ -1516,51 +1516,86 @@ __device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md
         __syncthreads();
         staged = true;
       }
-      // four y pairs per block of steps (rows past ny hold zero lambda)
+      // four y pairs per block of steps (rows past ny hold zero lambda);
+      // blocks alternate between two operand buffers, the next block's
+      // operands read and its exponentials taken behind the current MFMAs
       const int blocks = (((ny + 1) >> 1) + 3) >> 2;
       const float *yrow = L.ysq + kh * (YC / 2);
-      float4 a4[XT], y4 = *reinterpret_cast<const float4 *>(yrow);
-#pragma unroll
-      for (int bt = 0; bt < XT; ++bt)
-        a4[bt] = *reinterpret_cast<const float4 *>(&L.lam[32 * bt + c32][kh * (YC / 2)]);
-      for (int q = 0; q < blocks; ++q) {
-        const int qn = min(q + 1, YC / 8 - 1);
-        float4 an[XT];
+      float4 a4[2][XT], y4[2];
+      float bx[2][4], bxy[2][4];
+      auto load = [&](int buf, int q) {
+        q = min(q, YC / 8 - 1);                  // past the last block: a harmless re-read
 #pragma unroll
         for (int bt = 0; bt < XT; ++bt)
-          an[bt] = *reinterpret_cast<const float4 *>(&L.lam[32 * bt + c32][kh * (YC / 2) + 4 * qn]);
-        const float4 yn = *reinterpret_cast<const float4 *>(yrow + 4 * qn);
-        __builtin_amdgcn_sched_barrier(0);
-        const float ys[4] = {y4.x, y4.y, y4.z, y4.w};
+          a4[buf][bt] = *reinterpret_cast<const float4 *>(&L.lam[32 * bt + c32][kh * (YC / 2) + 4 * q]);
+        y4[buf] = *reinterpret_cast<const float4 *>(yrow + 4 * q);
+      };
+      auto expo = [&](int buf) {
+        const float ys[4] = {y4[buf].x, y4[buf].y, y4[buf].z, y4[buf].w};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float b = fast_exp2(c.y * ys[u]);
-          const float by = b * ys[u];
+          bx[buf][u] = fast_exp2(c.y * ys[u]);
+          bxy[buf][u] = bx[buf][u] * ys[u];
+        }
+      };
+      auto mfma4 = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int bt = 0; bt < XT; ++bt) {
-            const float av = u == 0 ? a4[bt].x : (u == 1 ? a4[bt].y : (u == 2 ? a4[bt].z : a4[bt].w));
-            dg[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b, dg[bt], 0, 0, 0);
-            dh[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, by, dh[bt], 0, 0, 0);
+            const float4 &av4 = a4[buf][bt];
+            const float av = u == 0 ? av4.x : (u == 1 ? av4.y : (u == 2 ? av4.z : av4.w));
+            dg[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bx[buf][u], dg[bt], 0, 0, 0);
+            dh[bt] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bxy[buf][u], dh[bt], 0, 0, 0);
           }
-        }
+      };
+      load(0, 0);
+      expo(0);
+      for (int q = 0; q < blocks; q += 2) {
+        load(1, q + 1);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int bt = 0; bt < XT; ++bt) a4[bt] = an[bt];
-        y4 = yn;
+        mfma4(0);
+        expo(1);
+        // taken here, not sunk into the branch below
+        asm volatile("" ::"v"(bx[1][0]), "v"(bx[1][1]), "v"(bx[1][2]), "v"(bx[1][3]),
+                     "v"(bxy[1][0]), "v"(bxy[1][1]), "v"(bxy[1][2]), "v"(bxy[1][3]));
+        // half the MFMAs go out before the exponentials wait for their reads
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * XT, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4 * XT, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (q + 1 < blocks) {                  // uniform
+          load(0, q + 2);
+          __builtin_amdgcn_sched_barrier(0);
+          mfma4(1);
+          expo(0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4 * XT, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4 * XT, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
-    // rows past the map have zero lambda, so zero g and h
+    // rows past the map have zero lambda, so zero g and h.  Each lane's 16
+    // rows of a tile are summed in FP32 (beside the FP32 matrix-core sums over
+    // y, a relative error of the same order), the tiles in FP64.
     double s0 = 0.0, s1 = 0.0, sg = 0.0;
 #pragma unroll
-    for (int bt = 0; bt < XT; ++bt)
+    for (int bt = 0; bt < XT; ++bt) {
+      float f0 = 0.f, f1 = 0.f, fg = 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const float x2 = L.xsq[32 * bt + mfma_row(r, lane)];
-        const double e = (double)fast_exp2(c.x * x2);
-        s0 += e * (double)dg[bt][r];
-        s1 += (double)x2 * e * (double)dg[bt][r];
-        sg += e * (double)fmaf(c.w, x2, c.z) * (double)dh[bt][r];
+        const float e = fast_exp2(c.x * x2);
+        const float ed = e * dg[bt][r];
+        f0 += ed;
+        f1 = fmaf(x2, ed, f1);
+        fg = fmaf(e * fmaf(c.w, x2, c.z), dh[bt][r], fg);
       }
+      s0 += (double)f0;
+      s1 += (double)f1;
+      sg += (double)fg;
+    }
     s0 += __shfl_xor(s0, 32, 64);
     s1 += __shfl_xor(s1, 32, 64);
     sg += __shfl_xor(sg, 32, 64);
