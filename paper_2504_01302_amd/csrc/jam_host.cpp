@@ -676,9 +676,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       it_red, it_sph, it_pro, it_adj, it_redf, it_sensw;
   std::vector<double> c_num, c_sens, c_sensw;
   // 32-term groups per wide-sensitivity item: one compute unit's share of
-  // the batch's groups (over all parts), a multiple of the 4 waves
+  // the batch's groups (over all parts), a multiple of the workgroup's waves
   std::vector<jam::Item> &wide_list = it_sensw;
-  int wide_per = 4;
+  constexpr int kWW = jam::kWideWaves;
+  int wide_per = kWW;
   if (ctx->opt.alignment != 1) {
     // work in units of (32-term group x 4 tiles)
     int64_t tot = 0;
@@ -688,7 +689,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       if (nx >= 2) tot += (int64_t)nx * ((g.T + 31) / 32);
     }
     const int64_t share = (tot / 4 + ctx->n_cu - 1) / std::max(1, ctx->n_cu);
-    wide_per = (int)std::max<int64_t>(4, (share + 3) / 4 * 4);
+    wide_per = (int)std::max<int64_t>(kWW, (share + kWW - 1) / kWW * kWW);
   }
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
@@ -774,7 +775,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       const int groups = (g.T + 31) / 32;
       for (int pt = 0; pt < d.n_sens_parts; ++pt) {
         const int xt = std::min(4, n_xt - 4 * pt);
-        const int per = std::max(4, (wide_per * 4 / xt + 3) / 4 * 4);
+        const int per = std::max(kWW, (wide_per * 4 / xt + kWW - 1) / kWW * kWW);
         for (int g0 = 0; g0 < groups; g0 += per)
           wide_list.push_back({m, pt | (xt << 16), g0, std::min(groups, g0 + per)});
       }

@@ -194,7 +194,9 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                  int *queue, int grid, hipStream_t st);
 // Wide matrix-core sensitivities: items (m, part p | tiles << 16 for the 1-4
 // consecutive 32-row x tiles 4p.., first 32-term group, end group); one
-// workgroup per CU; queue as launch_sens (the second counter).
+// workgroup of kWideWaves waves per CU, wave w taking the item's groups w,
+// w + kWideWaves, ...; queue as launch_sens (the second counter).
+constexpr int kWideWaves = 8;
 void launch_sens_wide(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                       const float4 *terms, const double *pix, const int *st_ws, double *sens,
                       int *queue, int grid, hipStream_t st);

@@ -1444,14 +1444,15 @@ __global__ void __launch_bounds__(256) k_sens(const GeomDev *__restrict__ geoms,
 // when the map has at most 256 distinct |y|) in the layout the MFMA steps
 // read: row x holds, for each half kh of the wave, the values at y = 2s + kh
 // for consecutive steps s, so one 16-byte read gives a lane four steps'
-// operands (LDS reads cost ~25 cycles each beside the MFMAs whatever their
-// width; rows are padded by 4 floats against bank conflicts).  Per term group
-// the FP32 matrix-core sums run over all y (no FP64 fold: the 2 XT
-// accumulator blocks take 128 registers at XT = 4), the next four steps'
-// operands read ahead.  Item (m, part p | XT << 16 covering x tiles 4p ..
-// 4p + XT - 1, first 32-term group, end group); wave w takes the item's
-// groups w, w + 4, ...; output per part, [S0 | S1 | Sg] (T doubles each), as
-// sens_mfma_item's per x tile.
+// operands (a quarter of the LDS instructions; rows are padded by 4 floats
+// against bank conflicts).  Per term group the FP32 matrix-core sums run over
+// all y (no FP64 fold: the 2 XT accumulator blocks take 128 registers at
+// XT = 4), the next four steps' operands read and their exponentials taken
+// behind the current MFMAs.  Item (m, part p | XT << 16 covering x tiles 4p ..
+// 4p + XT - 1, first 32-term group, end group); eight waves, two per SIMD,
+// so that one wave's exponentials and epilogue run beside the other's
+// MFMAs; wave w takes the item's groups w, w + 8, ...; output per part,
+// [S0 | S1 | Sg] (T doubles each), as sens_mfma_item's per x tile.
 // ---------------------------------------------------------------------------
 constexpr int kWideTiles = 4;
 constexpr int kWideLd = YC + 4;   // floats per staged x row: 2 halves x YC/2 steps + pad
@@ -1477,6 +1478,7 @@ __device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md
   const int g0 = it.b, g1 = it.c;
   const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   bool staged = false;
+  constexpr int NT = 64 * kWideWaves;
   if (threadIdx.x < 32 * XT) {
     const int xr = x0 + threadIdx.x;
     float v = 0.f;
@@ -1489,11 +1491,11 @@ __device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md
     return (gr < g1 && t < g.T) ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
   };
   float4 cnext = coef(g0 + wave);
-  for (int gr = g0 + wave; gr - wave < g1; gr += 4) {   // same trip count in every wave
+  for (int gr = g0 + wave; gr - wave < g1; gr += kWideWaves) {   // same trip count in every wave
     const int t = gr * 32 + c32;
     const bool vt = gr < g1 && t < g.T;
     const float4 c = cnext;
-    cnext = coef(gr + 4);
+    cnext = coef(gr + kWideWaves);
     v16f dg[XT], dh[XT];
 #pragma unroll
     for (int bt = 0; bt < XT; ++bt) dg[bt] = dh[bt] = zero;
@@ -1502,13 +1504,13 @@ __device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md
       const int ny = min(YC, n_uy - yb);
       if (!staged || n_yb > 1) {        // uniform per block
         __syncthreads();
-        for (int e = threadIdx.x; e < YC * 32 * XT; e += 256) {
+        for (int e = threadIdx.x; e < YC * 32 * XT; e += NT) {
           const int yy = e / (32 * XT), xx = e % (32 * XT);
           float v = 0.f;
           if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
           L.lam[xx][(yy & 1) * (YC / 2) + (yy >> 1)] = v;
         }
-        for (int e = threadIdx.x; e < YC; e += 256) {
+        for (int e = threadIdx.x; e < YC; e += NT) {
           float v = 0.f;
           if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
           L.ysq[(e & 1) * (YC / 2) + (e >> 1)] = v;
@@ -1608,9 +1610,10 @@ __device__ __forceinline__ void sens_wide_item(const Item it, const ModelDev &md
   }
 }
 
-// Wide adjoint sensitivities over a work list (one workgroup per CU: the
-// staged lambda takes 135 KB of LDS); queue-driven or strided as k_sens.
-__global__ void __launch_bounds__(256, 1) k_sens_wide(const GeomDev *__restrict__ geoms,
+// Wide adjoint sensitivities over a work list (one workgroup of eight waves
+// per CU: the staged lambda takes 135 KB of LDS); queue-driven or strided as
+// k_sens.
+__global__ void __launch_bounds__(64 * kWideWaves, 1) k_sens_wide(const GeomDev *__restrict__ geoms,
                                                       const ModelDev *__restrict__ models,
                                                       const Item *__restrict__ items, int n_it,
                                                       const float4 *__restrict__ terms,
@@ -3589,8 +3592,8 @@ void launch_sens(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 void launch_sens_wide(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                       const float4 *terms, const double *pix, const int *st_ws, double *sens,
                       int *queue, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_sens_wide, dim3(grid_of(grid)), dim3(256), 0, st, g, m, it, n_it, terms,
-                     pix, st_ws, sens, queue);
+  hipLaunchKernelGGL(k_sens_wide, dim3(grid_of(grid)), dim3(64 * kWideWaves), 0, st, g, m, it,
+                     n_it, terms, pix, st_ws, sens, queue);
 }
 int occupancy_num(bool mfma) {
   int nb = 0;
