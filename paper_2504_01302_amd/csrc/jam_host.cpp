@@ -656,6 +656,60 @@ void sort_by_cost(std::vector<jam::Item> &items, std::vector<double> &cost) {
   items.swap(out);
 }
 
+// The wide adjoint form (k_sens_wide) is used on maps of at least two x
+// tiles with at least this many distinct |y|: each 32-term group then runs
+// over enough y steps to amortise its accumulator set-up and epilogue
+// (measured: faster than the one-tile form at 215, slower at <= 128).
+constexpr int kWideMinY = 160;
+
+struct WidePart { int m, pt, xt, groups; };
+
+// Cut the wide parts into items.  A part of xt tiles takes items of
+// per(c, xt) 32-term groups, c for four tiles and proportionally more for
+// fewer, a multiple of the workgroup's waves; c is chosen by the modelled
+// completion time on n_cu compute units (one workgroup each, items taken
+// largest first), an item costing its critical wave's (group x tile) count
+// plus one for staging lambda.  Items are emitted largest first.
+void wide_items(const std::vector<WidePart> &parts, int n_cu, std::vector<jam::Item> &out) {
+  out.clear();
+  if (parts.empty()) return;
+  constexpr int kWW = jam::kWideWaves;
+  int64_t tot = 0;
+  for (const WidePart &w : parts) tot += (int64_t)w.xt * w.groups;
+  const int64_t share = std::max<int64_t>(1, (tot / 4 + n_cu - 1) / std::max(1, n_cu));
+  auto per_of = [](int64_t c, int xt) {
+    constexpr int64_t w = jam::kWideWaves;
+    return (int)std::max<int64_t>(w, (c * 4 / xt + w - 1) / w * w);
+  };
+  auto cost_of = [](int ng, int xt) {
+    constexpr int w = jam::kWideWaves;
+    return (double)((ng + w - 1) / w) * xt + 1.0;
+  };
+  const int64_t step = std::max<int64_t>(kWW, share / 64 / kWW * kWW);
+  int64_t best = kWW;
+  double best_t = -1.0;
+  std::vector<double> cost;
+  for (int64_t c = std::max<int64_t>(kWW, share / 4 / kWW * kWW); c <= 2 * share + kWW; c += step) {
+    cost.clear();
+    for (const WidePart &w : parts) {
+      const int per = per_of(c, w.xt);
+      for (int g0 = 0; g0 < w.groups; g0 += per) cost.push_back(cost_of(std::min(per, w.groups - g0), w.xt));
+    }
+    const double t = list_schedule_makespan(cost, n_cu);
+    if (best_t < 0.0 || t < best_t) { best = c; best_t = t; }
+  }
+  cost.clear();
+  for (const WidePart &w : parts) {
+    const int per = per_of(best, w.xt);
+    for (int g0 = 0; g0 < w.groups; g0 += per) {
+      const int g1 = std::min(w.groups, g0 + per);
+      out.push_back({w.m, w.pt | (w.xt << 16), g0, g1});
+      cost.push_back(cost_of(g1 - g0, w.xt));
+    }
+  }
+  sort_by_cost(out, cost);
+}
+
 jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tune &tune_in,
                       std::unique_ptr<Plan> &out) {
   auto p = std::make_unique<Plan>();
@@ -675,22 +729,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
       it_red, it_sph, it_pro, it_adj, it_redf, it_sensw;
   std::vector<double> c_num, c_sens, c_sensw;
-  // 32-term groups per wide-sensitivity item: one compute unit's share of
-  // the batch's groups (over all parts), a multiple of the workgroup's waves
-  std::vector<jam::Item> &wide_list = it_sensw;
-  constexpr int kWW = jam::kWideWaves;
-  int wide_per = kWW;
-  if (ctx->opt.alignment != 1) {
-    // work in units of (32-term group x 4 tiles)
-    int64_t tot = 0;
-    for (int m = 0; m < n; ++m) {
-      const GeomHost &g = ctx->gh[geom_idx[m]];
-      const int nx = (g.n_ux + 31) / 32;
-      if (nx >= 2) tot += (int64_t)nx * ((g.T + 31) / 32);
-    }
-    const int64_t share = (tot / 4 + ctx->n_cu - 1) / std::max(1, ctx->n_cu);
-    wide_per = (int)std::max<int64_t>(kWW, (share + kWW - 1) / kWW * kWW);
-  }
+  // wide-sensitivity parts (model, part, x tiles, 32-term groups); their
+  // items are cut after the model loop (wide_items)
+  std::vector<WidePart> wide_parts;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
   const bool spherical = ctx->opt.alignment == 1;
   for (int m = 0; m < n; ++m) {
@@ -709,8 +750,10 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     d.part_f32 = nc.map ? 1 : 0;
     // adjoint sensitivity blocks: one (per-pixel), none (small map), one per
     // x tile (one tile), one per part of up to four x tiles (wide)
+    // (the wide form pays off where each term group runs over many y steps:
+    // its per-group epilogue and accumulator set-up are fixed costs)
     const int n_xt = (g.n_ux + 31) / 32;
-    const bool wide = !spherical && !small && d.form != 1 && n_xt >= 2;
+    const bool wide = !spherical && !small && d.form != 1 && n_xt >= 2 && g.n_uy >= kWideMinY;
     d.n_sens_parts = d.form == 1 ? 1 : (small ? 0 : (wide ? (n_xt + 3) / 4 : n_xt));
     d.n_xt = (g.n_ux + 31) / 32;
     d.n_yt = (g.n_uy + 31) / 32;
@@ -769,16 +812,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
         c_sens.push_back((double)g.n_pix);
       }
     } else if (wide) {
-      // parts of up to four x tiles, each split into items of about one
-      // compute unit's share of the batch's 32-term groups
-      // (a part of fewer tiles takes proportionally more groups per item)
-      const int groups = (g.T + 31) / 32;
-      for (int pt = 0; pt < d.n_sens_parts; ++pt) {
-        const int xt = std::min(4, n_xt - 4 * pt);
-        const int per = std::max(kWW, (wide_per * 4 / xt + kWW - 1) / kWW * kWW);
-        for (int g0 = 0; g0 < groups; g0 += per)
-          wide_list.push_back({m, pt | (xt << 16), g0, std::min(groups, g0 + per)});
-      }
+      // parts of up to four x tiles
+      for (int pt = 0; pt < d.n_sens_parts; ++pt)
+        wide_parts.push_back({m, pt, std::min(4, n_xt - 4 * pt), (g.T + 31) / 32});
     } else {
       for (int xt = 0; xt < d.n_sens_parts; ++xt)
         for (int tt = 0; tt < (g.T + jam::kSensTerms - 1) / jam::kSensTerms; ++tt) {
@@ -830,6 +866,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
                                       [](const jam::Item &t) { return t.c == 1; });
   sort_by_cost(it_num, c_num);
   sort_by_cost(it_sens, c_sens);
+  wide_items(wide_parts, ctx->n_cu, it_sensw);
 
   constexpr int kLists = 14;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
