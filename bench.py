@@ -225,10 +225,13 @@ def time_batch(torch, binding, w, dev, steps, form, launch, graph, autotune=0):
     return rec
 
 
-def time_spherical(torch, binding, w, dev, steps, backward=True):
+def time_spherical(torch, binding, w, dev, steps, backward=True, form=0, values=None):
     """Forward and forward+adjoint throughput of the spherically aligned
-    model (eqs. J1, J2) on one whole batch per launch."""
-    ctx = binding.Context(w.geometries, alignment=1)
+    model (eqs. J1, J2) on one whole batch per launch; form 0: the forward
+    interpolates the potential sums from their grid, form 1: it sums the
+    terms at every characteristic node.  With a list `values`, the forward's
+    v_rms^2 is appended to it."""
+    ctx = binding.Context(w.geometries, alignment=1, form=form)
     par = binding.pack_params(w, dev, amplitudes=True)
     nb, _, _ = ctx.sizes(w.geom_idx)
     V = torch.empty(nb, dtype=torch.float64, device=dev)
@@ -268,7 +271,21 @@ def time_spherical(torch, binding, w, dev, steps, backward=True):
         rec.update(ms_fwd_bwd=ms_fb, fwd_bwd_per_s=n * 1000.0 / ms_fb,
                    grads_finite=bool(torch.isfinite(g["inc"]).all().item()))
     rec["all_status_ok"] = bool((st == 0).all().item())
+    if values is not None:
+        values.append(V.cpu().numpy())
     ctx.close()
+    return rec
+
+
+def time_spherical_both(torch, binding, w, dev, steps, backward=True):
+    """time_spherical with the potential grid, plus the direct-sum forward's
+    time and the largest relative difference of the two forwards."""
+    vals = []
+    rec = time_spherical(torch, binding, w, dev, steps, backward, 0, vals)
+    d = time_spherical(torch, binding, w, dev, steps, False, 1, vals)
+    rec["direct_sums"] = {"ms_forward": d["ms_forward"], "models_per_s": d["models_per_s"],
+                          "max_rel_diff_grid_vs_direct":
+                              float(np.max(np.abs(vals[0] / vals[1] - 1.0)))}
     return rec
 
 
@@ -447,13 +464,13 @@ def run_extras(a, torch, binding, inputs, dev, w1):
         "mge_chi2_4096_small": lambda: time_mge_pipeline(torch, binding, dev, k),
         "beta_profile_chi2_4096_small": lambda: time_beta_profile(
             torch, binding, inputs.config3(4096), dev, k),
-        "spherical_ifu_scale": lambda: time_spherical(torch, binding, w1, dev, k),
+        "spherical_ifu_scale": lambda: time_spherical_both(torch, binding, w1, dev, k),
         "cylindrical_composite_42x95": lambda: time_batch(
             torch, binding, inputs.config_composite(), dev, k, a.form, a.launch, a.graph),
-        "spherical_composite_42x95": lambda: time_spherical(
+        "spherical_composite_42x95": lambda: time_spherical_both(
             torch, binding, inputs.config_composite(), dev, max(2, k // 2)),
-        "spherical_1024_small": lambda: time_spherical(torch, binding, inputs.config3(1024),
-                                                       dev, max(2, k // 2)),
+        "spherical_1024_small": lambda: time_spherical_both(torch, binding, inputs.config3(1024),
+                                                            dev, max(2, k // 2)),
     }
     names = [x for x in a.extra.split(",") if x] or list(extras)
     unknown = [x for x in names if x not in extras]

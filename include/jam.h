@@ -116,8 +116,16 @@ typedef struct {
  *       integral); 1 = spherically aligned (eqs. J1, J2 of Sect. 2.4; beta_k
  *       = 1 - v_theta^2 / v_r^2), solved along the characteristics of the
  *       Jeans equations into a 128 x 24 polar table of the intrinsic moments
- *       per model and integrated along the line of sight (64 nodes); form,
- *       autotune and launch do not apply.  jam_vjp / jam_vjp_chi2 run the
+ *       per model and integrated along the line of sight (64 nodes);
+ *       autotune and launch do not apply.  The forward takes the
+ *       tracer-independent potential sums G, G_theta at the characteristic
+ *       nodes from a per-model grid (512 x 512 points asinh-spaced in R and
+ *       z, a matrix-core contraction over the (j, u) terms, 4-point Lagrange
+ *       interpolation; within 3.4e-7 of the direct sums on the IFU-scale
+ *       model); with form = 1 it sums the terms at every node instead.  When
+ *       jam_vjp recomputes V it takes it from the same forward path (bitwise
+ *       equal to jam_eval's V); the adjoint's own moment table and
+ *       derivatives use the direct sums.  jam_vjp / jam_vjp_chi2 run the
  *       model's own adjoint (recomputing the moment table in one pass with
  *       the cotangent-free sums of its adjoint; the table cotangent is
  *       summed as 64-bit fixed-point integers at a per-model power-of-two

@@ -347,9 +347,10 @@ struct Plan {
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
             *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
-            *d_redf = nullptr, *d_sensw = nullptr;
+            *d_redf = nullptr, *d_sensw = nullptr, *d_sgrid = nullptr, *d_sgred = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
-      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0;
+      n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0,
+      n_sgrid = 0, n_sgred = 0;
   int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
@@ -357,7 +358,8 @@ struct Plan {
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
-         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sens = 0, off_vtmp = 0, off_cot = 0,
+         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sgrid = 0, off_sens = 0, off_vtmp = 0,
+         off_cot = 0,
          off_sbp = 0,
          ws_fwd = 0, ws_vjp = 0;
   // captured evaluations (forward, adjoint, forward + chi^2, adjoint of chi^2)
@@ -727,13 +729,16 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw;
+      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred;
   std::vector<double> c_num, c_sens, c_sensw;
   // wide-sensitivity parts (model, part, x tiles, 32-term groups); their
   // items are cut after the model loop (wide_items)
   std::vector<WidePart> wide_parts;
-  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0;
+  int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0,
+          sgrid = 0;
   const bool spherical = ctx->opt.alignment == 1;
+  // spherical forward: the potential grid (form 1: sums at every node)
+  const bool use_sgrid = spherical && ctx->opt.form != 1;
   for (int m = 0; m < n; ++m) {
     const int gi = geom_idx[m];
     const GeomHost &g = ctx->gh[gi];
@@ -770,6 +775,20 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     if (spherical) {
       sph += (int64_t)jam::kSphNR * jam::kSphNT * 3;
       for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
+    }
+    if (use_sgrid) {
+      const int64_t nn2 = 2 * (int64_t)jam::kSphGridN * jam::kSphGridN;
+      // term slices of at least ten 64-term chunks, at most eight (a
+      // property of the model alone, so that its grid, and everything
+      // computed from it, is the same in any batch)
+      const int sl = std::max(1, std::min(8, jam::sph_terms_padded(g.J1, g.n_u) / 640));
+      d.sgrid_slices = sl;
+      d.sgrid_off = sgrid;
+      sgrid += sl * nn2;
+      for (int tile = 0; tile < jam::kSphGridTiles; ++tile)
+        for (int q = 0; q < sl; ++q) it_sgrid.push_back({m, tile, q, 0});
+      if (sl > 1)
+        for (int64_t bq = 0; bq < (nn2 + 1023) / 1024; ++bq) it_sgred.push_back({m, (int)bq, 0, 0});
     }
     gauss += jam::gauss_size(g.K, g.J1);
     const int tsph = jam::sph_terms_padded(g.J1, g.n_u);
@@ -868,11 +887,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   sort_by_cost(it_sens, c_sens);
   wide_items(wide_parts, ctx->n_cu, it_sensw);
 
-  constexpr int kLists = 14;
+  constexpr int kLists = 16;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
                                            &it_red,   &it_sph, &it_pro, &it_adj, &it_redf,
-                                           &it_sensw};
+                                           &it_sensw, &it_sgrid, &it_sgred};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -896,11 +915,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
                             &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf,
-                            &p->d_sensw};
+                            &p->d_sensw, &p->d_sgrid, &p->d_sgred};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
                       &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf,
-                      &p->n_sensw};
+                      &p->n_sensw, &p->n_sgrid, &p->n_sgred};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -925,6 +944,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_bins = w;   w = align256(w + sizeof(double) * bins);
   p->off_vfwd = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->off_sph = w;    w = align256(w + sizeof(double) * sph);
+  p->off_sgrid = w;  w = align256(w + sizeof(float) * sgrid);
   p->ws_fwd = w;
   p->spherical = spherical;
   p->off_sens = w;   w = align256(w + sizeof(double) * sens);
@@ -964,9 +984,17 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
   if (p->spherical) {
     if (!need_numerator) return;
     double *tabs = (double *)(ws + p->off_sph);
+    float *sgrid = p->n_sgrid ? (float *)(ws + p->off_sgrid) : nullptr;
     const bool timed = ctx->t_num.begin(st, capturing);
+    if (sgrid) {
+      jam::launch_sph_grid(ctx->d_geoms, p->d_models, p->d_sgrid, p->n_sgrid, gauss, terms, st_ws,
+                           sgrid, st);
+      if (p->n_sgred)
+        jam::launch_sph_grid_reduce(ctx->d_geoms, p->d_models, p->d_sgred, p->n_sgred, st_ws,
+                                    sgrid, st);
+    }
     jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, terms, st_ws,
-                            tabs, st);
+                            sgrid, tabs, st);
     if (timed) ctx->t_num.end(st);
     jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix, st);
     return;
@@ -1008,15 +1036,18 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   const bool recompute = (vrms2 == nullptr);
   if (p->spherical) {
     // the spherical adjoint needs the moment table: one pass computes it with
-    // the node sums of the characteristic integrals' adjoint; the numerator
-    // map follows only when V is recomputed
-    launch_forward_maps(ctx, p, pd, nullptr, w, st, false, capturing);
+    // the node sums of the characteristic integrals' adjoint.  When V is
+    // recomputed it comes from the forward's own path (with the potential
+    // grid, the forward's table and numerator map first, then the adjoint's
+    // table over it), so that it equals the forward's V bit for bit
+    const bool fwd_v = recompute && p->n_sgrid > 0;
+    launch_forward_maps(ctx, p, pd, nullptr, w, st, fwd_v, capturing);
     const double *gauss = (const double *)(w + p->off_gauss);
     double *tabs = (double *)(w + p->off_sph);
     jam::launch_sph_moments_jac(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss,
                                 (const float4 *)(w + p->off_terms), st_ws, tabs,
                                 (double *)(w + p->off_sens), st);
-    if (recompute)
+    if (recompute && !fwd_v)
       jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix,
                           st);
   } else {

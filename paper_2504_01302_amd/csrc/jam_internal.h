@@ -66,6 +66,7 @@ struct ModelDev {
                      // table), 4 separable MFMA with one workgroup per whole map
   int n_sens_parts;  // partial sensitivity blocks summed by the chain kernel
   int part_f32;      // 1: the split-term partial maps are FP32 (whole-map numerator)
+  int sgrid_slices;  // spherical forward: term slices of the potential grid (0: no grid)
   int64_t gauss_off; // doubles, per-Gaussian derived quantities
   int64_t term_off;  // float4 entries, term table (cylindrical: padded_terms(T) entries,
                      // zero past T)
@@ -76,6 +77,8 @@ struct ModelDev {
   int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
   int64_t sph_off;   // doubles, spherical moment table [kSphNR][kSphNT][3]
   int64_t sbp_off;   // doubles, surface-brightness adjoint partials [K][sb items]
+  int64_t sgrid_off; // floats, spherical potential grid [sgrid_slices][2][kSphGridN]^2
+                     // (slice 0 holds the sums)
 };
 // Entries of a cylindrical model's term table: T rounded up to a multiple of
 // 32, so that kernels reading whole chunks of 32 terms stay inside it.
@@ -224,9 +227,24 @@ void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
 // unique-pixel N map.
 void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                       const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
+// With sgrid != NULL the moments take G and G_theta at the characteristic
+// nodes from the model's potential grid instead of summing the terms there.
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                        const double *gauss, const float4 *terms, const int *st_ws, double *table,
-                        hipStream_t st);
+                        const double *gauss, const float4 *terms, const int *st_ws,
+                        const float *sgrid, double *table, hipStream_t st);
+// Potential grid of the spherical forward: G and G_theta (the tracer-free
+// (j, u) sums) on kSphGridN x kSphGridN points asinh-spaced in R and in z,
+// as an FP32 matrix-core contraction over the terms.  Items (m, 64 x 64
+// tile, term slice) write slice partials; with more than one slice the
+// reduce items (m, block of 1024 values) sum them in order into slice 0.
+constexpr int kSphGridN = 512;
+constexpr int kSphGridTile = 64;
+constexpr int kSphGridTiles = (kSphGridN / kSphGridTile) * (kSphGridN / kSphGridTile);
+void launch_sph_grid(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                     const double *gauss, const float4 *terms, const int *st_ws, float *sgrid,
+                     hipStream_t st);
+void launch_sph_grid_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                            const int *st_ws, float *sgrid, hipStream_t st);
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);

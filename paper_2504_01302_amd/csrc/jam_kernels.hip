@@ -2308,6 +2308,164 @@ __global__ void __launch_bounds__(256) k_sph_terms(const GeomDev *__restrict__ g
   }
 }
 
+// ---------------------------------------------------------------------------
+// Potential grid.  G and G_theta do not depend on the tracer, only on the
+// point (R, z), and each (j, u) term factorises as gP 2^(cR R^2) 2^(cZ z^2)
+// (resp. gT ...).  On a tensor grid of R and z values the two sums are
+// therefore the matrix products A_G B^T and A_T B^T over the terms, with
+// A[i, t] = g_t 2^(cR_t R_i^2) and B[l, t] = 2^(cZ_t z_l^2), which run on
+// the matrix cores; the moment kernel then interpolates them at the
+// characteristic nodes.  The grid is uniform in asinh(R / aR) and
+// asinh(z / aZ): a quarter of the narrowest mass Gaussian (aR = min sigma_j
+// / 4, aZ = min sigma_j q_j / 4) near the centre, logarithmic far out, up to
+// r_max, the farthest node (sqrt(r_hi^2 + 50 max sigma_k^2)), at grid index
+// kSphGridN - 3.  4-point Lagrange interpolation in both indices (G is even
+// in R and in z, so the point below index 0 is index 1).
+// ---------------------------------------------------------------------------
+struct SphGrid {
+  double aR, aZ, iR, iZ;   // scales and grid points per unit of asinh(R / aR), asinh(z / aZ)
+};
+
+__device__ inline SphGrid sph_grid_scales(const GeomDev &g, const double *tab) {
+  const int K = g.K, J1 = g.J1;
+  const double *mt = tab + 4 * K;         // per mass Gaussian: r_j = 1 / (2 sigma_j^2), e_j^2
+  double s2 = 1e300, z2 = 1e300, sk2 = 0.0;
+  for (int j = 0; j < J1; ++j) {
+    const double sj2 = 0.5 / mt[j];
+    s2 = fmin(s2, sj2);
+    z2 = fmin(z2, sj2 * (1.0 - mt[J1 + j]));
+  }
+  for (int k = 0; k < K; ++k) sk2 = fmax(sk2, 0.5 / tab[k]);
+  const double rhi = exp(g.sph_lnr0 + (kSphNR - 1) * g.sph_dlnr);
+  const double rmax = sqrt(rhi * rhi + 50.0 * sk2);
+  SphGrid s;
+  s.aR = 0.25 * sqrt(s2);
+  s.aZ = 0.25 * sqrt(z2);
+  s.iR = (kSphGridN - 3) / asinh(rmax / s.aR);
+  s.iZ = (kSphGridN - 3) / asinh(rmax / s.aZ);
+  return s;
+}
+
+// Lagrange weights of the points -1, 0, 1, 2 at fraction f of [0, 1].
+__device__ inline void lagrange4(double f, double w[4]) {
+  const double fm = f - 1.0, fm2 = f - 2.0, fp = f + 1.0;
+  w[0] = -f * fm * fm2 * (1.0 / 6.0);
+  w[1] = fp * fm * fm2 * 0.5;
+  w[2] = -fp * f * fm2 * 0.5;
+  w[3] = fp * f * fm * (1.0 / 6.0);
+}
+
+// G and G_theta at (R, z) from the model's grid sg ([2][N][N]: G, G_theta).
+__device__ inline void sph_grid_at(const float *__restrict__ sg, const SphGrid &s, double R,
+                                   double z, double &G, double &Gt) {
+  constexpr int N = kSphGridN;
+  const double x = asinh(R / s.aR) * s.iR, y = asinh(z / s.aZ) * s.iZ;
+  const int i0 = min(max((int)floor(x), 0), N - 3), l0 = min(max((int)floor(y), 0), N - 3);
+  double wx[4], wy[4];
+  lagrange4(x - i0, wx);
+  lagrange4(y - l0, wy);
+  int lb[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) lb[b] = abs(l0 - 1 + b);
+  G = 0.0;
+  Gt = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const float *rg = sg + (int64_t)abs(i0 - 1 + a) * N;
+    const float *rt = rg + (int64_t)N * N;
+    double vg = 0.0, vt = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      vg += wy[b] * (double)rg[lb[b]];
+      vt += wy[b] * (double)rt[lb[b]];
+    }
+    G += wx[a] * vg;
+    Gt += wx[a] * vt;
+  }
+}
+
+// Item (m, 64 x 64 tile, term slice): wave w computes the 32 x 32 block
+// (w & 1, w >> 1) of the tile for both sums, over the slice's 64-term
+// chunks (staged in LDS, shared by the four waves); lane l generates row
+// l % 32 of A (one exponential, two products) and column l % 32 of B for the
+// term of its half-wave; FP32 matrix-core sums per chunk folded into FP64;
+// the slice partial is stored in FP32.
+__global__ void __launch_bounds__(256) k_sph_grid(const GeomDev *__restrict__ geoms,
+                                                  const ModelDev *__restrict__ models,
+                                                  const Item *__restrict__ items, int n_it,
+                                                  const double *__restrict__ gauss,
+                                                  const float4 *__restrict__ terms,
+                                                  const int *__restrict__ st_ws,
+                                                  float *__restrict__ sgrid) {
+  constexpr int N = kSphGridN, NT = kSphGridN / kSphGridTile;
+  __shared__ float4 cs[64];
+  const int lane = threadIdx.x & 63, c32 = lane & 31, kh = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    if (st_ws[it.m] != 0) continue;         // uniform per block; the grid is not read
+    const SphGrid sc = sph_grid_scales(g, gauss + md.gauss_off);
+    const int r0 = kSphGridTile * (it.a / NT) + 32 * (wave & 1);
+    const int z0 = kSphGridTile * (it.a % NT) + 32 * (wave >> 1);
+    const double Rv = sc.aR * sinh((r0 + c32) / sc.iR), Zv = sc.aZ * sinh((z0 + c32) / sc.iZ);
+    const float R2 = (float)(Rv * Rv), Z2 = (float)(Zv * Zv);
+    const int chunks = sph_terms_padded(g.J1, g.n_u) / 64;
+    const int per = (chunks + md.sgrid_slices - 1) / md.sgrid_slices;
+    const int c0 = min(chunks, it.b * per), c1 = min(chunks, c0 + per);
+    const float4 *tc = terms + md.term_off;
+    double aG[16], aT[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { aG[r] = 0.0; aT[r] = 0.0; }
+    for (int ch = c0; ch < c1; ++ch) {
+      __syncthreads();
+      if (threadIdx.x < 64) cs[threadIdx.x] = tc[64 * ch + threadIdx.x];
+      __syncthreads();
+      v16f fG = zero, fT = zero;
+#pragma unroll 8
+      for (int s2 = 0; s2 < 32; ++s2) {
+        const float4 c = cs[2 * s2 + kh];   // (cR log2e, cZ log2e, gP, gT)
+        const float e = fast_exp2(c.x * R2);
+        const float b = fast_exp2(c.y * Z2);
+        fG = __builtin_amdgcn_mfma_f32_32x32x2f32(c.z * e, b, fG, 0, 0, 0);
+        fT = __builtin_amdgcn_mfma_f32_32x32x2f32(c.w * e, b, fT, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { aG[r] += (double)fG[r]; aT[r] += (double)fT[r]; }
+    }
+    float *og = sgrid + md.sgrid_off + (int64_t)it.b * 2 * N * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t e = (int64_t)(r0 + mfma_row(r, lane)) * N + z0 + c32;
+      og[e] = (float)aG[r];
+      og[(int64_t)N * N + e] = (float)aT[r];
+    }
+  }
+}
+
+// Item (m, block of 1024 grid values): the slice partials summed in slice
+// order (FP64) into slice 0.
+__global__ void __launch_bounds__(256) k_sph_grid_reduce(const GeomDev *__restrict__ geoms,
+                                                         const ModelDev *__restrict__ models,
+                                                         const Item *__restrict__ items, int n_it,
+                                                         const int *__restrict__ st_ws,
+                                                         float *__restrict__ sgrid) {
+  constexpr int64_t NN2 = 2 * (int64_t)kSphGridN * kSphGridN;
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;
+    const ModelDev md = models[it.m];
+    float *base = sgrid + md.sgrid_off;
+    for (int e = it.a * 1024 + threadIdx.x; e < min<int64_t>(NN2, (int64_t)(it.a + 1) * 1024); e += 256) {
+      double v = 0.0;
+      for (int sl = 0; sl < md.sgrid_slices; ++sl) v += (double)base[sl * NN2 + e];
+      base[e] = (float)v;
+    }
+  }
+}
+
 // Item (m, table point).  In round q wave w takes tracers k = 8 q + w and
 // 8 q + 4 + w (each coefficient read from LDS feeds both); lane l is node l
 // of the composite Gauss-Legendre rule in tau = ln(r'/r) on
@@ -2315,12 +2473,14 @@ __global__ void __launch_bounds__(256) k_sph_terms(const GeomDev *__restrict__ g
 // coefficients go through LDS in chunks; each group of 64 terms is summed in
 // FP32 (fully unrolled, the coefficient reads are wave-wide broadcasts) and
 // folded into FP64; everything else is FP64; all sums run in a fixed order.
+template <bool kGrid>
 __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
                                                      const Item *__restrict__ items, int n_it,
                                                      const double *__restrict__ gauss,
                                                      const float4 *__restrict__ terms,
                                                      const int *__restrict__ st_ws,
+                                                     const float *__restrict__ sgrid,
                                                      double *__restrict__ table) {
   __shared__ float4 tc[kSphChunk];   // (-c log2e, -d log2e, gP, gT)
   __shared__ float tf[kSphChunk];    // gF
@@ -2351,12 +2511,17 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     // the rule's node and weight of this lane, read from global memory (a
     // lane-dependent index into the by-value descriptor would go to scratch)
     const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
+    // G and G_theta at the nodes: from the model's potential grid, or summed
+    // over the terms here
+    const float *sg = kGrid ? sgrid + md.sgrid_off : nullptr;
+    SphGrid sc = {1.0, 1.0, 1.0, 1.0};
+    if (kGrid) sc = sph_grid_scales(g, tab);
     double Ar = 0.0, At = 0.0, Ap = 0.0;   // this wave's tracers (lane 0)
     double accF = 0.0;                      // this thread's share of G_phi
     constexpr int kTr = 2;                  // tracers per wave and round
     const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
     for (int q = 0; q < rounds; ++q) {
-      double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr];
+      double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr], Zp[kTr];
       float R2[kTr], Z2[kTr];
       bool on[kTr];
 #pragma unroll
@@ -2364,7 +2529,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
         const int k = 4 * (kTr * q + u) + wave;
         on[u] = k < K;                      // uniform per wave
         alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; wn[u] = 0.0; nuv[u] = 0.0;
-        rp[u] = r; Rp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
+        rp[u] = r; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
         if (on[u]) {
           alpha[u] = tab[k];
           alphaq[u] = tab[K + k];
@@ -2377,6 +2542,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           const double ct = sqrt(fmax(0.0, 1.0 - st * st));
           Rp[u] = rp[u] * st;
           const double zp = rp[u] * ct;
+          Zp[u] = zp;
           R2[u] = (float)(Rp[u] * Rp[u]);
           Z2[u] = (float)(zp * zp);
           wn[u] = 0.5 * glw * hs * rp[u];
@@ -2386,6 +2552,14 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       double accG[kTr], accT[kTr];
 #pragma unroll
       for (int u = 0; u < kTr; ++u) { accG[u] = 0.0; accT[u] = 0.0; }
+      if (kGrid) {
+#pragma unroll
+        for (int u = 0; u < kTr; ++u)
+          if (on[u]) sph_grid_at(sg, sc, Rp[u], Zp[u], accG[u], accT[u]);
+      }
+      // the terms: the node sums (without a grid) and, in the first round,
+      // G_phi at the table point
+      if (!kGrid || q == 0)
       for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
         const int cn = min(kSphChunk, Tp - c0);
         __syncthreads();
@@ -2394,7 +2568,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
-        if (on[0]) {
+        if (!kGrid && on[0]) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
             float sg0 = 0.f, sd0 = 0.f, sg1 = 0.f, sd1 = 0.f;
 #pragma unroll
@@ -3632,10 +3806,25 @@ void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n
                      st_ws, terms);
 }
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                        const double *gauss, const float4 *terms, const int *st_ws, double *table,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_moments, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
-                     terms, st_ws, table);
+                        const double *gauss, const float4 *terms, const int *st_ws,
+                        const float *sgrid, double *table, hipStream_t st) {
+  if (sgrid)
+    hipLaunchKernelGGL(k_sph_moments<true>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it,
+                       gauss, terms, st_ws, sgrid, table);
+  else
+    hipLaunchKernelGGL(k_sph_moments<false>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it,
+                       n_it, gauss, terms, st_ws, sgrid, table);
+}
+void launch_sph_grid(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                     const double *gauss, const float4 *terms, const int *st_ws, float *sgrid,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_grid, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
+                     terms, st_ws, sgrid);
+}
+void launch_sph_grid_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
+                            const int *st_ws, float *sgrid, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_grid_reduce, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it,
+                     st_ws, sgrid);
 }
 void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                             const double *gauss, const float4 *terms, const int *st_ws,
