@@ -347,10 +347,11 @@ struct Plan {
   jam::Item *d_terms = nullptr, *d_pix = nullptr, *d_num = nullptr, *d_bins = nullptr,
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
             *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
-            *d_redf = nullptr, *d_sensw = nullptr, *d_sgrid = nullptr, *d_sgred = nullptr;
+            *d_redf = nullptr, *d_sensw = nullptr, *d_sgrid = nullptr, *d_sgred = nullptr,
+            *d_sgred6 = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
       n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0,
-      n_sgrid = 0, n_sgred = 0;
+      n_sgrid = 0, n_sgred = 0, n_sgred6 = 0;
   int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
@@ -358,7 +359,8 @@ struct Plan {
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
-         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sgrid = 0, off_sens = 0, off_vtmp = 0,
+         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sgrid = 0, off_sgrid6 = 0, off_sens = 0,
+         off_vtmp = 0,
          off_cot = 0,
          off_sbp = 0,
          ws_fwd = 0, ws_vjp = 0;
@@ -729,13 +731,13 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred;
+      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred, it_sgred6;
   std::vector<double> c_num, c_sens, c_sensw;
   // wide-sensitivity parts (model, part, x tiles, 32-term groups); their
   // items are cut after the model loop (wide_items)
   std::vector<WidePart> wide_parts;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0,
-          sgrid = 0;
+          sgrid = 0, sgrid6 = 0;
   const bool spherical = ctx->opt.alignment == 1;
   // spherical forward: the potential grid (form 1: sums at every node)
   const bool use_sgrid = spherical && ctx->opt.form != 1;
@@ -777,18 +779,24 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
       for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
     }
     if (use_sgrid) {
+      // forward grid: 2 floats per point; the adjoint's: 8
       const int64_t nn2 = 2 * (int64_t)jam::kSphGridN * jam::kSphGridN;
+      const int64_t nn8 = 4 * nn2;
       // term slices of at least ten 64-term chunks, at most eight (a
       // property of the model alone, so that its grid, and everything
       // computed from it, is the same in any batch)
       const int sl = std::max(1, std::min(8, jam::sph_terms_padded(g.J1, g.n_u) / 640));
       d.sgrid_slices = sl;
       d.sgrid_off = sgrid;
+      d.sgrid6_off = sgrid6;
       sgrid += sl * nn2;
+      sgrid6 += sl * nn8;
       for (int tile = 0; tile < jam::kSphGridTiles; ++tile)
         for (int q = 0; q < sl; ++q) it_sgrid.push_back({m, tile, q, 0});
-      if (sl > 1)
+      if (sl > 1) {
         for (int64_t bq = 0; bq < (nn2 + 1023) / 1024; ++bq) it_sgred.push_back({m, (int)bq, 0, 0});
+        for (int64_t bq = 0; bq < (nn8 + 1023) / 1024; ++bq) it_sgred6.push_back({m, (int)bq, 0, 0});
+      }
     }
     gauss += jam::gauss_size(g.K, g.J1);
     const int tsph = jam::sph_terms_padded(g.J1, g.n_u);
@@ -887,11 +895,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   sort_by_cost(it_sens, c_sens);
   wide_items(wide_parts, ctx->n_cu, it_sensw);
 
-  constexpr int kLists = 16;
+  constexpr int kLists = 17;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
                                            &it_red,   &it_sph, &it_pro, &it_adj, &it_redf,
-                                           &it_sensw, &it_sgrid, &it_sgred};
+                                           &it_sensw, &it_sgrid, &it_sgred, &it_sgred6};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -915,11 +923,11 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
                             &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf,
-                            &p->d_sensw, &p->d_sgrid, &p->d_sgred};
+                            &p->d_sensw, &p->d_sgrid, &p->d_sgred, &p->d_sgred6};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
                       &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf,
-                      &p->n_sensw, &p->n_sgrid, &p->n_sgred};
+                      &p->n_sensw, &p->n_sgrid, &p->n_sgred, &p->n_sgred6};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -951,6 +959,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_vtmp = w;   w = align256(w + sizeof(double) * p->total_bins);
   p->off_cot = w;    w = align256(w + sizeof(double) * p->total_bins);
   p->off_sbp = w;    w = align256(w + sizeof(double) * sbp);
+  p->off_sgrid6 = w; w = align256(w + sizeof(float) * sgrid6);
   p->ws_vjp = w;
   out = std::move(p);
   return JAM_OK;
@@ -988,10 +997,9 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
     const bool timed = ctx->t_num.begin(st, capturing);
     if (sgrid) {
       jam::launch_sph_grid(ctx->d_geoms, p->d_models, p->d_sgrid, p->n_sgrid, gauss, terms, st_ws,
-                           sgrid, st);
+                           sgrid, false, st);
       if (p->n_sgred)
-        jam::launch_sph_grid_reduce(ctx->d_geoms, p->d_models, p->d_sgred, p->n_sgred, st_ws,
-                                    sgrid, st);
+        jam::launch_sph_grid_reduce(p->d_models, p->d_sgred, p->n_sgred, st_ws, sgrid, false, st);
     }
     jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, terms, st_ws,
                             sgrid, tabs, st);
@@ -1044,9 +1052,17 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
     launch_forward_maps(ctx, p, pd, nullptr, w, st, fwd_v, capturing);
     const double *gauss = (const double *)(w + p->off_gauss);
     double *tabs = (double *)(w + p->off_sph);
-    jam::launch_sph_moments_jac(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss,
-                                (const float4 *)(w + p->off_terms), st_ws, tabs,
-                                (double *)(w + p->off_sens), st);
+    const float4 *terms = (const float4 *)(w + p->off_terms);
+    float *sgrid6 = p->n_sgrid ? (float *)(w + p->off_sgrid6) : nullptr;
+    if (sgrid6) {
+      jam::launch_sph_grid(ctx->d_geoms, p->d_models, p->d_sgrid, p->n_sgrid, gauss, terms, st_ws,
+                           sgrid6, true, st);
+      if (p->n_sgred6)
+        jam::launch_sph_grid_reduce(p->d_models, p->d_sgred6, p->n_sgred6, st_ws, sgrid6, true,
+                                    st);
+    }
+    jam::launch_sph_moments_jac(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, terms,
+                                st_ws, sgrid6, tabs, (double *)(w + p->off_sens), st);
     if (recompute && !fwd_v)
       jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix,
                           st);

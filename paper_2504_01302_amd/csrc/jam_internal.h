@@ -77,8 +77,9 @@ struct ModelDev {
   int64_t bin_off;   // doubles, per-bin sums [Nb | Ib]
   int64_t sph_off;   // doubles, spherical moment table [kSphNR][kSphNT][3]
   int64_t sbp_off;   // doubles, surface-brightness adjoint partials [K][sb items]
-  int64_t sgrid_off; // floats, spherical potential grid [sgrid_slices][2][kSphGridN]^2
-                     // (slice 0 holds the sums)
+  int64_t sgrid_off; // floats, spherical forward potential grid
+                     // [sgrid_slices][kSphGridN][kSphGridN][2] (slice 0 holds the sums)
+  int64_t sgrid6_off;// floats, the adjoint's grid [sgrid_slices][kSphGridN][kSphGridN][8]
 };
 // Entries of a cylindrical model's term table: T rounded up to a multiple of
 // 32, so that kernels reading whole chunks of 32 terms stay inside it.
@@ -232,19 +233,21 @@ void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                         const double *gauss, const float4 *terms, const int *st_ws,
                         const float *sgrid, double *table, hipStream_t st);
-// Potential grid of the spherical forward: G and G_theta (the tracer-free
-// (j, u) sums) on kSphGridN x kSphGridN points asinh-spaced in R and in z,
-// as an FP32 matrix-core contraction over the terms.  Items (m, 64 x 64
-// tile, term slice) write slice partials; with more than one slice the
-// reduce items (m, block of 1024 values) sum them in order into slice 0.
+// Potential grid of the spherical model: the tracer-free (j, u) sums G and
+// G_theta (forward), or those and their four coefficient-weighted sums for
+// the R'^2, z'^2 derivatives (adjoint), on kSphGridN x kSphGridN points
+// asinh-spaced in R and in z, as FP32 matrix-core contractions over the
+// terms.  Items (m, 64 x 64 tile, term slice) write slice partials; with more
+// than one slice the reduce items (m, block of 1024 floats) sum them in order
+// into slice 0.
 constexpr int kSphGridN = 512;
 constexpr int kSphGridTile = 64;
 constexpr int kSphGridTiles = (kSphGridN / kSphGridTile) * (kSphGridN / kSphGridTile);
 void launch_sph_grid(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                      const double *gauss, const float4 *terms, const int *st_ws, float *sgrid,
-                     hipStream_t st);
-void launch_sph_grid_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                            const int *st_ws, float *sgrid, hipStream_t st);
+                     bool adjoint, hipStream_t st);
+void launch_sph_grid_reduce(const ModelDev *m, const Item *it, int n_it, const int *st_ws,
+                            float *sgrid, bool adjoint, hipStream_t st);
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st);
@@ -262,10 +265,11 @@ void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int 
 // 256-term tile)), and the per-model gradients (block per model; they read
 // the surface-brightness partials sbp).
 // The moment table together with the cotangent-free node sums of its
-// adjoint (SphAdj::jac, gphi), for the adjoint's forward pass.
+// adjoint (SphAdj::jac, gphi), for the adjoint's forward pass; with sgrid6
+// != NULL the six node sums come from the model's adjoint grid.
 void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                             const double *gauss, const float4 *terms, const int *st_ws,
-                            double *table, double *sens, hipStream_t st);
+                            const float *sgrid6, double *table, double *sens, hipStream_t st);
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
                         int n_sens, const Item *it_tile, int n_tile, ParamsDev p,

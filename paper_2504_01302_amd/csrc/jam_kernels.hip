@@ -2355,10 +2355,16 @@ __device__ inline void lagrange4(double f, double w[4]) {
   w[3] = fp * f * fm * (1.0 / 6.0);
 }
 
-// G and G_theta at (R, z) from the model's grid sg ([2][N][N]: G, G_theta).
+// Values per grid point: the forward's G, G_theta (2 floats), or the
+// adjoint's G, G_theta and their coefficient-weighted sums for the R'^2 and
+// z'^2 derivatives (6 values, stored in 8 floats for two 16-byte reads).
+template <int NC> struct SphGridVals { static constexpr int S = NC == 2 ? 2 : 8; };
+
+// The NC sums at (R, z) from a model's grid sg ([N][N][S]).
+template <int NC>
 __device__ inline void sph_grid_at(const float *__restrict__ sg, const SphGrid &s, double R,
-                                   double z, double &G, double &Gt) {
-  constexpr int N = kSphGridN;
+                                   double z, double (&v)[NC]) {
+  constexpr int N = kSphGridN, S = SphGridVals<NC>::S;
   const double x = asinh(R / s.aR) * s.iR, y = asinh(z / s.aZ) * s.iZ;
   const int i0 = min(max((int)floor(x), 0), N - 3), l0 = min(max((int)floor(y), 0), N - 3);
   double wx[4], wy[4];
@@ -2367,29 +2373,44 @@ __device__ inline void sph_grid_at(const float *__restrict__ sg, const SphGrid &
   int lb[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) lb[b] = abs(l0 - 1 + b);
-  G = 0.0;
-  Gt = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = 0.0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const float *rg = sg + (int64_t)abs(i0 - 1 + a) * N;
-    const float *rt = rg + (int64_t)N * N;
-    double vg = 0.0, vt = 0.0;
+    const float *row = sg + (int64_t)abs(i0 - 1 + a) * N * S;
+    double rv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rv[c] = 0.0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      vg += wy[b] * (double)rg[lb[b]];
-      vt += wy[b] * (double)rt[lb[b]];
+      const float *pt = row + lb[b] * S;
+      float f[NC];
+      if constexpr (NC == 2) {
+        const float2 q = *reinterpret_cast<const float2 *>(pt);
+        f[0] = q.x; f[1] = q.y;
+      } else {
+        const float4 q0 = *reinterpret_cast<const float4 *>(pt);
+        const float4 q1 = *reinterpret_cast<const float4 *>(pt + 4);
+        f[0] = q0.x; f[1] = q0.y; f[2] = q0.z; f[3] = q0.w; f[4] = q1.x; f[5] = q1.y;
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) rv[c] += wy[b] * (double)f[c];
     }
-    G += wx[a] * vg;
-    Gt += wx[a] * vt;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] += wx[a] * rv[c];
   }
 }
 
 // Item (m, 64 x 64 tile, term slice): wave w computes the 32 x 32 block
-// (w & 1, w >> 1) of the tile for both sums, over the slice's 64-term
+// (w & 1, w >> 1) of the tile for all NC sums, over the slice's 64-term
 // chunks (staged in LDS, shared by the four waves); lane l generates row
-// l % 32 of A (one exponential, two products) and column l % 32 of B for the
-// term of its half-wave; FP32 matrix-core sums per chunk folded into FP64;
-// the slice partial is stored in FP32.
+// l % 32 of the A operands (one exponential, NC products) and column l % 32
+// of B for the term of its half-wave; FP32 matrix-core sums per chunk
+// folded into FP64; the slice partial is stored in FP32 ([N][N][S] per
+// slice).  The sums, per term (c.x, c.y the exponent coefficients of R'^2,
+// z'^2 with log2 e, gP = c.z, gT = c.w): G = gP E, G_theta = gT E, and for
+// the adjoint gP c.x E, gP c.y E, gT c.x E, gT c.y E.
+template <int NC>
 __global__ void __launch_bounds__(256) k_sph_grid(const GeomDev *__restrict__ geoms,
                                                   const ModelDev *__restrict__ models,
                                                   const Item *__restrict__ items, int n_it,
@@ -2397,7 +2418,7 @@ __global__ void __launch_bounds__(256) k_sph_grid(const GeomDev *__restrict__ ge
                                                   const float4 *__restrict__ terms,
                                                   const int *__restrict__ st_ws,
                                                   float *__restrict__ sgrid) {
-  constexpr int N = kSphGridN, NT = kSphGridN / kSphGridTile;
+  constexpr int N = kSphGridN, NT = kSphGridN / kSphGridTile, S = SphGridVals<NC>::S;
   __shared__ float4 cs[64];
   const int lane = threadIdx.x & 63, c32 = lane & 31, kh = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2416,51 +2437,71 @@ __global__ void __launch_bounds__(256) k_sph_grid(const GeomDev *__restrict__ ge
     const int per = (chunks + md.sgrid_slices - 1) / md.sgrid_slices;
     const int c0 = min(chunks, it.b * per), c1 = min(chunks, c0 + per);
     const float4 *tc = terms + md.term_off;
-    double aG[16], aT[16];
+    double acc[NC][16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) { aG[r] = 0.0; aT[r] = 0.0; }
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0;
     for (int ch = c0; ch < c1; ++ch) {
       __syncthreads();
       if (threadIdx.x < 64) cs[threadIdx.x] = tc[64 * ch + threadIdx.x];
       __syncthreads();
-      v16f fG = zero, fT = zero;
-#pragma unroll 8
+      v16f f[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) f[c] = zero;
+#pragma unroll 4
       for (int s2 = 0; s2 < 32; ++s2) {
         const float4 c = cs[2 * s2 + kh];   // (cR log2e, cZ log2e, gP, gT)
         const float e = fast_exp2(c.x * R2);
         const float b = fast_exp2(c.y * Z2);
-        fG = __builtin_amdgcn_mfma_f32_32x32x2f32(c.z * e, b, fG, 0, 0, 0);
-        fT = __builtin_amdgcn_mfma_f32_32x32x2f32(c.w * e, b, fT, 0, 0, 0);
+        const float eP = c.z * e, eT = c.w * e;
+        f[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(eP, b, f[0], 0, 0, 0);
+        f[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(eT, b, f[1], 0, 0, 0);
+        if constexpr (NC == 6) {
+          f[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(eP * c.x, b, f[2], 0, 0, 0);
+          f[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(eP * c.y, b, f[3], 0, 0, 0);
+          f[4] = __builtin_amdgcn_mfma_f32_32x32x2f32(eT * c.x, b, f[4], 0, 0, 0);
+          f[5] = __builtin_amdgcn_mfma_f32_32x32x2f32(eT * c.y, b, f[5], 0, 0, 0);
+        }
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { aG[r] += (double)fG[r]; aT[r] += (double)fT[r]; }
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[c][r] += (double)f[c][r];
     }
-    float *og = sgrid + md.sgrid_off + (int64_t)it.b * 2 * N * N;
+    float *og = sgrid + (NC == 2 ? md.sgrid_off : md.sgrid6_off) + (int64_t)it.b * N * N * S;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t e = (int64_t)(r0 + mfma_row(r, lane)) * N + z0 + c32;
-      og[e] = (float)aG[r];
-      og[(int64_t)N * N + e] = (float)aT[r];
+      float *o = og + ((int64_t)(r0 + mfma_row(r, lane)) * N + z0 + c32) * S;
+      if constexpr (NC == 2) {
+        *reinterpret_cast<float2 *>(o) = make_float2((float)acc[0][r], (float)acc[1][r]);
+      } else {
+        *reinterpret_cast<float4 *>(o) = make_float4((float)acc[0][r], (float)acc[1][r],
+                                                     (float)acc[2][r], (float)acc[3][r]);
+        *reinterpret_cast<float4 *>(o + 4) =
+            make_float4((float)acc[4][r], (float)acc[5][r], 0.f, 0.f);
+      }
     }
   }
 }
 
-// Item (m, block of 1024 grid values): the slice partials summed in slice
-// order (FP64) into slice 0.
-__global__ void __launch_bounds__(256) k_sph_grid_reduce(const GeomDev *__restrict__ geoms,
-                                                         const ModelDev *__restrict__ models,
+// Item (m, block of 1024 grid floats): the slice partials summed in slice
+// order (FP64) into slice 0; len = N^2 S floats per slice, off selects the
+// forward's or the adjoint's grid.
+__global__ void __launch_bounds__(256) k_sph_grid_reduce(const ModelDev *__restrict__ models,
                                                          const Item *__restrict__ items, int n_it,
                                                          const int *__restrict__ st_ws,
-                                                         float *__restrict__ sgrid) {
-  constexpr int64_t NN2 = 2 * (int64_t)kSphGridN * kSphGridN;
+                                                         float *__restrict__ sgrid, int adjoint) {
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     if (st_ws[it.m] != 0) continue;
     const ModelDev md = models[it.m];
-    float *base = sgrid + md.sgrid_off;
-    for (int e = it.a * 1024 + threadIdx.x; e < min<int64_t>(NN2, (int64_t)(it.a + 1) * 1024); e += 256) {
+    const int64_t len = (int64_t)kSphGridN * kSphGridN * (adjoint ? 8 : 2);
+    float *base = sgrid + (adjoint ? md.sgrid6_off : md.sgrid_off);
+    const int64_t e1 = min(len, (int64_t)(it.a + 1) * 1024);
+    for (int64_t e = (int64_t)it.a * 1024 + threadIdx.x; e < e1; e += 256) {
       double v = 0.0;
-      for (int sl = 0; sl < md.sgrid_slices; ++sl) v += (double)base[sl * NN2 + e];
+      for (int sl = 0; sl < md.sgrid_slices; ++sl) v += (double)base[sl * len + e];
       base[e] = (float)v;
     }
   }
@@ -2555,7 +2596,12 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       if (kGrid) {
 #pragma unroll
         for (int u = 0; u < kTr; ++u)
-          if (on[u]) sph_grid_at(sg, sc, Rp[u], Zp[u], accG[u], accT[u]);
+          if (on[u]) {
+            double v[2];
+            sph_grid_at<2>(sg, sc, Rp[u], Zp[u], v);
+            accG[u] = v[0];
+            accT[u] = v[1];
+          }
       }
       // the terms: the node sums (without a grid) and, in the first round,
       // G_phi at the table point
@@ -2954,12 +3000,14 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
 // nu0_k (eP, eD) go to SphAdj::jac, none of which depends on the table
 // cotangent, and the cell's G_phi to SphAdj::gphi; k_sph_rows combines
 // them with the cotangent once the line-of-sight adjoint has produced it.
+template <bool kGrid>
 __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restrict__ geoms,
                                                          const ModelDev *__restrict__ models,
                                                          const Item *__restrict__ items, int n_it,
                                                          const double *__restrict__ gauss,
                                                          const float4 *__restrict__ terms,
                                                          const int *__restrict__ st_ws,
+                                                         const float *__restrict__ sgrid6,
                                                          double *__restrict__ table,
                                                          double *__restrict__ sens) {
   __shared__ float4 tc[kSphChunk];
@@ -2980,6 +3028,11 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
       continue;
     }
     const SphAdj adj = sph_adj_of(sens, md, g);
+    // the six node sums: from the model's adjoint grid, or summed over the
+    // terms here
+    const float *sg = kGrid ? sgrid6 + md.sgrid6_off : nullptr;
+    SphGrid sgs = {1.0, 1.0, 1.0, 1.0};
+    if (kGrid) sgs = sph_grid_scales(g, gauss + md.gauss_off);
     const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
     const float4 *gtc = terms + md.term_off;
     const float *gtf = (const float *)(gtc + Tp);
@@ -3022,6 +3075,18 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
       double aG[kTr], aT[kTr], aGR[kTr], aGZ[kTr], aTR[kTr], aTZ[kTr];
 #pragma unroll
       for (int u = 0; u < kTr; ++u) aG[u] = aT[u] = aGR[u] = aGZ[u] = aTR[u] = aTZ[u] = 0.0;
+      if (kGrid) {
+#pragma unroll
+        for (int u = 0; u < kTr; ++u)
+          if (on[u]) {
+            double v[6];
+            sph_grid_at<6>(sg, sgs, nd[u].Rp, nd[u].zp, v);
+            aG[u] = v[0]; aT[u] = v[1]; aGR[u] = v[2]; aGZ[u] = v[3]; aTR[u] = v[4]; aTZ[u] = v[5];
+          }
+      }
+      // the terms: the node sums (without a grid) and, in the first round,
+      // G_phi at the table point
+      if (!kGrid || q == 0)
       for (int c0 = 0; c0 < Tp; c0 += kSphChunk) {
         const int cn = min(kSphChunk, Tp - c0);
         __syncthreads();
@@ -3032,7 +3097,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
-        if (on[0]) {
+        if (!kGrid && on[0]) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
             float sG0 = 0.f, sT0 = 0.f, sGR0 = 0.f, sGZ0 = 0.f, sTR0 = 0.f, sTZ0 = 0.f;
             float sG1 = 0.f, sT1 = 0.f, sGR1 = 0.f, sGZ1 = 0.f, sTR1 = 0.f, sTZ1 = 0.f;
@@ -3817,20 +3882,28 @@ void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int
 }
 void launch_sph_grid(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                      const double *gauss, const float4 *terms, const int *st_ws, float *sgrid,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_grid, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
-                     terms, st_ws, sgrid);
+                     bool adjoint, hipStream_t st) {
+  if (adjoint)
+    hipLaunchKernelGGL(k_sph_grid<6>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
+                       terms, st_ws, sgrid);
+  else
+    hipLaunchKernelGGL(k_sph_grid<2>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it, gauss,
+                       terms, st_ws, sgrid);
 }
-void launch_sph_grid_reduce(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
-                            const int *st_ws, float *sgrid, hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_grid_reduce, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it,
-                     st_ws, sgrid);
+void launch_sph_grid_reduce(const ModelDev *m, const Item *it, int n_it, const int *st_ws,
+                            float *sgrid, bool adjoint, hipStream_t st) {
+  hipLaunchKernelGGL(k_sph_grid_reduce, dim3(grid_of(n_it)), dim3(256), 0, st, m, it, n_it, st_ws,
+                     sgrid, adjoint ? 1 : 0);
 }
 void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                             const double *gauss, const float4 *terms, const int *st_ws,
-                            double *table, double *sens, hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_moments_jac, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it, n_it,
-                     gauss, terms, st_ws, table, sens);
+                            const float *sgrid6, double *table, double *sens, hipStream_t st) {
+  if (sgrid6)
+    hipLaunchKernelGGL(k_sph_moments_jac<true>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it,
+                       n_it, gauss, terms, st_ws, sgrid6, table, sens);
+  else
+    hipLaunchKernelGGL(k_sph_moments_jac<false>, dim3(grid_of(n_it)), dim3(256), 0, st, g, m, it,
+                       n_it, gauss, terms, st_ws, sgrid6, table, sens);
 }
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
