@@ -348,10 +348,10 @@ struct Plan {
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
             *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
             *d_redf = nullptr, *d_sensw = nullptr, *d_sgrid = nullptr, *d_sgred = nullptr,
-            *d_sgred6 = nullptr;
+            *d_sgred6 = nullptr, *d_pcot = nullptr, *d_pfix = nullptr, *d_sgs = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
       n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0,
-      n_sgrid = 0, n_sgred = 0, n_sgred6 = 0;
+      n_sgrid = 0, n_sgred = 0, n_sgred6 = 0, n_pcot = 0, n_pfix = 0, n_sgs = 0;
   int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
@@ -359,7 +359,8 @@ struct Plan {
   int64_t total_bins = 0, total_lum = 0, total_mass = 0, total_map = 0;
   // workspace regions (bytes)
   size_t off_status = 0, off_queue = 0, off_gauss = 0, off_terms = 0, off_pix = 0, off_part = 0,
-         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sgrid = 0, off_sgrid6 = 0, off_sens = 0,
+         off_bins = 0, off_vfwd = 0, off_sph = 0, off_sgrid = 0, off_sgrid6 = 0, off_sgcot = 0,
+         off_sens = 0,
          off_vtmp = 0,
          off_cot = 0,
          off_sbp = 0,
@@ -731,13 +732,14 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   const Tune &tune = p->tune;
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
-      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred, it_sgred6;
+      it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred, it_sgred6, it_pcot,
+      it_pfix, it_sgs;
   std::vector<double> c_num, c_sens, c_sensw;
   // wide-sensitivity parts (model, part, x tiles, 32-term groups); their
   // items are cut after the model loop (wide_items)
   std::vector<WidePart> wide_parts;
   int64_t gauss = 0, terms = 0, pixd = 0, part = 0, bins = 0, sens = 0, sph = 0, sbp = 0,
-          sgrid = 0, sgrid6 = 0;
+          sgrid = 0, sgrid6 = 0, sgcot = 0;
   const bool spherical = ctx->opt.alignment == 1;
   // spherical forward: the potential grid (form 1: sums at every node)
   const bool use_sgrid = spherical && ctx->opt.form != 1;
@@ -809,7 +811,9 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     part += nc.map ? (part_elems + 1) / 2 : part_elems;
     bins += 2 * (int64_t)g.n_bins;
     if (spherical) {
-      d.n_sens_parts = jam::sph_ranges(g.K);
+      // term sensitivities: point ranges, or (with the potential grid) parts
+      // of the grid rows
+      d.n_sens_parts = use_sgrid ? jam::kSphIParts : jam::sph_ranges(g.K);
       sens += jam::sph_adj_size(g.K, g.n_pix, tsph, d.n_sens_parts);
     } else {
       sens += 3 * (int64_t)d.n_sens_parts * g.T + (int64_t)g.K * 3 * g.J1;
@@ -821,7 +825,14 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     if (!small)
       for (int tb = 0; tb < ((spherical ? tsph : g.T) + 255) / 256; ++tb)
         it_terms.push_back({m, tb, 0, 0});
-    if (spherical) {
+    if (spherical && use_sgrid) {
+      d.sgcot_off = sgcot;
+      sgcot += jam::sph_gcot_size(g.K);
+      for (int q = 0; q < jam::sph_pitems(g.K); ++q) it_pcot.push_back({m, q, 0, 0});
+      for (int b = 0; b < jam::kSphGridN * jam::kSphGridN / 1024; ++b) it_pfix.push_back({m, b, 0, 0});
+      for (int tb = 0; tb < tsph / 32; ++tb)
+        for (int ip = 0; ip < jam::kSphIParts; ++ip) it_sgs.push_back({m, tb, ip, 0});
+    } else if (spherical) {
       for (int tt = 0; tt < (tsph + 255) / 256; ++tt)
         for (int r = 0; r < d.n_sens_parts; ++r) {
           it_sens.push_back({m, tt, r, 0});
@@ -895,11 +906,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   sort_by_cost(it_sens, c_sens);
   wide_items(wide_parts, ctx->n_cu, it_sensw);
 
-  constexpr int kLists = 17;
+  constexpr int kLists = 20;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
                                            &it_red,   &it_sph, &it_pro, &it_adj, &it_redf,
-                                           &it_sensw, &it_sgrid, &it_sgred, &it_sgred6};
+                                           &it_sensw, &it_sgrid, &it_sgred, &it_sgred6,
+                                           &it_pcot,  &it_pfix,  &it_sgs};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -923,11 +935,13 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   jam::Item **dl[kLists] = {&p->d_terms, &p->d_pix,  &p->d_num, &p->d_bins,
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
                             &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf,
-                            &p->d_sensw, &p->d_sgrid, &p->d_sgred, &p->d_sgred6};
+                            &p->d_sensw, &p->d_sgrid, &p->d_sgred, &p->d_sgred6,
+                            &p->d_pcot,  &p->d_pfix,  &p->d_sgs};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
                       &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf,
-                      &p->n_sensw, &p->n_sgrid, &p->n_sgred, &p->n_sgred6};
+                      &p->n_sensw, &p->n_sgrid, &p->n_sgred, &p->n_sgred6,
+                      &p->n_pcot,  &p->n_pfix,  &p->n_sgs};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -960,6 +974,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   p->off_cot = w;    w = align256(w + sizeof(double) * p->total_bins);
   p->off_sbp = w;    w = align256(w + sizeof(double) * sbp);
   p->off_sgrid6 = w; w = align256(w + sizeof(float) * sgrid6);
+  p->off_sgcot = w;  w = align256(w + sizeof(double) * sgcot);
   p->ws_vjp = w;
   out = std::move(p);
   return JAM_OK;
@@ -1092,10 +1107,12 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
   if (p->spherical) {
     const bool ts = ctx->t_sens.begin(st, capturing);
     jam::launch_sph_adjoint(ctx->d_geoms, p->d_models, p->n, p->d_pix, p->n_pix, p->d_sph,
-                            p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, pd,
+                            p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, p->d_pcot,
+                            p->n_pcot, p->d_pfix, p->n_pfix, p->d_sgs, p->n_sgs, pd,
                             (const double *)(w + p->off_gauss),
                             (const float4 *)(w + p->off_terms), st_ws,
-                            (const double *)(w + p->off_sph), pix, sbp, sens, gd, st);
+                            (const double *)(w + p->off_sph), pix, sbp, sens,
+                            p->n_sgs ? (double *)(w + p->off_sgcot) : nullptr, gd, st);
     if (ts) ctx->t_sens.end(st);
     return;
   }

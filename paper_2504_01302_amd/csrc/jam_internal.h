@@ -80,6 +80,7 @@ struct ModelDev {
   int64_t sgrid_off; // floats, spherical forward potential grid
                      // [sgrid_slices][kSphGridN][kSphGridN][2] (slice 0 holds the sums)
   int64_t sgrid6_off;// floats, the adjoint's grid [sgrid_slices][kSphGridN][kSphGridN][8]
+  int64_t sgcot_off; // doubles, the adjoint's grid cotangent (sph_gcot_size)
 };
 // Entries of a cylindrical model's term table: T rounded up to a multiple of
 // 32, so that kernels reading whole chunks of 32 terms stay inside it.
@@ -270,12 +271,17 @@ void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int 
 void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                             const double *gauss, const float4 *terms, const int *st_ws,
                             const float *sgrid6, double *table, double *sens, hipStream_t st);
+// With sgcot != NULL the term sensitivities go through the potential grid
+// (items it_pcot (m, point item), it_pfix (m, 1024 grid points), it_sgs (m,
+// 32-term block, row part)) instead of the point-range items it_sens.
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
-                        int n_sens, const Item *it_tile, int n_tile, ParamsDev p,
-                        const double *gauss, const float4 *terms, const int *st_ws,
-                        const double *table, const double *pix, const double *sbp, double *sens,
-                        GradsDev out, hipStream_t st);
+                        int n_sens, const Item *it_tile, int n_tile, const Item *it_pcot,
+                        int n_pcot, const Item *it_pfix, int n_pfix, const Item *it_sgs,
+                        int n_sgs, ParamsDev p, const double *gauss, const float4 *terms,
+                        const int *st_ws, const double *table, const double *pix,
+                        const double *sbp, double *sens, double *sgcot, GradsDev out,
+                        hipStream_t st);
 // Adjoint of the spherically aligned model.  Per model, in the sensitivity
 // region (doubles): the table cotangent [kSphNR*kSphNT][3], per (tracer,
 // cell) rows (d/dbeta, d/dalphaq, d/dnu0) [K][cells][3], line-of-sight
@@ -318,6 +324,20 @@ __host__ __device__ inline int sph_ranges(int K) {
 __host__ __device__ inline int64_t sph_range_len(int K, int n_rng) {
   const int64_t per = (sph_points(K) + n_rng - 1) / n_rng;
   return (per + 255) / 256 * 256;
+}
+// Term-major sensitivities through the potential grid: point items of
+// kSphPtsItem points spread the point cotangents onto the grid (items (m,
+// q)); the fixed-point grid is converted in items (m, block of 1024 grid
+// points); the contraction runs in items (m, 32-term block, row part) over
+// kSphIParts parts of the grid rows, which are the sensitivities' ranges.
+// Workspace per model: sph_gcot_size doubles.
+constexpr int kSphPtsItem = 16384;
+constexpr int kSphIParts = 4;
+__host__ __device__ inline int sph_pitems(int K) {
+  return (int)((sph_points(K) + kSphPtsItem - 1) / kSphPtsItem);
+}
+__host__ __device__ inline int64_t sph_gcot_size(int K) {
+  return 3LL * kSphGridN * kSphGridN + 2LL * sph_pitems(K) + 2;
 }
 
 // Logistic radial anisotropy profile prof[m][0..3] = (beta_0, beta_inf, r_a,

@@ -3252,6 +3252,46 @@ __global__ void __launch_bounds__(64) k_sph_rows(const GeomDev *__restrict__ geo
   }
 }
 
+// Point p = (cell, tracer, node) of a model's characteristic integrals: the
+// node (as in the forward, with the powers of r and r' written as
+// exponentials of ln r and tau, r' = r e^tau) and the cotangents phi =
+// dL/dG and psi = dL/dG_theta there, from the table cotangent in adj.dtab.
+// sinth: sin of the table's polar angles; gp: the geometry (its 8-node rule
+// is read from global memory: a lane-dependent index into a by-value
+// descriptor would go to scratch).
+__device__ inline void sph_point_cot(const GeomDev &g, const GeomDev *__restrict__ gp,
+                                     const double *tab, const SphAdj &adj, const double *sinth,
+                                     int64_t p, double &Rp, double &zp, double &phi,
+                                     double &psi) {
+  const int K = g.K;
+  const int cell = (int)(p / ((int64_t)K * kSphNodes));
+  const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
+  const int ir = cell / kSphNT, ith = cell % kSphNT;
+  const double lnr = g.sph_lnr0 + ir * g.sph_dlnr, r = exp(lnr);
+  const double sth = sinth[ith];
+  const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1];
+  const double lp = adj.dtab[3 * cell + 2];
+  const double alpha = tab[k], alphaq = tab[K + k], nu0 = tab[2 * K + k];
+  const double beta = 1.0 - 1.0 / tab[3 * K + k];
+  const int gi = node & 7;
+  const double glx = gp->gl8_x[gi], glw = gp->gl8_w[gi];
+  const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
+  const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
+  const double lrp = lnr + tau, rp = exp(lrp);
+  const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
+  const double ct = sqrt(fmax(0.0, 1.0 - st * st));
+  Rp = rp * st;
+  zp = rp * ct;
+  const double wn = 0.5 * glw * hs * rp;
+  const double nu = nu0 * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
+  const double muP = lr + (1.0 - beta) * (lt + lp);
+  const double muD = lp * (1.0 - beta) * sth * exp((1.0 - 3.0 * beta) * lnr);
+  const double dD = muD * wn * exp((3.0 * beta + 1.0) * lrp) * Rp * nu;
+  phi = muP * wn * exp((2.0 * beta + 1.0) * lrp - 2.0 * beta * lnr) * nu +
+        dD * 2.0 * (alphaq - alpha);
+  psi = dD;
+}
+
 // Term-major sensitivities.  Item (m, 256-term tile, point range); thread =
 // term.  Each 256-point chunk of the range is regenerated (thread = point):
 // node position and the cotangents phi = dL/dG, psi = dL/dG_theta at the
@@ -3292,35 +3332,9 @@ __global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ ge
       const int64_t p = c0 + threadIdx.x;
       float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
       if (p < p1) {
-        // the node as in the forward, with the powers of r and r' written
-        // as exponentials of ln r and tau (r' = r e^tau)
-        const int cell = (int)(p / ((int64_t)K * kSphNodes));
-        const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
-        const int ir = cell / kSphNT, ith = cell % kSphNT;
-        const double lnr = g.sph_lnr0 + ir * g.sph_dlnr, r = exp(lnr);
-        const double sth = sc[0][ith];
-        const double lr = adj.dtab[3 * cell], lt = adj.dtab[3 * cell + 1];
-        const double lp = adj.dtab[3 * cell + 2];
-        const double alpha = tab[k], alphaq = tab[K + k], nu0 = tab[2 * K + k];
-        const double beta = 1.0 - 1.0 / tab[3 * K + k];
-        const int gi = node & 7;
-        const double glx = geoms[md.geom].gl8_x[gi], glw = geoms[md.geom].gl8_w[gi];
-        const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
-        const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
-        const double lrp = lnr + tau, rp = exp(lrp);
-        const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
-        const double ct = sqrt(fmax(0.0, 1.0 - st * st));
-        const double Rp = rp * st, zp = rp * ct;
-        const double wn = 0.5 * glw * hs * rp;
-        const double nu = nu0 * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
-        const double muP = lr + (1.0 - beta) * (lt + lp);
-        const double muD = lp * (1.0 - beta) * sth * exp((1.0 - 3.0 * beta) * lnr);
-        const double dD = muD * wn * exp((3.0 * beta + 1.0) * lrp) * Rp * nu;
-        const double phi = muP * wn * exp((2.0 * beta + 1.0) * lrp - 2.0 * beta * lnr) * nu +
-                           dD * 2.0 * (alphaq - alpha);
-        const SphNode nd{rp, st, ct, Rp, zp, wn, 0.0, tau, false};
-        const double psi = dD;
-        const float R2 = (float)(nd.Rp * nd.Rp), Z2 = (float)(nd.zp * nd.zp);
+        double Rp, zp, phi, psi;
+        sph_point_cot(g, geoms + md.geom, tab, adj, sc[0], p, Rp, zp, phi, psi);
+        const float R2 = (float)(Rp * Rp), Z2 = (float)(zp * zp);
         const float fphi = (float)phi, fpsi = (float)psi;
         va = make_float4(R2, Z2, fphi, fpsi);
         vb = make_float4(fphi * R2, fpsi * R2, fphi * Z2, fpsi * Z2);
@@ -3360,6 +3374,254 @@ __global__ void __launch_bounds__(256) k_sph_sens(const GeomDev *__restrict__ ge
       o[5] = SyT;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Term-major sensitivities through the potential grid.  With the adjoint's
+// node sums interpolated from the grid, the term sensitivities are those of
+// the grid values: the point cotangents phi, psi are spread onto the grid
+// with the interpolation's own weights (its transpose), and per term
+//   S_phi = sum_il Phi[i, l] E_t(R_i, z_l),  E_t = 2^(cx R_i^2) 2^(cy z_l^2),
+// with the R^2 and z^2 moments, is one more matrix-core contraction over the
+// grid.  The spreading adds 64-bit fixed-point integers at a per-model
+// power-of-two scale, so the grid cotangent, like the table cotangent, does
+// not depend on the order of the additions.
+// Workspace per model (8-byte slots from sgcot_off): the fixed-point grid
+// [N][N][2] (phi, psi), the FP32 grid [N][N][2], the bound partials
+// [items][2] and the two scales.
+// ---------------------------------------------------------------------------
+__device__ inline long long *sph_gcot_fixed(double *sgcot, const ModelDev &md) {
+  return reinterpret_cast<long long *>(sgcot + md.sgcot_off);
+}
+__device__ inline float *sph_gcot_float(double *sgcot, const ModelDev &md) {
+  return reinterpret_cast<float *>(sgcot + md.sgcot_off + 2LL * kSphGridN * kSphGridN);
+}
+__device__ inline double *sph_gcot_bounds(double *sgcot, const ModelDev &md) {
+  return sgcot + md.sgcot_off + 3LL * kSphGridN * kSphGridN;
+}
+
+// Item (m, point item q): clears a share of the fixed-point grid and sums
+// |phi|, |psi| over the item's points (fixed-order block sums).
+__global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restrict__ geoms,
+                                                        const ModelDev *__restrict__ models,
+                                                        const Item *__restrict__ items, int n_it,
+                                                        const double *__restrict__ gauss,
+                                                        const int *__restrict__ st_ws,
+                                                        double *__restrict__ sens,
+                                                        double *__restrict__ sgcot) {
+  __shared__ double sinth[kSphNT];
+  __shared__ double sh[256];
+  if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
+  __syncthreads();
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const double *tab = gauss + md.gauss_off;
+    const int np = sph_pitems(g.K);
+    const int64_t n2 = 2LL * kSphGridN * kSphGridN, share = (n2 + np - 1) / np;
+    long long *fx = sph_gcot_fixed(sgcot, md);
+    const int64_t e0 = (int64_t)it.a * share, e1 = min(n2, e0 + share);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) fx[e] = 0;
+    const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
+                  p1 = min(P, p0 + kSphPtsItem);
+    double sa = 0.0, sb = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+      double R, z, phi, psi;
+      sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
+      sa += fabs(phi);
+      sb += fabs(psi);
+    }
+    sa = block_sum256(sa, sh);
+    sb = block_sum256(sb, sh);
+    if (threadIdx.x == 0) {
+      double *bnd = sph_gcot_bounds(sgcot, md);
+      bnd[2 * it.a] = sa;
+      bnd[2 * it.a + 1] = sb;
+    }
+  }
+}
+
+// The power of two that maps 1.6 x bound (the interpolation weights of a
+// point sum to at most 1.25^2 in magnitude) below 2^60; NaN for a
+// non-finite bound.
+__device__ inline double sph_gcot_scale(double bound) {
+  if (bound == 0.0) return 1.0;
+  if (!(bound < __builtin_inf())) return __builtin_nan("");
+  return ldexp(1.0, min(1000, 60 - ilogb(1.6 * bound)));
+}
+
+// Item (m, point item q): spreads phi, psi of the item's points onto the
+// fixed-point grid with the interpolation weights of sph_grid_at.
+__global__ void __launch_bounds__(256) k_sph_pcot_scatter(const GeomDev *__restrict__ geoms,
+                                                          const ModelDev *__restrict__ models,
+                                                          const Item *__restrict__ items,
+                                                          int n_it,
+                                                          const double *__restrict__ gauss,
+                                                          const int *__restrict__ st_ws,
+                                                          double *__restrict__ sens,
+                                                          double *__restrict__ sgcot) {
+  constexpr int N = kSphGridN;
+  __shared__ double sinth[kSphNT];
+  __shared__ double sh[256];
+  if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
+  __syncthreads();
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const SphAdj adj = sph_adj_of(sens, md, g);
+    const double *tab = gauss + md.gauss_off;
+    const int np = sph_pitems(g.K);
+    double *bnd = sph_gcot_bounds(sgcot, md);
+    double ba = 0.0, bb = 0.0;
+    for (int q = threadIdx.x; q < np; q += 256) { ba += bnd[2 * q]; bb += bnd[2 * q + 1]; }
+    ba = block_sum256(ba, sh);
+    bb = block_sum256(bb, sh);
+    const double sa = sph_gcot_scale(ba), sb = sph_gcot_scale(bb);
+    if (it.a == 0 && threadIdx.x == 0) { bnd[2 * np] = sa; bnd[2 * np + 1] = sb; }
+    if (!(sa == sa) || !(sb == sb)) continue;   // uniform: a non-finite cotangent
+    const SphGrid sc = sph_grid_scales(g, tab);
+    unsigned long long *fx = reinterpret_cast<unsigned long long *>(sph_gcot_fixed(sgcot, md));
+    const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
+                  p1 = min(P, p0 + kSphPtsItem);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+      double R, z, phi, psi;
+      sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
+      const double x = asinh(R / sc.aR) * sc.iR, y = asinh(z / sc.aZ) * sc.iZ;
+      const int i0 = min(max((int)floor(x), 0), N - 3), l0 = min(max((int)floor(y), 0), N - 3);
+      double wx[4], wy[4];
+      lagrange4(x - i0, wx);
+      lagrange4(y - l0, wy);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t row = (int64_t)abs(i0 - 1 + a) * N;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const double w = wx[a] * wy[b];
+          const long long va = __double2ll_rn(phi * w * sa), vb = __double2ll_rn(psi * w * sb);
+          unsigned long long *c = fx + (row + abs(l0 - 1 + b)) * 2;
+          if (va) atomicAdd(c, (unsigned long long)va);
+          if (vb) atomicAdd(c + 1, (unsigned long long)vb);
+        }
+      }
+    }
+  }
+}
+
+// Item (m, block of 1024 grid points): the fixed-point grid cotangent back
+// to FP32 (NaN for a non-finite cotangent).
+__global__ void __launch_bounds__(256) k_sph_pcot_fix(const GeomDev *__restrict__ geoms,
+                                                      const ModelDev *__restrict__ models,
+                                                      const Item *__restrict__ items, int n_it,
+                                                      const int *__restrict__ st_ws,
+                                                      double *__restrict__ sgcot) {
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const double *bnd = sph_gcot_bounds(sgcot, md);
+    const int np = sph_pitems(g.K);
+    const double sa = bnd[2 * np], sb = bnd[2 * np + 1];
+    const long long *fx = sph_gcot_fixed(sgcot, md);
+    float *fl = sph_gcot_float(sgcot, md);
+    for (int e = it.a * 1024 + threadIdx.x; e < (it.a + 1) * 1024; e += 256) {
+      fl[2 * e] = (float)(sa == sa ? (double)fx[2 * e] / sa : sa);
+      fl[2 * e + 1] = (float)(sb == sb ? (double)fx[2 * e + 1] / sb : sb);
+    }
+  }
+}
+
+// Item (m, block of 32 terms, part ip of kSphIParts): wave w contracts grid
+// rows 32 (4 ip + w) .. + 31 with the terms' z factors, D = Phi B and
+// Dz = Phi (z^2 B) (and for psi), reading four grid columns per lane and
+// 16 bytes at a time; then per term the row sums with 2^(cx R_i^2) and
+// R_i^2 2^(cx R_i^2), FP32 per lane, FP64 across lanes and waves (fixed
+// order).  Output: the part's [S_phi, S_psi, R^2 S_phi, R^2 S_psi, z^2 S_phi,
+// z^2 S_psi] per term, as k_sph_sens's ranges.
+__global__ void __launch_bounds__(256) k_sph_sens_grid(const GeomDev *__restrict__ geoms,
+                                                       const ModelDev *__restrict__ models,
+                                                       const Item *__restrict__ items, int n_it,
+                                                       const double *__restrict__ gauss,
+                                                       const float4 *__restrict__ terms,
+                                                       const int *__restrict__ st_ws,
+                                                       double *__restrict__ sens,
+                                                       double *__restrict__ sgcot) {
+  constexpr int N = kSphGridN;
+  __shared__ __attribute__((aligned(16))) float zsq[N];
+  __shared__ float rsq[N];
+  __shared__ double red[4][6][32];
+  const int lane = threadIdx.x & 63, c32 = lane & 31, kh = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const v16f zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const SphGrid sc = sph_grid_scales(g, gauss + md.gauss_off);
+    __syncthreads();                         // the previous item's reads of zsq, rsq, red
+    for (int l = threadIdx.x; l < N; l += 256) {
+      const double zv = sc.aZ * sinh(l / sc.iZ), rv = sc.aR * sinh(l / sc.iR);
+      zsq[l] = (float)(zv * zv);
+      rsq[l] = (float)(rv * rv);
+    }
+    __syncthreads();
+    const int Tp = sph_terms_padded(g.J1, g.n_u);
+    const int t = 32 * it.a + c32;           // < Tp (Tp is a multiple of 64)
+    const float4 c = terms[md.term_off + t];
+    const float *fl = sph_gcot_float(sgcot, md);
+    const int row = 32 * (kSphIParts * it.b + wave) + c32;
+    const float *fr = fl + (int64_t)row * N * 2;
+    v16f dP = zero, dPz = zero, dT = zero, dTz = zero;
+    for (int q = 0; q < N / 8; ++q) {
+      const int l0 = 8 * q + 4 * kh;
+      const float4 pa = *reinterpret_cast<const float4 *>(fr + 2 * l0);
+      const float4 pb = *reinterpret_cast<const float4 *>(fr + 2 * l0 + 4);
+      const float4 zz = *reinterpret_cast<const float4 *>(&zsq[l0]);
+      const float ap[4] = {pa.x, pa.z, pb.x, pb.z}, at[4] = {pa.y, pa.w, pb.y, pb.w};
+      const float z4[4] = {zz.x, zz.y, zz.z, zz.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float b = fast_exp2(c.y * z4[j]), bz = b * z4[j];
+        dP = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[j], b, dP, 0, 0, 0);
+        dPz = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[j], bz, dPz, 0, 0, 0);
+        dT = __builtin_amdgcn_mfma_f32_32x32x2f32(at[j], b, dT, 0, 0, 0);
+        dTz = __builtin_amdgcn_mfma_f32_32x32x2f32(at[j], bz, dTz, 0, 0, 0);
+      }
+    }
+    // rows of this lane: 32 (4 ip + w) + mfma_row(r, lane); column = term t
+    float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int rbase = 32 * (kSphIParts * it.b + wave);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float r2 = rsq[rbase + mfma_row(r, lane)];
+      const float e = fast_exp2(c.x * r2);
+      s[0] = fmaf(e, dP[r], s[0]);
+      s[1] = fmaf(e, dT[r], s[1]);
+      s[2] = fmaf(e * r2, dP[r], s[2]);
+      s[3] = fmaf(e * r2, dT[r], s[3]);
+      s[4] = fmaf(e, dPz[r], s[4]);
+      s[5] = fmaf(e, dTz[r], s[5]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double v = (double)s[k];
+      v += __shfl_xor(v, 32, 64);
+      if (kh == 0) red[wave][k][c32] = v;
+    }
+    __syncthreads();
+    if (wave == 0 && kh == 0) {
+      const SphAdj adj = sph_adj_of(sens, md, g);
+      double *o = adj.sparts + ((int64_t)it.b * Tp + t) * 6;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) o[k] = ((red[0][k][c32] + red[1][k][c32]) + red[2][k][c32]) + red[3][k][c32];
+    }
   }
 }
 
@@ -3913,10 +4175,12 @@ void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_i
 }
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
                         int n_los, const Item *it_cell, int n_cell, const Item *it_sens,
-                        int n_sens, const Item *it_tile, int n_tile, ParamsDev p,
-                        const double *gauss, const float4 *terms, const int *st_ws,
-                        const double *table, const double *pix, const double *sbp, double *sens,
-                        GradsDev out, hipStream_t st) {
+                        int n_sens, const Item *it_tile, int n_tile, const Item *it_pcot,
+                        int n_pcot, const Item *it_pfix, int n_pfix, const Item *it_sgs,
+                        int n_sgs, ParamsDev p, const double *gauss, const float4 *terms,
+                        const int *st_ws, const double *table, const double *pix,
+                        const double *sbp, double *sens, double *sgcot, GradsDev out,
+                        hipStream_t st) {
   hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, gauss, st_ws, pix,
                      sens);
   hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
@@ -3924,8 +4188,19 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
   hipLaunchKernelGGL(k_sph_dtab_fix, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws, sens);
   hipLaunchKernelGGL(k_sph_rows, dim3(grid_of(n_cell)), dim3(64), 0, st, g, m, it_cell, n_cell,
                      gauss, st_ws, sens);
-  hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
-                     gauss, terms, st_ws, sens);
+  if (sgcot) {
+    hipLaunchKernelGGL(k_sph_pcot_bound, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
+                       n_pcot, gauss, st_ws, sens, sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_scatter, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
+                       n_pcot, gauss, st_ws, sens, sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_fix, dim3(grid_of(n_pfix)), dim3(256), 0, st, g, m, it_pfix,
+                       n_pfix, st_ws, sgcot);
+    hipLaunchKernelGGL(k_sph_sens_grid, dim3(grid_of(n_sgs)), dim3(256), 0, st, g, m, it_sgs,
+                       n_sgs, gauss, terms, st_ws, sens, sgcot);
+  } else {
+    hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
+                       gauss, terms, st_ws, sens);
+  }
   hipLaunchKernelGGL(k_sph_sens_cells, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile,
                      n_tile, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_chain, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile, n_tile,
