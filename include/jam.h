@@ -122,10 +122,13 @@ typedef struct {
  *       nodes from a per-model grid (512 x 512 points asinh-spaced in R and
  *       z, a matrix-core contraction over the (j, u) terms, 4-point Lagrange
  *       interpolation; within 3.4e-7 of the direct sums on the IFU-scale
- *       model); with form = 1 it sums the terms at every node instead.  When
- *       jam_vjp recomputes V it takes it from the same forward path (bitwise
- *       equal to jam_eval's V); the adjoint's own moment table and
- *       derivatives use the direct sums.  jam_vjp / jam_vjp_chi2 run the
+ *       model); with form = 1 it sums the terms at every node instead.  The
+ *       adjoint differentiates the same grid model (with form = 1, the
+ *       direct sums); when jam_vjp recomputes V it takes it from the
+ *       forward path (bitwise equal to jam_eval's V).  The grid's term
+ *       sensitivities spread the point cotangents onto the grid as 64-bit
+ *       fixed-point integers, so gradients stay bitwise reproducible.
+ *       jam_vjp / jam_vjp_chi2 run the
  *       model's own adjoint (recomputing the moment table in one pass with
  *       the cotangent-free sums of its adjoint; the table cotangent is
  *       summed as 64-bit fixed-point integers at a per-model power-of-two
