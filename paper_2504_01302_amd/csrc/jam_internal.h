@@ -98,7 +98,7 @@ struct KinDev {
   const double *vobs, *prec;
 };
 constexpr int kChi2MaxBins = 4096;
-constexpr int kSensTerms = 512;   // terms per matrix-core sensitivity item
+constexpr int kSensTerms = 2048;  // terms per matrix-core sensitivity item
 
 // Constants of the one-dimensional MGE transform (Euler inversion), passed
 // by value: nodes beta_k = beta_re + i beta_im[k] and signed weights eta[k]

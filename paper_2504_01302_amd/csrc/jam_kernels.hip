@@ -1310,8 +1310,12 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
                                                const double *__restrict__ pix,
                                                const int *__restrict__ st_ws,
                                                double *__restrict__ sens, char *smem) {
-  float (*lam)[32] = reinterpret_cast<float (*)[32]>(smem);
-  float *ysq = reinterpret_cast<float *>(smem + YC * 32 * sizeof(float));
+  // lambda[x][y] staged x-major with the y values of each half-wave kh
+  // (y = 2 s + kh) consecutive, so one 16-byte read gives a lane four steps'
+  // operands; rows padded by 4 floats
+  float (*lam)[YC + 4] = reinterpret_cast<float (*)[YC + 4]>(smem);
+  float *ysq = reinterpret_cast<float *>(smem + 32 * (YC + 4) * sizeof(float));
+  float *xsq = ysq + YC;                   // x^2 of the tile's rows (0 past the map)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c32 = lane & 31, kh = lane >> 5;
@@ -1335,39 +1339,44 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
       const int ny = min(YC, g.n_uy - yb);
       if (h == 0 || n_yb > 1) {         // uniform per block
         __syncthreads();
-        for (int e = threadIdx.x; e < YC * 32; e += 256) {
+        // the rows the steps read: ny rounded up to whole blocks of 8 y
+        const int rows = min(YC, (ny + 7) & ~7);
+        for (int e = threadIdx.x; e < rows * 32; e += 256) {
           const int yy = e >> 5, xx = e & 31;
           float v = 0.f;
           if (yy < ny && x0 + xx < g.n_ux) v = (float)lamN[(int64_t)(yb + yy) * g.n_ux + x0 + xx];
-          lam[yy][xx] = v;
+          lam[xx][(yy & 1) * (YC / 2) + (yy >> 1)] = v;
         }
-        for (int e = threadIdx.x; e < YC; e += 256) {
+        for (int e = threadIdx.x; e < rows; e += 256) {
           float v = 0.f;
           if (e < ny) { const double y = g.ys[yb + e]; v = (float)(y * y); }
-          ysq[e] = v;
+          ysq[(e & 1) * (YC / 2) + (e >> 1)] = v;
+        }
+        if (threadIdx.x < 32) {
+          const int xr = x0 + threadIdx.x;
+          float v = 0.f;
+          if (xr < g.n_ux) { const double xv = g.xs[xr]; v = (float)(xv * xv); }
+          xsq[threadIdx.x] = v;
         }
         __syncthreads();
       }
       for (int y0 = 0; y0 < ny; y0 += 128) {
-        // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2, up to 128 y values
-        // in quarters of 32 (rows past ny hold zero lambda; y0 + 127 < YC)
+        // operands lambda[x0 + c32][y0 + 2 s + kh] and y^2 for up to 128 y
+        // values, four steps (8 y) per 16-byte read (rows past ny hold zero
+        // lambda; y0 + 127 < YC)
         v16f dg = zero, dh = zero;
-        const int quarters = min(4, (ny - y0 + 31) / 32);   // uniform per block
+        const int nb = min(16, (ny - y0 + 7) / 8);   // uniform per block
+        const float *lrow = &lam[c32][kh * (YC / 2) + y0 / 2];
+        const float *yrow = ysq + kh * (YC / 2) + y0 / 2;
+        for (int qb = 0; qb < nb; ++qb) {
+          const float4 a4 = *reinterpret_cast<const float4 *>(lrow + 4 * qb);
+          const float4 y4 = *reinterpret_cast<const float4 *>(yrow + 4 * qb);
+          const float ra[4] = {a4.x, a4.y, a4.z, a4.w}, ry[4] = {y4.x, y4.y, y4.z, y4.w};
 #pragma unroll
-        for (int qy = 0; qy < 4; ++qy) {
-          if (qy >= quarters) break;
-          float ra[16], ry[16];
-#pragma unroll
-          for (int s2 = 0; s2 < 16; ++s2) {
-            const int yy = y0 + 32 * qy + 2 * s2 + kh;
-            ra[s2] = lam[yy][c32];
-            ry[s2] = ysq[yy];
-          }
-#pragma unroll
-          for (int s2 = 0; s2 < 16; ++s2) {
-            const float b = fast_exp2(c.y * ry[s2]);
-            dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b, dg, 0, 0, 0);
-            dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[s2], b * ry[s2], dh, 0, 0, 0);
+          for (int j = 0; j < 4; ++j) {
+            const float b = fast_exp2(c.y * ry[j]);
+            dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[j], b, dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[j], b * ry[j], dh, 0, 0, 0);
           }
         }
 #pragma unroll
@@ -1377,19 +1386,19 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
         }
       }
     }
-    double s0 = 0.0, s1 = 0.0, sg = 0.0;
+    // rows past the map have zero lambda, so zero sums; each lane's 16 rows
+    // in FP32, the lanes in FP64
+    float f0 = 0.f, f1 = 0.f, fg = 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int xr = x0 + mfma_row(r, lane);
-      if (xr < g.n_ux) {
-        const double xv = g.xs[xr];
-        const float x2 = (float)(xv * xv);
-        const double e = (double)fast_exp2(c.x * x2);
-        s0 += e * gacc[r];
-        s1 += (double)x2 * e * gacc[r];
-        sg += e * (double)fmaf(c.w, x2, c.z) * hacc[r];
-      }
+      const float x2 = xsq[mfma_row(r, lane)];
+      const float e = fast_exp2(c.x * x2);
+      const float ed = e * (float)gacc[r];
+      f0 += ed;
+      f1 = fmaf(x2, ed, f1);
+      fg = fmaf(e * fmaf(c.w, x2, c.z), (float)hacc[r], fg);
     }
+    double s0 = (double)f0, s1 = (double)f1, sg = (double)fg;
     s0 += __shfl_xor(s0, 32, 64);
     s1 += __shfl_xor(s1, 32, 64);
     sg += __shfl_xor(sg, 32, 64);
@@ -1402,7 +1411,7 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
   }
 }
 
-constexpr int kSensSmem = (YC * 32 + YC) * (int)sizeof(float);
+constexpr int kSensSmem = (32 * (YC + 4) + YC + 32) * (int)sizeof(float);
 static_assert(kSensSmem >= 3 * 256 * (int)sizeof(float), "per-pixel sensitivity LDS");
 
 // Adjoint sensitivities over a work list, variant in Item::c (0 per-pixel
