@@ -2552,7 +2552,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     const float *gtf = (const float *)(gtc + Tp);
     const double *tab = gauss + md.gauss_off;
     const int ir = it.a / kSphNT, ith = it.a % kSphNT;
-    const double r = exp(g.sph_lnr0 + ir * g.sph_dlnr);
+    const double lnr = g.sph_lnr0 + ir * g.sph_dlnr, r = exp(lnr);
     const double th = ith * (0.5 * kPi / (kSphNT - 1));
     const double sth = sin(th), cth = cos(th);
     const double Rp0 = r * sth, zp0 = r * cth;
@@ -2572,6 +2572,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
     for (int q = 0; q < rounds; ++q) {
       double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr], Zp[kTr];
+      double lrp[kTr];                       // ln r' (powers of r' as exponentials)
       float R2[kTr], Z2[kTr];
       bool on[kTr];
 #pragma unroll
@@ -2579,7 +2580,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
         const int k = 4 * (kTr * q + u) + wave;
         on[u] = k < K;                      // uniform per wave
         alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; wn[u] = 0.0; nuv[u] = 0.0;
-        rp[u] = r; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
+        rp[u] = r; lrp[u] = lnr; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
         if (on[u]) {
           alpha[u] = tab[k];
           alphaq[u] = tab[K + k];
@@ -2587,8 +2588,9 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha[u]) / (r * r));
           const double hs = tmax / kSphSeg;
           const double tau = (seg + 0.5 + 0.5 * glx) * hs;
-          rp[u] = r * exp(tau);
-          const double st = fmin(1.0, sth * pow(r / rp[u], 1.0 - beta[u]));
+          lrp[u] = lnr + tau;
+          rp[u] = exp(lrp[u]);
+          const double st = fmin(1.0, sth * exp(-(1.0 - beta[u]) * tau));
           const double ct = sqrt(fmax(0.0, 1.0 - st * st));
           Rp[u] = rp[u] * st;
           const double zp = rp[u] * ct;
@@ -2653,8 +2655,8 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       for (int u = 0; u < kTr; ++u) {
         if (!on[u]) continue;
         const double sk2 = 0.5 / alpha[u], qk2 = alpha[u] / alphaq[u];
-        double fP = wn[u] * pow(rp[u], 2.0 * beta[u] + 1.0) * nuv[u] * accG[u];
-        double fD = wn[u] * pow(rp[u], 3.0 * beta[u] + 1.0) * Rp[u] * nuv[u] *
+        double fP = wn[u] * exp((2.0 * beta[u] + 1.0) * lrp[u]) * nuv[u] * accG[u];
+        double fD = wn[u] * exp((3.0 * beta[u] + 1.0) * lrp[u]) * Rp[u] * nuv[u] *
                     (accT[u] + accG[u] * (1.0 / qk2 - 1.0) / sk2);
         fP = wave_sum(fP);
         fD = wave_sum(fD);
@@ -2759,14 +2761,14 @@ struct SphNode {
   double rp, st, ct, Rp, zp, wn, en, tau;
   bool clamped;
 };
-__device__ inline SphNode sph_node(double r, double sth, double alpha, double alphaq, double beta,
-                                   int seg, double glx, double glw) {
+__device__ inline SphNode sph_node(double r, double lnr, double sth, double alpha, double alphaq,
+                                   double beta, int seg, double glx, double glw) {
   SphNode o;
   const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r));
   const double hs = tmax / kSphSeg;
   o.tau = (seg + 0.5 + 0.5 * glx) * hs;
-  o.rp = r * exp(o.tau);
-  const double sraw = sth * pow(r / o.rp, 1.0 - beta);
+  o.rp = exp(lnr + o.tau);
+  const double sraw = sth * exp(-(1.0 - beta) * o.tau);
   o.clamped = !(sraw < 1.0);
   o.st = fmin(1.0, sraw);
   o.ct = sqrt(fmax(0.0, 1.0 - o.st * o.st));
@@ -3049,6 +3051,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
     const int cell = it.a;
     double r, sth, cth;
     sph_cell(g, cell, r, sth, cth);
+    const double lnr = g.sph_lnr0 + (cell / kSphNT) * g.sph_dlnr;   // ln r (r = e^lnr)
     const double Rp0 = r * sth, zp0 = r * cth;
     const float R20 = (float)(Rp0 * Rp0), Z20 = (float)(zp0 * zp0);
     const int seg = lane >> 3, gi = lane & 7;
@@ -3076,7 +3079,7 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
           alphaq[u] = tab[K + k];
           nu0[u] = tab[2 * K + k];
           beta[u] = 1.0 - 1.0 / tab[3 * K + k];
-          nd[u] = sph_node(r, sth, alpha[u], alphaq[u], beta[u], seg, glx, glw);
+          nd[u] = sph_node(r, lnr, sth, alpha[u], alphaq[u], beta[u], seg, glx, glw);
           R2[u] = (float)(nd[u].Rp * nd[u].Rp);
           Z2[u] = (float)(nd[u].zp * nd[u].zp);
         }
@@ -3166,9 +3169,9 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
         // the term coefficients carry log2 e: dE/d(R'^2) = ln 2 c.x E
         const double dG = kLn2 * (aGR[u] * dR2 + aGZ[u] * dZ2);
         const double dH = kLn2 * (aTR[u] * dR2 + aTZ[u] * dZ2) + kap * dG;
-        const double lrp = log(n.rp);
-        const double pP = n.wn * pow(n.rp, 2.0 * be + 1.0);
-        const double pD = n.wn * pow(n.rp, 3.0 * be + 1.0);
+        const double lrp = lnr + n.tau;     // ln r'
+        const double pP = n.wn * exp((2.0 * be + 1.0) * lrp);
+        const double pD = n.wn * exp((3.0 * be + 1.0) * lrp);
         double fP = pP * nu * aG[u];
         double fD = pD * n.Rp * nu * H;
         double bP = pP * (2.0 * lrp * nu * aG[u] + dnu * aG[u] + nu * dG);
