@@ -125,16 +125,18 @@ def _case(c):
     return g, p
 
 
-def test_adjoint_vs_oracle_differences():
+@pytest.mark.parametrize("form", [0, 1])
+def test_adjoint_vs_oracle_differences(form):
     """Gradient of sum_b cot_b v_rms^2_b against central differences of the
     FP64 oracle (stored), at the adjoint tests' bar: 1e-4 of the gradient's
-    norm and every component within 1e-3 relative or 1e-6 of the largest."""
+    norm and every component within 1e-3 relative or 1e-6 of the largest;
+    with the potential grid (form 0) and with the direct sums (form 1)."""
     dev = _dev()
     gold = json.load(open(os.path.join(HERE, "golden", "sph_grad.json")))
     for c in gold["cases"]:
         g, p = _case(c)
         w = inputs.Workload("g", [g], np.zeros(1, np.int32), [p])
-        ctx = binding.Context([g], alignment=1)
+        ctx = binding.Context([g], alignment=1, form=form)
         pk = binding.pack_params(w, dev, amplitudes=True)
         V, st = ctx.eval_batch(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
                                pk["lum_I0"], pk["mass_S0"])
@@ -432,12 +434,16 @@ def test_forward_k20_j20_vs_golden():
     ctx.close()
 
 
-def test_adjoint_multi_tile_vs_oracle_differences():
+@pytest.mark.parametrize("form", [0, 1])
+def test_adjoint_multi_tile_vs_oracle_differences(form):
     """Gradient at 9 tracers of mixed anisotropy x (8 mass Gaussians + BH) x
-    128 u-nodes = 1152 (j, u) terms: five 256-term tiles of the term-major
-    sensitivity pass, two 1024-term coefficient chunks and two tracer rounds
-    of the characteristic integrals' adjoint, against stored central
-    differences of the FP64 oracle, at the adjoint bar."""
+    128 u-nodes = 1152 (j, u) terms: with the direct sums (form 1) five
+    256-term tiles of the term-major sensitivity pass, two 1024-term
+    coefficient chunks and two tracer rounds of the characteristic
+    integrals' adjoint; with the potential grid (form 0) 36 32-term blocks
+    of the grid contraction and the point cotangents of 9 tracers spread
+    onto the grid; against stored central differences of the FP64 oracle,
+    at the adjoint bar."""
     dev = _dev()
     gold = json.load(open(os.path.join(HERE, "golden", "sph_grad_large.json")))
     g = inputs.small_geometry(seed=11, n_lum=9, n_mass=8, nx=6, ny=5, ss=1, psf_n=3,
@@ -445,7 +451,7 @@ def test_adjoint_multi_tile_vs_oracle_differences():
     p = inputs.small_params(g, seed=11)
     assert (np.array(p.beta) > 0).any() and (np.array(p.beta) < 0).any()
     w = inputs.Workload("g", [g], np.zeros(1, np.int32), [p])
-    ctx = binding.Context([g], alignment=1)
+    ctx = binding.Context([g], alignment=1, form=form)
     pk = binding.pack_params(w, dev, amplitudes=True)
     V, st = ctx.eval_batch(w.geom_idx, pk["inc"], pk["mass_scale"], pk["m_bh"], pk["beta"],
                            pk["lum_I0"], pk["mass_S0"])
@@ -459,7 +465,7 @@ def test_adjoint_multi_tile_vs_oracle_differences():
     b = np.concatenate([np.atleast_1d(np.array(gold["grad"][k])) for k in KEYS])
     err = np.linalg.norm(a - b) / np.linalg.norm(b)
     comp = np.abs(a - b) <= np.maximum(1e-3 * np.abs(b), 1e-6 * np.max(np.abs(b)))
-    print(f"1152 terms, 9 tracers: forward {ferr:.2e}; grad rel norm err {err:.3e}; "
+    print(f"form {form}, 1152 terms, 9 tracers: forward {ferr:.2e}; grad rel norm err {err:.3e}; "
           f"components ok {comp.sum()}/{comp.size}")
     assert err <= 1e-4 and comp.all(), np.nonzero(~comp)
     ctx.close()
