@@ -348,10 +348,11 @@ struct Plan {
             *d_maps = nullptr, *d_chain = nullptr, *d_sens = nullptr, *d_sb = nullptr,
             *d_red = nullptr, *d_sph = nullptr, *d_pro = nullptr, *d_adj = nullptr,
             *d_redf = nullptr, *d_sensw = nullptr, *d_sgrid = nullptr, *d_sgred = nullptr,
-            *d_sgred6 = nullptr, *d_pcot = nullptr, *d_pfix = nullptr, *d_sgs = nullptr;
+            *d_sgred6 = nullptr, *d_pcot = nullptr, *d_pfix = nullptr, *d_sgs = nullptr,
+            *d_sphm = nullptr;
   int n_terms = 0, n_pix = 0, n_num = 0, n_bins = 0, n_maps = 0, n_chain = 0, n_sens = 0,
       n_sb = 0, n_red = 0, n_sph = 0, n_pro = 0, n_adj = 0, n_redf = 0, n_sensw = 0,
-      n_sgrid = 0, n_sgred = 0, n_sgred6 = 0, n_pcot = 0, n_pfix = 0, n_sgs = 0;
+      n_sgrid = 0, n_sgred = 0, n_sgred6 = 0, n_pcot = 0, n_pfix = 0, n_sgs = 0, n_sphm = 0;
   int n_bins_wave = 0;   // leading bin items summed one bin per wave
   bool spherical = false;
   bool fused_prologue = true;
@@ -733,7 +734,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   std::vector<jam::ModelDev> md(n);
   std::vector<jam::Item> it_terms, it_pix, it_num, it_bins, it_maps, it_chain, it_sens, it_sb,
       it_red, it_sph, it_pro, it_adj, it_redf, it_sensw, it_sgrid, it_sgred, it_sgred6, it_pcot,
-      it_pfix, it_sgs;
+      it_pfix, it_sgs, it_sphm;
   std::vector<double> c_num, c_sens, c_sensw;
   // wide-sensitivity parts (model, part, x tiles, 32-term groups); their
   // items are cut after the model loop (wide_items)
@@ -779,6 +780,8 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     if (spherical) {
       sph += (int64_t)jam::kSphNR * jam::kSphNT * 3;
       for (int q = 0; q < jam::kSphNR * jam::kSphNT; ++q) it_sph.push_back({m, q, 0, 0});
+      // forward moments: four table points per item (a wave each)
+      for (int q = 0; q < jam::kSphNR * jam::kSphNT / 4; ++q) it_sphm.push_back({m, q, 0, 0});
     }
     if (use_sgrid) {
       // forward grid: 2 floats per point; the adjoint's: 8
@@ -906,12 +909,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
   sort_by_cost(it_sens, c_sens);
   wide_items(wide_parts, ctx->n_cu, it_sensw);
 
-  constexpr int kLists = 20;
+  constexpr int kLists = 21;
   std::vector<jam::Item> *lists[kLists] = {&it_terms, &it_pix, &it_num, &it_bins,
                                            &it_maps,  &it_chain, &it_sens, &it_sb,
                                            &it_red,   &it_sph, &it_pro, &it_adj, &it_redf,
                                            &it_sensw, &it_sgrid, &it_sgred, &it_sgred6,
-                                           &it_pcot,  &it_pfix,  &it_sgs};
+                                           &it_pcot,  &it_pfix,  &it_sgs,  &it_sphm};
   for (auto *l : lists)
     if (l->size() > (size_t)INT32_MAX) return fail(JAM_E_UNSUPPORTED, "batch too large");
   // one device arena: models then the item lists
@@ -936,12 +939,12 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
                             &p->d_maps,  &p->d_chain, &p->d_sens, &p->d_sb,
                             &p->d_red,   &p->d_sph,   &p->d_pro,  &p->d_adj, &p->d_redf,
                             &p->d_sensw, &p->d_sgrid, &p->d_sgred, &p->d_sgred6,
-                            &p->d_pcot,  &p->d_pfix,  &p->d_sgs};
+                            &p->d_pcot,  &p->d_pfix,  &p->d_sgs,  &p->d_sphm};
   int *cnt[kLists] = {&p->n_terms, &p->n_pix,  &p->n_num, &p->n_bins,
                       &p->n_maps,  &p->n_chain, &p->n_sens, &p->n_sb,
                       &p->n_red,   &p->n_sph,   &p->n_pro,  &p->n_adj, &p->n_redf,
                       &p->n_sensw, &p->n_sgrid, &p->n_sgred, &p->n_sgred6,
-                      &p->n_pcot,  &p->n_pfix,  &p->n_sgs};
+                      &p->n_pcot,  &p->n_pfix,  &p->n_sgs,  &p->n_sphm};
   for (int i = 0; i < kLists; ++i) {
     *dl[i] = (jam::Item *)(base + o_it[i]);
     *cnt[i] = (int)lists[i]->size();
@@ -1016,7 +1019,7 @@ void launch_forward_maps(jam_ctx *ctx, Plan *p, const jam::ParamsDev &pd, int32_
       if (p->n_sgred)
         jam::launch_sph_grid_reduce(p->d_models, p->d_sgred, p->n_sgred, st_ws, sgrid, false, st);
     }
-    jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sph, p->n_sph, gauss, terms, st_ws,
+    jam::launch_sph_moments(ctx->d_geoms, p->d_models, p->d_sphm, p->n_sphm, gauss, terms, st_ws,
                             sgrid, tabs, st);
     if (timed) ctx->t_num.end(st);
     jam::launch_sph_num(ctx->d_geoms, p->d_models, p->d_red, p->n_red, gauss, st_ws, tabs, pix, st);

@@ -229,8 +229,9 @@ void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, doubl
 // unique-pixel N map.
 void launch_sph_terms(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                       const double *gauss, const int *st_ws, float4 *terms, hipStream_t st);
-// With sgrid != NULL the moments take G and G_theta at the characteristic
-// nodes from the model's potential grid instead of summing the terms there.
+// Items (m, group of four table points), a wave per point.  With sgrid !=
+// NULL the moments take G and G_theta at the characteristic nodes from the
+// model's potential grid instead of summing the terms there.
 void launch_sph_moments(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                         const double *gauss, const float4 *terms, const int *st_ws,
                         const float *sgrid, double *table, hipStream_t st);

@@ -2516,13 +2516,15 @@ __global__ void __launch_bounds__(256) k_sph_grid_reduce(const ModelDev *__restr
   }
 }
 
-// Item (m, table point).  In round q wave w takes tracers k = 8 q + w and
-// 8 q + 4 + w (each coefficient read from LDS feeds both); lane l is node l
-// of the composite Gauss-Legendre rule in tau = ln(r'/r) on
-// [0, ln(r_max / r)], r_max^2 = r^2 + 50 sigma_k^2.  The per-model term
-// coefficients go through LDS in chunks; each group of 64 terms is summed in
-// FP32 (fully unrolled, the coefficient reads are wave-wide broadcasts) and
-// folded into FP64; everything else is FP64; all sums run in a fixed order.
+// Item (m, group of four table points): wave w computes point 4 q + w (one
+// table point per wave, so no block-wide reductions), taking the tracers two
+// per round (each coefficient read from LDS feeds both); lane l is node l of
+// the composite Gauss-Legendre rule in tau = ln(r'/r) on [0, ln(r_max / r)],
+// r_max^2 = r^2 + 50 sigma_k^2.  Without the grid the per-model term
+// coefficients go through LDS in chunks shared by the four waves; each group
+// of 64 terms is summed in FP32 (fully unrolled, the coefficient reads are
+// wave-wide broadcasts) and folded into FP64; everything else is FP64; all
+// sums run in a fixed order.
 template <bool kGrid>
 __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
@@ -2534,24 +2536,23 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
                                                      double *__restrict__ table) {
   __shared__ float4 tc[kSphChunk];   // (-c log2e, -d log2e, gP, gT)
   __shared__ float tf[kSphChunk];    // gF
-  __shared__ double sh[256];
-  __shared__ double wred[3][4];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
     const Item it = items[i];
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    double *out = table + md.sph_off + (int64_t)it.a * 3;
+    const int cell = 4 * it.a + wave;
+    double *out = table + md.sph_off + (int64_t)cell * 3;
     if (st_ws[it.m] != 0) {                 // uniform per block
-      if (threadIdx.x < 3) out[threadIdx.x] = 0.0;
+      if (lane < 3) out[lane] = 0.0;
       continue;
     }
     const int K = g.K, Tp = sph_terms_padded(g.J1, g.n_u);
     const float4 *gtc = terms + md.term_off;
     const float *gtf = (const float *)(gtc + Tp);
     const double *tab = gauss + md.gauss_off;
-    const int ir = it.a / kSphNT, ith = it.a % kSphNT;
+    const int ir = cell / kSphNT, ith = cell % kSphNT;
     const double lnr = g.sph_lnr0 + ir * g.sph_dlnr, r = exp(lnr);
     const double th = ith * (0.5 * kPi / (kSphNT - 1));
     const double sth = sin(th), cth = cos(th);
@@ -2566,10 +2567,10 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     const float *sg = kGrid ? sgrid + md.sgrid_off : nullptr;
     SphGrid sc = {1.0, 1.0, 1.0, 1.0};
     if (kGrid) sc = sph_grid_scales(g, tab);
-    double Ar = 0.0, At = 0.0, Ap = 0.0;   // this wave's tracers (lane 0)
-    double accF = 0.0;                      // this thread's share of G_phi
-    constexpr int kTr = 2;                  // tracers per wave and round
-    const int rounds = (K + 4 * kTr - 1) / (4 * kTr);
+    double Ar = 0.0, At = 0.0, Ap = 0.0;   // the point's moments (lane 0)
+    double accF = 0.0;                      // this lane's share of G_phi
+    constexpr int kTr = 2;                  // tracers per round
+    const int rounds = (K + kTr - 1) / kTr; // the same in every wave
     for (int q = 0; q < rounds; ++q) {
       double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr], Zp[kTr];
       double lrp[kTr];                       // ln r' (powers of r' as exponentials)
@@ -2577,8 +2578,8 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       bool on[kTr];
 #pragma unroll
       for (int u = 0; u < kTr; ++u) {
-        const int k = 4 * (kTr * q + u) + wave;
-        on[u] = k < K;                      // uniform per wave
+        const int k = kTr * q + u;
+        on[u] = k < K;                      // uniform
         alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; wn[u] = 0.0; nuv[u] = 0.0;
         rp[u] = r; lrp[u] = lnr; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
         if (on[u]) {
@@ -2625,7 +2626,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           tf[t] = gtf[c0 + t];
         }
         __syncthreads();
-        if (!kGrid && on[0]) {
+        if (!kGrid) {
           for (int t0 = 0; t0 < cn; t0 += 64) {
             float sg0 = 0.f, sd0 = 0.f, sg1 = 0.f, sd1 = 0.f;
 #pragma unroll
@@ -2645,7 +2646,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           }
         }
         if (q == 0) {
-          for (int t = threadIdx.x; t < cn; t += 256) {
+          for (int t = lane; t < cn; t += 64) {
             const float4 c = tc[t];
             accF += (double)(tf[t] * fast_exp2(fmaf(c.x, R20, c.y * Z20)));
           }
@@ -2666,21 +2667,17 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
         Ap += (1.0 - beta[u]) * P + (1.0 - beta[u]) * sth * pow(r, 1.0 - 3.0 * beta[u]) * fD;
       }
     }
+    // G_phi and the tracer density at the point, lane sums in a fixed order
+    const double Gphi = wave_sum(accF);
+    double nus = 0.0;
+    for (int k = lane; k < K; k += 64)
+      nus += tab[2 * K + k] * exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
+    nus = wave_sum(nus);
     if (lane == 0) {
-      wred[0][wave] = Ar;
-      wred[1][wave] = At;
-      wred[2][wave] = Ap;
+      out[0] = Ar;
+      out[1] = At;
+      out[2] = Ap - nus * Rp0 * Rp0 * Gphi;
     }
-    const double Gphi = block_sum256(accF, sh);   // synchronises the block
-    if (threadIdx.x == 0) {
-      double nus = 0.0;
-      for (int k = 0; k < K; ++k)
-        nus += tab[2 * K + k] * exp(-(tab[k] * Rp0 * Rp0 + tab[K + k] * zp0 * zp0));
-      out[0] = ((wred[0][0] + wred[0][1]) + wred[0][2]) + wred[0][3];
-      out[1] = ((wred[1][0] + wred[1][1]) + wred[1][2]) + wred[1][3];
-      out[2] = (((wred[2][0] + wred[2][1]) + wred[2][2]) + wred[2][3]) - nus * Rp0 * Rp0 * Gphi;
-    }
-    __syncthreads();
   }
 }
 
