@@ -1368,15 +1368,54 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
         const int nb = min(16, (ny - y0 + 7) / 8);   // uniform per block
         const float *lrow = &lam[c32][kh * (YC / 2) + y0 / 2];
         const float *yrow = ysq + kh * (YC / 2) + y0 / 2;
-        for (int qb = 0; qb < nb; ++qb) {
+        // blocks alternate between two register buffers: the next block's
+        // operands read and its exponentials taken behind the current MFMAs
+        // (a read one block past the last stays inside the padded row and is
+        // not used)
+        float ra[2][4], ry[2][4], bb[2][4], by[2][4];
+        auto load = [&](int u, int qb) {
           const float4 a4 = *reinterpret_cast<const float4 *>(lrow + 4 * qb);
           const float4 y4 = *reinterpret_cast<const float4 *>(yrow + 4 * qb);
-          const float ra[4] = {a4.x, a4.y, a4.z, a4.w}, ry[4] = {y4.x, y4.y, y4.z, y4.w};
+          ra[u][0] = a4.x; ra[u][1] = a4.y; ra[u][2] = a4.z; ra[u][3] = a4.w;
+          ry[u][0] = y4.x; ry[u][1] = y4.y; ry[u][2] = y4.z; ry[u][3] = y4.w;
+        };
+        auto expo = [&](int u) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float b = fast_exp2(c.y * ry[j]);
-            dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[j], b, dg, 0, 0, 0);
-            dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[j], b * ry[j], dh, 0, 0, 0);
+            bb[u][j] = fast_exp2(c.y * ry[u][j]);
+            by[u][j] = bb[u][j] * ry[u][j];
+          }
+        };
+        auto mfma4 = [&](int u) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            dg = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[u][j], bb[u][j], dg, 0, 0, 0);
+            dh = __builtin_amdgcn_mfma_f32_32x32x2f32(ra[u][j], by[u][j], dh, 0, 0, 0);
+          }
+        };
+        load(0, 0);
+        expo(0);
+        for (int qb = 0; qb < nb; qb += 2) {
+          load(1, qb + 1);
+          __builtin_amdgcn_sched_barrier(0);
+          mfma4(0);
+          expo(1);
+          // taken here, not sunk into the branch below
+          asm volatile("" ::"v"(bb[1][0]), "v"(bb[1][1]), "v"(bb[1][2]), "v"(bb[1][3]),
+                       "v"(by[1][0]), "v"(by[1][1]), "v"(by[1][2]), "v"(by[1][3]));
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if (qb + 1 < nb) {                 // uniform
+            load(0, qb + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma4(1);
+            expo(0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
 #pragma unroll
