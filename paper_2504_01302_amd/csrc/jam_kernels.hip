@@ -1295,11 +1295,13 @@ __device__ __forceinline__ void sens_pix_item(const Item it, const GeomDev *__re
 //   S0_t = sum_x E G,  S1_t = sum_x x^2 E G,  Sg_t = sum_x E (C0 + C1 x^2) H.
 // Item (m, 32-row x tile, tile of kSensTerms terms); wave w owns a quarter
 // of the tile's terms and takes them as 32-term column blocks one after the
-// other (lane l: term l % 32, y pair l / 32), so only one block's FP64
-// accumulators are live.  lambda is staged through LDS 256 rows of y at a
-// time (once per item when the map has at most 256 distinct |y|); FP32
-// partial sums over 128 y values are folded into FP64.  Output: per x tile,
-// [S0 | S1 | Sg] (T doubles each).
+// other (lane l: term l % 32, y pair l / 32).  lambda is staged through LDS
+// 256 rows of y at a time (once per item when the map has at most 256
+// distinct |y|).  G and H are summed in FP32 over up to 128 y values; each
+// such partial goes straight through the x epilogue (each lane's 16 rows in
+// FP32) and the partial S0, S1, Sg are added in FP64, so no per-row FP64
+// accumulators are live.  Output: per x tile, [S0 | S1 | Sg] (T doubles
+// each).
 // ---------------------------------------------------------------------------
 constexpr int YC = 256;
 constexpr int kSensWave = kSensTerms / 4;   // terms per wave of an item
@@ -1331,9 +1333,7 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
     const int t = it.b * kSensTerms + wave * kSensWave + h * 32 + c32;
     const bool vt = t < g.T;
     const float4 c = vt ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
-    double gacc[16], hacc[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) { gacc[r] = 0.0; hacc[r] = 0.0; }
+    double s0 = 0.0, s1 = 0.0, sg = 0.0;
     for (int ybi = 0; ybi < n_yb; ++ybi) {
       const int yb = ybi * YC;
       const int ny = min(YC, g.n_uy - yb);
@@ -1418,26 +1418,23 @@ __device__ __forceinline__ void sens_mfma_item(const Item it, const GeomDev *__r
             __builtin_amdgcn_sched_barrier(0);
           }
         }
+        // rows past the map have zero lambda, so zero sums; each lane's 16
+        // rows in FP32, the y blocks and the lanes in FP64
+        float f0 = 0.f, f1 = 0.f, fg = 0.f;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          gacc[r] += (double)dg[r];
-          hacc[r] += (double)dh[r];
+          const float x2 = xsq[mfma_row(r, lane)];
+          const float e = fast_exp2(c.x * x2);
+          const float ed = e * dg[r];
+          f0 += ed;
+          f1 = fmaf(x2, ed, f1);
+          fg = fmaf(e * fmaf(c.w, x2, c.z), dh[r], fg);
         }
+        s0 += (double)f0;
+        s1 += (double)f1;
+        sg += (double)fg;
       }
     }
-    // rows past the map have zero lambda, so zero sums; each lane's 16 rows
-    // in FP32, the lanes in FP64
-    float f0 = 0.f, f1 = 0.f, fg = 0.f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float x2 = xsq[mfma_row(r, lane)];
-      const float e = fast_exp2(c.x * x2);
-      const float ed = e * (float)gacc[r];
-      f0 += ed;
-      f1 = fmaf(x2, ed, f1);
-      fg = fmaf(e * fmaf(c.w, x2, c.z), (float)hacc[r], fg);
-    }
-    double s0 = (double)f0, s1 = (double)f1, sg = (double)fg;
     s0 += __shfl_xor(s0, 32, 64);
     s1 += __shfl_xor(s1, 32, 64);
     sg += __shfl_xor(sg, 32, 64);
