@@ -466,7 +466,8 @@ constexpr size_t kMaxPlans = 8;
 constexpr int kFusedPrologueModels = 32;
 // Unique-pixel maps with at most this many distinct |x'| and |y'| (one 32x32
 // matrix-core block) take the small-map form: terms computed in place by the
-// numerator, sensitivities and chain fused in the adjoint.
+// numerator, sensitivities and chain fused in the adjoint (for at most
+// jam::kSmallAdjMass mass Gaussians, the BH included).
 constexpr int kSmallMap = 32;
 // Whole-map numerator: longest slice, in units of 64 terms, summed in FP32.
 constexpr int kMapMaxUnits = 32;
@@ -535,7 +536,7 @@ NumChoice choose_numerator(const GeomHost &g, const Tune &t, int gran) {
     return c;
   }
   const int per = std::max(4, gran);
-  c.gen = g.n_ux <= kSmallMap && g.n_uy <= kSmallMap;
+  c.gen = g.n_ux <= kSmallMap && g.n_uy <= kSmallMap && g.J1 <= jam::kSmallAdjMass;
   c.n_slices = std::max(1, (chunks + per - 1) / per);
   c.units = chunks;
   for (const auto &ty : axis_tiles(g.n_uy, t.tau))
@@ -844,7 +845,7 @@ jam_status build_plan(jam_ctx *ctx, int32_t n, const int32_t *geom_idx, const Tu
     } else if (small) {
       // fused sensitivities + chain: items of whole tracers, about 8192
       // terms each
-      const int per = std::max(1, 8192 / (g.J1 * g.n_u));
+      const int per = std::max(1, std::min(jam::kSmallAdjTracers, 8192 / (g.J1 * g.n_u)));
       for (int k = 0; k < g.K; k += per)
         it_adj.push_back({m, k | (std::min(g.K, k + per) << 16), 0, 0});
     } else if (d.form == 1) {

@@ -215,8 +215,11 @@ void launch_chain(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
 // Small-map models (unique-pixel map within one 32x32 block): sensitivities
 // and chain in one pass, items (m, first tracer | end tracer << 16); writes
 // the chain rows (the model has no partial sensitivity blocks,
-// n_sens_parts = 0).
+// n_sens_parts = 0).  An item holds at most kSmallAdjTracers tracers; the
+// form needs at most kSmallAdjMass mass Gaussians (BH included).
 constexpr int kSmallAdjTerms = 1024;
+constexpr int kSmallAdjTracers = 64;
+constexpr int kSmallAdjMass = 256;
 void launch_adj_small(const GeomDev *g, const ModelDev *m, const Item *it, int n_it, ParamsDev p,
                       const double *pix, const int *st_ws, double *sens, hipStream_t st);
 void launch_grads(const GeomDev *g, const ModelDev *m, int n, ParamsDev p, double *sens,

@@ -1849,10 +1849,13 @@ __global__ void __launch_bounds__(256) k_chain(const GeomDev *__restrict__ geoms
 // are unrolled for the map's number of y quads.
 // The term's chain values (those of k_chain) go through LDS and every (k, j)
 // row is summed over its u-nodes by one wave in a fixed order.  Item (m,
-// first tracer k0 | k1 << 16): tracers k0 <= k < k1, each in groups of at
-// most 64 mass Gaussians with count * n_u <= kAdjTerms; lambda_N and the
-// squared coordinates are staged in LDS once per item.  Writes the chain
-// rows of k_chain (the model has no partial sensitivity blocks).
+// first tracer k0 | k1 << 16): tracers k0 <= k < k1 (at most
+// kSmallAdjTracers); lambda_N, the squared coordinates, every mass
+// Gaussian's and every tracer's set-up values are staged in LDS once per
+// item, and the item's (k, j) rows, tracer-major, are taken in windows of
+// whole rows with at most kAdjTerms terms, so that the passes of 256 terms
+// run across tracers.  Writes the chain rows of k_chain (the model has no
+// partial sensitivity blocks).
 // ---------------------------------------------------------------------------
 constexpr int kSmallMap = 32;
 constexpr int kAdjTerms = kSmallAdjTerms;
@@ -1913,7 +1916,11 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
                                                    double *__restrict__ sens) {
   __shared__ __attribute__((aligned(16))) float lam[kSmallMap][kSmallMap];   // [x][y]
   __shared__ float xsq[kSmallMap], ysq[kSmallMap];
-  __shared__ double jv[64][5];   // per mass Gaussian: e2, de2/di, r, K_j / M_j, M_j
+  // per mass Gaussian: e2, de2/di, r, K_j / M_j, M_j
+  __shared__ double jv[kSmallAdjMass][5];
+  // per tracer: alpha, alphaq and d/di, nu0 / I0 and d/di, cos^2 i + b sin^2 i
+  // and d/di, b, I0
+  __shared__ double tv[kSmallAdjTracers][9];
   __shared__ double vals[kAdjTerms][3];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -1930,8 +1937,6 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
     const int ny = __builtin_amdgcn_readfirstlane(g.n_uy);
     const int nu = __builtin_amdgcn_readfirstlane(g.n_u);
     const int J1 = __builtin_amdgcn_readfirstlane(g.J1), J = J1 - 1;
-    const int cap = max(1, min(64, kAdjTerms / nu));
-    const int cnt = (J1 + (J1 + cap - 1) / cap - 1) / ((J1 + cap - 1) / cap);   // balanced groups
     __syncthreads();                  // the previous item's LDS reads are done
     const double *lamN = pix + md.pix_off + 2 * (int64_t)g.n_pix;
     for (int e = threadIdx.x; e < kSmallMap * kSmallMap; e += 256) {
@@ -1948,109 +1953,123 @@ __global__ void __launch_bounds__(256) k_adj_small(const GeomDev *__restrict__ g
     const dual cs = {cos(inc), -sin(inc)};
     const dual si2 = sn * sn, ci2 = cs * cs;
     const double G = grav_const(), sp = g.s_pc;
-    double *rows = chain_rows(sens, md, g);
-    for (int k = k0; k < k1; ++k) {
+    for (int j = threadIdx.x; j < J1; j += 256) {
+      double *v = jv[j];
+      if (j < J) {
+        const double qo = g.mass_q[j], sj = g.mass_sigma[j];
+        const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
+        const dual qj = dsqrt(qo * qo - ci2) / sn;
+        const dual e2 = 1.0 - qj * qj;
+        v[0] = e2.v;
+        v[1] = e2.d;
+        v[2] = 0.5 / (sj * sj);
+        v[3] = sqrt(2.0 / kPi) * G / (sp * sj);
+        v[4] = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
+      } else {
+        v[0] = 0.0;
+        v[1] = 0.0;
+        v[2] = 0.5 / (g.bh_sigma * g.bh_sigma);
+        v[3] = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
+        v[4] = p.m_bh[it.m];
+      }
+    }
+    if (threadIdx.x < k1 - k0) {
       // tracer k: deprojection (App. A) with its inclination derivative
+      const int k = k0 + threadIdx.x;
       const double qok = g.lum_q[k], sk = g.lum_sigma[k];
-      const double I0 = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
       const double b = 1.0 / (1.0 - p.beta[md.lum_off + k]);
       const dual qk = dsqrt(qok * qok - ci2) / sn;
       const double alpha = 0.5 / (sk * sk);
       const dual alphaq = dconst(alpha) / (qk * qk);
       const dual nu1 = dconst(qok / (sqrt(2.0 * kPi) * sk)) / qk;   // nu0 / I0
       const dual pf = ci2 + b * si2;
-      for (int j0 = 0; j0 < J1; j0 += cnt) {
-        const int nj = min(cnt, J1 - j0);
-        __syncthreads();              // earlier readers of jv and vals are done
-        if (threadIdx.x < nj) {
-          const int j = j0 + threadIdx.x;
-          double *v = jv[threadIdx.x];
-          if (j < J) {
-            const double qo = g.mass_q[j], sj = g.mass_sigma[j];
-            const double S0 = p.mass_S0 ? p.mass_S0[md.mass_off + j] : g.mass_S0[j];
-            const dual qj = dsqrt(qo * qo - ci2) / sn;
-            const dual e2 = 1.0 - qj * qj;
-            v[0] = e2.v;
-            v[1] = e2.d;
-            v[2] = 0.5 / (sj * sj);
-            v[3] = sqrt(2.0 / kPi) * G / (sp * sj);
-            v[4] = p.mass_scale[it.m] * 2.0 * kPi * S0 * (sp * sj) * (sp * sj) * qo;
-          } else {
-            v[0] = 0.0;
-            v[1] = 0.0;
-            v[2] = 0.5 / (g.bh_sigma * g.bh_sigma);
-            v[3] = sqrt(2.0 / kPi) * G / (sp * g.bh_sigma);
-            v[4] = p.m_bh[it.m];
-          }
+      double *v = tv[threadIdx.x];
+      v[0] = alpha;
+      v[1] = alphaq.v;
+      v[2] = alphaq.d;
+      v[3] = nu1.v;
+      v[4] = nu1.d;
+      v[5] = pf.v;
+      v[6] = pf.d;
+      v[7] = b;
+      v[8] = p.lum_I0 ? p.lum_I0[md.lum_off + k] : g.lum_I0[k];
+    }
+    double *rows = chain_rows(sens, md, g);
+    const int n_rows = (k1 - k0) * J1;
+    const int per_win = max(1, kAdjTerms / nu);   // whole rows per window
+    for (int r0 = 0; r0 < n_rows; r0 += per_win) {
+      const int nr = min(per_win, n_rows - r0);
+      const int n_terms = nr * nu;
+      __syncthreads();                // staging done; earlier readers of vals done
+      for (int base = 0; base < n_terms; base += 256) {
+        const int tl = base + threadIdx.x;
+        if (tl >= n_terms) break;
+        const int rr = tl / nu, n = tl - rr * nu;
+        const int row = r0 + rr, kk = row / J1, jj = row - kk * J1;
+        const double *tk = tv[kk];
+        const double *v = jv[jj];
+        const double alpha = tk[0], b = tk[7];
+        const dual alphaq = {tk[1], tk[2]}, nu1 = {tk[3], tk[4]}, pf = {tk[5], tk[6]};
+        const double r = v[2], Mj = v[4];
+        const double u = g.u[n], wq = g.w[n], u2 = u * u;
+        const dual h = {fma(-v[0], u2, 1.0), -u2 * v[1]};
+        const double c1 = alpha + r * u2;
+        const double rhv = rcp64(h.v);
+        const dual rh = {rhv, -rhv * rhv * h.d};
+        const dual A = alphaq + (r * u2) * rh;
+        const dual a = c1 * si2 + A * ci2;
+        const double rav = rcp64(a.v);
+        const dual gam = c1 * A * dual{rav, -rav * rav * a.d};
+        const double rshv = rsq64(h.v);
+        const dual rsh = {rshv, -0.5 * rshv * rhv * h.d};
+        const dual bse = (v[3] * r * u2) * nu1;               // per unit I0 M
+        const double rAv = rcp64(A.v);
+        const dual gg = bse * dual{rAv, -rAv * rAv * A.d} * rh * rsh;
+        const dual ww = 2.0 * bse * rsh;
+        const dual P = pf * gg;
+        const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
+        const double fv = wq * kSqrtPi * rsq64(a.v);
+        const dual f = {fv, -0.5 * fv * rav * a.d};
+        const dual c0 = f * P, c1u = f * Q;                   // C = I0 M c
+        const double amp = tk[8] * Mj;
+        const float cx = (float)(-c1 * kLog2e), cy = (float)(-gam.v * kLog2e);
+        const float C0 = (float)(amp * c0.v), C1 = (float)(amp * c1u.v);
+        float s0, s1, sg;
+        switch ((ny + 3) >> 2) {    // uniform
+          case 1: small_sums<1>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 2: small_sums<2>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 3: small_sums<3>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 4: small_sums<4>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 5: small_sums<5>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 6: small_sums<6>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          case 7: small_sums<7>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
+          default: small_sums<8>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
         }
-        __syncthreads();
-        const int n_terms = nj * nu;
-        for (int base = 0; base < n_terms; base += 256) {
-          const int tl = base + threadIdx.x;
-          if (tl >= n_terms) break;
-          const int jj = tl / nu, n = tl - jj * nu;
-          const double *v = jv[jj];
-          const double r = v[2], Mj = v[4];
-          const double u = g.u[n], wq = g.w[n], u2 = u * u;
-          const dual h = {fma(-v[0], u2, 1.0), -u2 * v[1]};
-          const double c1 = alpha + r * u2;
-          const double rhv = rcp64(h.v);
-          const dual rh = {rhv, -rhv * rhv * h.d};
-          const dual A = alphaq + (r * u2) * rh;
-          const dual a = c1 * si2 + A * ci2;
-          const double rav = rcp64(a.v);
-          const dual gam = c1 * A * dual{rav, -rav * rav * a.d};
-          const double rshv = rsq64(h.v);
-          const dual rsh = {rshv, -0.5 * rshv * rhv * h.d};
-          const dual bse = (v[3] * r * u2) * nu1;               // per unit I0 M
-          const double rAv = rcp64(A.v);
-          const dual gg = bse * dual{rAv, -rAv * rAv * A.d} * rh * rsh;
-          const dual ww = 2.0 * bse * rsh;
-          const dual P = pf * gg;
-          const dual Q = si2 * (ww - (2.0 * c1 * b) * gg);
-          const double fv = wq * kSqrtPi * rsq64(a.v);
-          const dual f = {fv, -0.5 * fv * rav * a.d};
-          const dual c0 = f * P, c1u = f * Q;                   // C = I0 M c
-          const double amp = I0 * Mj;
-          const float cx = (float)(-c1 * kLog2e), cy = (float)(-gam.v * kLog2e);
-          const float C0 = (float)(amp * c0.v), C1 = (float)(amp * c1u.v);
-          float s0, s1, sg;
-          switch ((ny + 3) >> 2) {    // uniform
-            case 1: small_sums<1>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 2: small_sums<2>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 3: small_sums<3>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 4: small_sums<4>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 5: small_sums<5>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 6: small_sums<6>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            case 7: small_sums<7>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-            default: small_sums<8>(cx, cy, C0, C1, lam, xsq, ysq, nx, s0, s1, sg); break;
-          }
-          const double S0 = s0, S1 = s1, Sg = sg;
-          vals[tl][0] = amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
-          // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
-          vals[tl][1] = amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
-          vals[tl][2] = S0 * c0.v + S1 * c1u.v;
+        const double S0 = s0, S1 = s1, Sg = sg;
+        vals[tl][0] = amp * (S0 * c0.d + S1 * c1u.d) - Sg * gam.d;
+        // dC0/db = f si2 g, dC1/db = -2 f si2 c1 g
+        vals[tl][1] = amp * f.v * si2.v * gg.v * (S0 - 2.0 * c1 * S1);
+        vals[tl][2] = S0 * c0.v + S1 * c1u.v;
+      }
+      __syncthreads();
+      // (k, j) rows: one wave per row, lanes over the u-nodes in order, then
+      // a butterfly
+      for (int rr = wave; rr < nr; rr += 4) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int n = lane; n < nu; n += 64) {
+          const double *v = vals[rr * nu + n];
+          a0 += v[0];
+          a1 += v[1];
+          a2 += v[2];
         }
-        __syncthreads();
-        // (k, j) rows: one wave per mass Gaussian, lanes over the u-nodes in
-        // order, then a butterfly
-        for (int jj = wave; jj < nj; jj += 4) {
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-          for (int n = lane; n < nu; n += 64) {
-            const double *v = vals[jj * nu + n];
-            a0 += v[0];
-            a1 += v[1];
-            a2 += v[2];
-          }
-          a0 = wave_sum(a0);
-          a1 = wave_sum(a1);
-          a2 = wave_sum(a2);
-          if (lane == 0) {
-            double *o = rows + ((int64_t)k * J1 + j0 + jj) * 3;
-            o[0] = a0;
-            o[1] = a1;
-            o[2] = a2;
-          }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        if (lane == 0) {
+          double *o = rows + ((int64_t)k0 * J1 + r0 + rr) * 3;
+          o[0] = a0;
+          o[1] = a1;
+          o[2] = a2;
         }
       }
     }
