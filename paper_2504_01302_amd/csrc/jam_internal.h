@@ -329,19 +329,34 @@ __host__ __device__ inline int64_t sph_range_len(int K, int n_rng) {
   const int64_t per = (sph_points(K) + n_rng - 1) / n_rng;
   return (per + 255) / 256 * 256;
 }
-// Term-major sensitivities through the potential grid: point items of
-// kSphPtsItem points spread the point cotangents onto the grid (items (m,
-// q)); the fixed-point grid is converted in items (m, block of 1024 grid
+// Term-major sensitivities through the potential grid: the point
+// cotangents are spread onto the grid tile by tile.  Point items of
+// kSphPtsItem points (items (m, q)) count their points per grid tile (tiles
+// of kSphTileB x kSphTileB stencil base cells), a per-model scan turns the
+// counts into positions, the point items write their point indices sorted
+// by tile, and items (m, q) over kSphPtsItem consecutive entries of that
+// list accumulate each tile's stencils in LDS and add them to the grid.
+// The fixed-point grid is converted in items (m, block of 1024 grid
 // points); the contraction runs in items (m, 32-term block, row part) over
 // kSphIParts parts of the grid rows, which are the sensitivities' ranges.
 // Workspace per model: sph_gcot_size doubles.
 constexpr int kSphPtsItem = 16384;
 constexpr int kSphIParts = 4;
+constexpr int kSphTileB = 32;
+constexpr int kSphTilesAx = (kSphGridN - 2 + kSphTileB - 1) / kSphTileB;
+constexpr int kSphTiles = kSphTilesAx * kSphTilesAx;
 __host__ __device__ inline int sph_pitems(int K) {
   return (int)((sph_points(K) + kSphPtsItem - 1) / kSphPtsItem);
 }
+// Doubles: fixed-point grid [N][N][2], FP32 grid [N][N][2], bound partials
+// [items][2] and the two scales; then int32: per (item, tile) list
+// positions [items][kSphTiles], tile offsets [kSphTiles + 1], a consistency
+// flag and the point list [points].
+__host__ __device__ inline int64_t sph_gcot_ints(int K) {
+  return (int64_t)sph_pitems(K) * kSphTiles + kSphTiles + 2 + sph_points(K);
+}
 __host__ __device__ inline int64_t sph_gcot_size(int K) {
-  return 3LL * kSphGridN * kSphGridN + 2LL * sph_pitems(K) + 2;
+  return 3LL * kSphGridN * kSphGridN + 2LL * sph_pitems(K) + 2 + (sph_gcot_ints(K) + 1) / 2;
 }
 
 // Logistic radial anisotropy profile prof[m][0..3] = (beta_0, beta_inf, r_a,

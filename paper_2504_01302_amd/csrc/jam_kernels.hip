@@ -3465,8 +3465,54 @@ __device__ inline double *sph_gcot_bounds(double *sgcot, const ModelDev &md) {
   return sgcot + md.sgcot_off + 3LL * kSphGridN * kSphGridN;
 }
 
-// Item (m, point item q): clears a share of the fixed-point grid and sums
-// |phi|, |psi| over the item's points (fixed-order block sums).
+// The int32 part of the grid-cotangent workspace: per (point item, tile)
+// list positions, tile offsets, the consistency flag, the point list.
+__device__ inline int *sph_gcot_int(double *sgcot, const ModelDev &md, int K) {
+  return reinterpret_cast<int *>(sph_gcot_bounds(sgcot, md) + 2LL * sph_pitems(K) + 2);
+}
+
+// Stencil base cell (i0, l0) on the potential grid of point p, the
+// position as sph_point_cot computes it.  The tile counts and the sorted
+// list are built by different kernels and must agree point by point, so
+// the cell and the grid scales it uses each come from one compiled body
+// (not inlined), which also takes its own sin of the polar angle.
+struct SphCell {
+  int i0, l0;
+};
+__device__ __attribute__((noinline)) SphGrid sph_cell_scales(const GeomDev *__restrict__ gp,
+                                                             const double *__restrict__ tab) {
+  return sph_grid_scales(*gp, tab);
+}
+__device__ __attribute__((noinline)) SphCell sph_point_cell(const GeomDev *__restrict__ gp,
+                                                            const double *__restrict__ tab,
+                                                            SphGrid sc, int64_t p) {
+  const int K = gp->K;
+  const int cell = (int)(p / ((int64_t)K * kSphNodes));
+  const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
+  const int ir = cell / kSphNT, ith = cell % kSphNT;
+  const double lnr = gp->sph_lnr0 + ir * gp->sph_dlnr, r = exp(lnr);
+  const double sth = sin(ith * (0.5 * kPi / (kSphNT - 1)));
+  const double alpha = tab[k];
+  const double beta = 1.0 - 1.0 / tab[3 * K + k];
+  const double glx = gp->gl8_x[node & 7];
+  const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
+  const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
+  const double rp = exp(lnr + tau);
+  const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
+  const double ct = sqrt(fmax(0.0, 1.0 - st * st));
+  const double x = asinh(rp * st / sc.aR) * sc.iR, y = asinh(rp * ct / sc.aZ) * sc.iZ;
+  SphCell c;
+  c.i0 = min(max((int)floor(x), 0), kSphGridN - 3);
+  c.l0 = min(max((int)floor(y), 0), kSphGridN - 3);
+  return c;
+}
+__device__ inline int sph_tile_of(SphCell c) {
+  return (c.i0 / kSphTileB) * kSphTilesAx + c.l0 / kSphTileB;
+}
+
+// Item (m, point item q): clears a share of the fixed-point grid, sums
+// |phi|, |psi| over the item's points (fixed-order block sums) and counts
+// them per grid tile.
 __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restrict__ geoms,
                                                         const ModelDev *__restrict__ models,
                                                         const Item *__restrict__ items, int n_it,
@@ -3474,8 +3520,10 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
                                                         const int *__restrict__ st_ws,
                                                         double *__restrict__ sens,
                                                         double *__restrict__ sgcot) {
+  static_assert(kSphTiles == 256, "one thread per tile");
   __shared__ double sinth[kSphNT];
   __shared__ double sh[256];
+  __shared__ int hist[kSphTiles];
   if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
   __syncthreads();
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
@@ -3485,11 +3533,16 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
     const GeomDev g = geoms[md.geom];
     const SphAdj adj = sph_adj_of(sens, md, g);
     const double *tab = gauss + md.gauss_off;
+    const SphGrid sc = sph_cell_scales(geoms + md.geom, tab);
     const int np = sph_pitems(g.K);
     const int64_t n2 = 2LL * kSphGridN * kSphGridN, share = (n2 + np - 1) / np;
     long long *fx = sph_gcot_fixed(sgcot, md);
     const int64_t e0 = (int64_t)it.a * share, e1 = min(n2, e0 + share);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) fx[e] = 0;
+    int *gi = sph_gcot_int(sgcot, md, g.K);
+    if (it.a == 0 && threadIdx.x == 0) gi[(int64_t)np * kSphTiles + kSphTiles + 1] = 0;   // flag
+    hist[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
                   p1 = min(P, p0 + kSphPtsItem);
     double sa = 0.0, sb = 0.0;
@@ -3498,6 +3551,7 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
       sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
       sa += fabs(phi);
       sb += fabs(psi);
+      atomicAdd(&hist[sph_tile_of(sph_point_cell(geoms + md.geom, tab, sc, p))], 1);
     }
     sa = block_sum256(sa, sh);
     sb = block_sum256(sb, sh);
@@ -3506,6 +3560,88 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
       bnd[2 * it.a] = sa;
       bnd[2 * it.a + 1] = sb;
     }
+    __syncthreads();
+    gi[(int64_t)it.a * kSphTiles + threadIdx.x] = hist[threadIdx.x];
+  }
+}
+
+// Model m (thread = tile): the per-item tile counts become list positions,
+// items in order within a tile and tiles in order, and the tile offsets.
+__global__ void __launch_bounds__(256) k_sph_pcot_scan(const GeomDev *__restrict__ geoms,
+                                                       const ModelDev *__restrict__ models, int n,
+                                                       const int *__restrict__ st_ws,
+                                                       double *__restrict__ sgcot) {
+  __shared__ int tot[kSphTiles];
+  const int t = threadIdx.x;
+  for (int m = blockIdx.x; m < n; m += gridDim.x) {
+    if (st_ws[m] != 0) continue;             // uniform per block
+    const ModelDev md = models[m];
+    const int K = geoms[md.geom].K;
+    const int np = sph_pitems(K);
+    int *pos = sph_gcot_int(sgcot, md, K);
+    int *toff = pos + (int64_t)np * kSphTiles;
+    int acc = 0;
+    for (int q = 0; q < np; ++q) {
+      int *h = pos + (int64_t)q * kSphTiles + t;
+      const int v = *h;
+      *h = acc;
+      acc += v;
+    }
+    __syncthreads();                         // the previous model's reads of tot
+    tot[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < kSphTiles; off <<= 1) {
+      const int v = t >= off ? tot[t - off] : 0;
+      __syncthreads();
+      tot[t] += v;
+      __syncthreads();
+    }
+    const int base = tot[t] - acc;
+    toff[t] = base;
+    if (t == kSphTiles - 1) toff[kSphTiles] = tot[t];
+    for (int q = 0; q < np; ++q) pos[(int64_t)q * kSphTiles + t] += base;
+  }
+}
+
+// Item (m, point item q): the item's point indices into the list, each at
+// its tile's range for this item (the order within a range is immaterial:
+// the grid sums are exact).  A count that disagrees with the counting pass
+// sets the model's flag, and the tile pass then spreads that model's points
+// directly.
+__global__ void __launch_bounds__(256) k_sph_pcot_fill(const GeomDev *__restrict__ geoms,
+                                                       const ModelDev *__restrict__ models,
+                                                       const Item *__restrict__ items, int n_it,
+                                                       const double *__restrict__ gauss,
+                                                       const int *__restrict__ st_ws,
+                                                       double *__restrict__ sgcot) {
+  __shared__ int cur[kSphTiles], rb[kSphTiles], rl[kSphTiles];   // fill count, range
+  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
+    const Item it = items[i];
+    if (st_ws[it.m] != 0) continue;          // uniform per block
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const double *tab = gauss + md.gauss_off;
+    const SphGrid sc = sph_cell_scales(geoms + md.geom, tab);
+    const int np = sph_pitems(g.K);
+    int *pos = sph_gcot_int(sgcot, md, g.K);
+    const int *toff = pos + (int64_t)np * kSphTiles;
+    int *flag = pos + (int64_t)np * kSphTiles + kSphTiles + 1;
+    int *list = flag + 1;
+    rb[threadIdx.x] = pos[(int64_t)it.a * kSphTiles + threadIdx.x];
+    rl[threadIdx.x] = it.a + 1 < np ? pos[(int64_t)(it.a + 1) * kSphTiles + threadIdx.x]
+                                    : toff[threadIdx.x + 1];
+    cur[threadIdx.x] = 0;
+    __syncthreads();                         // ranges read, cur cleared
+    const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
+                  p1 = min(P, p0 + kSphPtsItem);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+      const int tile = sph_tile_of(sph_point_cell(geoms + md.geom, tab, sc, p));
+      const int at = rb[tile] + atomicAdd(&cur[tile], 1);
+      if (at < rl[tile]) list[at] = (int)p;
+    }
+    __syncthreads();
+    if (cur[threadIdx.x] != rl[threadIdx.x] - rb[threadIdx.x]) atomicOr(flag, 1);
+    __syncthreads();                         // before the next item rewrites cur, rb, rl
   }
 }
 
@@ -3518,19 +3654,60 @@ __device__ inline double sph_gcot_scale(double bound) {
   return ldexp(1.0, min(1000, 60 - ilogb(1.6 * bound)));
 }
 
-// Item (m, point item q): spreads phi, psi of the item's points onto the
-// fixed-point grid with the interpolation weights of sph_grid_at.
-__global__ void __launch_bounds__(256) k_sph_pcot_scatter(const GeomDev *__restrict__ geoms,
-                                                          const ModelDev *__restrict__ models,
-                                                          const Item *__restrict__ items,
-                                                          int n_it,
-                                                          const double *__restrict__ gauss,
-                                                          const int *__restrict__ st_ws,
-                                                          double *__restrict__ sens,
-                                                          double *__restrict__ sgcot) {
+// The point cotangents of p onto the grid through the interpolation's
+// weights, in fixed point: into the LDS block acc (rows r0 .. r0 + kL - 1,
+// columns c0 .. c0 + kL - 1) where the stencil lies inside it, else
+// straight into the grid.
+constexpr int kTileL = kSphTileB + 5;   // a tile's stencils with one cell to spare
+__device__ inline void sph_spread_point(const GeomDev &g, const GeomDev *__restrict__ gp,
+                                        const double *tab, const SphAdj &adj,
+                                        const double *sinth, const SphGrid &sc, double sa,
+                                        double sb, int64_t p, unsigned long long *fx,
+                                        unsigned long long *acc, int r0, int c0) {
+  constexpr int N = kSphGridN;
+  double R, z, phi, psi;
+  sph_point_cot(g, gp, tab, adj, sinth, p, R, z, phi, psi);
+  const double x = asinh(R / sc.aR) * sc.iR, y = asinh(z / sc.aZ) * sc.iZ;
+  const int i0 = min(max((int)floor(x), 0), N - 3), l0 = min(max((int)floor(y), 0), N - 3);
+  double wx[4], wy[4];
+  lagrange4(x - i0, wx);
+  lagrange4(y - l0, wy);
+  const int ra = abs(i0 - 1), ca = abs(l0 - 1);
+  const bool in = acc && ra >= r0 && i0 + 2 < r0 + kTileL && ca >= c0 && l0 + 2 < c0 + kTileL &&
+                  i0 >= r0 && l0 >= c0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = abs(i0 - 1 + a);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = abs(l0 - 1 + b);
+      const double w = wx[a] * wy[b];
+      const long long va = __double2ll_rn(phi * w * sa), vb = __double2ll_rn(psi * w * sb);
+      unsigned long long *c = in ? acc + ((row - r0) * kTileL + (col - c0)) * 2
+                                 : fx + ((int64_t)row * N + col) * 2;
+      if (va) atomicAdd(c, (unsigned long long)va);
+      if (vb) atomicAdd(c + 1, (unsigned long long)vb);
+    }
+  }
+}
+
+// Item (m, q): entries q * kSphPtsItem .. + kSphPtsItem - 1 of the model's
+// tile-sorted point list.  Per tile met there, the entries' stencils are
+// summed in an LDS block (fixed point, so in any order) and the block is
+// added to the grid; with the model's flag set, the item's own points are
+// spread straight onto the grid instead.
+__global__ void __launch_bounds__(256) k_sph_pcot_tiles(const GeomDev *__restrict__ geoms,
+                                                        const ModelDev *__restrict__ models,
+                                                        const Item *__restrict__ items, int n_it,
+                                                        const double *__restrict__ gauss,
+                                                        const int *__restrict__ st_ws,
+                                                        double *__restrict__ sens,
+                                                        double *__restrict__ sgcot) {
   constexpr int N = kSphGridN;
   __shared__ double sinth[kSphNT];
   __shared__ double sh[256];
+  __shared__ unsigned long long acc[kTileL * kTileL * 2];
+  __shared__ int tr[2];
   if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
   __syncthreads();
   for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
@@ -3551,28 +3728,43 @@ __global__ void __launch_bounds__(256) k_sph_pcot_scatter(const GeomDev *__restr
     if (!(sa == sa) || !(sb == sb)) continue;   // uniform: a non-finite cotangent
     const SphGrid sc = sph_grid_scales(g, tab);
     unsigned long long *fx = reinterpret_cast<unsigned long long *>(sph_gcot_fixed(sgcot, md));
-    const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
-                  p1 = min(P, p0 + kSphPtsItem);
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
-      double R, z, phi, psi;
-      sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
-      const double x = asinh(R / sc.aR) * sc.iR, y = asinh(z / sc.aZ) * sc.iZ;
-      const int i0 = min(max((int)floor(x), 0), N - 3), l0 = min(max((int)floor(y), 0), N - 3);
-      double wx[4], wy[4];
-      lagrange4(x - i0, wx);
-      lagrange4(y - l0, wy);
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int64_t row = (int64_t)abs(i0 - 1 + a) * N;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const double w = wx[a] * wy[b];
-          const long long va = __double2ll_rn(phi * w * sa), vb = __double2ll_rn(psi * w * sb);
-          unsigned long long *c = fx + (row + abs(l0 - 1 + b)) * 2;
-          if (va) atomicAdd(c, (unsigned long long)va);
-          if (vb) atomicAdd(c + 1, (unsigned long long)vb);
+    const int *pos = sph_gcot_int(sgcot, md, g.K);
+    const int *toff = pos + (int64_t)np * kSphTiles;
+    const int flag = toff[kSphTiles + 1];
+    const int *list = toff + kSphTiles + 2;
+    const int64_t P = sph_points(g.K), e0 = (int64_t)it.a * kSphPtsItem,
+                  e1 = min(P, e0 + kSphPtsItem);
+    if (flag) {                              // uniform
+      for (int64_t p = e0 + threadIdx.x; p < e1; p += 256)
+        sph_spread_point(g, geoms + md.geom, tab, adj, sinth, sc, sa, sb, p, fx, nullptr, 0, 0);
+      continue;
+    }
+    // the tiles whose list ranges meet [e0, e1)
+    const int t = threadIdx.x;
+    if (toff[t] <= e0 && e0 < toff[t + 1]) tr[0] = t;
+    if (toff[t] < e1 && e1 <= toff[t + 1]) tr[1] = t;
+    __syncthreads();
+    const int ta = tr[0], tb = tr[1];
+    __syncthreads();                         // tr read before the next item writes it
+    for (int tile = ta; tile <= tb; ++tile) {
+      const int64_t s0 = max(e0, (int64_t)toff[tile]), s1 = min(e1, (int64_t)toff[tile + 1]);
+      if (s0 >= s1) continue;                // uniform
+      const int r0 = (tile / kSphTilesAx) * kSphTileB - 2, c0 = (tile % kSphTilesAx) * kSphTileB - 2;
+      for (int e = t; e < kTileL * kTileL * 2; e += 256) acc[e] = 0ull;
+      __syncthreads();
+      for (int64_t e = s0 + t; e < s1; e += 256)
+        sph_spread_point(g, geoms + md.geom, tab, adj, sinth, sc, sa, sb, list[e], fx, acc, r0, c0);
+      __syncthreads();
+      for (int e = t; e < kTileL * kTileL; e += 256) {
+        const int row = r0 + e / kTileL, col = c0 + e % kTileL;
+        const unsigned long long va = acc[2 * e], vb = acc[2 * e + 1];
+        if (row >= 0 && row < N && col >= 0 && col < N) {
+          unsigned long long *c = fx + ((int64_t)row * N + col) * 2;
+          if (va) atomicAdd(c, va);
+          if (vb) atomicAdd(c + 1, vb);
         }
       }
+      __syncthreads();                       // the block is read before it is cleared
     }
   }
 }
@@ -4255,7 +4447,11 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
   if (sgcot) {
     hipLaunchKernelGGL(k_sph_pcot_bound, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
                        n_pcot, gauss, st_ws, sens, sgcot);
-    hipLaunchKernelGGL(k_sph_pcot_scatter, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
+    hipLaunchKernelGGL(k_sph_pcot_scan, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws,
+                       sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_fill, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
+                       n_pcot, gauss, st_ws, sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_tiles, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
                        n_pcot, gauss, st_ws, sens, sgcot);
     hipLaunchKernelGGL(k_sph_pcot_fix, dim3(grid_of(n_pfix)), dim3(256), 0, st, g, m, it_pfix,
                        n_pfix, st_ws, sgcot);
