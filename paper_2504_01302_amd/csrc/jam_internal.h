@@ -351,12 +351,14 @@ __host__ __device__ inline int sph_pitems(int K) {
 // Doubles: fixed-point grid [N][N][2], FP32 grid [N][N][2], bound partials
 // [items][2] and the two scales; then int32: per (item, tile) list
 // positions [items][kSphTiles], tile offsets [kSphTiles + 1], a consistency
-// flag and the point list [points].
+// flag and the point list [points]; then one byte per point, its tile.
+static_assert(kSphTiles <= 256, "a tile index fits one byte");
 __host__ __device__ inline int64_t sph_gcot_ints(int K) {
   return (int64_t)sph_pitems(K) * kSphTiles + kSphTiles + 2 + sph_points(K);
 }
 __host__ __device__ inline int64_t sph_gcot_size(int K) {
-  return 3LL * kSphGridN * kSphGridN + 2LL * sph_pitems(K) + 2 + (sph_gcot_ints(K) + 1) / 2;
+  return 3LL * kSphGridN * kSphGridN + 2LL * sph_pitems(K) + 2 + (sph_gcot_ints(K) + 1) / 2 +
+         (sph_points(K) + 7) / 8;
 }
 
 // Logistic radial anisotropy profile prof[m][0..3] = (beta_0, beta_inf, r_a,

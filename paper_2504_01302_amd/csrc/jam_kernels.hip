@@ -3466,53 +3466,27 @@ __device__ inline double *sph_gcot_bounds(double *sgcot, const ModelDev &md) {
 }
 
 // The int32 part of the grid-cotangent workspace: per (point item, tile)
-// list positions, tile offsets, the consistency flag, the point list.
+// list positions, tile offsets, the consistency flag, the point list; then
+// one byte per point, its tile.
 __device__ inline int *sph_gcot_int(double *sgcot, const ModelDev &md, int K) {
   return reinterpret_cast<int *>(sph_gcot_bounds(sgcot, md) + 2LL * sph_pitems(K) + 2);
 }
+__device__ inline unsigned char *sph_gcot_ptile(double *sgcot, const ModelDev &md, int K) {
+  return reinterpret_cast<unsigned char *>(sph_gcot_int(sgcot, md, K) + sph_gcot_ints(K));
+}
 
-// Stencil base cell (i0, l0) on the potential grid of point p, the
-// position as sph_point_cot computes it.  The tile counts and the sorted
-// list are built by different kernels and must agree point by point, so
-// the cell and the grid scales it uses each come from one compiled body
-// (not inlined), which also takes its own sin of the polar angle.
-struct SphCell {
-  int i0, l0;
-};
-__device__ __attribute__((noinline)) SphGrid sph_cell_scales(const GeomDev *__restrict__ gp,
-                                                             const double *__restrict__ tab) {
-  return sph_grid_scales(*gp, tab);
-}
-__device__ __attribute__((noinline)) SphCell sph_point_cell(const GeomDev *__restrict__ gp,
-                                                            const double *__restrict__ tab,
-                                                            SphGrid sc, int64_t p) {
-  const int K = gp->K;
-  const int cell = (int)(p / ((int64_t)K * kSphNodes));
-  const int k = (int)((p / kSphNodes) % K), node = (int)(p % kSphNodes);
-  const int ir = cell / kSphNT, ith = cell % kSphNT;
-  const double lnr = gp->sph_lnr0 + ir * gp->sph_dlnr, r = exp(lnr);
-  const double sth = sin(ith * (0.5 * kPi / (kSphNT - 1)));
-  const double alpha = tab[k];
-  const double beta = 1.0 - 1.0 / tab[3 * K + k];
-  const double glx = gp->gl8_x[node & 7];
-  const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
-  const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
-  const double rp = exp(lnr + tau);
-  const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
-  const double ct = sqrt(fmax(0.0, 1.0 - st * st));
-  const double x = asinh(rp * st / sc.aR) * sc.iR, y = asinh(rp * ct / sc.aZ) * sc.iZ;
-  SphCell c;
-  c.i0 = min(max((int)floor(x), 0), kSphGridN - 3);
-  c.l0 = min(max((int)floor(y), 0), kSphGridN - 3);
-  return c;
-}
-__device__ inline int sph_tile_of(SphCell c) {
-  return (c.i0 / kSphTileB) * kSphTilesAx + c.l0 / kSphTileB;
+// The grid tile (of kSphTileB x kSphTileB stencil base cells) that holds
+// the stencil base cell of a point at (R, z), as sph_spread_point places it.
+__device__ inline int sph_tile_at(const SphGrid &sc, double R, double z) {
+  const double x = asinh(R / sc.aR) * sc.iR, y = asinh(z / sc.aZ) * sc.iZ;
+  const int i0 = min(max((int)floor(x), 0), kSphGridN - 3);
+  const int l0 = min(max((int)floor(y), 0), kSphGridN - 3);
+  return (i0 / kSphTileB) * kSphTilesAx + l0 / kSphTileB;
 }
 
 // Item (m, point item q): clears a share of the fixed-point grid, sums
-// |phi|, |psi| over the item's points (fixed-order block sums) and counts
-// them per grid tile.
+// |phi|, |psi| over the item's points (fixed-order block sums), and counts
+// them per grid tile, recording each point's tile.
 __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restrict__ geoms,
                                                         const ModelDev *__restrict__ models,
                                                         const Item *__restrict__ items, int n_it,
@@ -3533,13 +3507,14 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
     const GeomDev g = geoms[md.geom];
     const SphAdj adj = sph_adj_of(sens, md, g);
     const double *tab = gauss + md.gauss_off;
-    const SphGrid sc = sph_cell_scales(geoms + md.geom, tab);
+    const SphGrid sc = sph_grid_scales(g, tab);
     const int np = sph_pitems(g.K);
     const int64_t n2 = 2LL * kSphGridN * kSphGridN, share = (n2 + np - 1) / np;
     long long *fx = sph_gcot_fixed(sgcot, md);
     const int64_t e0 = (int64_t)it.a * share, e1 = min(n2, e0 + share);
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) fx[e] = 0;
     int *gi = sph_gcot_int(sgcot, md, g.K);
+    unsigned char *ptile = sph_gcot_ptile(sgcot, md, g.K);
     if (it.a == 0 && threadIdx.x == 0) gi[(int64_t)np * kSphTiles + kSphTiles + 1] = 0;   // flag
     hist[threadIdx.x] = 0;
     __syncthreads();
@@ -3551,7 +3526,9 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
       sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
       sa += fabs(phi);
       sb += fabs(psi);
-      atomicAdd(&hist[sph_tile_of(sph_point_cell(geoms + md.geom, tab, sc, p))], 1);
+      const int tile = sph_tile_at(sc, R, z);
+      ptile[p] = (unsigned char)tile;
+      atomicAdd(&hist[tile], 1);
     }
     sa = block_sum256(sa, sh);
     sb = block_sum256(sb, sh);
@@ -3604,10 +3581,10 @@ __global__ void __launch_bounds__(256) k_sph_pcot_scan(const GeomDev *__restrict
 }
 
 // Item (m, point item q): the item's point indices into the list, each at
-// its tile's range for this item (the order within a range is immaterial:
-// the grid sums are exact).  A count that disagrees with the counting pass
-// sets the model's flag, and the tile pass then spreads that model's points
-// directly.
+// its recorded tile's range for this item (the order within a range is
+// immaterial: the grid sums are exact).  A count that disagrees with the
+// counting pass sets the model's flag, and the tile pass then spreads that
+// model's points directly.
 __global__ void __launch_bounds__(256) k_sph_pcot_fill(const GeomDev *__restrict__ geoms,
                                                        const ModelDev *__restrict__ models,
                                                        const Item *__restrict__ items, int n_it,
@@ -3620,10 +3597,9 @@ __global__ void __launch_bounds__(256) k_sph_pcot_fill(const GeomDev *__restrict
     if (st_ws[it.m] != 0) continue;          // uniform per block
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
-    const double *tab = gauss + md.gauss_off;
-    const SphGrid sc = sph_cell_scales(geoms + md.geom, tab);
     const int np = sph_pitems(g.K);
     int *pos = sph_gcot_int(sgcot, md, g.K);
+    const unsigned char *ptile = sph_gcot_ptile(sgcot, md, g.K);
     const int *toff = pos + (int64_t)np * kSphTiles;
     int *flag = pos + (int64_t)np * kSphTiles + kSphTiles + 1;
     int *list = flag + 1;
@@ -3635,7 +3611,7 @@ __global__ void __launch_bounds__(256) k_sph_pcot_fill(const GeomDev *__restrict
     const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
                   p1 = min(P, p0 + kSphPtsItem);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
-      const int tile = sph_tile_of(sph_point_cell(geoms + md.geom, tab, sc, p));
+      const int tile = ptile[p];
       const int at = rb[tile] + atomicAdd(&cur[tile], 1);
       if (at < rl[tile]) list[at] = (int)p;
     }
