@@ -3476,12 +3476,25 @@ __device__ inline unsigned char *sph_gcot_ptile(double *sgcot, const ModelDev &m
 }
 
 // The grid tile (of kSphTileB x kSphTileB stencil base cells) that holds
-// the stencil base cell of a point at (R, z), as sph_spread_point places it.
-__device__ inline int sph_tile_at(const SphGrid &sc, double R, double z) {
-  const double x = asinh(R / sc.aR) * sc.iR, y = asinh(z / sc.aZ) * sc.iZ;
-  const int i0 = min(max((int)floor(x), 0), kSphGridN - 3);
-  const int l0 = min(max((int)floor(y), 0), kSphGridN - 3);
-  return (i0 / kSphTileB) * kSphTilesAx + l0 / kSphTileB;
+// the stencil base cell of a point at (R, z): tile row b starts at
+// R = aR sinh(kSphTileB b / iR) (bR[b], b = 1 .. kSphTilesAx - 1), and
+// likewise in z (bZ).  A point within rounding of a boundary may land in
+// the neighbouring tile; the tile pass takes its stencil all the same.
+__device__ inline void sph_tile_bounds(const SphGrid &sc, double *bR, double *bZ) {
+  for (int b = threadIdx.x; b < kSphTilesAx; b += blockDim.x) {
+    bR[b] = sc.aR * sinh(kSphTileB * b / sc.iR);
+    bZ[b] = sc.aZ * sinh(kSphTileB * b / sc.iZ);
+  }
+}
+__device__ inline int sph_tile_at(const double *bR, const double *bZ, double R, double z) {
+  static_assert(kSphTilesAx == 16, "a four-step search");
+  int tx = 0, tz = 0;
+#pragma unroll
+  for (int step = 8; step >= 1; step >>= 1) {
+    if (R >= bR[tx + step]) tx += step;
+    if (z >= bZ[tz + step]) tz += step;
+  }
+  return tx * kSphTilesAx + tz;
 }
 
 // Item (m, point item q): clears a share of the fixed-point grid, sums
@@ -3497,6 +3510,7 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
   static_assert(kSphTiles == 256, "one thread per tile");
   __shared__ double sinth[kSphNT];
   __shared__ double sh[256];
+  __shared__ double bR[kSphTilesAx], bZ[kSphTilesAx];
   __shared__ int hist[kSphTiles];
   if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
   __syncthreads();
@@ -3517,6 +3531,7 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
     unsigned char *ptile = sph_gcot_ptile(sgcot, md, g.K);
     if (it.a == 0 && threadIdx.x == 0) gi[(int64_t)np * kSphTiles + kSphTiles + 1] = 0;   // flag
     hist[threadIdx.x] = 0;
+    sph_tile_bounds(sc, bR, bZ);
     __syncthreads();
     const int64_t P = sph_points(g.K), p0 = (int64_t)it.a * kSphPtsItem,
                   p1 = min(P, p0 + kSphPtsItem);
@@ -3526,7 +3541,7 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
       sph_point_cot(g, geoms + md.geom, tab, adj, sinth, p, R, z, phi, psi);
       sa += fabs(phi);
       sb += fabs(psi);
-      const int tile = sph_tile_at(sc, R, z);
+      const int tile = sph_tile_at(bR, bZ, R, z);
       ptile[p] = (unsigned char)tile;
       atomicAdd(&hist[tile], 1);
     }
@@ -3539,17 +3554,20 @@ __global__ void __launch_bounds__(256) k_sph_pcot_bound(const GeomDev *__restric
     }
     __syncthreads();
     gi[(int64_t)it.a * kSphTiles + threadIdx.x] = hist[threadIdx.x];
+    __syncthreads();                         // hist, bR, bZ read before the next item
   }
 }
 
-// Model m (thread = tile): the per-item tile counts become list positions,
-// items in order within a tile and tiles in order, and the tile offsets.
-__global__ void __launch_bounds__(256) k_sph_pcot_scan(const GeomDev *__restrict__ geoms,
-                                                       const ModelDev *__restrict__ models, int n,
-                                                       const int *__restrict__ st_ws,
-                                                       double *__restrict__ sgcot) {
-  __shared__ int tot[kSphTiles];
-  const int t = threadIdx.x;
+// Model m: the per-item tile counts become list positions, items in order
+// within a tile and tiles in order, and the tile offsets.  Thread (tile,
+// part) takes a quarter of the items; the parts are added in order.
+constexpr int kScanParts = 4;
+__global__ void __launch_bounds__(kSphTiles * kScanParts) k_sph_pcot_scan(
+    const GeomDev *__restrict__ geoms, const ModelDev *__restrict__ models, int n,
+    const int *__restrict__ st_ws, double *__restrict__ sgcot) {
+  __shared__ int part[kScanParts][kSphTiles];   // per part: its count, then its offset
+  __shared__ int tsz[kSphTiles], tot[kSphTiles];
+  const int t = threadIdx.x % kSphTiles, r = threadIdx.x / kSphTiles;
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     if (st_ws[m] != 0) continue;             // uniform per block
     const ModelDev md = models[m];
@@ -3557,26 +3575,55 @@ __global__ void __launch_bounds__(256) k_sph_pcot_scan(const GeomDev *__restrict
     const int np = sph_pitems(K);
     int *pos = sph_gcot_int(sgcot, md, K);
     int *toff = pos + (int64_t)np * kSphTiles;
+    const int per = (np + kScanParts - 1) / kScanParts;
+    const int q0 = min(np, r * per), q1 = min(np, q0 + per);
+    // the part's items: counts to offsets within the part
     int acc = 0;
-    for (int q = 0; q < np; ++q) {
-      int *h = pos + (int64_t)q * kSphTiles + t;
-      const int v = *h;
-      *h = acc;
-      acc += v;
+    for (int q = q0; q < q1; q += 8) {
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = q + u < q1 ? pos[(int64_t)(q + u) * kSphTiles + t] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (q + u < q1) pos[(int64_t)(q + u) * kSphTiles + t] = acc;
+        acc += v[u];
+      }
     }
-    __syncthreads();                         // the previous model's reads of tot
-    tot[t] = acc;
+    __syncthreads();                         // the previous model's reads of part, tsz, tot
+    part[r][t] = acc;
     __syncthreads();
+    if (r == 0) {
+      int s0 = 0;
+      for (int rr = 0; rr < kScanParts; ++rr) {
+        const int v = part[rr][t];
+        part[rr][t] = s0;
+        s0 += v;
+      }
+      tsz[t] = s0;
+      tot[t] = s0;
+    }
+    __syncthreads();
+    // inclusive scan of the tile sizes over the tiles
     for (int off = 1; off < kSphTiles; off <<= 1) {
-      const int v = t >= off ? tot[t - off] : 0;
+      const int v = (r == 0 && t >= off) ? tot[t - off] : 0;
       __syncthreads();
-      tot[t] += v;
+      if (r == 0) tot[t] += v;
       __syncthreads();
     }
-    const int base = tot[t] - acc;
-    toff[t] = base;
-    if (t == kSphTiles - 1) toff[kSphTiles] = tot[t];
-    for (int q = 0; q < np; ++q) pos[(int64_t)q * kSphTiles + t] += base;
+    const int tile0 = tot[t] - tsz[t];
+    if (r == 0) {
+      toff[t] = tile0;
+      if (t == kSphTiles - 1) toff[kSphTiles] = tot[t];
+    }
+    const int base = tile0 + part[r][t];
+    for (int q = q0; q < q1; q += 8) {
+      int v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = q + u < q1 ? pos[(int64_t)(q + u) * kSphTiles + t] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q + u < q1) pos[(int64_t)(q + u) * kSphTiles + t] = v[u] + base;
+    }
   }
 }
 
@@ -3635,6 +3682,7 @@ __device__ inline double sph_gcot_scale(double bound) {
 // columns c0 .. c0 + kL - 1) where the stencil lies inside it, else
 // straight into the grid.
 constexpr int kTileL = kSphTileB + 5;   // a tile's stencils with one cell to spare
+constexpr int kTileSub = 4;             // list parts per point item in the tile pass
 __device__ inline void sph_spread_point(const GeomDev &g, const GeomDev *__restrict__ gp,
                                         const double *tab, const SphAdj &adj,
                                         const double *sinth, const SphGrid &sc, double sa,
@@ -3667,11 +3715,12 @@ __device__ inline void sph_spread_point(const GeomDev &g, const GeomDev *__restr
   }
 }
 
-// Item (m, q): entries q * kSphPtsItem .. + kSphPtsItem - 1 of the model's
-// tile-sorted point list.  Per tile met there, the entries' stencils are
-// summed in an LDS block (fixed point, so in any order) and the block is
-// added to the grid; with the model's flag set, the item's own points are
-// spread straight onto the grid instead.
+// Item (m, q) split in kTileSub parts: part s takes entries
+// q * kSphPtsItem + s * kSphPtsItem / kTileSub onwards (kSphPtsItem /
+// kTileSub of them) of the model's tile-sorted point list.  Per tile met
+// there, the entries' stencils are summed in an LDS block (fixed point, so
+// in any order) and the block is added to the grid; with the model's flag
+// set, the same range of points is spread straight onto the grid instead.
 __global__ void __launch_bounds__(256) k_sph_pcot_tiles(const GeomDev *__restrict__ geoms,
                                                         const ModelDev *__restrict__ models,
                                                         const Item *__restrict__ items, int n_it,
@@ -3686,21 +3735,26 @@ __global__ void __launch_bounds__(256) k_sph_pcot_tiles(const GeomDev *__restric
   __shared__ int tr[2];
   if (threadIdx.x < kSphNT) sinth[threadIdx.x] = sin(threadIdx.x * (0.5 * kPi / (kSphNT - 1)));
   __syncthreads();
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
-    const Item it = items[i];
+  constexpr int kSub = kSphPtsItem / kTileSub;
+  for (int vi = blockIdx.x; vi < n_it * kTileSub; vi += gridDim.x) {
+    const Item it = items[vi / kTileSub];
+    const int sub = vi % kTileSub;
     if (st_ws[it.m] != 0) continue;          // uniform per block
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
     const SphAdj adj = sph_adj_of(sens, md, g);
     const double *tab = gauss + md.gauss_off;
     const int np = sph_pitems(g.K);
+    const int64_t P = sph_points(g.K), e0 = (int64_t)it.a * kSphPtsItem + sub * kSub,
+                  e1 = min(P, e0 + kSub);
+    if (e0 >= P) continue;                   // uniform: the model's last item ends early
     double *bnd = sph_gcot_bounds(sgcot, md);
     double ba = 0.0, bb = 0.0;
     for (int q = threadIdx.x; q < np; q += 256) { ba += bnd[2 * q]; bb += bnd[2 * q + 1]; }
     ba = block_sum256(ba, sh);
     bb = block_sum256(bb, sh);
     const double sa = sph_gcot_scale(ba), sb = sph_gcot_scale(bb);
-    if (it.a == 0 && threadIdx.x == 0) { bnd[2 * np] = sa; bnd[2 * np + 1] = sb; }
+    if (it.a == 0 && sub == 0 && threadIdx.x == 0) { bnd[2 * np] = sa; bnd[2 * np + 1] = sb; }
     if (!(sa == sa) || !(sb == sb)) continue;   // uniform: a non-finite cotangent
     const SphGrid sc = sph_grid_scales(g, tab);
     unsigned long long *fx = reinterpret_cast<unsigned long long *>(sph_gcot_fixed(sgcot, md));
@@ -3708,8 +3762,6 @@ __global__ void __launch_bounds__(256) k_sph_pcot_tiles(const GeomDev *__restric
     const int *toff = pos + (int64_t)np * kSphTiles;
     const int flag = toff[kSphTiles + 1];
     const int *list = toff + kSphTiles + 2;
-    const int64_t P = sph_points(g.K), e0 = (int64_t)it.a * kSphPtsItem,
-                  e1 = min(P, e0 + kSphPtsItem);
     if (flag) {                              // uniform
       for (int64_t p = e0 + threadIdx.x; p < e1; p += 256)
         sph_spread_point(g, geoms + md.geom, tab, adj, sinth, sc, sa, sb, p, fx, nullptr, 0, 0);
@@ -4423,12 +4475,12 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
   if (sgcot) {
     hipLaunchKernelGGL(k_sph_pcot_bound, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
                        n_pcot, gauss, st_ws, sens, sgcot);
-    hipLaunchKernelGGL(k_sph_pcot_scan, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws,
-                       sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_scan, dim3(grid_of(n)), dim3(kSphTiles * kScanParts), 0, st, g,
+                       m, n, st_ws, sgcot);
     hipLaunchKernelGGL(k_sph_pcot_fill, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
                        n_pcot, gauss, st_ws, sgcot);
-    hipLaunchKernelGGL(k_sph_pcot_tiles, dim3(grid_of(n_pcot)), dim3(256), 0, st, g, m, it_pcot,
-                       n_pcot, gauss, st_ws, sens, sgcot);
+    hipLaunchKernelGGL(k_sph_pcot_tiles, dim3(grid_of(n_pcot * kTileSub)), dim3(256), 0, st, g, m,
+                       it_pcot, n_pcot, gauss, st_ws, sens, sgcot);
     hipLaunchKernelGGL(k_sph_pcot_fix, dim3(grid_of(n_pfix)), dim3(256), 0, st, g, m, it_pfix,
                        n_pfix, st_ws, sgcot);
     hipLaunchKernelGGL(k_sph_sens_grid, dim3(grid_of(n_sgs)), dim3(256), 0, st, g, m, it_sgs,
