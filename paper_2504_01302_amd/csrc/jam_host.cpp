@@ -1110,7 +1110,7 @@ void launch_vjp(jam_ctx *ctx, Plan *p, const jam_batch *b, const double *vrms2, 
                          grads->mass_S0};
   if (p->spherical) {
     const bool ts = ctx->t_sens.begin(st, capturing);
-    jam::launch_sph_adjoint(ctx->d_geoms, p->d_models, p->n, p->d_pix, p->n_pix, p->d_sph,
+    jam::launch_sph_adjoint(ctx->d_geoms, p->d_models, p->n, p->d_red, p->n_red, p->d_sph,
                             p->n_sph, p->d_sens, p->n_sens, p->d_terms, p->n_terms, p->d_pcot,
                             p->n_pcot, p->d_pfix, p->n_pfix, p->d_sgs, p->n_sgs, pd,
                             (const double *)(w + p->off_gauss),

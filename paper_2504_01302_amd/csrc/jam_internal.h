@@ -263,7 +263,7 @@ void launch_sb_adjoint(const GeomDev *g, const ModelDev *m, const Item *it, int 
                        const int *st_ws, const double *pix, double *sbp, hipStream_t st);
 // Adjoint of the spherically aligned model, after the bin adjoint has filled
 // lambda_N and lambda_I: zero the table cotangents (block per model), the
-// line-of-sight adjoint (items (m, 256-pixel block)), the characteristic
+// line-of-sight adjoint (items (m, 64-pixel block)), the characteristic
 // integrals' adjoint (items as launch_sph_moments), the term-major
 // sensitivities over point ranges (items (m, 256-term tile, range)) and over
 // the table points (items (m, 256-term tile)), the per-term chain (items (m,

@@ -2907,15 +2907,22 @@ __global__ void __launch_bounds__(256) k_sph_dtab_fix(const GeomDev *__restrict_
   }
 }
 
-// Line-of-sight adjoint.  Item (m, 256-pixel block), thread = pixel.  The
-// table cotangent receives lambda_N w_z (n.e_f)^2 times the interpolation
-// weights, each rounded to a 64-bit fixed-point integer at the model's scale
-// (k_sph_zero), accumulated in a block-private LDS copy of the table
-// (integer LDS atomics) and added to the model's table once per block
-// (integer global atomics, non-zero entries only): integer sums, so the
-// result does not depend on the order of the additions.  The derivatives of
-// the node's integrand at fixed table with respect to i (line of sight and
-// node position) and to the node scale a are summed per 64-pixel wave.
+// Line-of-sight kernels: four lanes per pixel, each taking a quarter of the
+// line-of-sight nodes.
+constexpr int kLosLanes = 4;                       // lanes per pixel
+constexpr int kLosNodes = kSphNodes / kLosLanes;   // nodes per lane
+
+// Line-of-sight adjoint.  Item (m, 64-pixel block), one workgroup each, the
+// lanes as in k_sph_num.  The table cotangent receives lambda_N w_z
+// (n.e_f)^2 times the interpolation weights, each rounded to a 64-bit
+// fixed-point integer at the model's scale (k_sph_zero), accumulated in a
+// block-private LDS copy of the table (integer LDS atomics) and added to the
+// model's table once per block (integer global atomics, non-zero entries
+// only): integer sums, so the result does not depend on the order of the
+// additions.  The derivatives of the node's integrand at fixed table with
+// respect to i (line of sight and node position) and to the node scale a
+// are summed per block in a fixed order (butterflies over each wave, then
+// the waves in order).
 __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__ geoms,
                                                      const ModelDev *__restrict__ models,
                                                      const Item *__restrict__ items, int n_it,
@@ -2925,6 +2932,8 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
                                                      const double *__restrict__ pix,
                                                      double *__restrict__ sens) {
   __shared__ unsigned long long ldt[3 * kSphCells];
+  __shared__ double wred[4][2];
+  const int pl = threadIdx.x / kLosLanes, h = threadIdx.x % kLosLanes;
   for (int ii = blockIdx.x; ii < n_it; ii += gridDim.x) {
     const Item it = items[ii];
     const ModelDev md = models[it.m];
@@ -2935,7 +2944,7 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
     const bool fixed = scale == scale;           // NaN: non-finite cotangent
     for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) ldt[i] = 0ull;
     __syncthreads();
-    const int q = it.a * 256 + threadIdx.x;
+    const int q = it.a * 64 + pl;
     const bool on = q < g.n_pix;
     const int K = g.K;
     const double *tab = gauss + md.gauss_off;
@@ -2956,7 +2965,7 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
     const double hw = 2.0 * W / kSphSeg;
     const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
     double acc_i = 0.0, acc_a = 0.0;
-    for (int nd = 0; on && nd < kSphNodes; ++nd) {
+    for (int nd = h * kLosNodes; on && nd < (h + 1) * kLosNodes; ++nd) {
       const int seg = nd >> 3, gi = nd & 7;
       const double om = -1.0 + (seg + 0.5 + 0.5 * glx[gi]) / 4.0;   // w = W om
       const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
@@ -3035,16 +3044,18 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
                          (Wa * a * chw + W * chw + W * a * shw * om * Wa);
       acc_a += lamN * (dwz * F + wz * (FY * si + FZ * ci) * dzp);
     }
+    // fixed-order sums: each wave's 64 lanes by a butterfly, then the waves
     acc_i = wave_sum(acc_i);
     acc_a = wave_sum(acc_a);
     if ((threadIdx.x & 63) == 0) {
-      const int wb = it.a * 4 + (threadIdx.x >> 6);   // 64-pixel block of this wave
-      if (wb < (g.n_pix + 63) / 64) {
-        adj.losp[2 * wb] = acc_i;
-        adj.losp[2 * wb + 1] = acc_a;
-      }
+      wred[threadIdx.x >> 6][0] = acc_i;
+      wred[threadIdx.x >> 6][1] = acc_a;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      adj.losp[2 * it.a] = ((wred[0][0] + wred[1][0]) + wred[2][0]) + wred[3][0];
+      adj.losp[2 * it.a + 1] = ((wred[0][1] + wred[1][1]) + wred[2][1]) + wred[3][1];
+    }
     unsigned long long *dt = reinterpret_cast<unsigned long long *>(adj.dtab);
     for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) {
       const unsigned long long v = ldt[i];
@@ -4216,8 +4227,10 @@ __global__ void __launch_bounds__(256) k_beta_logistic_vjp(const GeomDev *__rest
 }
 
 // Line-of-sight integral of the projected moment table into the unique-pixel
-// N map.  Item (m, 64-pixel block); thread = pixel.  Nodes z' = a sinh(w), w
-// on [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
+// N map.  Item (m, 64-pixel block), one workgroup each: four lanes per pixel
+// (thread = 4 pixel + h), lane h taking nodes 16 h .. 16 h + 15, and the
+// four partial sums added in a fixed order.  Nodes z' = a sinh(w), w on
+// [-W, W] by the composite rule, a = min_k sigma_k q_k / 4,
 // a sinh(W) = 12 max_k sigma_k; the table is interpolated bicubically
 // (sph_radial_weights, sph_angular_weights), the first radius standing for
 // smaller ones and zero beyond the last.  FP64.
@@ -4228,71 +4241,75 @@ __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geo
                                                  const int *__restrict__ st_ws,
                                                  const double *__restrict__ table,
                                                  double *__restrict__ pix) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (int64_t)n_it * 64) return;
-  const Item it = items[gid >> 6];
-  const ModelDev md = models[it.m];
-  const GeomDev g = geoms[md.geom];
-  const int q = it.a * 64 + (int)(gid & 63);
-  if (q >= g.n_pix) return;
-  double *Nout = pix + md.pix_off + q;
-  if (st_ws[it.m] != 0) {
-    *Nout = 0.0;
-    return;
-  }
-  const int K = g.K;
-  const double *tab = gauss + md.gauss_off;
-  const double *mt = tab + 4 * K;
-  const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
-  double smin = 1e300, smax = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
-    smin = fmin(smin, sk * qk);
-    smax = fmax(smax, sk);
-  }
-  const double a = 0.25 * smin, W = asinh(12.0 * smax / a);
-  const double x = g.xs[q % g.n_ux], y = g.ys[q / g.n_ux];
-  const double *T = table + md.sph_off;
-  const double dth = 0.5 * kPi / (kSphNT - 1);
-  const double hw = 2.0 * W / kSphSeg;
-  const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
-  double acc = 0.0;
-  for (int nd = 0; nd < kSphNodes; ++nd) {
-    const int seg = nd >> 3, gi = nd & 7;
-    const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
-    const double zp = a * sinh(w), wz = 0.5 * glw[gi] * hw * a * cosh(w);
-    const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
-    const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
-    const double ct = Z / r, st = R / r;
-    const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
-    const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
-    if (xf > kSphNR - 1) continue;
-    const double yf = acos(fmin(1.0, fabs(ct))) / dth;
-    const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
-    const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
-    const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
-    double ew[4], dew[4], tw[4], dtw[4];
-    sph_radial_weights(xi, fx, ew, dew);
-    sph_angular_weights(yi, fy, tw, dtw);
-    double A[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      if (ew[a] == 0.0) continue;           // out of range (folded) or a zero weight
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (tw[b] == 0.0) continue;
-        const double *c = T + ((int64_t)(xi - 1 + a) * kSphNT + (yi - 1 + b)) * 3;
-        const double wab = ew[a] * tw[b];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) A[f] += wab * c[f];
-      }
+  const int pl = threadIdx.x / kLosLanes, h = threadIdx.x % kLosLanes;
+  for (int ii = blockIdx.x; ii < n_it; ii += gridDim.x) {
+    const Item it = items[ii];
+    const ModelDev md = models[it.m];
+    const GeomDev g = geoms[md.geom];
+    const int q = it.a * 64 + pl;
+    const bool on = q < g.n_pix;
+    double *Nout = pix + md.pix_off + q;
+    if (st_ws[it.m] != 0) {                  // uniform per block
+      if (on && h == 0) *Nout = 0.0;
+      continue;
     }
-    const double ner = si * st * sp + ci * ct;
-    const double net = si * ct * sp - ci * st;
-    const double nep = si * cp;
-    acc += wz * (ner * ner * A[0] + net * net * A[1] + nep * nep * A[2]);
+    const int K = g.K;
+    const double *tab = gauss + md.gauss_off;
+    const double *mt = tab + 4 * K;
+    const double si = sqrt(mt[3 * g.J1]), ci = sqrt(mt[3 * g.J1 + 1]);
+    double smin = 1e300, smax = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double sk = sqrt(0.5 / tab[k]), qk = sqrt(tab[k] / tab[K + k]);
+      smin = fmin(smin, sk * qk);
+      smax = fmax(smax, sk);
+    }
+    const double a = 0.25 * smin, W = asinh(12.0 * smax / a);
+    const double x = on ? g.xs[q % g.n_ux] : 0.0, y = on ? g.ys[q / g.n_ux] : 0.0;
+    const double *T = table + md.sph_off;
+    const double dth = 0.5 * kPi / (kSphNT - 1);
+    const double hw = 2.0 * W / kSphSeg;
+    const double *glx = geoms[md.geom].gl8_x, *glw = geoms[md.geom].gl8_w;
+    double acc = 0.0;
+    for (int nd = h * kLosNodes; on && nd < (h + 1) * kLosNodes; ++nd) {
+      const int seg = nd >> 3, gi = nd & 7;
+      const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
+      const double zp = a * sinh(w), wz = 0.5 * glw[gi] * hw * a * cosh(w);
+      const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
+      const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
+      const double ct = Z / r, st = R / r;
+      const double sp = R > 0.0 ? Y / R : 0.0, cp = R > 0.0 ? X / R : 0.0;
+      const double xf = (log(r) - g.sph_lnr0) / g.sph_dlnr;
+      if (xf > kSphNR - 1) continue;
+      const double yf = acos(fmin(1.0, fabs(ct))) / dth;
+      const int xi = (int)fmin(fmax(floor(xf), 0.0), (double)(kSphNR - 2));
+      const int yi = (int)fmin(fmax(floor(yf), 0.0), (double)(kSphNT - 2));
+      const double fx = fmin(fmax(xf - xi, 0.0), 1.0), fy = fmin(fmax(yf - yi, 0.0), 1.0);
+      double ew[4], dew[4], tw[4], dtw[4];
+      sph_radial_weights(xi, fx, ew, dew);
+      sph_angular_weights(yi, fy, tw, dtw);
+      double A[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (ew[a] == 0.0) continue;           // out of range (folded) or a zero weight
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if (tw[b] == 0.0) continue;
+          const double *c = T + ((int64_t)(xi - 1 + a) * kSphNT + (yi - 1 + b)) * 3;
+          const double wab = ew[a] * tw[b];
+#pragma unroll
+          for (int f = 0; f < 3; ++f) A[f] += wab * c[f];
+        }
+      }
+      const double ner = si * st * sp + ci * ct;
+      const double net = si * ct * sp - ci * st;
+      const double nep = si * cp;
+      acc += wz * (ner * ner * A[0] + net * net * A[1] + nep * nep * A[2]);
+    }
+    // (h0 + h1) + (h2 + h3) in every lane of the pixel
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (on && h == 0) *Nout = acc;
   }
-  *Nout = acc;
 }
 
 inline int grid_of(int n_it) { return n_it < 1 ? 1 : n_it; }
@@ -4454,7 +4471,7 @@ void launch_sph_moments_jac(const GeomDev *g, const ModelDev *m, const Item *it,
 void launch_sph_num(const GeomDev *g, const ModelDev *m, const Item *it, int n_it,
                     const double *gauss, const int *st_ws, const double *table, double *pix,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_num, dim3(grid_of((n_it + 3) / 4)), dim3(256), 0, st, g, m, it, n_it,
+  hipLaunchKernelGGL(k_sph_num, dim3(grid_of(n_it)), dim3(64 * kLosLanes), 0, st, g, m, it, n_it,
                      gauss, st_ws, table, pix);
 }
 void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *it_los,
