@@ -291,17 +291,21 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
 // cell) rows (d/dbeta, d/dalphaq, d/dnu0) [K][cells][3], line-of-sight
 // partials (d/di at fixed node scale, d/d node scale) per 64-pixel block,
 // per-term sensitivities per point range [n_rng][Tp][6] and of the cell
-// points [Tp][3], per-term chain values (d/de2, d/dKp) [Tp][2], the table
+// points per 256-cell part [kSphCellParts][Tp][3], per-term chain values
+// (d/de2, d/dKp) [Tp][2], the table
 // cotangent's fixed-point scale [1], the cotangent-free node sums of the
 // characteristic integrals' adjoint per (tracer, cell) [K][cells][8] and
 // G_phi per cell [cells].  n_rng is ModelDev::n_sens_parts.
 constexpr int kSphCells = kSphNR * kSphNT;
+// The cell sensitivities come in parts of 256 cells, summed in order.
+constexpr int kSphCellParts = kSphCells / 256;
+static_assert(kSphCellParts * 256 == kSphCells, "whole 256-cell parts");
 struct SphAdj {
   double *dtab, *rows, *losp, *sparts, *cparts, *tchain, *dscale, *jac, *gphi;
 };
 __host__ __device__ inline int64_t sph_adj_size(int K, int n_pix, int Tp, int n_rng) {
   return 3LL * kSphCells + 3LL * kSphCells * K + 2LL * ((n_pix + 63) / 64) +
-         6LL * n_rng * Tp + 5LL * Tp + 1 + 8LL * kSphCells * K + kSphCells;
+         6LL * n_rng * Tp + (3LL * kSphCellParts + 2) * Tp + 1 + 8LL * kSphCells * K + kSphCells;
 }
 __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix, int Tp,
                                                  int n_rng) {
@@ -311,7 +315,7 @@ __host__ __device__ inline SphAdj sph_adj_layout(double *base, int K, int n_pix,
   a.losp = a.rows + 3LL * kSphCells * K;
   a.sparts = a.losp + 2LL * ((n_pix + 63) / 64);
   a.cparts = a.sparts + 6LL * n_rng * Tp;
-  a.tchain = a.cparts + 3LL * Tp;
+  a.tchain = a.cparts + 3LL * kSphCellParts * Tp;
   a.dscale = a.tchain + 2LL * Tp;
   a.jac = a.dscale + 1;
   a.gphi = a.jac + 8LL * kSphCells * K;

@@ -2871,8 +2871,16 @@ __global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ ge
     for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) d[i] = 0ull;
     if (st_ws[m] != 0) continue;   // uniform per block
     const double *lam = pix + md.pix_off + 2 * (int64_t)g.n_pix;
-    double s = 0.0;
-    for (int q = threadIdx.x; q < g.n_pix; q += 256) s += fabs(lam[q]);
+    // eight loads in flight per thread; partial sums added in a fixed order
+    double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < g.n_pix; q0 += 8 * 256) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * 256 + threadIdx.x;
+        if (q < g.n_pix) sp[u] += fabs(lam[q]);
+      }
+    }
+    double s = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
     s = block_sum256(s, sh);
     if (threadIdx.x == 0) {
       const double *tab = gauss + md.gauss_off;
@@ -3921,7 +3929,8 @@ __global__ void __launch_bounds__(256) k_sph_sens_grid(const GeomDev *__restrict
 }
 
 // Term sensitivities of the table points' G_phi term (chi = -lambda_phi nu
-// R0^2 per cell).  Item (m, 256-term tile); thread = term, 256 cells a chunk.
+// R0^2 per cell).  Item (m, 256-term tile) split in kSphCellParts parts of
+// 256 cells; thread = term.  Each part's FP32 sums go to their own slot.
 __global__ void __launch_bounds__(256) k_sph_sens_cells(const GeomDev *__restrict__ geoms,
                                                         const ModelDev *__restrict__ models,
                                                         const Item *__restrict__ items, int n_it,
@@ -3930,8 +3939,9 @@ __global__ void __launch_bounds__(256) k_sph_sens_cells(const GeomDev *__restric
                                                         const int *__restrict__ st_ws,
                                                         double *__restrict__ sens) {
   __shared__ float4 pc[256];   // (R0^2, z0^2, chi, 0)
-  for (int i = blockIdx.x; i < n_it; i += gridDim.x) {
-    const Item it = items[i];
+  for (int vi = blockIdx.x; vi < n_it * kSphCellParts; vi += gridDim.x) {
+    const Item it = items[vi / kSphCellParts];
+    const int part = vi % kSphCellParts;
     const ModelDev md = models[it.m];
     const GeomDev g = geoms[md.geom];
     if (st_ws[it.m] != 0) continue;
@@ -3942,8 +3952,8 @@ __global__ void __launch_bounds__(256) k_sph_sens_cells(const GeomDev *__restric
     const bool tv = t < Tp;
     const float4 c = tv ? terms[md.term_off + t] : make_float4(0.f, 0.f, 0.f, 0.f);
     double SF = 0.0, SxF = 0.0, SyF = 0.0;
-    for (int c0 = 0; c0 < kSphCells; c0 += 256) {
-      const int cell = c0 + threadIdx.x;
+    {
+      const int cell = part * 256 + threadIdx.x;
       double r, sth, cth;
       sph_cell(g, cell, r, sth, cth);
       const double R0 = r * sth, z0 = r * cth;
@@ -3968,7 +3978,7 @@ __global__ void __launch_bounds__(256) k_sph_sens_cells(const GeomDev *__restric
       SyF += (double)sy;
     }
     if (tv) {
-      double *o = adj.cparts + (int64_t)t * 3;
+      double *o = adj.cparts + ((int64_t)part * Tp + t) * 3;
       o[0] = SF;
       o[1] = SxF;
       o[2] = SyF;
@@ -4002,7 +4012,13 @@ __global__ void __launch_bounds__(256) k_sph_chain(const GeomDev *__restrict__ g
 #pragma unroll
       for (int c = 0; c < 6; ++c) S[c] += o[c];
     }
-    const double *cp = adj.cparts + (int64_t)t * 3;
+    // the cell parts in order
+    double cp[3] = {0.0, 0.0, 0.0};
+    for (int pt = 0; pt < kSphCellParts; ++pt) {
+      const double *o = adj.cparts + ((int64_t)pt * Tp + t) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cp[c] += o[c];
+    }
     const double *mt = gauss + md.gauss_off + 4 * g.K;
     const int j = t / g.n_u, n = t % g.n_u;
     const double rj = mt[j], e2 = mt[g.J1 + j], Kp = mt[2 * g.J1 + j];
@@ -4506,8 +4522,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
     hipLaunchKernelGGL(k_sph_sens, dim3(grid_of(n_sens)), dim3(256), 0, st, g, m, it_sens, n_sens,
                        gauss, terms, st_ws, sens);
   }
-  hipLaunchKernelGGL(k_sph_sens_cells, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile,
-                     n_tile, gauss, terms, st_ws, sens);
+  hipLaunchKernelGGL(k_sph_sens_cells, dim3(grid_of(n_tile * kSphCellParts)), dim3(256), 0, st, g,
+                     m, it_tile, n_tile, gauss, terms, st_ws, sens);
   hipLaunchKernelGGL(k_sph_chain, dim3(grid_of(n_tile)), dim3(256), 0, st, g, m, it_tile, n_tile,
                      gauss, st_ws, sens);
   hipLaunchKernelGGL(k_sph_grads, dim3(grid_of(n)), dim3(512), 0, st, g, m, n, p, gauss, st_ws,

@@ -98,3 +98,39 @@ def test_edge_case_forward_and_adjoint(name, size, form):
     assert rel <= RTOL, (name, rel)
     assert gerr <= 1e-4 and comp.all(), (name, gerr, np.nonzero(~comp))
     ctx.close()
+
+
+@pytest.mark.parametrize("n_lum,n_mass", [(70, 1), (2, 256)])
+def test_small_map_beyond_fused_adjoint_limits(n_lum, n_mass):
+    """A map of one 32x32 block with 70 tracers (the fused small-map adjoint
+    takes them as items of at most 64 tracers: two items) and with 256 mass
+    Gaussians + BH (over the fused adjoint's 256, so the matrix-core tiles
+    and the separate chain run: two 2048-term adjoint items), forward and
+    adjoint against the FP64 oracle at the same bars."""
+    dev = _dev()
+    g = inputs.small_geometry(seed=23, n_lum=n_lum, n_mass=n_mass, nx=9, ny=7, psf_n=3,
+                              n_bins=4, n_u=4)
+    p = inputs.small_params(g, seed=23)
+    w = inputs.Workload("limits", [g], np.zeros(1, np.int32), [p])
+    cot = np.random.default_rng(7).standard_normal(g.n_bins)
+    ref_V, ref_g = ojam.vrms2_and_grad(g, p, cot)
+    ref_V = ref_V.numpy()
+    ctx = binding.Context([g], form=0)
+    assert ctx.plan_info(np.zeros(1, np.int32))["sens_items"] == 2
+    par = binding.pack_params(w, dev, amplitudes=True)
+    V, st = ctx.eval_batch(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                           par["lum_I0"], par["mass_S0"])
+    gr = ctx.vjp(w.geom_idx, par["inc"], par["mass_scale"], par["m_bh"], par["beta"],
+                 par["lum_I0"], par["mass_S0"], V, torch.as_tensor(cot, device=dev))
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == 0
+    rel = np.max(np.abs(V.cpu().numpy() / ref_V - 1.0))
+    a = _flat({k: v.cpu().numpy() for k, v in gr.items()})
+    b = _flat({k: v.numpy() for k, v in ref_g.items()})
+    gerr = np.linalg.norm(a - b) / np.linalg.norm(b)
+    comp = np.abs(a - b) <= np.maximum(1e-3 * np.abs(b), 1e-6 * np.max(np.abs(b)))
+    print(f"K={n_lum} J={n_mass}: max rel err {rel:.3e}; gradient rel norm err {gerr:.3e}, "
+          f"components ok {comp.sum()}/{comp.size}")
+    assert rel <= RTOL, rel
+    assert gerr <= 1e-4 and comp.all(), (gerr, np.nonzero(~comp))
+    ctx.close()
