@@ -2856,33 +2856,41 @@ __device__ inline SphAdj sph_adj_of(double *sens, const ModelDev &md, const Geom
 // on the order of the additions.
 // A non-finite bound stores NaN, which k_sph_dtab_fix turns into a NaN
 // cotangent.
-__global__ void __launch_bounds__(256) k_sph_zero(const GeomDev *__restrict__ geoms,
-                                                  const ModelDev *__restrict__ models, int n,
-                                                  const double *__restrict__ gauss,
-                                                  const int *__restrict__ st_ws,
-                                                  const double *__restrict__ pix,
-                                                  double *__restrict__ sens) {
-  __shared__ double sh[256];
+constexpr int kZeroThreads = 1024;
+__global__ void __launch_bounds__(kZeroThreads) k_sph_zero(const GeomDev *__restrict__ geoms,
+                                                           const ModelDev *__restrict__ models,
+                                                           int n, const double *__restrict__ gauss,
+                                                           const int *__restrict__ st_ws,
+                                                           const double *__restrict__ pix,
+                                                           double *__restrict__ sens) {
+  constexpr int kWaves = kZeroThreads / 64;
+  __shared__ double sh[kWaves];
   for (int m = blockIdx.x; m < n; m += gridDim.x) {
     const ModelDev md = models[m];
     const GeomDev g = geoms[md.geom];
     const SphAdj adj = sph_adj_of(sens, md, g);
     unsigned long long *d = reinterpret_cast<unsigned long long *>(adj.dtab);
-    for (int i = threadIdx.x; i < 3 * kSphCells; i += 256) d[i] = 0ull;
+    for (int i = threadIdx.x; i < 3 * kSphCells; i += kZeroThreads) d[i] = 0ull;
     if (st_ws[m] != 0) continue;   // uniform per block
     const double *lam = pix + md.pix_off + 2 * (int64_t)g.n_pix;
-    // eight loads in flight per thread; partial sums added in a fixed order
+    // eight loads in flight per thread; partial sums added in a fixed order,
+    // then the lanes by butterflies and the waves in order
     double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < g.n_pix; q0 += 8 * 256) {
+    for (int q0 = 0; q0 < g.n_pix; q0 += 8 * kZeroThreads) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * 256 + threadIdx.x;
+        const int q = q0 + u * kZeroThreads + threadIdx.x;
         if (q < g.n_pix) sp[u] += fabs(lam[q]);
       }
     }
     double s = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
-    s = block_sum256(s, sh);
+    s = wave_sum(s);
+    __syncthreads();                 // the previous model's reads of sh
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
+      s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += sh[w];
       const double *tab = gauss + md.gauss_off;
       double smax = 0.0;
       for (int k = 0; k < g.K; ++k) smax = fmax(smax, sqrt(0.5 / tab[k]));
@@ -4143,11 +4151,11 @@ __global__ void __launch_bounds__(512) k_sph_grads(const GeomDev *__restrict__ g
     double li = 0.0, la = 0.0;
     const int npb = (g.n_pix + 63) / 64;
     if (ok)
-      for (int b = threadIdx.x; b < npb; b += 512) {
+      for (int b = threadIdx.x; b < npb; b += 64 * kW) {
         li += adj.losp[2 * b];
         la += adj.losp[2 * b + 1];
       }
-    // fixed-order block sums: wave butterflies, then the 16 wave partials
+    // fixed-order block sums: wave butterflies, then the wave partials
     di = wave_sum(di);
     dml = wave_sum(dml);
     li = wave_sum(li);
@@ -4498,8 +4506,8 @@ void launch_sph_adjoint(const GeomDev *g, const ModelDev *m, int n, const Item *
                         const int *st_ws, const double *table, const double *pix,
                         const double *sbp, double *sens, double *sgcot, GradsDev out,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, gauss, st_ws, pix,
-                     sens);
+  hipLaunchKernelGGL(k_sph_zero, dim3(grid_of(n)), dim3(kZeroThreads), 0, st, g, m, n, gauss,
+                     st_ws, pix, sens);
   hipLaunchKernelGGL(k_sph_num_adj, dim3(grid_of(n_los)), dim3(256), 0, st, g, m, it_los, n_los,
                      gauss, st_ws, table, pix, sens);
   hipLaunchKernelGGL(k_sph_dtab_fix, dim3(grid_of(n)), dim3(256), 0, st, g, m, n, st_ws, sens);
