@@ -73,6 +73,32 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Eight wave sums at once, in a fixed order: three halving exchanges (lanes
+// 32 apart swap halves of the eight values, then 16 apart, then 8 apart)
+// leave each lane a partial of value lane / 8, and three butterflies over
+// the lane's group of eight finish it.  Returns the full sum of value
+// lane / 8 in every lane of group lane / 8 (10 exchanges instead of 48).
+__device__ inline double wave_sum8(const double (&v)[8], int lane) {
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double w[4], x[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = h5 ? v[i + 4] : v[i], send = h5 ? v[i] : v[i + 4];
+    w[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = h4 ? w[i + 2] : w[i], send = h4 ? w[i] : w[i + 2];
+    x[i] = keep + __shfl_xor(send, 16, 64);
+  }
+  const double keep = h3 ? x[1] : x[0], send = h3 ? x[0] : x[1];
+  double y = keep + __shfl_xor(send, 8, 64);
+  y += __shfl_xor(y, 4, 64);
+  y += __shfl_xor(y, 2, 64);
+  y += __shfl_xor(y, 1, 64);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // Set-up: App. A deprojection and per-Gaussian derived quantities (FP64),
 // per-model validity.
@@ -3260,18 +3286,14 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
         double qD = pD * n.Rp * (-n.zp * n.zp * nu * H + nu * 2.0 * aG[u]);
         double eP = pP * n.en * aG[u];
         double eD = pD * n.Rp * n.en * H;
-        fP = wave_sum(fP);
-        fD = wave_sum(fD);
-        bP = wave_sum(bP);
-        bD = wave_sum(bD);
-        qP = wave_sum(qP);
-        qD = wave_sum(qD);
-        eP = wave_sum(eP);
-        eD = wave_sum(eD);
+        // the eight node sums; lanes 8 f .. 8 f + 7 hold sum f
+        const double vs[8] = {fP, fD, bP, bD, qP, qD, eP, eD};
+        const double ys = wave_sum8(vs, lane);
+        if ((lane & 7) == 0)
+          adj.jac[((int64_t)kk[u] * kSphCells + cell) * 8 + (lane >> 3)] = ys;
+        fP = ys;                            // in lane 0
+        fD = __shfl(ys, 8, 64);
         if (lane == 0) {
-          double *jr = adj.jac + ((int64_t)kk[u] * kSphCells + cell) * 8;
-          jr[0] = fP; jr[1] = fD; jr[2] = bP; jr[3] = bD;
-          jr[4] = qP; jr[5] = qD; jr[6] = eP; jr[7] = eD;
           const double P = pow(r, -2.0 * be) * fP;
           Ar += P;
           At += (1.0 - be) * P;
