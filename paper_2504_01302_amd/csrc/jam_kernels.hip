@@ -2654,7 +2654,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
     const int rounds = (K + kTr - 1) / kTr; // the same in every wave
     for (int q = 0; q < rounds; ++q) {
       double alpha[kTr], alphaq[kTr], beta[kTr], wn[kTr], nuv[kTr], rp[kTr], Rp[kTr], Zp[kTr];
-      double lrp[kTr];                       // ln r' (powers of r' as exponentials)
+      double rbe[kTr], rpb[kTr];             // r^beta, r'^beta (the powers are their products)
       float R2[kTr], Z2[kTr];
       bool on[kTr];
 #pragma unroll
@@ -2662,7 +2662,7 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
         const int k = kTr * q + u;
         on[u] = k < K;                      // uniform
         alpha[u] = 1.0; alphaq[u] = 1.0; beta[u] = 0.0; wn[u] = 0.0; nuv[u] = 0.0;
-        rp[u] = r; lrp[u] = lnr; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
+        rp[u] = r; rbe[u] = 1.0; rpb[u] = 1.0; Rp[u] = 0.0; Zp[u] = 0.0; R2[u] = 0.f; Z2[u] = 0.f;
         if (on[u]) {
           alpha[u] = tab[k];
           alphaq[u] = tab[K + k];
@@ -2670,9 +2670,12 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
           const double tmax = 0.5 * log1p(50.0 * (0.5 / alpha[u]) / (r * r));
           const double hs = tmax / kSphSeg;
           const double tau = (seg + 0.5 + 0.5 * glx) * hs;
-          lrp[u] = lnr + tau;
-          rp[u] = exp(lrp[u]);
-          const double st = fmin(1.0, sth * exp(-(1.0 - beta[u]) * tau));
+          rp[u] = exp(lnr + tau);
+          // (r'/r)^beta; sin theta' = sin theta (r / r')^(1 - beta)
+          const double rbt = exp(beta[u] * tau);
+          rbe[u] = exp(beta[u] * lnr);
+          rpb[u] = rbe[u] * rbt;
+          const double st = fmin(1.0, sth * (r / rp[u]) * rbt);
           const double ct = sqrt(fmax(0.0, 1.0 - st * st));
           Rp[u] = rp[u] * st;
           const double zp = rp[u] * ct;
@@ -2737,15 +2740,18 @@ __global__ void __launch_bounds__(256) k_sph_moments(const GeomDev *__restrict__
       for (int u = 0; u < kTr; ++u) {
         if (!on[u]) continue;
         const double sk2 = 0.5 / alpha[u], qk2 = alpha[u] / alphaq[u];
-        double fP = wn[u] * exp((2.0 * beta[u] + 1.0) * lrp[u]) * nuv[u] * accG[u];
-        double fD = wn[u] * exp((3.0 * beta[u] + 1.0) * lrp[u]) * Rp[u] * nuv[u] *
-                    (accT[u] + accG[u] * (1.0 / qk2 - 1.0) / sk2);
+        // r'^(2 beta + 1) and r'^(3 beta + 1)
+        const double p2 = rp[u] * rpb[u] * rpb[u], p3 = p2 * rpb[u];
+        double fP = wn[u] * p2 * nuv[u] * accG[u];
+        double fD = wn[u] * p3 * Rp[u] * nuv[u] * (accT[u] + accG[u] * (1.0 / qk2 - 1.0) / sk2);
         fP = wave_sum(fP);
         fD = wave_sum(fD);
-        const double P = pow(r, -2.0 * beta[u]) * fP;
+        // r^(-2 beta) and r^(1 - 3 beta)
+        const double rb2 = rbe[u] * rbe[u];
+        const double P = fP / rb2;
         Ar += P;
         At += (1.0 - beta[u]) * P;
-        Ap += (1.0 - beta[u]) * P + (1.0 - beta[u]) * sth * pow(r, 1.0 - 3.0 * beta[u]) * fD;
+        Ap += (1.0 - beta[u]) * P + (1.0 - beta[u]) * sth * (r / (rb2 * rbe[u])) * fD;
       }
     }
     // G_phi and the tracer density at the point, lane sums in a fixed order
@@ -2836,7 +2842,7 @@ __device__ inline void sph_angular_weights(int yi, double fy, double *ew, double
 // Node of tracer k's characteristic through table point (r, theta): the same
 // FP64 operations as the forward moment kernel.
 struct SphNode {
-  double rp, st, ct, Rp, zp, wn, en, tau;
+  double rp, st, ct, Rp, zp, wn, en, tau, rbt;   // rbt = (r'/r)^beta
   bool clamped;
 };
 __device__ inline SphNode sph_node(double r, double lnr, double sth, double alpha, double alphaq,
@@ -2846,7 +2852,8 @@ __device__ inline SphNode sph_node(double r, double lnr, double sth, double alph
   const double hs = tmax / kSphSeg;
   o.tau = (seg + 0.5 + 0.5 * glx) * hs;
   o.rp = exp(lnr + o.tau);
-  const double sraw = sth * exp(-(1.0 - beta) * o.tau);
+  o.rbt = exp(beta * o.tau);
+  const double sraw = sth * (r / o.rp) * o.rbt;   // sin theta (r / r')^(1 - beta)
   o.clamped = !(sraw < 1.0);
   o.st = fmin(1.0, sraw);
   o.ct = sqrt(fmax(0.0, 1.0 - o.st * o.st));
@@ -3275,8 +3282,10 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
         const double dG = kLn2 * (aGR[u] * dR2 + aGZ[u] * dZ2);
         const double dH = kLn2 * (aTR[u] * dR2 + aTZ[u] * dZ2) + kap * dG;
         const double lrp = lnr + n.tau;     // ln r'
-        const double pP = n.wn * exp((2.0 * be + 1.0) * lrp);
-        const double pD = n.wn * exp((3.0 * be + 1.0) * lrp);
+        // r'^beta = r^beta (r'/r)^beta; r'^(2 beta + 1), r'^(3 beta + 1)
+        const double rbe = exp(be * lnr), rpb = rbe * n.rbt;
+        const double pP = n.wn * n.rp * rpb * rpb;
+        const double pD = pP * rpb;
         double fP = pP * nu * aG[u];
         double fD = pD * n.Rp * nu * H;
         double bP = pP * (2.0 * lrp * nu * aG[u] + dnu * aG[u] + nu * dG);
@@ -3294,10 +3303,11 @@ __global__ void __launch_bounds__(256) k_sph_moments_jac(const GeomDev *__restri
         fP = ys;                            // in lane 0
         fD = __shfl(ys, 8, 64);
         if (lane == 0) {
-          const double P = pow(r, -2.0 * be) * fP;
+          const double rb2 = rbe * rbe;     // r^(-2 beta), r^(1 - 3 beta) below
+          const double P = fP / rb2;
           Ar += P;
           At += (1.0 - be) * P;
-          Ap += (1.0 - be) * P + (1.0 - be) * sth * pow(r, 1.0 - 3.0 * be) * fD;
+          Ap += (1.0 - be) * P + (1.0 - be) * sth * (r / (rb2 * rbe)) * fD;
         }
       }
     }
@@ -3350,7 +3360,8 @@ __global__ void __launch_bounds__(64) k_sph_rows(const GeomDev *__restrict__ geo
       const double fP = jr[0], fD = jr[1], bP = jr[2], bD = jr[3];
       const double qP = jr[4], qD = jr[5], eP = jr[6], eD = jr[7];
       const double be = 1.0 - 1.0 / tab[3 * K + k];
-      const double rb = pow(r, -2.0 * be), rd = pow(r, 1.0 - 3.0 * be);
+      const double rbe = exp(be * lnr);   // r^beta: r^(-2 beta), r^(1 - 3 beta)
+      const double rb = 1.0 / (rbe * rbe), rd = r * rb / rbe;
       const double P = rb * fP;
       const double muP = lr + (1.0 - be) * (lt + lp);
       const double muD = lp * (1.0 - be) * sth * rd;
@@ -3390,18 +3401,21 @@ __device__ inline void sph_point_cot(const GeomDev &g, const GeomDev *__restrict
   const double glx = gp->gl8_x[gi], glw = gp->gl8_w[gi];
   const double hs = 0.5 * log1p(50.0 * (0.5 / alpha) / (r * r)) / kSphSeg;
   const double tau = ((node >> 3) + 0.5 + 0.5 * glx) * hs;
-  const double lrp = lnr + tau, rp = exp(lrp);
-  const double st = fmin(1.0, sth * exp(-(1.0 - beta) * tau));
+  const double rp = exp(lnr + tau);
+  const double rbt = exp(beta * tau);    // (r'/r)^beta
+  const double st = fmin(1.0, sth * (r / rp) * rbt);
   const double ct = sqrt(fmax(0.0, 1.0 - st * st));
   Rp = rp * st;
   zp = rp * ct;
   const double wn = 0.5 * glw * hs * rp;
   const double nu = nu0 * exp(-(alpha * Rp * Rp + alphaq * zp * zp));
   const double muP = lr + (1.0 - beta) * (lt + lp);
-  const double muD = lp * (1.0 - beta) * sth * exp((1.0 - 3.0 * beta) * lnr);
-  const double dD = muD * wn * exp((3.0 * beta + 1.0) * lrp) * Rp * nu;
-  phi = muP * wn * exp((2.0 * beta + 1.0) * lrp - 2.0 * beta * lnr) * nu +
-        dD * 2.0 * (alphaq - alpha);
+  // r^beta, r'^beta; r^(1 - 3 beta), r'^(3 beta + 1) and r'^(2 beta + 1)
+  // r^(-2 beta) = r' (r'/r)^(2 beta) as their products
+  const double rbe = exp(beta * lnr), rpb = rbe * rbt;
+  const double muD = lp * (1.0 - beta) * sth * (r / (rbe * rbe * rbe));
+  const double dD = muD * wn * (rp * rpb * rpb * rpb) * Rp * nu;
+  phi = muP * wn * (rp * rbt * rbt) * nu + dD * 2.0 * (alphaq - alpha);
   psi = dD;
 }
 
