@@ -3018,7 +3018,9 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
       const int seg = nd >> 3, gi = nd & 7;
       const double om = -1.0 + (seg + 0.5 + 0.5 * glx[gi]) / 4.0;   // w = W om
       const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
-      const double shw = sinh(w), chw = cosh(w);
+      // sinh w, cosh w from one exponential (|w| > 0.004 W at every node)
+      const double ex = exp(w), iex = 1.0 / ex;
+      const double shw = 0.5 * (ex - iex), chw = 0.5 * (ex + iex);
       const double zp = a * shw, wz = 0.5 * glw[gi] * hw * a * chw;
       const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
       const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
@@ -3055,10 +3057,16 @@ __global__ void __launch_bounds__(256) k_sph_num_adj(const GeomDev *__restrict__
             if (cf != 0.0 && fixed)
               atomicAdd(d + f, (unsigned long long)__double2ll_rn(cf * scale));
             A[f] += ew[a] * tw[b] * c[f];
-            if (xin) AL[f] += dew[a] * tw[b] * c[f] / g.sph_dlnr;
-            AT[f] += ew[a] * dtw[b] * c[f] / dth;
+            if (xin) AL[f] += dew[a] * tw[b] * c[f];
+            AT[f] += ew[a] * dtw[b] * c[f];
           }
         }
+      }
+      // the weight derivatives are per unit of the table's index steps
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        AL[f] /= g.sph_dlnr;
+        AT[f] /= dth;
       }
       // derivatives of ln r and theta = atan2(R, |Z|) with respect to Y and Z
       const double r2 = r * r, sz = Z < 0.0 ? -1.0 : 1.0;
@@ -4333,7 +4341,9 @@ __global__ void __launch_bounds__(256) k_sph_num(const GeomDev *__restrict__ geo
     for (int nd = h * kLosNodes; on && nd < (h + 1) * kLosNodes; ++nd) {
       const int seg = nd >> 3, gi = nd & 7;
       const double w = -W + (seg + 0.5 + 0.5 * glx[gi]) * hw;
-      const double zp = a * sinh(w), wz = 0.5 * glw[gi] * hw * a * cosh(w);
+      // sinh w, cosh w from one exponential (|w| > 0.004 W at every node)
+      const double ex = exp(w), iex = 1.0 / ex;
+      const double zp = a * (0.5 * (ex - iex)), wz = 0.5 * glw[gi] * hw * a * (0.5 * (ex + iex));
       const double X = x, Y = zp * si - y * ci, Z = y * si + zp * ci;
       const double R = sqrt(X * X + Y * Y), r = sqrt(R * R + Z * Z);
       const double ct = Z / r, st = R / r;
